@@ -1,0 +1,377 @@
+/*
+ * hepkref -- CPU oracle of the jagged-array analysis kernels (arXiv:1906.06242).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark, never by the GPU library.
+ *
+ * Plain and single-threaded on purpose: events in ascending order, objects of
+ * an event in ascending content index, one operation at a time, so that each
+ * function can be checked against the paper by eye.  Build with
+ * -O2 -ffp-contract=off and without -ffast-math so float32 expressions are
+ * rounded operation by operation.
+ */
+#include "hepkref.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* float32 pi and 2*pi, rounded to nearest (0x40490FDB, 0x40C90FDB) */
+static const float REF_PI = 0x1.921fb6p+1f;
+static const float REF_TWO_PI = 0x1.921fb6p+2f;
+
+/* IEEE 754 binary16: 1 sign bit, 5 exponent bits (bias 15), 10 fraction bits. */
+float hepkref_half_to_float(uint16_t h)
+{
+    uint32_t sign = (uint32_t)(h >> 15) & 1u;
+    uint32_t ex = (uint32_t)(h >> 10) & 0x1fu;
+    uint32_t fr = (uint32_t)h & 0x3ffu;
+    float mag;
+    if (ex == 0) {
+        /* zero or subnormal: fr * 2^-24, exact in float32 */
+        mag = ldexpf((float)fr, -24);
+    } else if (ex == 31) {
+        if (fr == 0) {
+            mag = INFINITY;
+        } else {
+            /* NaN: keep the payload in the top fraction bits, as a widening does */
+            uint32_t bits = (sign << 31) | 0x7f800000u | (fr << 13);
+            float f;
+            memcpy(&f, &bits, 4);
+            return f;
+        }
+    } else {
+        /* normal: (1 + fr/1024) * 2^(ex-15), exact in float32 */
+        mag = ldexpf((float)(1024u + fr), (int)ex - 25);
+    }
+    return sign ? -mag : mag;
+}
+
+static float load_f(const void *col, int32_t dtype, int64_t i)
+{
+    if (dtype == HEPKREF_F16)
+        return hepkref_half_to_float(((const uint16_t *)col)[i]);
+    return ((const float *)col)[i];
+}
+
+static int valid_float_dtype(int32_t dtype)
+{
+    return dtype == HEPKREF_F32 || dtype == HEPKREF_F16;
+}
+
+/* ---- object and event masks (Sec. III: masks chained between kernels) ---- */
+
+static int cmp_float(float v, int32_t op, float t)
+{
+    switch (op) {
+    case HEPKREF_GT: return v > t;
+    case HEPKREF_GE: return v >= t;
+    case HEPKREF_LT: return v < t;
+    case HEPKREF_LE: return v <= t;
+    case HEPKREF_ABS_LT: return fabsf(v) < t;
+    case HEPKREF_ABS_LE: return fabsf(v) <= t;
+    }
+    return 0;
+}
+
+static int cmp_int(int32_t v, int32_t op, int32_t t)
+{
+    switch (op) {
+    case HEPKREF_GT: return v > t;
+    case HEPKREF_GE: return v >= t;
+    case HEPKREF_LT: return v < t;
+    case HEPKREF_LE: return v <= t;
+    case HEPKREF_ABS_LT: return abs(v) < t;
+    case HEPKREF_ABS_LE: return abs(v) <= t;
+    }
+    return 0;
+}
+
+int hepkref_select(const hepkref_cut *cuts, int32_t n_cuts, int64_t n,
+                   const uint8_t *mask_in, uint8_t *mask_out)
+{
+    if (n < 0 || n_cuts < 0 || (n > 0 && !mask_out) || (n_cuts > 0 && !cuts))
+        return HEPKREF_EINVAL;
+    for (int32_t k = 0; k < n_cuts; k++) {
+        if (!cuts[k].col && n > 0) return HEPKREF_EINVAL;
+        if (cuts[k].op < HEPKREF_GT || cuts[k].op > HEPKREF_ABS_LE) return HEPKREF_EINVAL;
+        if (cuts[k].dtype != HEPKREF_F32 && cuts[k].dtype != HEPKREF_F16 &&
+            cuts[k].dtype != HEPKREF_I32)
+            return HEPKREF_EINVAL;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        int pass = mask_in ? (mask_in[i] != 0) : 1;
+        for (int32_t k = 0; k < n_cuts; k++) {
+            const hepkref_cut *c = &cuts[k];
+            int ok;
+            if (c->dtype == HEPKREF_I32)
+                ok = cmp_int(((const int32_t *)c->col)[i], c->op, c->ithr);
+            else
+                ok = cmp_float(load_f(c->col, c->dtype, i), c->op, c->thr);
+            pass = pass && ok;
+        }
+        mask_out[i] = (uint8_t)(pass ? 1 : 0);
+    }
+    return HEPKREF_OK;
+}
+
+/* ---- per-event reductions (Sec. III: the H_T kernel of Listing 1 and the
+ * sum/max/min-within-offsets kernels).  Listing 1 visits events one by one and
+ * the objects of an event in order, adding selected objects into the event's
+ * output; here every event's output is written, with the empty result when
+ * the event is masked out or has no selected object. ---- */
+
+int hepkref_reduce(int32_t op, const int64_t *offsets, int64_t n_events,
+                   const void *content, int32_t dtype,
+                   const uint8_t *obj_mask, const uint8_t *evt_mask,
+                   void *out, int32_t *out_arg, int64_t *offsets_out)
+{
+    if (n_events < 0 || !offsets || (n_events > 0 && !out)) return HEPKREF_EINVAL;
+    if (op < HEPKREF_COUNT || op > HEPKREF_ARGMIN) return HEPKREF_EINVAL;
+    if (op != HEPKREF_COUNT) {
+        if (!valid_float_dtype(dtype)) return HEPKREF_EUNSUPPORTED;
+        if (!content && n_events > 0 && offsets[n_events] > 0) return HEPKREF_EINVAL;
+    }
+    int64_t running = 0;
+    if (offsets_out) offsets_out[0] = 0;
+    for (int64_t e = 0; e < n_events; e++) {
+        int take_event = evt_mask ? (evt_mask[e] != 0) : 1;
+        int64_t i0 = offsets[e], i1 = offsets[e + 1];
+        if (op == HEPKREF_COUNT) {
+            int32_t cnt = 0;
+            if (take_event)
+                for (int64_t i = i0; i < i1; i++)
+                    if (!obj_mask || obj_mask[i]) cnt++;
+            ((int32_t *)out)[e] = cnt;
+            running += cnt;
+            if (offsets_out) offsets_out[e + 1] = running;
+        } else if (op == HEPKREF_SUM) {
+            float acc = 0.0f;
+            if (take_event)
+                for (int64_t i = i0; i < i1; i++)
+                    if (!obj_mask || obj_mask[i]) acc = acc + load_f(content, dtype, i);
+            ((float *)out)[e] = acc;
+        } else {
+            int want_max = (op == HEPKREF_MAX || op == HEPKREF_ARGMAX);
+            float best = want_max ? -INFINITY : INFINITY;
+            int32_t bi = -1;
+            if (take_event)
+                for (int64_t i = i0; i < i1; i++) {
+                    if (obj_mask && !obj_mask[i]) continue;
+                    float v = load_f(content, dtype, i);
+                    int better = want_max ? (v > best) : (v < best);
+                    if (bi < 0 || better) {
+                        best = v;
+                        bi = (int32_t)(i - i0);
+                    }
+                }
+            if (op == HEPKREF_MAX || op == HEPKREF_MIN) {
+                ((float *)out)[e] = best;
+                if (out_arg) out_arg[e] = bi;
+            } else {
+                ((int32_t *)out)[e] = bi;
+            }
+        }
+    }
+    return HEPKREF_OK;
+}
+
+/* ---- Delta-R matching between two collections (Sec. III: the kernel that
+ * masks objects of a first collection lying within a given Delta-R of an object
+ * of a second collection; Sec. IV: jet-lepton matching).
+ * dR^2 = deta^2 + dphi^2, dphi brought back into [-pi, pi] once. ---- */
+
+int hepkref_match_dr(const int64_t *off_a, const void *eta_a, const void *phi_a,
+                     const uint8_t *mask_a,
+                     const int64_t *off_b, const void *eta_b, const void *phi_b,
+                     const uint8_t *mask_b, int32_t dtype, int64_t n_events,
+                     float dr, float *min_dr2, int32_t *idx_b, uint8_t *clean)
+{
+    if (n_events < 0 || !off_a || !off_b) return HEPKREF_EINVAL;
+    if (!valid_float_dtype(dtype)) return HEPKREF_EUNSUPPORTED;
+    float thr2 = dr * dr;
+    for (int64_t e = 0; e < n_events; e++) {
+        for (int64_t a = off_a[e]; a < off_a[e + 1]; a++) {
+            float ea = load_f(eta_a, dtype, a);
+            float pa = load_f(phi_a, dtype, a);
+            float best = INFINITY;
+            int32_t bi = -1;
+            for (int64_t b = off_b[e]; b < off_b[e + 1]; b++) {
+                if (mask_b && !mask_b[b]) continue;
+                float deta = ea - load_f(eta_b, dtype, b);
+                float dphi = pa - load_f(phi_b, dtype, b);
+                if (dphi > REF_PI)
+                    dphi = dphi - REF_TWO_PI;
+                else if (dphi < -REF_PI)
+                    dphi = dphi + REF_TWO_PI;
+                float dr2 = deta * deta + dphi * dphi;
+                if (dr2 < best) {
+                    best = dr2;
+                    bi = (int32_t)(b - off_b[e]);
+                }
+            }
+            if (min_dr2) min_dr2[a] = best;
+            if (idx_b) idx_b[a] = bi;
+            if (clean) {
+                int keep = mask_a ? (mask_a[a] != 0) : 1;
+                clean[a] = (uint8_t)((keep && !(best <= thr2)) ? 1 : 0);
+            }
+        }
+    }
+    return HEPKREF_OK;
+}
+
+/* ---- weighted histogram fill (Sec. III: the fill-histogram kernel) ---- */
+
+int hepkref_hist_fill(const void *x, int32_t dtype, const float *w,
+                      const uint8_t *evt_mask, int64_t n,
+                      const float *edges, int32_t nbins,
+                      double *sumw, uint64_t *counts)
+{
+    if (n < 0 || nbins < 1 || !edges || !sumw || !counts || (n > 0 && !x))
+        return HEPKREF_EINVAL;
+    if (dtype != HEPKREF_F32 && dtype != HEPKREF_F16 && dtype != HEPKREF_I32)
+        return HEPKREF_EINVAL;
+    for (int64_t i = 0; i < n; i++) {
+        if (evt_mask && !evt_mask[i]) continue;
+        float v = (dtype == HEPKREF_I32) ? (float)((const int32_t *)x)[i] : load_f(x, dtype, i);
+        if (v != v) continue; /* NaN */
+        int32_t b;
+        if (v < edges[0]) {
+            b = 0;
+        } else {
+            b = nbins + 1;
+            for (int32_t k = 0; k < nbins; k++) {
+                if (v < edges[k + 1]) {
+                    b = k + 1;
+                    break;
+                }
+            }
+        }
+        counts[b] += 1u;
+        sumw[b] += (double)(w ? w[i] : 1.0f);
+    }
+    return HEPKREF_OK;
+}
+
+/* ---- the analysis pass: object selection, lepton-jet cleaning, per-event
+ * reductions, event selection and histograms (Sec. IV feature list), built from
+ * the kernels above as the steering code of Sec. III would chain them. ---- */
+
+static void *xmalloc(size_t n)
+{
+    return malloc(n ? n : 1);
+}
+
+static hepkref_cut mkcut(const void *col, int32_t dtype, int32_t op, float thr)
+{
+    hepkref_cut c;
+    c.col = col;
+    c.dtype = dtype;
+    c.op = op;
+    c.thr = thr;
+    c.ithr = 0;
+    return c;
+}
+
+static hepkref_cut mkicut(const void *col, int32_t op, int32_t ithr)
+{
+    hepkref_cut c;
+    c.col = col;
+    c.dtype = HEPKREF_I32;
+    c.op = op;
+    c.thr = 0.0f;
+    c.ithr = ithr;
+    return c;
+}
+
+int hepkref_pipeline(const hepkref_dataset *ds, const hepkref_query *qs, int32_t n_query,
+                     double *const *sumw, uint64_t *const *counts)
+{
+    if (!ds || !qs || n_query < 0 || !sumw || !counts) return HEPKREF_EINVAL;
+    if (!valid_float_dtype(ds->dtype) || ds->n_events < 0) return HEPKREF_EINVAL;
+    const int64_t N = ds->n_events;
+    const int32_t dt = ds->dtype;
+    const int has_el = ds->electrons.off != NULL;
+    const int has_btag = ds->jets.extra != NULL;
+    const int64_t Mj = ds->jets.off[N], Mm = ds->muons.off[N];
+    const int64_t Me = has_el ? ds->electrons.off[N] : 0;
+
+    uint8_t *msel = xmalloc((size_t)Mm), *esel = xmalloc((size_t)Me);
+    uint8_t *clean = xmalloc((size_t)Mj), *clean_e = xmalloc((size_t)Mj);
+    uint8_t *jsel = xmalloc((size_t)Mj), *bsel = xmalloc((size_t)Mj);
+    float *ptv = xmalloc(sizeof(float) * (size_t)Mj);
+    int32_t *n_mu = xmalloc(sizeof(int32_t) * (size_t)N);
+    int32_t *n_jet = xmalloc(sizeof(int32_t) * (size_t)N);
+    int32_t *n_b = xmalloc(sizeof(int32_t) * (size_t)N);
+    float *ht = xmalloc(sizeof(float) * (size_t)N);
+    float *lead = xmalloc(sizeof(float) * (size_t)N);
+    uint8_t *pass = xmalloc((size_t)N);
+
+    int32_t k = 0;
+    for (int32_t iq = 0; iq < n_query; iq++) {
+        const hepkref_query *q = &qs[iq];
+        /* muon selection: pt, |eta|, isolation */
+        hepkref_cut mc[3];
+        int nmc = 0;
+        mc[nmc++] = mkcut(ds->muons.pt, dt, HEPKREF_GT, q->mu_pt);
+        mc[nmc++] = mkcut(ds->muons.eta, dt, HEPKREF_ABS_LT, q->mu_abseta);
+        if (ds->muons.extra) mc[nmc++] = mkcut(ds->muons.extra, dt, HEPKREF_LT, q->mu_iso);
+        hepkref_select(mc, nmc, Mm, NULL, msel);
+        hepkref_reduce(HEPKREF_COUNT, ds->muons.off, N, NULL, dt, msel, NULL, n_mu, NULL, NULL);
+
+        /* jets cleaned against selected muons (and selected electrons) */
+        hepkref_match_dr(ds->jets.off, ds->jets.eta, ds->jets.phi, NULL,
+                         ds->muons.off, ds->muons.eta, ds->muons.phi, msel,
+                         dt, N, q->dr, NULL, NULL, clean);
+        if (has_el) {
+            hepkref_cut ec[2];
+            ec[0] = mkcut(ds->electrons.pt, dt, HEPKREF_GT, q->el_pt);
+            ec[1] = mkcut(ds->electrons.eta, dt, HEPKREF_ABS_LT, q->el_abseta);
+            hepkref_select(ec, 2, Me, NULL, esel);
+            hepkref_match_dr(ds->jets.off, ds->jets.eta, ds->jets.phi, clean,
+                             ds->electrons.off, ds->electrons.eta, ds->electrons.phi, esel,
+                             dt, N, q->dr, NULL, NULL, clean_e);
+            memcpy(clean, clean_e, (size_t)Mj);
+        }
+
+        for (int32_t v = 0; v < q->n_scale; v++) {
+            /* jet energy scale applied to pt (one float32 product) */
+            const float s = q->scales[v];
+            for (int64_t j = 0; j < Mj; j++) ptv[j] = load_f(ds->jets.pt, dt, j) * s;
+            hepkref_cut jc[2];
+            jc[0] = mkcut(ptv, HEPKREF_F32, HEPKREF_GT, q->jet_pt);
+            jc[1] = mkcut(ds->jets.eta, dt, HEPKREF_ABS_LT, q->jet_abseta);
+            hepkref_select(jc, 2, Mj, clean, jsel);
+
+            hepkref_reduce(HEPKREF_COUNT, ds->jets.off, N, NULL, dt, jsel, NULL, n_jet, NULL, NULL);
+            hepkref_reduce(HEPKREF_SUM, ds->jets.off, N, ptv, HEPKREF_F32, jsel, NULL, ht, NULL, NULL);
+            hepkref_reduce(HEPKREF_MAX, ds->jets.off, N, ptv, HEPKREF_F32, jsel, NULL, lead, NULL, NULL);
+
+            hepkref_cut ev[3];
+            int nev = 0;
+            ev[nev++] = mkicut(n_mu, HEPKREF_GE, q->min_mu);
+            ev[nev++] = mkicut(n_jet, HEPKREF_GE, q->min_jet);
+            if (has_btag) {
+                hepkref_cut bc = mkcut(ds->jets.extra, dt, HEPKREF_GT, q->btag);
+                hepkref_select(&bc, 1, Mj, jsel, bsel);
+                hepkref_reduce(HEPKREF_COUNT, ds->jets.off, N, NULL, dt, bsel, NULL, n_b, NULL, NULL);
+                ev[nev++] = mkicut(n_b, HEPKREF_GE, q->min_b);
+            }
+            hepkref_select(ev, nev, N, NULL, pass);
+
+            hepkref_hist_fill(ht, HEPKREF_F32, ds->weights, pass, N, q->edges[0], q->nbins[0],
+                              sumw[k], counts[k]);
+            k++;
+            hepkref_hist_fill(lead, HEPKREF_F32, ds->weights, pass, N, q->edges[1], q->nbins[1],
+                              sumw[k], counts[k]);
+            k++;
+            hepkref_hist_fill(n_jet, HEPKREF_I32, ds->weights, pass, N, q->edges[2], q->nbins[2],
+                              sumw[k], counts[k]);
+            k++;
+        }
+    }
+    free(msel); free(esel); free(clean); free(clean_e); free(jsel); free(bsel); free(ptv);
+    free(n_mu); free(n_jet); free(n_b); free(ht); free(lead); free(pass);
+    return HEPKREF_OK;
+}

@@ -1,0 +1,222 @@
+"""Python access to the CPU oracle (hepkref.c) on numpy arrays.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark.  The GPU library never imports it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import List, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "hepkref.c")
+LIB = os.environ.get("HEPKREF_LIB") or os.path.join(HERE, "libhepkref.so")
+
+# float32 cut arithmetic rounded operation by operation: no contraction into
+# fused multiply-adds and no fast-math reassociation.
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+          "-Wall", "-Wextra", "-Wno-unused-parameter"]
+
+F32, F16, I32 = 0, 1, 2
+GT, GE, LT, LE, ABS_LT, ABS_LE = range(6)
+COUNT, SUM, MAX, MIN, ARGMAX, ARGMIN = range(6)
+
+
+def build(force: bool = False, extra_flags: Sequence[str] = ()) -> str:
+    """Compile libhepkref.so with gcc (also the "does it build" step)."""
+    if os.environ.get("HEPKREF_LIB"):
+        return LIB
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
+            os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "hepkref.h"))):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, *extra_flags, "-shared", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Cut(C.Structure):
+    _fields_ = [("col", C.c_void_p), ("dtype", C.c_int32), ("op", C.c_int32),
+                ("thr", C.c_float), ("ithr", C.c_int32)]
+
+
+class Coll(C.Structure):
+    _fields_ = [("off", C.c_void_p), ("pt", C.c_void_p), ("eta", C.c_void_p),
+                ("phi", C.c_void_p), ("extra", C.c_void_p)]
+
+
+class DatasetS(C.Structure):
+    _fields_ = [("n_events", C.c_int64), ("dtype", C.c_int32),
+                ("jets", Coll), ("muons", Coll), ("electrons", Coll),
+                ("weights", C.c_void_p)]
+
+
+class QueryS(C.Structure):
+    _fields_ = [("mu_pt", C.c_float), ("mu_abseta", C.c_float), ("mu_iso", C.c_float),
+                ("el_pt", C.c_float), ("el_abseta", C.c_float),
+                ("jet_pt", C.c_float), ("jet_abseta", C.c_float),
+                ("dr", C.c_float), ("btag", C.c_float),
+                ("min_mu", C.c_int32), ("min_jet", C.c_int32), ("min_b", C.c_int32),
+                ("n_scale", C.c_int32), ("scales", C.c_void_p),
+                ("edges", C.c_void_p * 3), ("nbins", C.c_int32 * 3)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        _lib.hepkref_half_to_float.restype = C.c_float
+        _lib.hepkref_half_to_float.argtypes = [C.c_uint16]
+        _lib.hepkref_select.argtypes = [C.POINTER(Cut), C.c_int32, C.c_int64, C.c_void_p, C.c_void_p]
+        _lib.hepkref_reduce.argtypes = [C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib.hepkref_match_dr.argtypes = [C.c_void_p] * 4 + [C.c_void_p] * 4 + [
+            C.c_int32, C.c_int64, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib.hepkref_hist_fill.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
+                                           C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+        _lib.hepkref_pipeline.argtypes = [C.POINTER(DatasetS), C.POINTER(QueryS), C.c_int32,
+                                          C.c_void_p, C.c_void_p]
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _dt(a: np.ndarray) -> int:
+    return {np.dtype(np.float32): F32, np.dtype(np.float16): F16,
+            np.dtype(np.int32): I32}[a.dtype]
+
+
+def _check(rc):
+    if rc != 0:
+        raise ValueError(f"oracle returned {rc}")
+
+
+def half_to_float(h: int) -> float:
+    return lib().hepkref_half_to_float(h)
+
+
+def select(cuts, n: int, mask_in=None) -> np.ndarray:
+    """cuts: list of (column array, op, threshold)."""
+    arr = (Cut * max(1, len(cuts)))()
+    keep = []
+    for i, (col, op, thr) in enumerate(cuts):
+        col = np.ascontiguousarray(col)
+        keep.append(col)
+        if col.dtype == np.int32:
+            arr[i] = Cut(col.ctypes.data, I32, op, 0.0, int(thr))
+        else:
+            arr[i] = Cut(col.ctypes.data, _dt(col), op, float(thr), 0)
+    out = np.empty(n, np.uint8)
+    _check(lib().hepkref_select(arr, len(cuts), n, _p(mask_in), out.ctypes.data))
+    return out
+
+
+def reduce(op: int, offsets: np.ndarray, content=None, obj_mask=None, evt_mask=None,
+           want_arg: bool = False, want_offsets: bool = False):
+    n = len(offsets) - 1
+    if op in (COUNT, ARGMAX, ARGMIN):
+        out = np.empty(n, np.int32)
+    else:
+        out = np.empty(n, np.float32)
+    arg = np.empty(n, np.int32) if want_arg else None
+    offo = np.empty(n + 1, np.int64) if want_offsets else None
+    dt = _dt(content) if content is not None else F32
+    _check(lib().hepkref_reduce(op, offsets.ctypes.data, n, _p(content), dt,
+                                _p(obj_mask), _p(evt_mask), out.ctypes.data,
+                                _p(arg), _p(offo)))
+    res = [out]
+    if want_arg:
+        res.append(arg)
+    if want_offsets:
+        res.append(offo)
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def match_dr(off_a, eta_a, phi_a, off_b, eta_b, phi_b, dr: float,
+             mask_a=None, mask_b=None):
+    """Returns (min_dr2 float32[Ma], idx int32[Ma], clean uint8[Ma])."""
+    ma = int(off_a[-1])
+    md = np.empty(ma, np.float32)
+    ix = np.empty(ma, np.int32)
+    cl = np.empty(ma, np.uint8)
+    _check(lib().hepkref_match_dr(off_a.ctypes.data, eta_a.ctypes.data, phi_a.ctypes.data,
+                                  _p(mask_a), off_b.ctypes.data, eta_b.ctypes.data,
+                                  phi_b.ctypes.data, _p(mask_b), _dt(eta_a), len(off_a) - 1,
+                                  dr, md.ctypes.data, ix.ctypes.data, cl.ctypes.data))
+    return md, ix, cl
+
+
+def hist_fill(x, edges, w=None, evt_mask=None, sumw=None, counts=None):
+    nb = len(edges) - 1
+    if sumw is None:
+        sumw = np.zeros(nb + 2, np.float64)
+    if counts is None:
+        counts = np.zeros(nb + 2, np.uint64)
+    edges = np.ascontiguousarray(edges, np.float32)
+    _check(lib().hepkref_hist_fill(x.ctypes.data, _dt(x), _p(w), _p(evt_mask), len(x),
+                                   edges.ctypes.data, nb, sumw.ctypes.data, counts.ctypes.data))
+    return sumw, counts
+
+
+def _coll(c, names):
+    if c is None:
+        return Coll(None, None, None, None, None), []
+    keep = [c.offsets] + [c.cols[k] for k in names if k in c.cols]
+    extra = None
+    for k in ("iso", "btag"):
+        if k in c.cols:
+            extra = c.cols[k].ctypes.data
+    return Coll(c.offsets.ctypes.data, c.cols["pt"].ctypes.data, c.cols["eta"].ctypes.data,
+                c.cols["phi"].ctypes.data, extra), keep
+
+
+def pipeline(ds, queries) -> List[List[tuple]]:
+    """Run the analysis pass on a datagen.Dataset for a list of datagen.Query.
+
+    Returns hists[q][v] = [(sumw, counts)] * 3 for (HT, leading pt, nJet).
+    """
+    keep = []
+    jets, k1 = _coll(ds.jets, ("pt", "eta", "phi", "btag"))
+    mus, k2 = _coll(ds.muons, ("pt", "eta", "phi", "iso"))
+    els, k3 = _coll(ds.electrons, ("pt", "eta", "phi"))
+    keep += k1 + k2 + k3
+    dss = DatasetS(ds.n_events, F16 if ds.content_dtype == "f16" else F32,
+                   jets, mus, els, ds.weight.ctypes.data)
+    qarr = (QueryS * max(1, len(queries)))()
+    out, ptr_s, ptr_c = [], [], []
+    for i, q in enumerate(queries):
+        sc = np.ascontiguousarray(q.scales, np.float32)
+        eds = [np.ascontiguousarray(e, np.float32) for e in q.edges()]
+        keep += [sc] + eds
+        qs = QueryS(q.mu_pt, q.mu_abseta, q.mu_iso, q.el_pt, q.el_abseta, q.jet_pt,
+                    q.jet_abseta, q.dr, q.btag, q.min_mu, q.min_jet, q.min_b,
+                    len(sc), sc.ctypes.data)
+        for h in range(3):
+            qs.edges[h] = eds[h].ctypes.data
+            qs.nbins[h] = len(eds[h]) - 1
+        qarr[i] = qs
+        per_q = []
+        for v in range(len(sc)):
+            per_v = []
+            for h in range(3):
+                s = np.zeros(len(eds[h]) + 1, np.float64)
+                c = np.zeros(len(eds[h]) + 1, np.uint64)
+                ptr_s.append(s.ctypes.data)
+                ptr_c.append(c.ctypes.data)
+                per_v.append((s, c))
+            per_q.append(per_v)
+        out.append(per_q)
+    ps = (C.c_void_p * max(1, len(ptr_s)))(*ptr_s)
+    pc = (C.c_void_p * max(1, len(ptr_c)))(*ptr_c)
+    _check(lib().hepkref_pipeline(C.byref(dss), qarr, len(queries),
+                                  C.cast(ps, C.c_void_p), C.cast(pc, C.c_void_p)))
+    del keep
+    return out

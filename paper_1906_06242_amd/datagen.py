@@ -1,0 +1,266 @@
+"""Seeded synthetic collider events stored as jagged columns.
+
+Events follow the jagged layout of Sec. II: per collection an int64
+``offsets`` array of N+1 entries and one contiguous content array of M
+entries per feature, ``offsets[e]:offsets[e+1]`` being the objects of event
+e.  The CMS Open Data of Sec. IV is not available, so these draws stand in
+for it with the shapes of the paper's workload (jets, muons and, in the
+extended schema, electrons; pt/eta/phi/mass kinematics; a per-event weight).
+
+This module holds inputs only -- event content, histogram bin edges,
+jet-energy-scale factors and query parameters -- and none of the analysis
+arithmetic.  Both the HIP library and the CPU oracle consume what it makes.
+
+Draws are made in float64 with ``numpy.random.default_rng`` and cast once
+to the storage dtype.  Generation is split into chunks of ``CHUNK`` events,
+chunk c of seed s drawn from ``default_rng([s, c])``, so a dataset is
+defined independently of how many chunks are generated at once and large
+datasets can be generated in parallel or streamed.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Dict, Iterator, List, Optional
+
+import numpy as np
+
+CHUNK = 1 << 20  # events per independently seeded chunk
+
+# Column names of each collection, in draw order.
+JET_COLS = ("pt", "eta", "phi", "mass")
+MU_COLS = ("pt", "eta", "phi", "mass", "iso")
+EL_COLS = ("pt", "eta", "phi", "mass")
+
+
+@dataclass
+class Collection:
+    """One jagged collection: offsets (int64, N+1) and named content columns."""
+    offsets: np.ndarray
+    cols: Dict[str, np.ndarray] = field(default_factory=dict)
+
+    @property
+    def n_objects(self) -> int:
+        return int(self.offsets[-1])
+
+
+@dataclass
+class Dataset:
+    """Events of one sample: jets, muons, optional electrons, event weights."""
+    n_events: int
+    jets: Collection
+    muons: Collection
+    weight: np.ndarray                     # float32[N]
+    electrons: Optional[Collection] = None
+    content_dtype: str = "f32"             # "f32" or "f16"
+    seed: int = 0
+
+    def collections(self):
+        out = [("jets", self.jets), ("muons", self.muons)]
+        if self.electrons is not None:
+            out.append(("electrons", self.electrons))
+        return out
+
+    def nbytes_read(self) -> int:
+        """Bytes of the columns the analysis reads (mass columns excluded)."""
+        esz = 2 if self.content_dtype == "f16" else 4
+        b = 8 * (self.n_events + 1) * 2 + 4 * self.n_events
+        b += esz * self.jets.n_objects * (4 if "btag" in self.jets.cols else 3)
+        b += esz * self.muons.n_objects * 4
+        if self.electrons is not None:
+            b += 8 * (self.n_events + 1) + esz * self.electrons.n_objects * 3
+        return b
+
+    def nbytes_stored(self) -> int:
+        b = self.weight.nbytes
+        for _, c in self.collections():
+            b += c.offsets.nbytes + sum(a.nbytes for a in c.cols.values())
+        return b
+
+
+def _offsets(counts: np.ndarray) -> np.ndarray:
+    off = np.zeros(len(counts) + 1, dtype=np.int64)
+    np.cumsum(counts, out=off[1:])
+    return off
+
+
+def _draw_chunk(seed: int, c: int, n: int, extended: bool):
+    """Draw chunk c (n events) of the dataset with this seed.
+
+    Returns (counts dict, content dict of float64 arrays, weight float64).
+    Order of draws: multiplicities, weight, jet columns, muon columns,
+    then (extended) electron columns and the jet b-tag score.
+    """
+    rng = np.random.default_rng([seed, c])
+    nj = np.minimum(rng.poisson(5.0, n), 20)
+    nm = np.minimum(rng.poisson(1.5, n), 8)
+    ne = np.minimum(rng.poisson(0.8, n), 8) if extended else None
+    w = rng.normal(1.0, 0.1, n)
+    mj, mm = int(nj.sum()), int(nm.sum())
+    jets = {
+        "pt": 20.0 + rng.exponential(30.0, mj),
+        "eta": np.clip(rng.normal(0.0, 1.5, mj), -4.7, 4.7),
+        "phi": rng.uniform(-math.pi, math.pi, mj),
+        "mass": rng.uniform(0.0, 20.0, mj),
+    }
+    mus = {
+        "pt": 20.0 + rng.exponential(30.0, mm),
+        "eta": np.clip(rng.normal(0.0, 1.5, mm), -4.7, 4.7),
+        "phi": rng.uniform(-math.pi, math.pi, mm),
+        "mass": rng.uniform(0.0, 20.0, mm),
+        "iso": rng.exponential(0.1, mm),
+    }
+    els = None
+    if extended:
+        me = int(ne.sum())
+        els = {
+            "pt": 20.0 + rng.exponential(30.0, me),
+            "eta": np.clip(rng.normal(0.0, 1.5, me), -4.7, 4.7),
+            "phi": rng.uniform(-math.pi, math.pi, me),
+            "mass": rng.uniform(0.0, 20.0, me),
+        }
+        jets["btag"] = rng.beta(0.5, 2.0, mj)
+    counts = {"jets": nj, "muons": nm}
+    if extended:
+        counts["electrons"] = ne
+    cont = {"jets": jets, "muons": mus}
+    if extended:
+        cont["electrons"] = els
+    return counts, cont, w
+
+
+def _chunk_sizes(n_events: int):
+    n_full, rem = divmod(n_events, CHUNK)
+    return [CHUNK] * n_full + ([rem] if rem else [])
+
+
+def iter_chunks(seed: int, n_events: int, extended: bool = False,
+                content_dtype: str = "f32", start_chunk: int = 0
+                ) -> Iterator[Dataset]:
+    """Yield the dataset chunk by chunk, each a Dataset with local offsets."""
+    cdt = np.float16 if content_dtype == "f16" else np.float32
+    for c, n in enumerate(_chunk_sizes(n_events)):
+        if c < start_chunk:
+            continue
+        counts, cont, w = _draw_chunk(seed, c, n, extended)
+        colls = {}
+        for name, cnt in counts.items():
+            colls[name] = Collection(_offsets(cnt),
+                                     {k: v.astype(cdt) for k, v in cont[name].items()})
+        yield Dataset(n, colls["jets"], colls["muons"], w.astype(np.float32),
+                      colls.get("electrons"), content_dtype, seed)
+
+
+def concat(parts: List[Dataset]) -> Dataset:
+    """Concatenate chunk datasets into one (offsets rebased)."""
+    def cat_coll(cs: List[Collection]) -> Collection:
+        offs, base = [np.zeros(1, np.int64)], 0
+        for c in cs:
+            offs.append(c.offsets[1:] + base)
+            base += c.n_objects
+        cols = {k: np.concatenate([c.cols[k] for c in cs]) for k in cs[0].cols}
+        return Collection(np.concatenate(offs), cols)
+    p0 = parts[0]
+    return Dataset(sum(p.n_events for p in parts),
+                   cat_coll([p.jets for p in parts]),
+                   cat_coll([p.muons for p in parts]),
+                   np.concatenate([p.weight for p in parts]),
+                   cat_coll([p.electrons for p in parts]) if p0.electrons is not None else None,
+                   p0.content_dtype, p0.seed)
+
+
+def make_dataset(seed: int, n_events: int, extended: bool = False,
+                 content_dtype: str = "f32") -> Dataset:
+    """The whole dataset in host memory."""
+    if n_events == 0:
+        z = np.zeros(1, np.int64)
+        cdt = np.float16 if content_dtype == "f16" else np.float32
+        mk = lambda cols: Collection(z.copy(), {k: np.zeros(0, cdt) for k in cols})
+        jc = JET_COLS + (("btag",) if extended else ())
+        return Dataset(0, mk(jc), mk(MU_COLS), np.zeros(0, np.float32),
+                       mk(EL_COLS) if extended else None, content_dtype, seed)
+    return concat(list(iter_chunks(seed, n_events, extended, content_dtype)))
+
+
+# ---------------------------------------------------------------------------
+# analysis inputs
+# ---------------------------------------------------------------------------
+
+def uniform_edges(nbins: int, lo: float, hi: float) -> np.ndarray:
+    """nbins+1 float32 edges lo + (hi-lo)*i/nbins, computed in float64."""
+    i = np.arange(nbins + 1, dtype=np.float64)
+    return (lo + (hi - lo) * i / nbins).astype(np.float32)
+
+
+def jes_scales(n_steps: int = 10, step: float = 0.01) -> np.ndarray:
+    """Jet-energy-scale factors 1+k*step (k=1..n) then 1-k*step, float32."""
+    up = [1.0 + k * step for k in range(1, n_steps + 1)]
+    dn = [1.0 - k * step for k in range(1, n_steps + 1)]
+    return np.array(up + dn, dtype=np.float64).astype(np.float32)
+
+
+@dataclass
+class Query:
+    """Cuts, event requirements and binnings of one analysis pass.
+
+    Object cuts: muon pt > mu_pt, |eta| < mu_abseta, iso < mu_iso; electron
+    pt > el_pt, |eta| < el_abseta; jet pt*scale > jet_pt, |eta| < jet_abseta,
+    no selected lepton within dr; b-tagged jet: selected and btag > btag.
+    Event: nMu >= min_mu, nJet >= min_jet, nB >= min_b.
+    Histograms (HT, leading-jet pt, nJet) per jet-energy scale.
+    """
+    mu_pt: float = 20.0
+    mu_abseta: float = 2.4
+    mu_iso: float = 0.15
+    el_pt: float = 20.0
+    el_abseta: float = 2.5
+    jet_pt: float = 30.0
+    jet_abseta: float = 2.5
+    dr: float = 0.4
+    btag: float = 0.5
+    min_mu: int = 1
+    min_jet: int = 4
+    min_b: int = 0
+    scales: np.ndarray = field(default_factory=lambda: np.ones(1, np.float32))
+    edges_ht: np.ndarray = field(default_factory=lambda: uniform_edges(100, 0.0, 2000.0))
+    edges_lead: np.ndarray = field(default_factory=lambda: uniform_edges(100, 0.0, 1000.0))
+    edges_njet: np.ndarray = field(default_factory=lambda: uniform_edges(21, 0.0, 21.0))
+    arrival: float = 0.0                   # seconds (serving stream only)
+
+    def edges(self):
+        return (self.edges_ht, self.edges_lead, self.edges_njet)
+
+    @property
+    def n_scale(self) -> int:
+        return int(len(self.scales))
+
+
+def extended_query() -> Query:
+    """Extended schema: b-tag requirement and 20 jet-energy-scale variations."""
+    return Query(min_b=1, scales=jes_scales())
+
+
+def batch_sizes(seed: int = 0, n: int = 64, lo: float = 1e4, hi: float = 5e6) -> np.ndarray:
+    """Event counts log-uniform in [lo, hi] for a batch of uneven datasets."""
+    rng = np.random.default_rng(seed)
+    return np.floor(np.exp(rng.uniform(math.log(lo), math.log(hi), n))).astype(np.int64)
+
+
+def draw_queries(seed: int, n: int, qps: float = 50.0) -> List[Query]:
+    """Poisson stream of queries with random cut thresholds and binnings."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / qps, n)
+    t = np.cumsum(gaps)
+    mu_pt = rng.uniform(15.0, 40.0, n).astype(np.float32)
+    jet_pt = rng.uniform(25.0, 60.0, n).astype(np.float32)
+    min_jet = rng.integers(2, 7, n)
+    nb_ht = rng.integers(50, 201, n)
+    nb_lead = rng.integers(50, 201, n)
+    out = []
+    for i in range(n):
+        out.append(Query(mu_pt=float(mu_pt[i]), jet_pt=float(jet_pt[i]),
+                         min_jet=int(min_jet[i]),
+                         edges_ht=uniform_edges(int(nb_ht[i]), 0.0, 2000.0),
+                         edges_lead=uniform_edges(int(nb_lead[i]), 0.0, 1000.0),
+                         arrival=float(t[i])))
+    return out

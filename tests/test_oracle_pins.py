@@ -1,0 +1,452 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+The paper prints no worked example, so the pins are: hand-built events with
+hand-derived outputs (tests/golden/tiny_events.json), library routines that
+compute the same quantity another way (numpy searchsorted/bincount/reduceat,
+numpy's float16 widening), float64 brute force, the error bound of
+recursive float32 summation, and invariants of the analysis (histogram
+integrals, monotonicity in the jet-energy scale, permutation symmetry).
+Each is chosen so that a plausible slip in the oracle (dropped term, wrong
+sign or index, transposed operand, wrong boundary) fails at least one.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_1906_06242_amd import datagen
+
+import golden_io
+
+PI32 = np.float32(np.pi)
+
+
+# ---------------------------------------------------------------- widening
+
+def test_half_widening_every_bit_pattern():
+    h = np.arange(1 << 16, dtype=np.uint32).astype(np.uint16)
+    want = h.view(np.float16).astype(np.float32)
+    got = np.array([ref.half_to_float(int(x)) for x in h], np.float32)
+    nan = np.isnan(want)
+    assert np.array_equal(np.isnan(got), nan)
+    assert np.array_equal(got[~nan].view(np.uint32), want[~nan].view(np.uint32))
+
+
+# ---------------------------------------------------------------- masks
+
+def test_select_golden_thresholds():
+    g, ds, q = golden_io.load()
+    mu = ds.muons.cols
+    msel = ref.select([(mu["pt"], ref.GT, q.mu_pt), (mu["eta"], ref.ABS_LT, q.mu_abseta),
+                       (mu["iso"], ref.LT, q.mu_iso)], ds.muons.n_objects)
+    assert msel.tolist() == golden_io.per_object(g, "msel", np.uint8).tolist()
+
+
+def test_select_boundaries_and_nan():
+    v = np.array([30.0, np.nextafter(np.float32(30), np.float32(31)), 29.0, np.nan, -31.0], np.float32)
+    assert ref.select([(v, ref.GT, 30.0)], 5).tolist() == [0, 1, 0, 0, 0]
+    assert ref.select([(v, ref.GE, 30.0)], 5).tolist() == [1, 1, 0, 0, 0]
+    assert ref.select([(v, ref.LT, 30.0)], 5).tolist() == [0, 0, 1, 0, 1]
+    assert ref.select([(v, ref.LE, 30.0)], 5).tolist() == [1, 0, 1, 0, 1]
+    assert ref.select([(v, ref.ABS_LT, 30.5)], 5).tolist() == [1, 1, 1, 0, 0]
+    assert ref.select([(v, ref.ABS_LE, 31.0)], 5).tolist() == [1, 1, 1, 0, 1]
+    iv = np.array([0, 3, 4, 5, -4], np.int32)
+    assert ref.select([(iv, ref.GE, 4)], 5).tolist() == [0, 0, 1, 1, 0]
+    assert ref.select([(iv, ref.ABS_LE, 4)], 5).tolist() == [1, 1, 1, 0, 1]
+    m = np.array([1, 0, 1, 1, 1], np.uint8)
+    assert ref.select([(v, ref.GE, 30.0)], 5, mask_in=m).tolist() == [1, 0, 0, 0, 0]
+    assert ref.select([], 3).tolist() == [1, 1, 1]
+
+
+def test_select_matches_numpy_float32_compares():
+    ds = datagen.make_dataset(7, 5000)
+    j = ds.jets.cols
+    got = ref.select([(j["pt"], ref.GT, 30.0), (j["eta"], ref.ABS_LT, 2.5)], ds.jets.n_objects)
+    want = (j["pt"] > np.float32(30.0)) & (np.abs(j["eta"]) < np.float32(2.5))
+    assert np.array_equal(got.astype(bool), want)
+
+
+# ---------------------------------------------------------------- reductions
+
+def _event_ids(off):
+    return np.repeat(np.arange(len(off) - 1), np.diff(off))
+
+
+def test_count_and_offsets_match_bincount():
+    ds = datagen.make_dataset(3, 4000)
+    off = ds.jets.offsets
+    mask = (ds.jets.cols["pt"] > np.float32(40)).astype(np.uint8)
+    evm = (np.arange(ds.n_events) % 3 != 0).astype(np.uint8)
+    cnt, offo = ref.reduce(ref.COUNT, off, obj_mask=mask, evt_mask=evm, want_offsets=True)
+    want = np.bincount(_event_ids(off), weights=mask, minlength=ds.n_events).astype(np.int64)
+    want[evm == 0] = 0
+    assert np.array_equal(cnt, want)
+    assert offo[0] == 0 and np.array_equal(np.diff(offo), want)
+    # counts sum to the selected objects of the kept events
+    assert int(cnt.sum()) == int(mask[np.repeat(evm, np.diff(off)) == 1].sum())
+
+
+def test_sum_is_left_to_right_float32():
+    off = np.array([0, 3, 6, 6], np.int64)
+    x = np.array([16777216.0, 1.0, 1.0, 1.0, 16777216.0, 1.0], np.float32)
+    s = ref.reduce(ref.SUM, off, x)
+    # ((2^24 + 1) + 1): each +1 is lost to round-to-even; a pairwise order gives 2^24 + 2
+    assert s[0] == np.float32(16777216.0)
+    # (1 + 2^24) rounds to 2^24, then + 1 again rounds to 2^24
+    assert s[1] == np.float32(16777216.0)
+    assert s[2] == np.float32(0.0)
+
+
+def test_sum_within_recursive_summation_bound():
+    ds = datagen.make_dataset(11, 3000)
+    off, pt = ds.jets.offsets, ds.jets.cols["pt"]
+    mask = (np.abs(ds.jets.cols["eta"]) < np.float32(2.5)).astype(np.uint8)
+    s = ref.reduce(ref.SUM, off, pt, obj_mask=mask)
+    w = np.where(mask == 1, pt.astype(np.float64), 0.0)
+    exact = np.add.reduceat(np.append(w, 0.0), off[:-1]) * (np.diff(off) > 0)
+    absum = exact  # all pt > 0
+    n = np.diff(off).astype(np.float64)
+    u = 2.0 ** -24
+    assert np.all(np.abs(s.astype(np.float64) - exact) <= np.maximum(n - 1, 0) * u * absum * 1.0001)
+    # integer-valued content with small totals is summed exactly
+    xi = np.floor(pt).astype(np.float32)
+    si = ref.reduce(ref.SUM, off, xi)
+    ei = np.add.reduceat(np.append(xi.astype(np.float64), 0.0), off[:-1]) * (np.diff(off) > 0)
+    assert np.array_equal(si.astype(np.float64), ei)
+
+
+def test_max_min_and_args_match_numpy():
+    ds = datagen.make_dataset(5, 3000)
+    off, pt = ds.jets.offsets, ds.jets.cols["pt"]
+    mask = (ds.jets.cols["eta"] > np.float32(0)).astype(np.uint8)
+    mx, amx = ref.reduce(ref.MAX, off, pt, obj_mask=mask, want_arg=True)
+    mn, amn = ref.reduce(ref.MIN, off, pt, obj_mask=mask, want_arg=True)
+    am2 = ref.reduce(ref.ARGMAX, off, pt, obj_mask=mask)
+    for e in range(ds.n_events):
+        seg = pt[off[e]:off[e + 1]]
+        sel = mask[off[e]:off[e + 1]] == 1
+        if not sel.any():
+            assert mx[e] == -np.inf and amx[e] == -1 and mn[e] == np.inf and amn[e] == -1
+            continue
+        vmax = np.where(sel, seg, -np.inf)
+        vmin = np.where(sel, seg, np.inf)
+        assert mx[e] == vmax.max() and amx[e] == int(np.argmax(vmax)) == am2[e]
+        assert mn[e] == vmin.min() and amn[e] == int(np.argmin(vmin))
+
+
+def test_max_ties_take_lowest_index_and_event_mask():
+    off = np.array([0, 3, 5, 5], np.int64)
+    x = np.array([7.0, 9.0, 9.0, 2.0, 2.0], np.float32)
+    mx, a = ref.reduce(ref.MAX, off, x, want_arg=True)
+    assert mx.tolist() == [9.0, 2.0, -np.inf] and a.tolist() == [1, 0, -1]
+    mn, b = ref.reduce(ref.MIN, off, x, want_arg=True, evt_mask=np.array([0, 1, 1], np.uint8))
+    assert mn.tolist() == [np.inf, 2.0, np.inf] and b.tolist() == [-1, 0, -1]
+
+
+def test_reduce_golden():
+    g, ds, q = golden_io.load()
+    jsel = golden_io.per_object(g, "jsel", np.uint8)
+    off, pt = ds.jets.offsets, ds.jets.cols["pt"]
+    assert ref.reduce(ref.COUNT, off, obj_mask=jsel).tolist() == golden_io.per_event(g, "njet", np.int32).tolist()
+    assert ref.reduce(ref.SUM, off, pt, obj_mask=jsel).tolist() == golden_io.per_event(g, "ht", np.float32).tolist()
+    lead, li = ref.reduce(ref.MAX, off, pt, obj_mask=jsel, want_arg=True)
+    assert lead.tolist() == golden_io.per_event(g, "lead", np.float32).tolist()
+    assert li.tolist() == golden_io.per_event(g, "lead_idx", np.int32).tolist()
+
+
+# ---------------------------------------------------------------- Delta-R
+
+def test_match_dr_golden():
+    g, ds, q = golden_io.load()
+    j, m = ds.jets, ds.muons
+    msel = golden_io.per_object(g, "msel", np.uint8)
+    md, ix, cl = ref.match_dr(j.offsets, j.cols["eta"], j.cols["phi"],
+                              m.offsets, m.cols["eta"], m.cols["phi"], q.dr, mask_b=msel)
+    assert cl.tolist() == golden_io.per_object(g, "clean", np.uint8).tolist()
+    k = 0
+    for e in g["events"]:
+        n = len(e["jets"])
+        if "min_dr2" in e:
+            assert md[k:k + n].tolist() == [golden_io.fnum(v) for v in e["min_dr2"]]
+        if "argmin" in e:
+            assert ix[k:k + n].tolist() == e["argmin"]
+        k += n
+
+
+def test_match_dr_phi_wrap_value():
+    # jet phi 3, muon phi -3: dphi = 6 - 2 pi_f exactly (Sterbenz), squared once
+    off = np.array([0, 1], np.int64)
+    md, ix, cl = ref.match_dr(off, np.array([1.0], np.float32), np.array([3.0], np.float32),
+                              off, np.array([1.0], np.float32), np.array([-3.0], np.float32), 0.4)
+    d = np.float32(6.0) - np.float32(2.0) * PI32
+    assert md[0] == d * d and cl[0] == 0 and ix[0] == 0
+    assert abs(float(md[0]) - (2 * math.pi - 6) ** 2) < 1e-6
+
+
+def test_match_dr_equality_is_masked():
+    off = np.array([0, 1], np.int64)
+    z = np.zeros(1, np.float32)
+    md, ix, cl = ref.match_dr(off, z, np.array([0.4], np.float32), off, z, z, 0.4)
+    assert md[0] == np.float32(0.4) * np.float32(0.4) and cl[0] == 0
+    md, ix, cl = ref.match_dr(off, z, np.array([np.nextafter(np.float32(0.4), np.float32(1))], np.float32),
+                              off, z, z, 0.4)
+    assert cl[0] == 1
+
+
+def test_match_dr_float64_brute_force():
+    ds = datagen.make_dataset(21, 2000)
+    j, m = ds.jets, ds.muons
+    msel = (m.cols["pt"] > np.float32(25)).astype(np.uint8)
+    md, ix, cl = ref.match_dr(j.offsets, j.cols["eta"], j.cols["phi"],
+                              m.offsets, m.cols["eta"], m.cols["phi"], 0.4, mask_b=msel)
+    thr = 0.4 ** 2
+    nchk = 0
+    for e in range(ds.n_events):
+        a0, a1 = j.offsets[e], j.offsets[e + 1]
+        b0, b1 = m.offsets[e], m.offsets[e + 1]
+        sel = np.nonzero(msel[b0:b1])[0]
+        for a in range(a0, a1):
+            if len(sel) == 0:
+                assert md[a] == np.inf and ix[a] == -1 and cl[a] == 1
+                continue
+            de = j.cols["eta"][a].astype(np.float64) - m.cols["eta"][b0 + sel].astype(np.float64)
+            dp = j.cols["phi"][a].astype(np.float64) - m.cols["phi"][b0 + sel].astype(np.float64)
+            dp = (dp + np.pi) % (2 * np.pi) - np.pi
+            d2 = de * de + dp * dp
+            best = d2.min()
+            assert abs(float(md[a]) - best) <= 2e-6 * max(1.0, best)
+            if abs(best - thr) > 1e-5:
+                assert cl[a] == (1 if best > thr else 0)
+            order = np.argsort(d2, kind="stable")
+            if len(d2) == 1 or d2[order[1]] - d2[order[0]] > 1e-5 * max(1.0, best):
+                assert ix[a] == sel[order[0]]
+            nchk += 1
+    assert nchk > 5000
+
+
+def test_match_dr_permutation_invariant():
+    rng = np.random.default_rng(4)
+    n_ev, nb = 200, 6
+    offb = np.arange(n_ev + 1, dtype=np.int64) * nb
+    offa = np.arange(n_ev + 1, dtype=np.int64) * 3
+    eb = rng.normal(0, 1, n_ev * nb).astype(np.float32)
+    pb = rng.uniform(-np.pi, np.pi, n_ev * nb).astype(np.float32)
+    ea = rng.normal(0, 1, n_ev * 3).astype(np.float32)
+    pa = rng.uniform(-np.pi, np.pi, n_ev * 3).astype(np.float32)
+    md, ix, cl = ref.match_dr(offa, ea, pa, offb, eb, pb, 0.8)
+    perm = np.concatenate([e * nb + rng.permutation(nb) for e in range(n_ev)])
+    md2, ix2, cl2 = ref.match_dr(offa, ea, pa, offb, eb[perm], pb[perm], 0.8)
+    assert np.array_equal(md, md2) and np.array_equal(cl, cl2)
+    ev = np.repeat(np.arange(n_ev), 3)
+    assert np.array_equal(perm[ev * nb + ix2] - ev * nb, ix)
+    # swapping the roles of a and b does not change the pairwise minimum set:
+    # every a whose min is below the cone has a b whose min is below the cone
+    md3, ix3, _ = ref.match_dr(offb, eb, pb, offa, ea, pa, 0.8)
+    for e in range(n_ev):
+        assert (md[e * 3:(e + 1) * 3].min() == md3[e * nb:(e + 1) * nb].min())
+
+
+# ---------------------------------------------------------------- histograms
+
+def test_hist_fill_matches_searchsorted_bincount():
+    rng = np.random.default_rng(9)
+    x = rng.uniform(-100, 2200, 20000).astype(np.float32)
+    w = rng.normal(1, 0.1, 20000).astype(np.float32)
+    edges = datagen.uniform_edges(100, 0.0, 2000.0)
+    x[:50] = edges[rng.integers(0, 101, 50)]          # exactly on edges
+    x[50] = np.nan
+    m = (rng.uniform(size=20000) < 0.7).astype(np.uint8)
+    s, c = ref.hist_fill(x, edges, w, m)
+    keep = (m == 1) & ~np.isnan(x)
+    slot = np.searchsorted(edges, x[keep], side="right")
+    wc = np.bincount(slot, minlength=102)
+    ws = np.bincount(slot, weights=w[keep].astype(np.float64), minlength=102)
+    assert np.array_equal(c, wc.astype(np.uint64))
+    assert np.array_equal(s, ws)       # weights >= 0.25 and sums < 2^28: exact in any order
+    assert int(c.sum()) == int(keep.sum())
+
+
+def test_hist_fill_edges_underflow_overflow_accumulate():
+    edges = np.array([0.0, 1.0, 2.0, 4.0], np.float32)
+    x = np.array([-1.0, 0.0, 0.999, 1.0, 3.99, 4.0, 100.0, np.nan], np.float32)
+    s, c = ref.hist_fill(x, edges)
+    assert c.tolist() == [1, 2, 1, 1, 2]
+    s, c = ref.hist_fill(x, edges, w=np.full(8, 0.5, np.float32), sumw=s, counts=c)
+    assert c.tolist() == [2, 4, 2, 2, 4] and s.tolist() == [1.5, 3.0, 1.5, 1.5, 3.0]
+    xi = np.array([3, 4, 4, 20, 21, -1], np.int32)
+    s, c = ref.hist_fill(xi, datagen.uniform_edges(21, 0, 21))
+    assert c[4] == 1 and c[5] == 2 and c[21] == 1 and c[22] == 1 and c[0] == 1
+
+
+# ---------------------------------------------------------------- whole pass
+
+def _hists_equal(got, want):
+    return np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+
+
+def test_pipeline_golden():
+    g, ds, q = golden_io.load()
+    h = ref.pipeline(ds, [q])[0][0]
+    for k, name in enumerate(("ht", "lead", "njet")):
+        nb = len(q.edges()[k]) - 1
+        assert _hists_equal(h[k], golden_io.expected_hist(g, name, nb)), name
+
+
+def _pass_mask_numpy(ds, q, scale=np.float32(1.0)):
+    """Event pass flags from numpy primitives plus the oracle's pinned cleaning."""
+    j, m = ds.jets, ds.muons
+    jc = {k: v.astype(np.float32) for k, v in j.cols.items()}
+    mc = {k: v.astype(np.float32) for k, v in m.cols.items()}
+    msel = ((mc["pt"] > np.float32(q.mu_pt)) & (np.abs(mc["eta"]) < np.float32(q.mu_abseta))
+            & (mc["iso"] < np.float32(q.mu_iso)))
+    _, _, clean = ref.match_dr(j.offsets, jc["eta"], jc["phi"], m.offsets, mc["eta"], mc["phi"],
+                               q.dr, mask_b=msel.astype(np.uint8))
+    ptv = jc["pt"] * scale
+    jsel = (ptv > np.float32(q.jet_pt)) & (np.abs(jc["eta"]) < np.float32(q.jet_abseta)) & (clean == 1)
+    nmu = np.bincount(_event_ids(m.offsets), weights=msel, minlength=ds.n_events)
+    nj = np.bincount(_event_ids(j.offsets), weights=jsel, minlength=ds.n_events)
+    return (nmu >= q.min_mu) & (nj >= q.min_jet), nj
+
+
+def test_pipeline_invariants_seeded():
+    ds = datagen.make_dataset(0, 20000)
+    q = datagen.Query()
+    h = ref.pipeline(ds, [q])[0][0]
+    passed, nj = _pass_mask_numpy(ds, q)
+    sw = ds.weight[passed].astype(np.float64).sum()
+    for k in range(3):
+        assert int(h[k][1].sum()) == int(passed.sum())
+        assert h[k][0].sum() == sw             # exact: weights >= 0.25, sums < 2^28
+    # nJet histogram: bin of k jets is slot k+1, bins below min_jet empty
+    want = np.bincount(nj[passed].astype(np.int64), minlength=23)[:23]
+    assert np.array_equal(h[2][1][1:22], want[:21].astype(np.uint64))
+    assert h[2][1][1:5].sum() == 0
+    # every selected jet has pt > 30, so the leading-pt histogram is empty below 30
+    assert h[1][1][:4].sum() == 0
+    # H_T >= 4 * 30 for passing events: H_T bins below 120 are empty
+    assert h[0][1][:7].sum() == 0
+
+
+def test_pipeline_scale_one_and_monotone_in_scale():
+    ds = datagen.make_dataset(1, 10000)
+    q1 = datagen.Query()
+    qs = datagen.Query(scales=np.array([1.0, 1.1, 0.9, 1.0], np.float32))
+    h1 = ref.pipeline(ds, [q1])[0][0]
+    hs = ref.pipeline(ds, [qs])[0]
+    for k in range(3):
+        assert _hists_equal(hs[0][k], h1[k]) and _hists_equal(hs[3][k], h1[k])
+    n_up, n_nom, n_dn = (int(hs[v][2][1].sum()) for v in (1, 0, 2))
+    assert n_up >= n_nom >= n_dn and n_up > n_dn
+    p_up, _ = _pass_mask_numpy(ds, qs, np.float32(1.1))
+    assert n_up == int(p_up.sum())
+
+
+def test_pipeline_special_cases():
+    ds = datagen.make_dataset(2, 5000)
+    # no muon can be selected -> nothing passes
+    h = ref.pipeline(ds, [datagen.Query(mu_pt=1e9)])[0][0]
+    assert all(int(h[k][1].sum()) == 0 for k in range(3))
+    # no event requirement on muons and a zero cone: no cleaning happens, so the
+    # nJet histogram equals the bincount of kinematic jets per event
+    q = datagen.Query(min_mu=0, dr=0.0, min_jet=0)
+    h = ref.pipeline(ds, [q])[0][0]
+    jk = (ds.jets.cols["pt"] > np.float32(30)) & (np.abs(ds.jets.cols["eta"]) < np.float32(2.5))
+    nj = np.bincount(_event_ids(ds.jets.offsets), weights=jk, minlength=ds.n_events).astype(np.int64)
+    assert np.array_equal(h[2][1][1:22], np.bincount(nj, minlength=21)[:21].astype(np.uint64))
+    assert int(h[0][1].sum()) == ds.n_events
+
+
+def test_pipeline_multi_query_equals_single():
+    ds = datagen.make_dataset(3, 5000)
+    qs = datagen.draw_queries(1, 4)
+    together = ref.pipeline(ds, qs)
+    for i, q in enumerate(qs):
+        alone = ref.pipeline(ds, [q])[0]
+        for k in range(3):
+            assert _hists_equal(together[i][0][k], alone[0][k])
+
+
+def test_pipeline_extended_schema_reductions():
+    ds16 = datagen.make_dataset(4, 5000, extended=True, content_dtype="f16")
+    q = datagen.Query(min_b=1, scales=datagen.jes_scales()[:4])
+    h16 = ref.pipeline(ds16, [q])[0]
+    # float16 content behaves exactly as its float32 widening
+    ds32 = datagen.Dataset(ds16.n_events,
+                           datagen.Collection(ds16.jets.offsets, {k: v.astype(np.float32) for k, v in ds16.jets.cols.items()}),
+                           datagen.Collection(ds16.muons.offsets, {k: v.astype(np.float32) for k, v in ds16.muons.cols.items()}),
+                           ds16.weight,
+                           datagen.Collection(ds16.electrons.offsets, {k: v.astype(np.float32) for k, v in ds16.electrons.cols.items()}),
+                           "f32")
+    h32 = ref.pipeline(ds32, [q])[0]
+    for v in range(4):
+        for k in range(3):
+            assert _hists_equal(h16[v][k], h32[v][k])
+    # no electron selectable and no b-tag requirement == the base schema
+    qb = datagen.Query(el_pt=1e9, min_b=0)
+    base = datagen.Dataset(ds32.n_events,
+                           datagen.Collection(ds32.jets.offsets, {k: v for k, v in ds32.jets.cols.items() if k != "btag"}),
+                           ds32.muons, ds32.weight, None, "f32")
+    he = ref.pipeline(ds32, [qb])[0][0]
+    hb = ref.pipeline(base, [qb])[0][0]
+    for k in range(3):
+        assert _hists_equal(he[k], hb[k])
+    # b-tag requirement only removes events
+    assert int(h32[0][0][1].sum()) <= int(ref.pipeline(ds32, [datagen.Query(min_b=0, scales=q.scales[:1])])[0][0][0][1].sum())
+
+
+def test_pipeline_empty_dataset():
+    ds = datagen.make_dataset(0, 0)
+    h = ref.pipeline(ds, [datagen.Query()])[0][0]
+    assert all(int(h[k][1].sum()) == 0 for k in range(3))
+
+
+def test_pipeline_power_of_two_scale_covariance():
+    """Scaling pt by 2 is exact in float32, and so is every partial H_T sum:
+    (scale 2, jet cut 60, edges x2) must give the histograms of
+    (scale 1, jet cut 30, edges x1) slot for slot."""
+    ds = datagen.make_dataset(6, 20000)
+    q1 = datagen.Query()
+    q2 = datagen.Query(jet_pt=60.0, scales=np.array([2.0], np.float32),
+                       edges_ht=datagen.uniform_edges(100, 0.0, 4000.0),
+                       edges_lead=datagen.uniform_edges(100, 0.0, 2000.0))
+    h1 = ref.pipeline(ds, [q1])[0][0]
+    h2 = ref.pipeline(ds, [q2])[0][0]
+    for k in range(3):
+        assert _hists_equal(h1[k], h2[k])
+    # and the histograms are not trivially empty
+    assert int(h1[0][1].sum()) > 1000
+
+
+def _extended_numpy(ds, q, scale):
+    j, m, el = ds.jets, ds.muons, ds.electrons
+    f = lambda c: {k: v.astype(np.float32) for k, v in c.cols.items()}
+    jc, mc, ec = f(j), f(m), f(el)
+    msel = ((mc["pt"] > np.float32(q.mu_pt)) & (np.abs(mc["eta"]) < np.float32(q.mu_abseta))
+            & (mc["iso"] < np.float32(q.mu_iso)))
+    esel = (ec["pt"] > np.float32(q.el_pt)) & (np.abs(ec["eta"]) < np.float32(q.el_abseta))
+    _, _, c1 = ref.match_dr(j.offsets, jc["eta"], jc["phi"], m.offsets, mc["eta"], mc["phi"],
+                            q.dr, mask_b=msel.astype(np.uint8))
+    _, _, c2 = ref.match_dr(j.offsets, jc["eta"], jc["phi"], el.offsets, ec["eta"], ec["phi"],
+                            q.dr, mask_b=esel.astype(np.uint8))
+    ptv = jc["pt"] * np.float32(scale)
+    jsel = (ptv > np.float32(q.jet_pt)) & (np.abs(jc["eta"]) < np.float32(q.jet_abseta)) & (c1 == 1) & (c2 == 1)
+    ev = _event_ids(j.offsets)
+    nmu = np.bincount(_event_ids(m.offsets), weights=msel, minlength=ds.n_events)
+    nj = np.bincount(ev, weights=jsel, minlength=ds.n_events)
+    nb = np.bincount(ev, weights=jsel & (jc["btag"] > np.float32(q.btag)), minlength=ds.n_events)
+    return (nmu >= q.min_mu) & (nj >= q.min_jet) & (nb >= q.min_b), nj
+
+
+def test_pipeline_extended_counts_match_numpy():
+    ds = datagen.make_dataset(8, 20000, extended=True, content_dtype="f16")
+    sc = datagen.jes_scales()
+    q = datagen.Query(min_b=1, scales=sc)
+    h = ref.pipeline(ds, [q])[0]
+    assert len(h) == 20
+    for v in (0, 9, 10, 19):
+        passed, nj = _extended_numpy(ds, q, sc[v])
+        assert int(h[v][2][1].sum()) == int(passed.sum()) > 0
+        want = np.bincount(nj[passed].astype(np.int64), minlength=21)[:21]
+        assert np.array_equal(h[v][2][1][1:22], want.astype(np.uint64))
+        assert h[v][0][0].sum() == ds.weight[passed].astype(np.float64).sum()
