@@ -1,0 +1,249 @@
+/*
+ * hepk -- columnar jagged-array analysis kernels for AMD MI355X (gfx950).
+ *
+ * A C ABI over hand-written HIP kernels for the method of "Processing
+ * Columnar Collider Data with GPU-Accelerated Kernels" (Pata & Spiropulu,
+ * arXiv:1906.06242): collider events stored as jagged columns are reduced to
+ * weighted histograms by object selection, lepton-jet Delta-R cleaning,
+ * per-event reductions, event selection and histogram filling.
+ *
+ * Data model (Sec. II).  A collection of N events holding M objects in total
+ * is an int64 offsets array of N+1 entries plus one contiguous content array
+ * of M entries per feature; the objects of event e are
+ * offsets[e] .. offsets[e+1]-1.  Preconditions the caller guarantees (checked
+ * only by hepk_validate_offsets): offsets[0] == 0, offsets non-decreasing,
+ * offsets[N] == M.  Object masks (M bytes) and event masks (N bytes) chain
+ * between calls without copying the data (Sec. III); a mask byte is "true"
+ * when non-zero, and masks written by this library hold exactly 0 or 1.
+ *
+ * Arithmetic.  Cuts, Delta-R and sums of per-object data are float32, each
+ * operation rounded on its own (no fused multiply-add contraction); float16
+ * content is widened exactly to float32 first.  Histogram weights are summed
+ * in float64, counts in uint64.
+ *
+ * Memory and ownership.  Every array argument is a device pointer into memory
+ * the caller allocated and owns, unless marked (host); host structs are read
+ * before the call returns.  Per-object and per-event outputs are overwritten
+ * for every row; histograms accumulate into the caller's contents.  The only
+ * allocations the library makes are inside a hepk_plan (released by
+ * hepk_plan_destroy) and stream-ordered temporaries of hepk_reduce's prefix
+ * offsets, freed on the same stream.
+ *
+ * Execution.  Every call enqueues its kernels on `stream` (NULL: the null
+ * stream of the current device) and returns without synchronising.
+ *
+ * Errors.  Calls return HEPK_OK or a negative hepk_status; invalid
+ * arguments are rejected before anything is enqueued.  hepk_last_error()
+ * gives a message for the calling thread's last failure.
+ */
+#ifndef HEPK_H
+#define HEPK_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HEPK_ABI_VERSION 1
+#define HEPK_MAX_CUTS 8
+
+typedef enum hepk_status {
+    HEPK_OK = 0,
+    HEPK_EINVAL = -1,        /* bad argument: null pointer, negative size, bad enum */
+    HEPK_EHIP = -2,          /* a HIP runtime call or kernel launch failed */
+    HEPK_EUNSUPPORTED = -3,  /* valid but unsupported combination (e.g. int32 sum) */
+    HEPK_ENOMEM = -4         /* device allocation failed */
+} hepk_status;
+
+typedef enum hepk_dtype { HEPK_F32 = 0, HEPK_F16 = 1, HEPK_I32 = 2 } hepk_dtype;
+
+/* v > t, v >= t, v < t, v <= t, |v| < t, |v| <= t */
+typedef enum hepk_cmp {
+    HEPK_GT = 0, HEPK_GE = 1, HEPK_LT = 2, HEPK_LE = 3, HEPK_ABS_LT = 4, HEPK_ABS_LE = 5
+} hepk_cmp;
+
+/* One cut on one column: float columns (F32, F16) compare against `thr`,
+ * int32 columns against `ithr`.  (host struct; `col` is a device pointer) */
+typedef struct hepk_cut {
+    const void *col;
+    int32_t dtype;
+    int32_t op;
+    float thr;
+    int32_t ithr;
+} hepk_cut;
+
+/* Object or event selection mask (Sec. III object/event masks; Sec. IV
+ * object selection on pt and eta, event selection on event variables):
+ *   mask_out[i] = (mask_in == NULL || mask_in[i]) && cut_0(i) && ... && cut_{n_cuts-1}(i)
+ * for i in [0, n).  0 <= n_cuts <= HEPK_MAX_CUTS; every column has n entries.
+ * NaN fails every float comparison. */
+int hepk_select(const hepk_cut *cuts /* host, n_cuts */, int32_t n_cuts, int64_t n,
+                const uint8_t *mask_in /* nullable, n */, uint8_t *mask_out /* n */,
+                hipStream_t stream);
+
+typedef enum hepk_reduce_op {
+    HEPK_COUNT = 0, HEPK_SUM = 1, HEPK_MAX = 2, HEPK_MIN = 3, HEPK_ARGMAX = 4, HEPK_ARGMIN = 5
+} hepk_reduce_op;
+
+/* Per-event reduction over the objects of each event (Sec. III: the H_T kernel
+ * of Listing 1 and the sum/max/min-within-offsets kernels).  An object counts
+ * when obj_mask is NULL or obj_mask[i] != 0; an event with evt_mask[e] == 0
+ * gets the empty result.
+ *   COUNT  out int32[N]: number of counted objects; offsets_out (nullable,
+ *          int64[N+1]): 0 followed by the running sum of out (the offsets of
+ *          the selected sub-collection).  content may be NULL.
+ *   SUM    out float32[N]: left-to-right float32 sum from 0.0f, in object
+ *          order -- the order of Listing 1's inner loop, kept exactly.
+ *   MAX/MIN out float32[N]: extremum (-inf/+inf when empty); out_arg
+ *          (nullable, int32[N]): local index of the first extremum, -1 if empty.
+ *   ARGMAX/ARGMIN out int32[N]: that local index only.
+ * content dtype F32 or F16 for SUM/MAX/MIN/ARG*.  Reduced content must be
+ * NaN-free for MAX/MIN results to be meaningful. */
+int hepk_reduce(int32_t op, const int64_t *offsets /* N+1 */, int64_t n_events,
+                const void *content /* M, nullable for COUNT */, int32_t dtype,
+                const uint8_t *obj_mask /* nullable, M */, const uint8_t *evt_mask /* nullable, N */,
+                void *out /* N */, int32_t *out_arg /* nullable, N */,
+                int64_t *offsets_out /* nullable, N+1, COUNT only */, hipStream_t stream);
+
+/* Delta-R matching of collection a against collection b of the same event
+ * (Sec. III: masking objects of a first collection within a Delta-R cone of an
+ * object of a second collection; Sec. IV: jet-lepton matching).  For every
+ * object of a, over the objects of b with mask_b (NULL: all):
+ *   dR^2 = deta^2 + dphi^2, dphi = phi_a - phi_b brought into [-pi, pi] by
+ *   one subtraction or addition of 2*pi (inputs are angles in [-pi, pi]);
+ *   min_dr2 = smallest dR^2 (+inf if none), idx_b = local index of that b
+ *   (lowest on ties, -1 if none), clean = (mask_a == NULL || mask_a[a]) &&
+ *   !(min_dr2 <= dr*dr), dr*dr rounded to float32.
+ * eta/phi of both collections share `dtype` (F32 or F16).  Any output may be
+ * NULL. */
+int hepk_match_dr(const int64_t *off_a, const void *eta_a, const void *phi_a,
+                  const uint8_t *mask_a,
+                  const int64_t *off_b, const void *eta_b, const void *phi_b,
+                  const uint8_t *mask_b, int32_t dtype, int64_t n_events, float dr,
+                  float *min_dr2 /* nullable, Ma */, int32_t *idx_b /* nullable, Ma */,
+                  uint8_t *clean_out /* nullable, Ma */, hipStream_t stream);
+
+/* A 1-D histogram: nbins half-open bins [edges[i], edges[i+1]) with strictly
+ * increasing float32 edges; slot 0 holds x < edges[0] (underflow), slots
+ * 1..nbins the bins, slot nbins+1 x >= edges[nbins] (overflow).  (host struct;
+ * arrays are device pointers: edges nbins+1, sumw and counts nbins+2) */
+typedef struct hepk_hist {
+    const float *edges;
+    int32_t nbins;
+    double *sumw;
+    uint64_t *counts;
+} hepk_hist;
+
+/* Weighted histogram fill (Sec. III fill-histogram kernel): for each row i
+ * with evt_mask[i] (NULL: all) and x[i] not NaN, counts[slot] += 1 and
+ * sumw[slot] += (double)w[i] (w NULL: 1).  x dtype F32, F16 or I32 (converted
+ * to float32).  Accumulates. */
+int hepk_hist_fill(const void *x, int32_t dtype, const float *w /* nullable, n */,
+                   const uint8_t *evt_mask /* nullable, n */, int64_t n,
+                   const hepk_hist *h /* host */, hipStream_t stream);
+
+/* Checks offsets[0] == 0, offsets non-decreasing and offsets[n_events] ==
+ * n_objects; writes the number of violations to *bad (device int64). */
+int hepk_validate_offsets(const int64_t *offsets, int64_t n_events, int64_t n_objects,
+                          int64_t *bad /* device, 1 */, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * The fused analysis pass.
+ *
+ * One launch of one persistent kernel runs the whole pass of Sec. IV's
+ * analysis for every (dataset, query, jet-energy scale):
+ *   muons      sel = pt > mu_pt && |eta| < mu_abseta && iso < mu_iso
+ *   electrons  sel = pt > el_pt && |eta| < el_abseta            (if present)
+ *   jets       clean = no selected muon or electron with dR^2 <= dr*dr
+ *              (dR^2 as in hepk_match_dr); for scale s: ptv = pt * s
+ *              (float32), sel = ptv > jet_pt && |eta| < jet_abseta && clean,
+ *              b-tagged = sel && btag > btag_thr                (if present)
+ *   event      nMu = #sel muons, nJet = #sel jets, nB = #b-tagged jets,
+ *              H_T = left-to-right float32 sum of ptv over selected jets,
+ *              lead = max ptv over selected jets,
+ *              pass = nMu >= min_mu && nJet >= min_jet && nB >= min_b
+ *   histograms for passing events, weight w: H_T, lead and (float)nJet
+ * exactly as the chain hepk_select -> hepk_match_dr -> hepk_reduce ->
+ * hepk_select -> hepk_hist_fill computes them.  Per-object and per-event
+ * intermediates stay on chip; only the input columns are read from HBM.
+ * Scheduling and fusion (Sec. IV: hundreds of kernel calls left the GPU half
+ * idle) are what this entry point is for.
+ * ------------------------------------------------------------------------- */
+
+typedef struct hepk_collection {
+    const int64_t *offsets;          /* n_events+1; NULL: collection absent */
+    const void *pt, *eta, *phi;      /* content, dataset dtype */
+    const void *extra;               /* muons: isolation (required);
+                                        jets: b-tag score (optional); electrons: unused */
+} hepk_collection;
+
+typedef struct hepk_dataset {
+    int64_t n_events;                /* 0 <= n_events < 2^31 */
+    int32_t dtype;                   /* content dtype: HEPK_F32 or HEPK_F16 */
+    hepk_collection jets, muons, electrons;
+    const float *weights;            /* float32[n_events]; NULL: weight 1 */
+} hepk_dataset;
+
+typedef struct hepk_query {
+    float mu_pt, mu_abseta, mu_iso;
+    float el_pt, el_abseta;
+    float jet_pt, jet_abseta;
+    float dr, btag;
+    int32_t min_mu, min_jet, min_b;
+    int32_t n_scale;                 /* >= 1 */
+    const float *scales;             /* (host) n_scale jet-energy-scale factors */
+    const float *edges[3];           /* H_T, lead, nJet bin edges (device, nbins+1) */
+    int32_t nbins[3];
+} hepk_query;
+
+/* Launch configuration of the fused kernel.  block: threads per workgroup
+ * (256 or 512); ev_per_thread: events per thread in a tile (1 or 2); hist_mode:
+ * 0 = per-workgroup LDS histograms merged with global atomics, 1 = global
+ * atomics only; grid: workgroups (0: enough to fill the device). */
+typedef struct hepk_tune {
+    int32_t block;
+    int32_t ev_per_thread;
+    int32_t hist_mode;
+    int32_t grid;
+} hepk_tune;
+
+typedef struct hepk_plan_s *hepk_plan;
+
+/* Builds a plan for datasets ds[0..n_ds) and queries q[0..n_query): uploads
+ * the dataset and query tables to device memory and fixes the launch
+ * configuration (tune NULL: a default for the device).  Histogram layout in
+ * the sumw/counts buffers given to hepk_pipeline: one block of nbins+2 slots
+ * per (dataset, query, scale, observable), blocks ordered dataset-major, then
+ * query, then scale, then observable (H_T, lead, nJet). */
+int hepk_plan_create(const hepk_dataset *ds /* host, n_ds */, int32_t n_ds,
+                     const hepk_query *q /* host, n_query */, int32_t n_query,
+                     const hepk_tune *tune /* host, nullable */, hepk_plan *out /* host */);
+
+/* Total histogram slots of the plan (length of sumw and counts). */
+int hepk_plan_hist_slots(hepk_plan p, int64_t *n_slots /* host */);
+
+/* Slot offset and bin count of histogram (dataset d, query iq, scale v, observable h). */
+int hepk_plan_hist_offset(hepk_plan p, int32_t d, int32_t iq, int32_t v, int32_t h,
+                          int64_t *offset /* host */, int32_t *nbins /* host */);
+
+/* The launch configuration the plan uses. */
+int hepk_plan_get_tune(hepk_plan p, hepk_tune *tune /* host */);
+
+/* Runs the fused pass, accumulating into sumw/counts (hepk_plan_hist_slots
+ * entries each). */
+int hepk_pipeline(hepk_plan p, double *sumw, uint64_t *counts, hipStream_t stream);
+
+int hepk_plan_destroy(hepk_plan p);
+
+/* Message for the calling thread's last non-OK return ("" if none). */
+const char *hepk_last_error(void);
+
+/* HEPK_ABI_VERSION of the built library. */
+int hepk_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

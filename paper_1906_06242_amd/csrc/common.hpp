@@ -1,0 +1,156 @@
+// Internal helpers of libhepk: error reporting, launch bookkeeping and the
+// float32 device primitives every kernel shares (column loads with exact
+// float16 widening, cut comparisons, the Delta-phi wrap, histogram slots).
+//
+// Build flags matter for exactness: -ffp-contract=off keeps a*b+c as a
+// rounded multiply followed by a rounded add (no v_fma_f32), and denormals
+// are kept (no flush-to-zero), so every float32 operation is the IEEE one.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+
+#include "hepk.h"
+
+namespace hepk {
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define HEPK_REQUIRE(cond, ...)                                   \
+    do {                                                          \
+        if (!(cond)) {                                            \
+            ::hepk::set_error(__VA_ARGS__);                       \
+            return HEPK_EINVAL;                                   \
+        }                                                         \
+    } while (0)
+
+#define HEPK_HIP(call)                                                            \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            ::hepk::set_error("%s failed: %s", #call, hipGetErrorString(e_));     \
+            return HEPK_EHIP;                                                     \
+        }                                                                         \
+    } while (0)
+
+// Checks the launch that was just enqueued.
+int check_launch(const char *what);
+
+// Compute units of the current device (cached per device).
+int device_cus();
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- device
+
+// float32 pi and 2*pi rounded to nearest (bit patterns 0x40490FDB, 0x40C90FDB).
+constexpr float kPi = 0x1.921fb6p+1f;
+constexpr float kTwoPi = 0x1.921fb6p+2f;
+
+template <typename T>
+__device__ __forceinline__ float ldf(const T *p, int64_t i) {
+    return static_cast<float>(p[i]);  // _Float16 -> float is v_cvt_f32_f16: exact
+}
+
+__device__ __forceinline__ float ld_any(const void *p, int32_t dtype, int64_t i) {
+    if (dtype == HEPK_F16) return static_cast<float>(static_cast<const _Float16 *>(p)[i]);
+    if (dtype == HEPK_I32) return static_cast<float>(static_cast<const int32_t *>(p)[i]);
+    return static_cast<const float *>(p)[i];
+}
+
+__device__ __forceinline__ bool cmp_f(float v, int32_t op, float t) {
+    switch (op) {
+    case HEPK_GT: return v > t;
+    case HEPK_GE: return v >= t;
+    case HEPK_LT: return v < t;
+    case HEPK_LE: return v <= t;
+    case HEPK_ABS_LT: return fabsf(v) < t;
+    default: return fabsf(v) <= t;
+    }
+}
+
+__device__ __forceinline__ bool cmp_i(int32_t v, int32_t op, int32_t t) {
+    switch (op) {
+    case HEPK_GT: return v > t;
+    case HEPK_GE: return v >= t;
+    case HEPK_LT: return v < t;
+    case HEPK_LE: return v <= t;
+    case HEPK_ABS_LT: return abs(v) < t;
+    default: return abs(v) <= t;
+    }
+}
+
+// dR^2 = deta^2 + dphi^2 with dphi brought into [-pi, pi] by one step of 2*pi.
+// Written as separate rounded float32 operations; -ffp-contract=off keeps
+// the compiler from fusing the square and the sum.
+__device__ __forceinline__ float delta_r2(float eta_a, float phi_a, float eta_b, float phi_b) {
+    float deta = eta_a - eta_b;
+    float dphi = phi_a - phi_b;
+    if (dphi > kPi)
+        dphi = dphi - kTwoPi;
+    else if (dphi < -kPi)
+        dphi = dphi + kTwoPi;
+    float a = deta * deta;
+    float b = dphi * dphi;
+    return a + b;
+}
+
+// Histogram slot of x (not NaN) for edges E[0..nbins]: 0 if x < E[0],
+// nbins+1 if x >= E[nbins], else s with E[s-1] <= x < E[s].  A guess from the
+// uniform-bin formula (lo, inv_w) is verified against the edges and replaced by
+// a binary search when wrong, so any increasing edges give the exact slot.
+__device__ __forceinline__ int hist_slot(float x, const float *E, int nbins, float lo, float inv_w) {
+    if (!(x >= E[0])) return 0;
+    if (x >= E[nbins]) return nbins + 1;
+    float g = (x - lo) * inv_w;
+    int s = (g >= 0.0f) ? ((g < static_cast<float>(nbins)) ? static_cast<int>(g) + 1 : nbins) : 1;
+    if (x < E[s - 1] || x >= E[s]) {
+        int a = 0, b = nbins;  // E[a] <= x < E[b]
+        while (b - a > 1) {
+            int m = (a + b) >> 1;
+            if (E[m] <= x)
+                a = m;
+            else
+                b = m;
+        }
+        s = a + 1;
+    }
+    return s;
+}
+
+// Read-only data seen through the constant address space: the compiler may then
+// fetch it with scalar loads into SGPRs when the address is uniform (a kernel
+// that also does global atomics otherwise has to assume the data may change
+// and keeps every field of a table entry in VGPRs).  Only for memory the
+// kernel never writes.
+// (The host pass of this single-source file only type-checks device code; it
+// sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using const_ptr = const __attribute__((address_space(4))) T *;
+#else
+template <typename T>
+using const_ptr = const T *;
+#endif
+
+template <typename T>
+__device__ __forceinline__ const_ptr<T> as_const(const T *p) {
+    return reinterpret_cast<const_ptr<T>>(reinterpret_cast<uintptr_t>(p));
+}
+
+__device__ __forceinline__ void atomic_add_f64(double *p, double v) {
+    unsafeAtomicAdd(p, v);  // global_atomic_add_f64 / ds_add_f64 on gfx950
+}
+
+__device__ __forceinline__ void atomic_add_u64(uint64_t *p, uint64_t v) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(p), static_cast<unsigned long long>(v));
+}
+
+}  // namespace hepk

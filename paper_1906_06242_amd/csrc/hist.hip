@@ -1,0 +1,98 @@
+// hepk_hist_fill: weighted 1-D histogram fill (Sec. III fill-histogram
+// kernel), accumulating into the caller's histogram.
+//
+// Each workgroup keeps a private copy of the histogram in LDS (float64 sums
+// via ds_add_f64, uint32 counts via ds_add_u32), walks a grid-stride range of
+// rows, and merges its non-empty slots into HBM with global atomics at the
+// end.  Histograms too large for LDS go straight to global atomics.  Sums of
+// float64 weights are exact in any order while every partial sum is a
+// multiple of the smallest weight's ulp below 2^53 of it, which holds for the
+// float32 weights of this analysis; otherwise the order changes only the
+// last bits.
+#include "common.hpp"
+
+namespace hepk {
+
+constexpr int HB = 256;
+constexpr int kMaxLdsSlots = 4096;  // 48 KiB of LDS per workgroup
+
+template <typename X, bool LDS>
+__global__ __launch_bounds__(HB) void hist_kernel(const X *__restrict__ x, const float *__restrict__ w,
+                                                  const uint8_t *__restrict__ m, int64_t n,
+                                                  const float *__restrict__ edges, int nbins,
+                                                  double *__restrict__ sumw, uint64_t *__restrict__ counts) {
+    extern __shared__ double hist_lds[];
+    // start values of the bin guess (verified against the edges in hist_slot)
+    const float lo = edges[0];
+    const float span = edges[nbins] - lo;
+    const float inv_w = (span > 0.0f && span < INFINITY) ? static_cast<float>(nbins) / span : 0.0f;
+    const int nslots = nbins + 2;
+    double *sw_s = hist_lds;
+    uint32_t *c_s = reinterpret_cast<uint32_t *>(hist_lds + (LDS ? nslots : 0));
+    if (LDS) {
+        for (int i = threadIdx.x; i < nslots; i += HB) {
+            sw_s[i] = 0.0;
+            c_s[i] = 0u;
+        }
+        __syncthreads();
+    }
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * HB;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * HB + threadIdx.x; i < n; i += stride) {
+        if (m && !m[i]) continue;
+        const float v = static_cast<float>(x[i]);
+        if (v != v) continue;
+        const int s = hist_slot(v, edges, nbins, lo, inv_w);
+        const double wt = w ? static_cast<double>(w[i]) : 1.0;
+        if (LDS) {
+            atomic_add_f64(&sw_s[s], wt);
+            atomicAdd(&c_s[s], 1u);
+        } else {
+            atomic_add_f64(&sumw[s], wt);
+            atomic_add_u64(&counts[s], 1u);
+        }
+    }
+    if (LDS) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < nslots; i += HB) {
+            const uint32_t c = c_s[i];
+            if (c) {
+                atomic_add_u64(&counts[i], c);
+                atomic_add_f64(&sumw[i], sw_s[i]);
+            }
+        }
+    }
+}
+
+template <typename X>
+static int launch_hist(const void *x, const float *w, const uint8_t *m, int64_t n, const hepk_hist *h,
+                       hipStream_t stream) {
+    const int nslots = h->nbins + 2;
+    const bool lds = nslots <= kMaxLdsSlots;
+    const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n, HB * 16), 4 * device_cus()));
+    if (lds)
+        hist_kernel<X, true><<<grid, HB, nslots * (sizeof(double) + sizeof(uint32_t)), stream>>>(
+            static_cast<const X *>(x), w, m, n, h->edges, h->nbins, h->sumw, h->counts);
+    else
+        hist_kernel<X, false><<<grid, HB, 0, stream>>>(static_cast<const X *>(x), w, m, n, h->edges, h->nbins,
+                                                       h->sumw, h->counts);
+    return check_launch("hepk_hist_fill");
+}
+
+}  // namespace hepk
+
+extern "C" int hepk_hist_fill(const void *x, int32_t dtype, const float *w, const uint8_t *evt_mask, int64_t n,
+                              const hepk_hist *h, hipStream_t stream) {
+    using namespace hepk;
+    clear_error();
+    HEPK_REQUIRE(h, "hepk_hist_fill: hist is NULL");
+    HEPK_REQUIRE(n >= 0, "hepk_hist_fill: n < 0");
+    HEPK_REQUIRE(h->nbins >= 1, "hepk_hist_fill: nbins %d < 1", h->nbins);
+    HEPK_REQUIRE(h->edges && h->sumw && h->counts, "hepk_hist_fill: histogram array is NULL");
+    HEPK_REQUIRE(n == 0 || x, "hepk_hist_fill: x is NULL");
+    HEPK_REQUIRE(dtype == HEPK_F32 || dtype == HEPK_F16 || dtype == HEPK_I32, "hepk_hist_fill: bad dtype %d",
+                 dtype);
+    if (n == 0) return HEPK_OK;
+    if (dtype == HEPK_F16) return launch_hist<_Float16>(x, w, evt_mask, n, h, stream);
+    if (dtype == HEPK_I32) return launch_hist<int32_t>(x, w, evt_mask, n, h, stream);
+    return launch_hist<float>(x, w, evt_mask, n, h, stream);
+}

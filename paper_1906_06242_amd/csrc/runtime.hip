@@ -1,0 +1,80 @@
+// libhepk runtime pieces: per-thread error text, device properties, the
+// ABI version and the offsets validator.
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace hepk {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = 0; }
+
+int check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("%s launch failed: %s", what, hipGetErrorString(e));
+        return HEPK_EHIP;
+    }
+    return HEPK_OK;
+}
+
+int device_cus() {
+    static std::mutex mu;
+    static std::vector<int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev >= static_cast<int>(cache.size())) cache.resize(dev + 1, 0);
+    if (cache[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        cache[dev] = n;
+    }
+    return cache[dev];
+}
+
+// Counts offsets[0] != 0, offsets[i+1] < offsets[i] and offsets[N] != M.
+__global__ void validate_offsets_kernel(const int64_t *off, int64_t n, int64_t m,
+                                        unsigned long long *bad) {
+    unsigned long long local = 0;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+        local += (off[i + 1] < off[i]) ? 1ull : 0ull;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        local += (off[0] != 0) ? 1ull : 0ull;
+        local += (off[n] != m) ? 1ull : 0ull;
+    }
+    if (local) atomicAdd(bad, local);
+}
+
+__global__ void zero_i64_kernel(int64_t *p) { *p = 0; }
+
+}  // namespace hepk
+
+extern "C" const char *hepk_last_error(void) { return hepk::g_err; }
+
+extern "C" int hepk_abi_version(void) { return HEPK_ABI_VERSION; }
+
+extern "C" int hepk_validate_offsets(const int64_t *offsets, int64_t n_events, int64_t n_objects,
+                                     int64_t *bad, hipStream_t stream) {
+    using namespace hepk;
+    clear_error();
+    HEPK_REQUIRE(offsets && bad, "hepk_validate_offsets: null pointer");
+    HEPK_REQUIRE(n_events >= 0 && n_objects >= 0, "hepk_validate_offsets: negative size");
+    zero_i64_kernel<<<1, 1, 0, stream>>>(bad);
+    int grid = static_cast<int>(std::min<int64_t>(std::max<int64_t>(1, ceil_div(n_events, 256)), 4 * device_cus()));
+    validate_offsets_kernel<<<grid, 256, 0, stream>>>(offsets, n_events, n_objects,
+                                                      reinterpret_cast<unsigned long long *>(bad));
+    return check_launch("hepk_validate_offsets");
+}

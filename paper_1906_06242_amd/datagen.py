@@ -20,6 +20,7 @@ datasets can be generated in parallel or streamed.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 from typing import Dict, Iterator, List, Optional
 
@@ -169,9 +170,19 @@ def concat(parts: List[Dataset]) -> Dataset:
                    p0.content_dtype, p0.seed)
 
 
+def _chunk_job(args):
+    seed, c, n, extended, content_dtype = args
+    return next(iter_chunks(seed, (c + 1) * CHUNK if n == CHUNK else c * CHUNK + n,
+                            extended, content_dtype, start_chunk=c))
+
+
 def make_dataset(seed: int, n_events: int, extended: bool = False,
-                 content_dtype: str = "f32") -> Dataset:
-    """The whole dataset in host memory."""
+                 content_dtype: str = "f32", jobs: int = 0) -> Dataset:
+    """The whole dataset in host memory.
+
+    jobs > 1 draws the chunks in that many processes (same result: every
+    chunk has its own seed).  jobs = 0 picks min(8, cpus) for large datasets.
+    """
     if n_events == 0:
         z = np.zeros(1, np.int64)
         cdt = np.float16 if content_dtype == "f16" else np.float32
@@ -179,7 +190,16 @@ def make_dataset(seed: int, n_events: int, extended: bool = False,
         jc = JET_COLS + (("btag",) if extended else ())
         return Dataset(0, mk(jc), mk(MU_COLS), np.zeros(0, np.float32),
                        mk(EL_COLS) if extended else None, content_dtype, seed)
-    return concat(list(iter_chunks(seed, n_events, extended, content_dtype)))
+    sizes = _chunk_sizes(n_events)
+    if jobs == 0:
+        jobs = min(8, os.cpu_count() or 1) if len(sizes) > 2 else 1
+    if jobs <= 1 or len(sizes) == 1:
+        return concat(list(iter_chunks(seed, n_events, extended, content_dtype)))
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(min(jobs, len(sizes))) as pool:
+        parts = pool.map(_chunk_job, [(seed, c, n, extended, content_dtype)
+                                      for c, n in enumerate(sizes)])
+    return concat(parts)
 
 
 # ---------------------------------------------------------------------------

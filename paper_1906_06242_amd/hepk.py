@@ -1,0 +1,322 @@
+"""Python binding of libhepk.so (include/hepk.h): argument marshalling only.
+
+Every function takes torch tensors that live on the current HIP device,
+passes their device pointers and the current stream to the C ABI, and
+raises HepkError on a non-OK status.  Every step of the analysis runs in the
+library's HIP kernels; there is no host fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhepk.so")
+
+OK, EINVAL, EHIP, EUNSUPPORTED, ENOMEM = 0, -1, -2, -3, -4
+F32, F16, I32 = 0, 1, 2
+GT, GE, LT, LE, ABS_LT, ABS_LE = range(6)
+COUNT, SUM, MAX, MIN, ARGMAX, ARGMIN = range(6)
+MAX_CUTS = 8
+
+EXPORTS = (
+    "hepk_select", "hepk_reduce", "hepk_match_dr", "hepk_hist_fill", "hepk_validate_offsets",
+    "hepk_plan_create", "hepk_plan_hist_slots", "hepk_plan_hist_offset", "hepk_plan_get_tune",
+    "hepk_pipeline", "hepk_plan_destroy", "hepk_last_error", "hepk_abi_version",
+)
+
+
+class HepkError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn} returned {status}: {msg}")
+        self.status = status
+
+
+class Cut(C.Structure):
+    _fields_ = [("col", C.c_void_p), ("dtype", C.c_int32), ("op", C.c_int32),
+                ("thr", C.c_float), ("ithr", C.c_int32)]
+
+
+class Hist(C.Structure):
+    _fields_ = [("edges", C.c_void_p), ("nbins", C.c_int32),
+                ("sumw", C.c_void_p), ("counts", C.c_void_p)]
+
+
+class Collection(C.Structure):
+    _fields_ = [("offsets", C.c_void_p), ("pt", C.c_void_p), ("eta", C.c_void_p),
+                ("phi", C.c_void_p), ("extra", C.c_void_p)]
+
+
+class DatasetS(C.Structure):
+    _fields_ = [("n_events", C.c_int64), ("dtype", C.c_int32),
+                ("jets", Collection), ("muons", Collection), ("electrons", Collection),
+                ("weights", C.c_void_p)]
+
+
+class QueryS(C.Structure):
+    _fields_ = [("mu_pt", C.c_float), ("mu_abseta", C.c_float), ("mu_iso", C.c_float),
+                ("el_pt", C.c_float), ("el_abseta", C.c_float),
+                ("jet_pt", C.c_float), ("jet_abseta", C.c_float),
+                ("dr", C.c_float), ("btag", C.c_float),
+                ("min_mu", C.c_int32), ("min_jet", C.c_int32), ("min_b", C.c_int32),
+                ("n_scale", C.c_int32), ("scales", C.c_void_p),
+                ("edges", C.c_void_p * 3), ("nbins", C.c_int32 * 3)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("block", C.c_int32), ("ev_per_thread", C.c_int32),
+                ("hist_mode", C.c_int32), ("grid", C.c_int32)]
+
+    def as_dict(self):
+        return {"block": self.block, "ev_per_thread": self.ev_per_thread,
+                "hist_mode": self.hist_mode, "grid": self.grid}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libhepk.so (built in-tree by paper_1906_06242_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run __graft_entry__.build() "
+                           "(or python paper_1906_06242_amd/build.py) first")
+    lib = C.CDLL(path)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.hepk_select.argtypes = [C.POINTER(Cut), i32, i64, vp, vp, vp]
+    lib.hepk_reduce.argtypes = [i32, vp, i64, vp, i32, vp, vp, vp, vp, vp, vp]
+    lib.hepk_match_dr.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i32, i64, C.c_float, vp, vp, vp, vp]
+    lib.hepk_hist_fill.argtypes = [vp, i32, vp, vp, i64, C.POINTER(Hist), vp]
+    lib.hepk_validate_offsets.argtypes = [vp, i64, i64, vp, vp]
+    lib.hepk_plan_create.argtypes = [C.POINTER(DatasetS), i32, C.POINTER(QueryS), i32,
+                                     C.POINTER(Tune), C.POINTER(vp)]
+    lib.hepk_plan_hist_slots.argtypes = [vp, C.POINTER(i64)]
+    lib.hepk_plan_hist_offset.argtypes = [vp, i32, i32, i32, i32, C.POINTER(i64), C.POINTER(i32)]
+    lib.hepk_plan_get_tune.argtypes = [vp, C.POINTER(Tune)]
+    lib.hepk_pipeline.argtypes = [vp, vp, vp, vp]
+    lib.hepk_plan_destroy.argtypes = [vp]
+    lib.hepk_last_error.restype = C.c_char_p
+    lib.hepk_last_error.argtypes = []
+    lib.hepk_abi_version.restype = C.c_int
+    for name in EXPORTS:
+        if name not in ("hepk_last_error", "hepk_abi_version"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().hepk_last_error().decode()
+
+
+def _call(name: str, *args) -> None:
+    rc = getattr(load(), name)(*args)
+    if rc != OK:
+        raise HepkError(name, rc, last_error())
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("hepk expects device tensors")
+    if not t.is_contiguous():
+        raise ValueError("hepk expects contiguous tensors")
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def dtype_code(t) -> int:
+    import torch
+    return {torch.float32: F32, torch.float16: F16, torch.int32: I32}[t.dtype]
+
+
+# ---------------------------------------------------------------- primitives
+
+def select(cuts: Sequence, n: int, mask_in=None, out=None, stream=None):
+    """cuts: [(column tensor, op, threshold)]; returns a uint8 mask of n rows."""
+    import torch
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8, device="cuda")
+    arr = (Cut * max(1, len(cuts)))()
+    for i, (col, op, thr) in enumerate(cuts):
+        dt = dtype_code(col)
+        if dt == I32:
+            arr[i] = Cut(_ptr(col), dt, op, 0.0, int(thr))
+        else:
+            arr[i] = Cut(_ptr(col), dt, op, float(thr), 0)
+    _call("hepk_select", arr, len(cuts), n, _ptr(mask_in), _ptr(out), _stream(stream))
+    return out
+
+
+def reduce(op: int, offsets, content=None, obj_mask=None, evt_mask=None, want_arg=False,
+           want_offsets=False, out=None, stream=None):
+    import torch
+    n = offsets.numel() - 1
+    if out is None:
+        dt = torch.int32 if op in (COUNT, ARGMAX, ARGMIN) else torch.float32
+        out = torch.empty(n, dtype=dt, device="cuda")
+    arg = torch.empty(n, dtype=torch.int32, device="cuda") if want_arg else None
+    offo = torch.empty(n + 1, dtype=torch.int64, device="cuda") if want_offsets else None
+    dt = dtype_code(content) if content is not None else F32
+    _call("hepk_reduce", op, _ptr(offsets), n, _ptr(content), dt, _ptr(obj_mask), _ptr(evt_mask),
+          _ptr(out), _ptr(arg), _ptr(offo), _stream(stream))
+    res = [out] + ([arg] if want_arg else []) + ([offo] if want_offsets else [])
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def match_dr(off_a, eta_a, phi_a, off_b, eta_b, phi_b, dr: float, mask_a=None, mask_b=None,
+             want=("min_dr2", "idx", "clean"), stream=None):
+    import torch
+    ma = eta_a.numel()
+    md = torch.empty(ma, dtype=torch.float32, device="cuda") if "min_dr2" in want else None
+    ix = torch.empty(ma, dtype=torch.int32, device="cuda") if "idx" in want else None
+    cl = torch.empty(ma, dtype=torch.uint8, device="cuda") if "clean" in want else None
+    _call("hepk_match_dr", _ptr(off_a), _ptr(eta_a), _ptr(phi_a), _ptr(mask_a), _ptr(off_b),
+          _ptr(eta_b), _ptr(phi_b), _ptr(mask_b), dtype_code(eta_a), off_a.numel() - 1, dr,
+          _ptr(md), _ptr(ix), _ptr(cl), _stream(stream))
+    return md, ix, cl
+
+
+def hist_fill(x, edges, sumw, counts, w=None, evt_mask=None, stream=None):
+    h = Hist(_ptr(edges), edges.numel() - 1, _ptr(sumw), _ptr(counts))
+    _call("hepk_hist_fill", _ptr(x), dtype_code(x), _ptr(w), _ptr(evt_mask), x.numel(),
+          C.byref(h), _stream(stream))
+    return sumw, counts
+
+
+def validate_offsets(offsets, n_objects: int, stream=None) -> int:
+    import torch
+    bad = torch.empty(1, dtype=torch.int64, device="cuda")
+    _call("hepk_validate_offsets", _ptr(offsets), offsets.numel() - 1, n_objects, _ptr(bad),
+          _stream(stream))
+    return int(bad.item())
+
+
+# ---------------------------------------------------------------- fused pass
+
+class DeviceDataset:
+    """A datagen.Dataset with every column resident in device memory."""
+
+    def __init__(self, ds, device="cuda"):
+        import numpy as np
+        import torch
+        self.n_events = ds.n_events
+        self.content_dtype = ds.content_dtype
+        self.tensors: Dict[str, "torch.Tensor"] = {}
+        for cname, coll in ds.collections():
+            self.tensors[f"{cname}.offsets"] = torch.from_numpy(coll.offsets).to(device)
+            for k, v in coll.cols.items():
+                if k == "mass":
+                    continue  # stored in the dataset, never read by the analysis
+                if v.size == 0:  # keep a valid (never read) pointer for empty columns
+                    v = np.zeros(1, v.dtype)
+                self.tensors[f"{cname}.{k}"] = torch.from_numpy(v).to(device)
+        w = ds.weight if ds.weight.size else np.ones(1, np.float32)
+        self.tensors["weight"] = torch.from_numpy(w).to(device)
+        self.has_electrons = ds.electrons is not None
+
+    def t(self, key):
+        return self.tensors.get(key)
+
+    def struct(self) -> DatasetS:
+        def coll(name, extra):
+            if self.t(f"{name}.offsets") is None:
+                return Collection(None, None, None, None, None)
+            return Collection(_ptr(self.t(f"{name}.offsets")), _ptr(self.t(f"{name}.pt")),
+                              _ptr(self.t(f"{name}.eta")), _ptr(self.t(f"{name}.phi")),
+                              _ptr(self.t(f"{name}.{extra}")) if extra else None)
+        return DatasetS(self.n_events, F16 if self.content_dtype == "f16" else F32,
+                        coll("jets", "btag" if self.t("jets.btag") is not None else None),
+                        coll("muons", "iso"), coll("electrons", None), _ptr(self.t("weight")))
+
+
+
+class Plan:
+    """hepk_plan over device datasets and datagen.Query objects."""
+
+    def __init__(self, datasets: List[DeviceDataset], queries, tune: Optional[dict] = None):
+        import torch
+        self._keep = []
+        dsa = (DatasetS * len(datasets))(*[d.struct() for d in datasets])
+        qa = (QueryS * len(queries))()
+        self.edges = []
+        for i, q in enumerate(queries):
+            sc = (C.c_float * q.n_scale)(*[float(x) for x in q.scales])
+            self._keep.append(sc)
+            eds = [torch.from_numpy(e.astype("float32")).to("cuda") for e in q.edges()]
+            self.edges.append(eds)
+            qs = QueryS(q.mu_pt, q.mu_abseta, q.mu_iso, q.el_pt, q.el_abseta, q.jet_pt, q.jet_abseta,
+                        q.dr, q.btag, q.min_mu, q.min_jet, q.min_b, q.n_scale,
+                        C.cast(sc, C.c_void_p))
+            for h in range(3):
+                qs.edges[h] = _ptr(eds[h])
+                qs.nbins[h] = eds[h].numel() - 1
+            qa[i] = qs
+        tn = None
+        if tune is not None:
+            tn = Tune(tune.get("block", 256), tune.get("ev_per_thread", 1),
+                      tune.get("hist_mode", 0), tune.get("grid", 0))
+        h = C.c_void_p()
+        _call("hepk_plan_create", dsa, len(datasets), qa, len(queries),
+              C.byref(tn) if tn is not None else None, C.byref(h))
+        self.handle = h
+        self.datasets = datasets
+        self.queries = queries
+        n = C.c_int64()
+        _call("hepk_plan_hist_slots", h, C.byref(n))
+        self.n_slots = n.value
+        t = Tune()
+        _call("hepk_plan_get_tune", h, C.byref(t))
+        self.tune = t.as_dict()
+
+    def hist_offset(self, d: int, q: int, v: int, h: int):
+        off, nb = C.c_int64(), C.c_int32()
+        _call("hepk_plan_hist_offset", self.handle, d, q, v, h, C.byref(off), C.byref(nb))
+        return off.value, nb.value
+
+    def new_hists(self):
+        import torch
+        return (torch.zeros(self.n_slots, dtype=torch.float64, device="cuda"),
+                torch.zeros(self.n_slots, dtype=torch.int64, device="cuda"))
+
+    def run(self, sumw, counts, stream=None):
+        _call("hepk_pipeline", self.handle, _ptr(sumw), _ptr(counts), _stream(stream))
+
+    def split(self, sumw, counts):
+        """Host copies as hists[d][q][v][h] = (sumw, counts) numpy arrays."""
+        s = sumw.cpu().numpy()
+        c = counts.cpu().numpy().view("uint64")
+        out = []
+        for d in range(len(self.datasets)):
+            per_d = []
+            for qi, q in enumerate(self.queries):
+                per_q = []
+                for v in range(q.n_scale):
+                    per_v = []
+                    for h in range(3):
+                        off, nb = self.hist_offset(d, qi, v, h)
+                        per_v.append((s[off:off + nb + 2].copy(), c[off:off + nb + 2].copy()))
+                    per_q.append(per_v)
+                per_d.append(per_q)
+            out.append(per_d)
+        return out
+
+    def close(self):
+        if self.handle:
+            _call("hepk_plan_destroy", self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,428 @@
+"""GPU parity: every libhepk entry point against the CPU oracle.
+
+Same seeded inputs on both sides; masks, counts, offsets, indices and
+per-event float32 values must match bit for bit, histogram counts exactly and
+float64 weight sums within a relative 1e-5 per bin (they are exact for the
+weights used here, see test_oracle_pins).  Sizes span several tiles with a
+ragged last tile; dedicated cases drive the large-event fallbacks, empty
+inputs, unaligned masks and every launch configuration of the fused kernel.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_1906_06242_amd import datagen
+from paper_1906_06242_amd import hepk as H
+from paper_1906_06242_amd import plain
+
+import golden_io
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    H.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def bits(a):
+    a = np.asarray(a)
+    return a.view(np.uint32) if a.dtype == np.float32 else a
+
+
+def assert_hist(got, want, what=""):
+    gs, gc = got
+    ws, wc = want
+    assert np.array_equal(np.asarray(gc).astype(np.uint64), np.asarray(wc).astype(np.uint64)), f"counts {what}"
+    err = np.abs(np.asarray(gs) - np.asarray(ws))
+    assert np.all(err <= RTOL * np.abs(ws)), f"sumw {what}: max rel err {np.max(err / np.maximum(np.abs(ws), 1e-300))}"
+
+
+# ------------------------------------------------------------------ select
+
+@pytest.mark.parametrize("n", [0, 1, 3, 4, 1023, 4097, 100003])
+def test_select_matches_oracle(n):
+    say(f"select n={n}")
+    rng = np.random.default_rng(n)
+    a = rng.normal(30, 10, n).astype(np.float32)
+    a[rng.integers(0, max(n, 1), n // 10)] = 30.0
+    if n > 5:
+        a[:3] = [np.nan, np.inf, -np.inf]
+    b = rng.normal(0, 2, n).astype(np.float16)
+    c = rng.integers(-5, 6, n).astype(np.int32)
+    m = (rng.uniform(size=n) < 0.8).astype(np.uint8)
+    for cuts in ([(a, H.GT, 30.0)], [(a, H.LE, 31.0), (b, H.ABS_LT, 1.5)],
+                 [(c, H.GE, 2), (b, H.GE, -0.5), (a, H.LT, 40.0), (c, H.ABS_LE, 4)],
+                 [(b, H.ABS_LE, 1.0), (a, H.GE, 25.0)]):
+        for mask in (None, m):
+            want = ref.select([(x, op, t) for x, op, t in cuts], n, mask_in=mask)
+            got = H.select([(dev(x), op, t) for x, op, t in cuts], n,
+                           mask_in=dev(mask) if mask is not None else None)
+            assert np.array_equal(host(got), want)
+
+
+def test_select_unaligned_masks():
+    import torch
+    say("select unaligned")
+    n = 5001
+    rng = np.random.default_rng(1)
+    a = rng.normal(30, 10, n).astype(np.float32)
+    m = (rng.uniform(size=n) < 0.5).astype(np.uint8)
+    big_in = torch.zeros(n + 3, dtype=torch.uint8, device="cuda")
+    big_in[1:n + 1] = dev(m)
+    big_out = torch.full((n + 3,), 7, dtype=torch.uint8, device="cuda")
+    H.select([(dev(a), H.GT, 30.0)], n, mask_in=big_in[1:n + 1], out=big_out[3:3 + n])
+    assert np.array_equal(host(big_out[3:3 + n]), ref.select([(a, H.GT, 30.0)], n, mask_in=m))
+    assert host(big_out[:3]).tolist() == [7, 7, 7]
+
+
+# ------------------------------------------------------------------ reduce
+
+def _jagged(seed, n_events, big_events=()):
+    rng = np.random.default_rng(seed)
+    cnt = np.minimum(rng.poisson(5, n_events), 20)
+    cnt[rng.integers(0, n_events, n_events // 7)] = 0
+    for e, k in big_events:
+        cnt[e] = k
+    off = np.zeros(n_events + 1, np.int64)
+    off[1:] = np.cumsum(cnt)
+    m = int(off[-1])
+    x = (20 + rng.exponential(30, m)).astype(np.float32)
+    x[rng.integers(0, max(m, 1), m // 50)] = 42.0  # ties
+    return off, x, rng
+
+
+@pytest.mark.parametrize("case", ["ragged", "giant_event", "empty"])
+def test_reduce_matches_oracle(case):
+    if case == "ragged":
+        off, x, rng = _jagged(3, 3001)
+    elif case == "giant_event":
+        off, x, rng = _jagged(4, 1200, big_events=[(700, 10000), (701, 5000), (1199, 4097)])
+    else:
+        off, x, rng = np.zeros(1, np.int64), np.zeros(0, np.float32), np.random.default_rng(0)
+    n = len(off) - 1
+    m = len(x)
+    om = (rng.uniform(size=m) < 0.6).astype(np.uint8)
+    em = (rng.uniform(size=n) < 0.8).astype(np.uint8)
+    doff = dev(off)
+    for dt in (np.float32, np.float16):
+        xv = x.astype(dt)
+        dx = dev(xv)
+        for omask in (None, om):
+            for emask in (None, em):
+                say(f"reduce {case} dtype={dt.__name__} obj_mask={omask is not None} evt_mask={emask is not None}")
+                dom = dev(omask) if omask is not None else None
+                dem = dev(emask) if emask is not None else None
+                cw, ow = ref.reduce(ref.COUNT, off, obj_mask=omask, evt_mask=emask, want_offsets=True)
+                cg, og = H.reduce(H.COUNT, doff, obj_mask=dom, evt_mask=dem, want_offsets=True)
+                assert np.array_equal(host(cg), cw) and np.array_equal(host(og), ow)
+                sw = ref.reduce(ref.SUM, off, xv, obj_mask=omask, evt_mask=emask)
+                sg = H.reduce(H.SUM, doff, dx, obj_mask=dom, evt_mask=dem)
+                assert np.array_equal(bits(host(sg)), bits(sw))
+                for op in (ref.MAX, ref.MIN):
+                    vw, aw = ref.reduce(op, off, xv, obj_mask=omask, evt_mask=emask, want_arg=True)
+                    vg, ag = H.reduce(op, doff, dx, obj_mask=dom, evt_mask=dem, want_arg=True)
+                    assert np.array_equal(bits(host(vg)), bits(vw)) and np.array_equal(host(ag), aw)
+                for op in (ref.ARGMAX, ref.ARGMIN):
+                    assert np.array_equal(host(H.reduce(op, doff, dx, obj_mask=dom, evt_mask=dem)),
+                                          ref.reduce(op, off, xv, obj_mask=omask, evt_mask=emask))
+
+
+def test_reduce_sum_order_case():
+    say("reduce sum order")
+    off = np.array([0, 3, 6, 6], np.int64)
+    x = np.array([16777216.0, 1.0, 1.0, 1.0, 16777216.0, 1.0], np.float32)
+    s = host(H.reduce(H.SUM, dev(off), dev(x)))
+    assert s.tolist() == [16777216.0, 16777216.0, 0.0]
+
+
+# ------------------------------------------------------------------ Delta-R
+
+def test_match_dr_golden():
+    say("match_dr golden")
+    g, ds, q = golden_io.load()
+    j, m = ds.jets, ds.muons
+    msel = golden_io.per_object(g, "msel", np.uint8)
+    md, ix, cl = H.match_dr(dev(j.offsets), dev(j.cols["eta"]), dev(j.cols["phi"]),
+                            dev(m.offsets), dev(m.cols["eta"]), dev(m.cols["phi"]), q.dr, mask_b=dev(msel))
+    assert host(cl).tolist() == golden_io.per_object(g, "clean", np.uint8).tolist()
+    wmd, wix, _ = ref.match_dr(j.offsets, j.cols["eta"], j.cols["phi"], m.offsets, m.cols["eta"],
+                               m.cols["phi"], q.dr, mask_b=msel)
+    assert np.array_equal(bits(host(md)), bits(wmd)) and np.array_equal(host(ix), wix)
+
+
+@pytest.mark.parametrize("case", ["config0", "f16", "large_events"])
+def test_match_dr_matches_oracle(case):
+    if case == "large_events":
+        n = 2000
+        rng = np.random.default_rng(5)
+        ca = np.minimum(rng.poisson(5, n), 20)
+        cb = np.minimum(rng.poisson(2, n), 8)
+        ca[300:310] = 900     # one tile with > 4096 a objects
+        cb[1500:1510] = 300   # one tile with > 2048 b objects
+        offa = np.concatenate([[0], np.cumsum(ca)]).astype(np.int64)
+        offb = np.concatenate([[0], np.cumsum(cb)]).astype(np.int64)
+        ea = rng.normal(0, 1.5, offa[-1]).astype(np.float32)
+        pa = rng.uniform(-np.pi, np.pi, offa[-1]).astype(np.float32)
+        eb = rng.normal(0, 1.5, offb[-1]).astype(np.float32)
+        pb = rng.uniform(-np.pi, np.pi, offb[-1]).astype(np.float32)
+        mb = (rng.uniform(size=offb[-1]) < 0.7).astype(np.uint8)
+        ma = (rng.uniform(size=offa[-1]) < 0.9).astype(np.uint8)
+    else:
+        ds = datagen.make_dataset(0, 100000 if case == "config0" else 30000,
+                                  content_dtype="f16" if case == "f16" else "f32")
+        j, m = ds.jets, ds.muons
+        offa, ea, pa = j.offsets, j.cols["eta"], j.cols["phi"]
+        offb, eb, pb = m.offsets, m.cols["eta"], m.cols["phi"]
+        mb = ((m.cols["pt"] > 20) & (np.abs(m.cols["eta"].astype(np.float32)) < np.float32(2.4))
+              & (m.cols["iso"] < np.float32(0.15))).astype(np.uint8)
+        ma = None
+    say(f"match_dr {case} n={len(offa) - 1}")
+    for dr in (0.4, 0.0, 1.2):
+        wmd, wix, wcl = ref.match_dr(offa, ea, pa, offb, eb, pb, dr, mask_a=ma, mask_b=mb)
+        md, ix, cl = H.match_dr(dev(offa), dev(ea), dev(pa), dev(offb), dev(eb), dev(pb), dr,
+                                mask_a=dev(ma) if ma is not None else None, mask_b=dev(mb))
+        assert np.array_equal(bits(host(md)), bits(wmd))
+        assert np.array_equal(host(ix), wix)
+        assert np.array_equal(host(cl), wcl)
+    # no mask on b, only the clean output requested
+    _, _, wcl = ref.match_dr(offa, ea, pa, offb, eb, pb, 0.4)
+    _, _, cl = H.match_dr(dev(offa), dev(ea), dev(pa), dev(offb), dev(eb), dev(pb), 0.4, want=("clean",))
+    assert np.array_equal(host(cl), wcl)
+
+
+# ------------------------------------------------------------------ histograms
+
+@pytest.mark.parametrize("edges_kind", ["uniform", "nonuniform", "wide", "single"])
+def test_hist_fill_matches_oracle(edges_kind):
+    import torch
+    say(f"hist {edges_kind}")
+    rng = np.random.default_rng(7)
+    n = 200003
+    if edges_kind == "uniform":
+        edges = datagen.uniform_edges(100, 0.0, 2000.0)
+    elif edges_kind == "nonuniform":
+        edges = np.sort(rng.uniform(-100, 2100, 38)).astype(np.float32)
+    elif edges_kind == "wide":
+        edges = datagen.uniform_edges(6000, 0.0, 2000.0)   # beyond LDS: global atomics
+    else:
+        edges = np.array([100.0, 1000.0], np.float32)
+    x = rng.uniform(-200, 2300, n).astype(np.float32)
+    x[:1000] = edges[rng.integers(0, len(edges), 1000)]
+    x[1000:1010] = [np.nan, np.inf, -np.inf, 0.0, -0.0, 2000.0, 1e30, -1e30, np.nan, 1999.9999]
+    w = rng.normal(1, 0.1, n).astype(np.float32)
+    m = (rng.uniform(size=n) < 0.75).astype(np.uint8)
+    de = dev(edges)
+    for wt, mk in ((w, m), (None, None), (w, None)):
+        ws, wc = ref.hist_fill(x, edges, wt, mk)
+        s = torch.zeros(len(edges) + 1, dtype=torch.float64, device="cuda")
+        c = torch.zeros(len(edges) + 1, dtype=torch.int64, device="cuda")
+        H.hist_fill(dev(x), de, s, c, w=dev(wt) if wt is not None else None,
+                    evt_mask=dev(mk) if mk is not None else None)
+        assert_hist((host(s), host(c)), (ws, wc), edges_kind)
+        # accumulation: a second fill doubles every slot
+        H.hist_fill(dev(x), de, s, c, w=dev(wt) if wt is not None else None,
+                    evt_mask=dev(mk) if mk is not None else None)
+        assert_hist((host(s), host(c)), (2 * ws, 2 * wc), edges_kind + " twice")
+
+
+def test_hist_fill_int_and_half_inputs():
+    import torch
+    say("hist int32/f16")
+    rng = np.random.default_rng(8)
+    xi = rng.integers(-2, 25, 50001).astype(np.int32)
+    xh = rng.normal(500, 400, 50001).astype(np.float16)
+    for x, edges in ((xi, datagen.uniform_edges(21, 0, 21)), (xh, datagen.uniform_edges(100, 0, 1000))):
+        ws, wc = ref.hist_fill(x, edges)
+        s = torch.zeros(len(edges) + 1, dtype=torch.float64, device="cuda")
+        c = torch.zeros(len(edges) + 1, dtype=torch.int64, device="cuda")
+        H.hist_fill(dev(x), dev(edges), s, c)
+        assert_hist((host(s), host(c)), (ws, wc))
+
+
+def test_validate_offsets():
+    say("validate offsets")
+    off = np.array([0, 2, 2, 5, 9], np.int64)
+    assert H.validate_offsets(dev(off), 9) == 0
+    assert H.validate_offsets(dev(off), 8) == 1
+    assert H.validate_offsets(dev(np.array([1, 0, 3, 9], np.int64)), 9) == 2
+
+
+# ------------------------------------------------------------------ fused pass
+
+def fused(datasets, queries, tune=None):
+    dds = [H.DeviceDataset(d) for d in datasets]
+    plan = H.Plan(dds, queries, tune)
+    s, c = plan.new_hists()
+    plan.run(s, c)
+    out = plan.split(s, c)
+    plan.close()
+    return out
+
+
+def check_against_oracle(ds, queries, got_d, what=""):
+    want = ref.pipeline(ds, queries)
+    for qi, q in enumerate(queries):
+        for v in range(q.n_scale):
+            for h in range(3):
+                assert_hist(got_d[qi][v][h], want[qi][v][h], f"{what} q{qi} v{v} h{h}")
+
+
+def test_pipeline_golden_hand_values():
+    say("pipeline golden")
+    g, ds, q = golden_io.load()
+    got = fused([ds], [q])[0][0][0]
+    for k, name in enumerate(("ht", "lead", "njet")):
+        nb = len(q.edges()[k]) - 1
+        assert_hist(got[k], golden_io.expected_hist(g, name, nb), name)
+
+
+TUNES = [None, dict(block=512), dict(ev_per_thread=2), dict(block=512, ev_per_thread=2),
+         dict(hist_mode=1), dict(grid=7)]
+
+
+@pytest.mark.parametrize("tune", TUNES, ids=[str(t) for t in TUNES])
+def test_pipeline_config0_all_tunes(tune):
+    say(f"pipeline config0 tune={tune}")
+    ds = datagen.make_dataset(0, 100000)
+    q = datagen.Query()
+    got = fused([ds], [q], tune)[0]
+    check_against_oracle(ds, [q], got, f"tune={tune}")
+    assert int(got[0][0][0][1].sum()) > 20000
+
+
+def test_pipeline_multi_query():
+    say("pipeline multi query")
+    ds = datagen.make_dataset(2, 50000)
+    qs = datagen.draw_queries(1, 6)
+    got = fused([ds], qs)[0]
+    check_against_oracle(ds, qs, got, "multi")
+
+
+@pytest.mark.parametrize("dtype", ["f16", "f32"])
+def test_pipeline_extended_schema_jes(dtype):
+    say(f"pipeline extended {dtype}")
+    ds = datagen.make_dataset(5, 40000, extended=True, content_dtype=dtype)
+    q = datagen.extended_query()
+    got = fused([ds], [q])[0]
+    check_against_oracle(ds, [q], got, "ext")
+    assert len(got[0]) == 20
+
+
+def test_pipeline_batch_uneven():
+    say("pipeline batch")
+    sizes = [0, 1, 255, 256, 257, 30000, 5, 12345]
+    dss = [datagen.make_dataset(1000 + i, n) for i, n in enumerate(sizes)]
+    q = datagen.Query()
+    got = fused(dss, [q], dict(grid=5))
+    for d, ds in enumerate(dss):
+        check_against_oracle(ds, [q], got[d], f"dataset {d} n={sizes[d]}")
+    got2 = fused(dss, [q])
+    for d, ds in enumerate(dss):
+        check_against_oracle(ds, [q], got2[d], f"dataset {d} default grid")
+
+
+def _with_giant_events(ds, rng):
+    """Make a few events huge so their tiles exceed the on-chip capacity."""
+    n = ds.n_events
+    idx = [3, 600, 601, n - 1]
+    jc = np.diff(ds.jets.offsets).copy()
+    mc = np.diff(ds.muons.offsets).copy()
+    for e, (a, b) in zip(idx, [(3000, 10), (10, 1500), (2500, 1200), (700, 300)]):
+        jc[e], mc[e] = a, b
+
+    def rebuild(coll, counts, names, near):
+        off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        cols = {}
+        for k in names:
+            src = coll.cols[k]
+            cols[k] = rng.choice(src, int(off[-1])).astype(src.dtype)
+        return datagen.Collection(off, cols)
+
+    jets = rebuild(ds.jets, jc, list(ds.jets.cols), None)
+    mus = rebuild(ds.muons, mc, list(ds.muons.cols), None)
+    els = None
+    if ds.electrons is not None:
+        ec = np.diff(ds.electrons.offsets).copy()
+        ec[601] = 2000
+        els = rebuild(ds.electrons, ec, list(ds.electrons.cols), None)
+    return datagen.Dataset(n, jets, mus, ds.weight, els, ds.content_dtype)
+
+
+@pytest.mark.parametrize("extended", [False, True])
+def test_pipeline_oversized_tiles(extended):
+    say(f"pipeline oversized tiles extended={extended}")
+    base = datagen.make_dataset(9, 3000, extended=extended)
+    ds = _with_giant_events(base, np.random.default_rng(3))
+    q = datagen.extended_query() if extended else datagen.Query()
+    if extended:
+        q = datagen.Query(min_b=1, scales=q.scales[:3])
+    for tune in (None, dict(hist_mode=1)):
+        got = fused([ds], [q], tune)[0]
+        check_against_oracle(ds, [q], got, f"giant tune={tune}")
+
+
+def test_pipeline_repeated_runs_accumulate():
+    say("pipeline accumulate")
+    ds = datagen.make_dataset(4, 20000)
+    q = datagen.Query()
+    plan = H.Plan([H.DeviceDataset(ds)], [q])
+    s, c = plan.new_hists()
+    for _ in range(3):
+        plan.run(s, c)
+    got = plan.split(s, c)[0][0][0]
+    plan.close()
+    want = ref.pipeline(ds, [q])[0][0]
+    for h in range(3):
+        assert_hist(got[h], (3 * want[h][0], 3 * want[h][1]), f"h{h}")
+
+
+def test_plain_pipeline_matches_oracle():
+    say("plain pipeline")
+    ds = datagen.make_dataset(0, 100000)
+    q = datagen.Query()
+    got = plain.run(H.DeviceDataset(ds), q)
+    want = ref.pipeline(ds, [q])[0][0]
+    for h in range(3):
+        assert_hist((host(got[h][0]), host(got[h][1]).view(np.uint64)), want[h], f"h{h}")
+
+
+def test_plain_pipeline_extended_nominal():
+    say("plain pipeline extended")
+    ds = datagen.make_dataset(6, 30000, extended=True, content_dtype="f16")
+    q = datagen.Query(min_b=1)
+    got = plain.run(H.DeviceDataset(ds), q)
+    want = ref.pipeline(ds, [q])[0][0]
+    for h in range(3):
+        assert_hist((host(got[h][0]), host(got[h][1]).view(np.uint64)), want[h], f"h{h}")
+
+
+def test_pipeline_full_size_1e7():
+    """The benchmark workload (1e7 events, default launch configuration),
+    checked in full against the oracle."""
+    say("pipeline full size 1e7")
+    ds = datagen.make_dataset(0, 10_000_000)
+    q = datagen.Query()
+    got = fused([ds], [q])[0]
+    check_against_oracle(ds, [q], got, "1e7")
