@@ -9,31 +9,37 @@
 // so a pass reads each input column from HBM once and writes only the
 // histograms.
 //
-// Work decomposition.  Events are cut into tiles of TILE = BLOCK * EVPT
-// consecutive events; a (dataset, tile) pair is one work item, and workgroup
-// g owns a contiguous run of items (so it meets few dataset boundaries).  For
-// one tile:
-//   1. Three scalar loads give the tile's object ranges; then every lane
-//      issues its loads at once -- offsets and weight of its events, up to JK
-//      jets, MK muons and EK electrons (consecutive lanes, consecutive
-//      objects: coalesced) -- into registers.
-//   2. Offsets go to LDS (tile-relative int32) and each event lane writes its
-//      event index over its jets (the jet -> event map).
-//   3. Per query: muon lanes evaluate the muon cuts and stage eta/phi in LDS,
+// Work decomposition.  Each wavefront owns tiles of TW = 64 * EVPL
+// consecutive events and works through them without waiting for the other
+// wavefronts of its workgroup (no workgroup barrier inside a tile: the four
+// or eight wavefronts of a workgroup only share the LDS histograms, updated
+// with atomics).  The host cuts every dataset's tiles into chunks; a
+// workgroup takes whole chunks, so a chunk never mixes datasets and the LDS
+// histograms are merged into HBM only when the workgroup moves to another
+// dataset.  For one tile a wavefront
+//   1. reads the tile's object ranges with scalar loads, then issues all of
+//      its loads at once -- offsets and weight of its events, up to JK jets,
+//      MK muons and EK electrons per lane (consecutive lanes, consecutive
+//      objects: coalesced) -- into registers, and waits once;
+//   2. puts the offsets in LDS (tile-relative int32) and lets each event lane
+//      write its event index over its jets (the jet -> event map);
+//   3. per query: muon lanes evaluate the muon cuts and stage eta/phi in LDS,
 //      eta = NaN for muons that fail (a NaN dR^2 never passes the cone test,
-//      which is the same as skipping them); electrons likewise.
-//   4. Jet lanes test the cone against their event's staged leptons and store
-//      pt (or NaN when removed or outside |eta|) in LDS.
-//   5. Event lanes walk their jets in order for each jet-energy scale s:
+//      which is the same as skipping them); electrons likewise;
+//   4. jet lanes test the cone against their event's staged leptons and store
+//      pt (or NaN when removed or outside |eta|) in LDS;
+//   5. event lanes walk their jets in order for each jet-energy scale s:
 //      ptv = pt * s, the jet cut, the count, the left-to-right float32 H_T,
 //      the maximum, the b-tag count; then the event cut and three fills into
-//      workgroup-private LDS histograms (float64 sums, uint32 counts), merged
-//      into HBM with atomics when the workgroup leaves a dataset.
-// A tile whose objects exceed the register/LDS capacity (never for the
-// distributions of the paper's workload, always possible for arbitrary
-// input) is processed by one lane per event straight from HBM with the same
-// arithmetic.
+//      the workgroup's LDS histograms (float64 sums, uint32 counts).
+// Steps 2-5 exchange data through the wavefront's own LDS region; a
+// wavefront's LDS operations complete in issue order, so only compiler
+// ordering fences are needed between them.  A tile whose objects exceed the
+// register capacity (a 5-sigma fluctuation for the paper's multiplicities,
+// always possible for arbitrary input) is processed one lane per event
+// straight from HBM with the same arithmetic.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -56,59 +62,49 @@ struct QDev {
     int32_t min_mu, min_jet, min_b;
     int32_t n_scale, scale0;
     int32_t nbins[3];
-    int32_t hoff[3];   // slot offset of each observable within one scale's block
-    int32_t slot0;     // first slot of this query within a dataset block
-    int32_t per_scale; // slots per scale
-    const float *edges[3];
+    int32_t hoff[3];    // slot offset of each observable within one scale's block
+    int32_t slot0;      // first slot of this query within a dataset block
+    int32_t per_scale;  // slots per scale
+    int32_t ebase[3];   // first edge of each observable in the plan's edge table
+    float lo[3], inv_w[3];  // start values of the bin guess (verified against the edges)
+};
+
+struct Chunk {
+    int32_t d, pad;
+    int64_t t0, t1;  // tiles [t0, t1) of dataset d
 };
 
 struct PipeArgs {
     const DsDev *ds;
-    const int64_t *item_prefix;  // n_ds + 1: first work item of each dataset
     const QDev *qs;
     const float *scales;
-    int64_t n_items;
-    int64_t items_per_wg;
-    int32_t n_ds, n_q;
-    int32_t ds_slots;            // histogram slots per dataset block
+    const Chunk *chunks;
+    const float *edges;  // all queries' bin edges, concatenated
+    int32_t n_chunks, n_q, ds_slots, n_edges, edges_in_lds;
     double *sumw;
     uint64_t *counts;
 };
 
 template <bool LDSH>
 struct HistSink {
-    double *sw_s;      // LDS (LDSH)
-    uint32_t *c_s;     // LDS (LDSH)
-    double *sumw;      // HBM (dataset block base when !LDSH)
-    uint64_t *counts;
+    double *sw;        // LDS (LDSH) or the dataset's block in HBM
+    uint32_t *c32;     // LDS (LDSH)
+    uint64_t *c64;     // HBM (!LDSH)
 
     __device__ __forceinline__ void add(int slot, double w) const {
         if (LDSH) {
-            atomic_add_f64(&sw_s[slot], w);
-            atomicAdd(&c_s[slot], 1u);
+            atomic_add_f64(&sw[slot], w);
+            atomicAdd(&c32[slot], 1u);
         } else {
-            atomic_add_f64(&sumw[slot], w);
-            atomic_add_u64(&counts[slot], 1u);
-        }
-    }
-};
-
-struct EdgeGuess {
-    float lo[3], inv_w[3];
-    __device__ __forceinline__ void init(const QDev &Q) {
-#pragma unroll
-        for (int h = 0; h < 3; ++h) {
-            const float a = as_const(Q.edges[h])[0];
-            const float span = as_const(Q.edges[h])[Q.nbins[h]] - a;
-            lo[h] = a;
-            inv_w[h] = (span > 0.0f && span < INFINITY) ? static_cast<float>(Q.nbins[h]) / span : 0.0f;
+            atomic_add_f64(&sw[slot], w);
+            atomic_add_u64(&c64[slot], 1u);
         }
     }
 };
 
 // Fills H_T, lead and nJet of one passing event for scale v of query Q.
 template <bool LDSH>
-__device__ __forceinline__ void fill3(const HistSink<LDSH> &sink, const QDev &Q, const EdgeGuess &g, int v,
+__device__ __forceinline__ void fill3(const HistSink<LDSH> &sink, const QDev &Q, const float *edges, int v,
                                       float ht, float lead, int nj, double w) {
     const int base = Q.slot0 + v * Q.per_scale;
     const float xs[3] = {ht, lead, static_cast<float>(nj)};
@@ -116,340 +112,350 @@ __device__ __forceinline__ void fill3(const HistSink<LDSH> &sink, const QDev &Q,
     for (int h = 0; h < 3; ++h) {
         const float x = xs[h];
         if (x != x) continue;
-        const int s = hist_slot(x, Q.edges[h], Q.nbins[h], g.lo[h], g.inv_w[h]);
+        const int s = hist_slot(x, edges + Q.ebase[h], Q.nbins[h], Q.lo[h], Q.inv_w[h]);
         sink.add(base + Q.hoff[h] + s, w);
     }
 }
 
-// One tile, one lane per event, columns read straight from HBM.
+// Orders this wavefront's LDS accesses around the point (LDS executes one
+// wavefront's operations in issue order, so no wait is needed, only that the
+// compiler keeps the order).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One event, one lane, columns read straight from HBM.
 template <typename T, bool EXT, bool LDSH>
-__device__ void slow_tile(const PipeArgs &P, const DsDev &D, int64_t e0, int ne, int lanes,
-                          const HistSink<LDSH> &sink) {
+__device__ void event_direct(const PipeArgs &P, const DsDev &D, int64_t e, const float *edges,
+                             const HistSink<LDSH> &sink) {
     const bool has_iso = D.miso != nullptr;
     const bool has_el = EXT && D.eoff != nullptr;
     const bool has_bt = EXT && D.jbt != nullptr;
-    for (int ev = threadIdx.x; ev < ne; ev += lanes) {
-        const int64_t e = e0 + ev;
-        const double w = D.w ? static_cast<double>(D.w[e]) : 1.0;
-        const int64_t j0 = D.joff[e], j1 = D.joff[e + 1];
-        const int64_t m0 = D.moff[e], m1 = D.moff[e + 1];
-        const int64_t l0 = has_el ? D.eoff[e] : 0, l1 = has_el ? D.eoff[e + 1] : 0;
-        for (int q = 0; q < P.n_q; ++q) {
-            const QDev Q = as_const(P.qs)[q];
-            EdgeGuess g;
-            g.init(Q);
-            auto mu_sel = [&](int64_t m) {
-                return ldf(static_cast<const T *>(D.mpt), m) > Q.mu_pt &&
-                       fabsf(ldf(static_cast<const T *>(D.meta), m)) < Q.mu_abseta &&
-                       (!has_iso || ldf(static_cast<const T *>(D.miso), m) < Q.mu_iso);
-            };
-            auto el_sel = [&](int64_t m) {
-                return ldf(static_cast<const T *>(D.ept), m) > Q.el_pt &&
-                       fabsf(ldf(static_cast<const T *>(D.eeta), m)) < Q.el_abseta;
-            };
-            int nmu = 0;
-            for (int64_t m = m0; m < m1; ++m) nmu += mu_sel(m) ? 1 : 0;
-            for (int v = 0; v < Q.n_scale; ++v) {
-                const float s = as_const(P.scales)[Q.scale0 + v];
-                int nj = 0, nb = 0;
-                float ht = 0.0f, lead = -INFINITY;
-                for (int64_t j = j0; j < j1; ++j) {
-                    const float x = ldf(static_cast<const T *>(D.jpt), j) * s;
-                    const float eta = ldf(static_cast<const T *>(D.jeta), j);
-                    if (!(x > Q.jet_pt && fabsf(eta) < Q.jet_abseta)) continue;
-                    const float phi = ldf(static_cast<const T *>(D.jphi), j);
-                    bool hit = false;
-                    for (int64_t m = m0; m < m1 && !hit; ++m)
-                        hit = mu_sel(m) && delta_r2(eta, phi, ldf(static_cast<const T *>(D.meta), m),
-                                                    ldf(static_cast<const T *>(D.mphi), m)) <= Q.thr2;
-                    for (int64_t m = l0; m < l1 && !hit; ++m)
-                        hit = el_sel(m) && delta_r2(eta, phi, ldf(static_cast<const T *>(D.eeta), m),
-                                                    ldf(static_cast<const T *>(D.ephi), m)) <= Q.thr2;
-                    if (hit) continue;
-                    if (nj == 0 || x > lead) lead = x;
-                    ++nj;
-                    ht = ht + x;
-                    if (has_bt && ldf(static_cast<const T *>(D.jbt), j) > Q.btag) ++nb;
-                }
-                const bool pass = nmu >= Q.min_mu && nj >= Q.min_jet && (!has_bt || nb >= Q.min_b);
-                if (pass) fill3(sink, Q, g, v, ht, lead, nj, w);
+    const double w = D.w ? static_cast<double>(D.w[e]) : 1.0;
+    const int64_t j0 = D.joff[e], j1 = D.joff[e + 1];
+    const int64_t m0 = D.moff[e], m1 = D.moff[e + 1];
+    const int64_t l0 = has_el ? D.eoff[e] : 0, l1 = has_el ? D.eoff[e + 1] : 0;
+    const T *jpt = static_cast<const T *>(D.jpt), *jeta = static_cast<const T *>(D.jeta);
+    const T *jphi = static_cast<const T *>(D.jphi), *jbt = static_cast<const T *>(D.jbt);
+    const T *mpt = static_cast<const T *>(D.mpt), *meta = static_cast<const T *>(D.meta);
+    const T *mphi = static_cast<const T *>(D.mphi), *miso = static_cast<const T *>(D.miso);
+    const T *ept = static_cast<const T *>(D.ept), *eeta = static_cast<const T *>(D.eeta);
+    const T *ephi = static_cast<const T *>(D.ephi);
+    for (int q = 0; q < P.n_q; ++q) {
+        const QDev Q = as_const(P.qs)[q];
+        auto mu_sel = [&](int64_t m) {
+            return ldf(mpt, m) > Q.mu_pt && fabsf(ldf(meta, m)) < Q.mu_abseta &&
+                   (!has_iso || ldf(miso, m) < Q.mu_iso);
+        };
+        auto el_sel = [&](int64_t m) { return ldf(ept, m) > Q.el_pt && fabsf(ldf(eeta, m)) < Q.el_abseta; };
+        int nmu = 0;
+        for (int64_t m = m0; m < m1; ++m) nmu += mu_sel(m) ? 1 : 0;
+        for (int v = 0; v < Q.n_scale; ++v) {
+            const float s = as_const(P.scales)[Q.scale0 + v];
+            int nj = 0, nb = 0;
+            float ht = 0.0f, lead = -INFINITY;
+            for (int64_t j = j0; j < j1; ++j) {
+                const float x = ldf(jpt, j) * s;
+                const float eta = ldf(jeta, j);
+                if (!(x > Q.jet_pt && fabsf(eta) < Q.jet_abseta)) continue;
+                const float phi = ldf(jphi, j);
+                bool hit = false;
+                for (int64_t m = m0; m < m1 && !hit; ++m)
+                    hit = mu_sel(m) && delta_r2(eta, phi, ldf(meta, m), ldf(mphi, m)) <= Q.thr2;
+                for (int64_t m = l0; m < l1 && !hit; ++m)
+                    hit = el_sel(m) && delta_r2(eta, phi, ldf(eeta, m), ldf(ephi, m)) <= Q.thr2;
+                if (hit) continue;
+                if (nj == 0 || x > lead) lead = x;
+                ++nj;
+                ht = ht + x;
+                if (has_bt && ldf(jbt, j) > Q.btag) ++nb;
             }
+            const bool pass = nmu >= Q.min_mu && nj >= Q.min_jet && (!has_bt || nb >= Q.min_b);
+            if (pass) fill3(sink, Q, edges, v, ht, lead, nj, w);
         }
     }
 }
 
-template <typename T, bool EXT, int BLOCK, int EVPT, bool LDSH>
-__global__ __launch_bounds__(BLOCK) void pipeline_kernel(PipeArgs P) {
-    constexpr int TILE = BLOCK * EVPT;
-    constexpr int JK = 8 * EVPT;                 // jet slots per lane
-    constexpr int MK = 4 * EVPT;                 // muon slots per lane
-    constexpr int EK = EXT ? 4 * EVPT : 1;       // electron slots per lane
-    constexpr int JCAP = JK * BLOCK, MCAP = MK * BLOCK, ECAP = EK * BLOCK;
-    __shared__ int32_t joff_s[TILE + 1], moff_s[TILE + 1];
-    __shared__ int32_t eoff_s[EXT ? TILE + 1 : 1];
-    __shared__ uint16_t jev_s[JCAP];
-    __shared__ float meta_s[MCAP], mphi_s[MCAP];
-    __shared__ float eeta_s[EXT ? ECAP : 1], ephi_s[EXT ? ECAP : 1];
-    __shared__ float ptc_s[JCAP];
-    __shared__ uint8_t bt_s[EXT ? JCAP : 1];
-    extern __shared__ double hist_dyn[];
+template <int EVPL, bool EXT>
+struct Caps {
+    static constexpr int TW = 64 * EVPL;             // events per wavefront tile
+    static constexpr int JK = 6 * EVPL + 1;          // jet slots per lane
+    static constexpr int MK = 2 * EVPL + 1;          // muon slots per lane
+    static constexpr int EK = EXT ? 2 * EVPL : 1;    // electron slots per lane
+    static constexpr int JC = 64 * JK, MC = 64 * MK, EC = 64 * EK;
+};
+
+template <int EVPL, bool EXT>
+struct WaveLds {
+    using C = Caps<EVPL, EXT>;
+    int32_t joff[C::TW + 1], moff[C::TW + 1];
+    int32_t eoff[EXT ? C::TW + 1 : 1];
+    float ptc[C::JC];
+    float meta[C::MC], mphi[C::MC];
+    float eeta[EXT ? C::EC : 1], ephi[EXT ? C::EC : 1];
+    uint8_t jev[C::JC];
+    uint8_t bt[EXT ? C::JC : 1];
+};
+
+template <typename T, bool EXT, int WAVES, int EVPL, bool LDSH>
+__global__ __launch_bounds__(64 * WAVES) void pipeline_kernel(PipeArgs P) {
+    using C = Caps<EVPL, EXT>;
+    constexpr int TW = C::TW, JK = C::JK, MK = C::MK, EK = C::EK;
+    __shared__ WaveLds<EVPL, EXT> wl[WAVES];
+    extern __shared__ double dyn[];  // [sumw | counts (u32) | edges] per workgroup
 
     const int tid = threadIdx.x;
-    const auto prefc = as_const(P.item_prefix);
-    const auto dsc = as_const(P.ds);
-    const auto qsc = as_const(P.qs);
-    const int64_t it0 = static_cast<int64_t>(blockIdx.x) * P.items_per_wg;
-    const int64_t it1 = min(it0 + P.items_per_wg, P.n_items);
-    if (it0 >= it1) return;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    auto &L = wl[wave];
 
-    HistSink<LDSH> sink;
-    sink.sw_s = hist_dyn;
-    sink.c_s = reinterpret_cast<uint32_t *>(hist_dyn + (LDSH ? P.ds_slots : 0));
+    double *sw_s = dyn;
+    uint32_t *c_s = reinterpret_cast<uint32_t *>(dyn + (LDSH ? P.ds_slots : 0));
+    float *e_s = reinterpret_cast<float *>(c_s + (LDSH ? P.ds_slots : 0));
     if (LDSH) {
-        for (int i = tid; i < P.ds_slots; i += BLOCK) {
-            sink.sw_s[i] = 0.0;
-            sink.c_s[i] = 0u;
+        for (int i = tid; i < P.ds_slots; i += 64 * WAVES) {
+            sw_s[i] = 0.0;
+            c_s[i] = 0u;
         }
     }
-    // dataset of the first item: last d with item_prefix[d] <= it0
-    int d = 0;
-    {
-        int lo = 0, hi = P.n_ds;  // item_prefix[lo] <= it0 < item_prefix[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (prefc[mid] <= it0)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        d = lo;
-    }
-    auto flush = [&](int dd) {
-        if (!LDSH) return;
-        __syncthreads();
-        const int64_t h0 = dsc[dd].hist0;
-        for (int i = tid; i < P.ds_slots; i += BLOCK) {
-            const uint32_t c = sink.c_s[i];
-            if (c) {
-                atomic_add_u64(&P.counts[h0 + i], c);
-                atomic_add_f64(&P.sumw[h0 + i], sink.sw_s[i]);
-                sink.c_s[i] = 0u;
-                sink.sw_s[i] = 0.0;
-            }
-        }
-        __syncthreads();
-    };
-    if (!LDSH) {
-        sink.sumw = P.sumw + dsc[d].hist0;
-        sink.counts = P.counts + dsc[d].hist0;
+    const float *edges = P.edges;
+    if (P.edges_in_lds) {
+        for (int i = tid; i < P.n_edges; i += 64 * WAVES) e_s[i] = as_const(P.edges)[i];
+        edges = e_s;
     }
     __syncthreads();
 
-    for (int64_t item = it0; item < it1; ++item) {
-        while (item >= prefc[d + 1]) {
-            flush(d);
-            ++d;
-            if (!LDSH) {
-                sink.sumw = P.sumw + dsc[d].hist0;
-                sink.counts = P.counts + dsc[d].hist0;
-            }
+    for (int ci = blockIdx.x; ci < P.n_chunks; ci += gridDim.x) {
+        const Chunk CH = as_const(P.chunks)[ci];
+        const DsDev D = as_const(P.ds)[CH.d];
+        HistSink<LDSH> sink;
+        if (LDSH) {
+            sink.sw = sw_s;
+            sink.c32 = c_s;
+        } else {
+            sink.sw = P.sumw + D.hist0;
+            sink.c64 = P.counts + D.hist0;
         }
-        const DsDev D = dsc[d];
         const bool has_iso = D.miso != nullptr;
         const bool has_el = EXT && D.eoff != nullptr;
         const bool has_bt = EXT && D.jbt != nullptr;
-        const int64_t e0 = (item - prefc[d]) * TILE;
-        const int ne = static_cast<int>(min<int64_t>(TILE, D.n_events - e0));
-        const int64_t J0 = as_const(D.joff)[e0], J1 = as_const(D.joff)[e0 + ne];
-        const int64_t M0 = as_const(D.moff)[e0], M1 = as_const(D.moff)[e0 + ne];
-        const int64_t L0 = has_el ? as_const(D.eoff)[e0] : 0, L1 = has_el ? as_const(D.eoff)[e0 + ne] : 0;
-        if (J1 - J0 > JCAP || M1 - M0 > MCAP || L1 - L0 > ECAP) {
-            slow_tile<T, EXT, LDSH>(P, D, e0, ne, BLOCK, sink);
-            continue;  // slow_tile touches no staging LDS; no barrier needed
-        }
-        const int nj = static_cast<int>(J1 - J0), nm = static_cast<int>(M1 - M0);
-        const int nl = static_cast<int>(L1 - L0);
 
-        // ---- 1. every load of the tile in flight at once
-        int32_t jo[EVPT], mo[EVPT], lo_[EVPT];
-        float wv[EVPT];
+        for (int64_t t = CH.t0 + wave; t < CH.t1; t += WAVES) {
+            const int64_t e0 = t * TW;
+            const int ne = static_cast<int>(min<int64_t>(TW, D.n_events - e0));
+            const int64_t J0 = as_const(D.joff)[e0], J1 = as_const(D.joff)[e0 + ne];
+            const int64_t M0 = as_const(D.moff)[e0], M1 = as_const(D.moff)[e0 + ne];
+            const int64_t L0 = has_el ? as_const(D.eoff)[e0] : 0, L1 = has_el ? as_const(D.eoff)[e0 + ne] : 0;
+            if (J1 - J0 > C::JC || M1 - M0 > C::MC || L1 - L0 > C::EC) {
 #pragma unroll
-        for (int r = 0; r < EVPT; ++r) {
-            const int ev = tid + r * BLOCK;
-            if (ev < ne) {
-                jo[r] = static_cast<int32_t>(D.joff[e0 + ev] - J0);
-                mo[r] = static_cast<int32_t>(D.moff[e0 + ev] - M0);
-                lo_[r] = has_el ? static_cast<int32_t>(D.eoff[e0 + ev] - L0) : 0;
-                wv[r] = D.w ? D.w[e0 + ev] : 1.0f;
+                for (int r = 0; r < EVPL; ++r) {
+                    const int ev = lane + 64 * r;
+                    if (ev < ne) event_direct<T, EXT, LDSH>(P, D, e0 + ev, edges, sink);
+                }
+                continue;
             }
-        }
-        float jpt[JK] = {}, jeta[JK] = {}, jphi[JK] = {}, jbt[EXT ? JK : 1] = {};
+            const int nj = static_cast<int>(J1 - J0), nm = static_cast<int>(M1 - M0);
+            const int nl = static_cast<int>(L1 - L0);
+
+            // ---- 1. all of the tile's loads in flight at once
+            int32_t jo[EVPL], mo[EVPL], lo_[EVPL];
+            float wv[EVPL];
 #pragma unroll
-        for (int k = 0; k < JK; ++k) {
-            const int j = tid + k * BLOCK;
-            if (j < nj) {
-                jpt[k] = ldf(static_cast<const T *>(D.jpt), J0 + j);
-                jeta[k] = ldf(static_cast<const T *>(D.jeta), J0 + j);
-                jphi[k] = ldf(static_cast<const T *>(D.jphi), J0 + j);
-                if (EXT) jbt[EXT ? k : 0] = has_bt ? ldf(static_cast<const T *>(D.jbt), J0 + j) : 0.0f;
-            }
-        }
-        float mpt[MK] = {}, meta[MK] = {}, mphi[MK] = {}, miso[MK] = {};
-#pragma unroll
-        for (int k = 0; k < MK; ++k) {
-            const int m = tid + k * BLOCK;
-            if (m < nm) {
-                mpt[k] = ldf(static_cast<const T *>(D.mpt), M0 + m);
-                meta[k] = ldf(static_cast<const T *>(D.meta), M0 + m);
-                mphi[k] = ldf(static_cast<const T *>(D.mphi), M0 + m);
-                miso[k] = has_iso ? ldf(static_cast<const T *>(D.miso), M0 + m) : 0.0f;
-            }
-        }
-        float lpt[EK] = {}, leta[EK] = {}, lphi[EK] = {};
-        if (EXT) {
-#pragma unroll
-            for (int k = 0; k < EK; ++k) {
-                const int m = tid + k * BLOCK;
-                if (m < nl) {
-                    lpt[k] = ldf(static_cast<const T *>(D.ept), L0 + m);
-                    leta[k] = ldf(static_cast<const T *>(D.eeta), L0 + m);
-                    lphi[k] = ldf(static_cast<const T *>(D.ephi), L0 + m);
+            for (int r = 0; r < EVPL; ++r) {
+                const int ev = lane + 64 * r;
+                jo[r] = mo[r] = lo_[r] = 0;
+                wv[r] = 1.0f;
+                if (ev < ne) {
+                    jo[r] = static_cast<int32_t>(D.joff[e0 + ev] - J0);
+                    mo[r] = static_cast<int32_t>(D.moff[e0 + ev] - M0);
+                    if (has_el) lo_[r] = static_cast<int32_t>(D.eoff[e0 + ev] - L0);
+                    if (D.w) wv[r] = D.w[e0 + ev];
                 }
             }
-        }
-
-        // Every value above is used here, so the compiler issues all of the
-        // tile's loads before this point and waits once, instead of sinking
-        // each load to its first use after a barrier (one HBM round trip per
-        // tile rather than three).
+            float jpt[JK] = {}, jeta[JK] = {}, jphi[JK] = {}, jbt[EXT ? JK : 1] = {};
 #pragma unroll
-        for (int k = 0; k < JK; ++k) asm volatile("" ::"v"(jpt[k]), "v"(jeta[k]), "v"(jphi[k]));
-#pragma unroll
-        for (int k = 0; k < MK; ++k) asm volatile("" ::"v"(mpt[k]), "v"(meta[k]), "v"(mphi[k]), "v"(miso[k]));
-        if (EXT) {
-#pragma unroll
-            for (int k = 0; k < JK; ++k) asm volatile("" ::"v"(jbt[EXT ? k : 0]));
-#pragma unroll
-            for (int k = 0; k < EK; ++k) asm volatile("" ::"v"(lpt[k]), "v"(leta[k]), "v"(lphi[k]));
-        }
-
-        // ---- 2. offsets and the jet -> event map
-#pragma unroll
-        for (int r = 0; r < EVPT; ++r) {
-            const int ev = tid + r * BLOCK;
-            if (ev < ne) {
-                joff_s[ev] = jo[r];
-                moff_s[ev] = mo[r];
-                if (EXT) eoff_s[ev] = lo_[r];
+            for (int k = 0; k < JK; ++k) {
+                const int j = lane + 64 * k;
+                if (j < nj) {
+                    jpt[k] = ldf(static_cast<const T *>(D.jpt), J0 + j);
+                    jeta[k] = ldf(static_cast<const T *>(D.jeta), J0 + j);
+                    jphi[k] = ldf(static_cast<const T *>(D.jphi), J0 + j);
+                    if (EXT && has_bt) jbt[EXT ? k : 0] = ldf(static_cast<const T *>(D.jbt), J0 + j);
+                }
             }
-        }
-        if (tid == 0) {
-            joff_s[ne] = nj;
-            moff_s[ne] = nm;
-            if (EXT) eoff_s[ne] = nl;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < EVPT; ++r) {
-            const int ev = tid + r * BLOCK;
-            if (ev < ne)
-                for (int k = joff_s[ev]; k < joff_s[ev + 1]; ++k) jev_s[k] = static_cast<uint16_t>(ev);
-        }
-
-        for (int q = 0; q < P.n_q; ++q) {
-            const QDev Q = qsc[q];
-            // ---- 3. lepton selection, staged in LDS
+            float mpt[MK] = {}, meta[MK] = {}, mphi[MK] = {}, miso[MK] = {};
 #pragma unroll
             for (int k = 0; k < MK; ++k) {
-                const int m = tid + k * BLOCK;
+                const int m = lane + 64 * k;
                 if (m < nm) {
-                    const bool sel = mpt[k] > Q.mu_pt && fabsf(meta[k]) < Q.mu_abseta &&
-                                     (!has_iso || miso[k] < Q.mu_iso);
-                    meta_s[m] = sel ? meta[k] : __builtin_nanf("");
-                    mphi_s[m] = mphi[k];
+                    mpt[k] = ldf(static_cast<const T *>(D.mpt), M0 + m);
+                    meta[k] = ldf(static_cast<const T *>(D.meta), M0 + m);
+                    mphi[k] = ldf(static_cast<const T *>(D.mphi), M0 + m);
+                    if (has_iso) miso[k] = ldf(static_cast<const T *>(D.miso), M0 + m);
                 }
             }
+            float lpt[EK] = {}, leta[EK] = {}, lphi[EK] = {};
             if (EXT) {
 #pragma unroll
                 for (int k = 0; k < EK; ++k) {
-                    const int m = tid + k * BLOCK;
+                    const int m = lane + 64 * k;
                     if (m < nl) {
-                        const bool sel = lpt[k] > Q.el_pt && fabsf(leta[k]) < Q.el_abseta;
-                        eeta_s[m] = sel ? leta[k] : __builtin_nanf("");
-                        ephi_s[m] = lphi[k];
+                        lpt[k] = ldf(static_cast<const T *>(D.ept), L0 + m);
+                        leta[k] = ldf(static_cast<const T *>(D.eeta), L0 + m);
+                        lphi[k] = ldf(static_cast<const T *>(D.ephi), L0 + m);
                     }
                 }
             }
-            __syncthreads();
-            // ---- 4. cone test per jet
+            // Every value above is used here, so the compiler issues all of the
+            // tile's loads before this point and waits once, instead of sinking
+            // each load to its first use (one HBM round trip per tile).
 #pragma unroll
-            for (int k = 0; k < JK; ++k) {
-                const int j = tid + k * BLOCK;
-                if (j < nj) {
-                    const int ev = jev_s[j];
-                    bool hit = false;
-                    for (int m = moff_s[ev]; m < moff_s[ev + 1]; ++m)
-                        hit |= delta_r2(jeta[k], jphi[k], meta_s[m], mphi_s[m]) <= Q.thr2;
-                    if (EXT)
-                        for (int m = eoff_s[ev]; m < eoff_s[ev + 1]; ++m)
-                            hit |= delta_r2(jeta[k], jphi[k], eeta_s[m], ephi_s[m]) <= Q.thr2;
-                    const bool ok = !hit && fabsf(jeta[k]) < Q.jet_abseta;
-                    ptc_s[j] = ok ? jpt[k] : __builtin_nanf("");
-                    if (EXT) bt_s[j] = (has_bt && jbt[EXT ? k : 0] > Q.btag) ? 1 : 0;
-                }
+            for (int k = 0; k < JK; ++k) asm volatile("" ::"v"(jpt[k]), "v"(jeta[k]), "v"(jphi[k]));
+#pragma unroll
+            for (int k = 0; k < MK; ++k) asm volatile("" ::"v"(mpt[k]), "v"(meta[k]), "v"(mphi[k]), "v"(miso[k]));
+            if (EXT) {
+#pragma unroll
+                for (int k = 0; k < JK; ++k) asm volatile("" ::"v"(jbt[EXT ? k : 0]));
+#pragma unroll
+                for (int k = 0; k < EK; ++k) asm volatile("" ::"v"(lpt[k]), "v"(leta[k]), "v"(lphi[k]));
             }
-            __syncthreads();
-            // ---- 5. per-event reductions, event cut, fills
-            EdgeGuess g;
-            g.init(Q);
+
+            // ---- 2. offsets and the jet -> event map
 #pragma unroll
-            for (int r = 0; r < EVPT; ++r) {
-                const int ev = tid + r * BLOCK;
+            for (int r = 0; r < EVPL; ++r) {
+                const int ev = lane + 64 * r;
                 if (ev < ne) {
-                    int nmu = 0;
-                    for (int m = moff_s[ev]; m < moff_s[ev + 1]; ++m) nmu += (meta_s[m] == meta_s[m]) ? 1 : 0;
-                    const int j0 = joff_s[ev], j1 = joff_s[ev + 1];
-                    const double w = static_cast<double>(wv[r]);
-                    for (int v = 0; v < Q.n_scale; ++v) {
-                        const float s = as_const(P.scales)[Q.scale0 + v];
-                        int njs = 0, nb = 0;
-                        float ht = 0.0f, lead = -INFINITY;
-                        for (int k = j0; k < j1; ++k) {
-                            const float x = ptc_s[k] * s;
-                            if (x > Q.jet_pt) {
-                                if (njs == 0 || x > lead) lead = x;
-                                ++njs;
-                                ht = ht + x;
-                                if (EXT) nb += bt_s[k];
-                            }
-                        }
-                        const bool pass = nmu >= Q.min_mu && njs >= Q.min_jet && (!has_bt || nb >= Q.min_b);
-                        if (pass) fill3(sink, Q, g, v, ht, lead, njs, w);
-                    }
+                    L.joff[ev] = jo[r];
+                    L.moff[ev] = mo[r];
+                    if (EXT) L.eoff[ev] = lo_[r];
                 }
             }
-            __syncthreads();
+            if (lane == 0) {
+                L.joff[ne] = nj;
+                L.moff[ne] = nm;
+                if (EXT) L.eoff[ne] = nl;
+            }
+            wave_sync();
+#pragma unroll
+            for (int r = 0; r < EVPL; ++r) {
+                const int ev = lane + 64 * r;
+                if (ev < ne)
+                    for (int k = L.joff[ev]; k < L.joff[ev + 1]; ++k) L.jev[k] = static_cast<uint8_t>(ev);
+            }
+
+            for (int q = 0; q < P.n_q; ++q) {
+                const QDev Q = as_const(P.qs)[q];
+                // ---- 3. lepton selection, staged in LDS
+#pragma unroll
+                for (int k = 0; k < MK; ++k) {
+                    const int m = lane + 64 * k;
+                    if (m < nm) {
+                        const bool sel = mpt[k] > Q.mu_pt && fabsf(meta[k]) < Q.mu_abseta &&
+                                         (!has_iso || miso[k] < Q.mu_iso);
+                        L.meta[m] = sel ? meta[k] : __builtin_nanf("");
+                        L.mphi[m] = mphi[k];
+                    }
+                }
+                if (EXT) {
+#pragma unroll
+                    for (int k = 0; k < EK; ++k) {
+                        const int m = lane + 64 * k;
+                        if (m < nl) {
+                            const bool sel = lpt[k] > Q.el_pt && fabsf(leta[k]) < Q.el_abseta;
+                            L.eeta[m] = sel ? leta[k] : __builtin_nanf("");
+                            L.ephi[m] = lphi[k];
+                        }
+                    }
+                }
+                wave_sync();
+                // ---- 4. cone test per jet
+#pragma unroll
+                for (int k = 0; k < JK; ++k) {
+                    const int j = lane + 64 * k;
+                    if (j < nj) {
+                        const int ev = L.jev[j];
+                        bool hit = false;
+                        for (int m = L.moff[ev]; m < L.moff[ev + 1]; ++m)
+                            hit |= delta_r2(jeta[k], jphi[k], L.meta[m], L.mphi[m]) <= Q.thr2;
+                        if (EXT)
+                            for (int m = L.eoff[ev]; m < L.eoff[ev + 1]; ++m)
+                                hit |= delta_r2(jeta[k], jphi[k], L.eeta[m], L.ephi[m]) <= Q.thr2;
+                        const bool ok = !hit && fabsf(jeta[k]) < Q.jet_abseta;
+                        L.ptc[j] = ok ? jpt[k] : __builtin_nanf("");
+                        if (EXT) L.bt[j] = (has_bt && jbt[EXT ? k : 0] > Q.btag) ? 1 : 0;
+                    }
+                }
+                wave_sync();
+                // ---- 5. per-event reductions, event cut, fills
+#pragma unroll
+                for (int r = 0; r < EVPL; ++r) {
+                    const int ev = lane + 64 * r;
+                    if (ev < ne) {
+                        int nmu = 0;
+                        for (int m = L.moff[ev]; m < L.moff[ev + 1]; ++m) nmu += (L.meta[m] == L.meta[m]) ? 1 : 0;
+                        const int j0 = L.joff[ev], j1 = L.joff[ev + 1];
+                        const double w = static_cast<double>(wv[r]);
+                        for (int v = 0; v < Q.n_scale; ++v) {
+                            const float s = as_const(P.scales)[Q.scale0 + v];
+                            int njs = 0, nb = 0;
+                            float ht = 0.0f, lead = -INFINITY;
+                            for (int k = j0; k < j1; ++k) {
+                                const float x = L.ptc[k] * s;
+                                if (x > Q.jet_pt) {
+                                    if (njs == 0 || x > lead) lead = x;
+                                    ++njs;
+                                    ht = ht + x;
+                                    if (EXT) nb += L.bt[k];
+                                }
+                            }
+                            const bool pass =
+                                nmu >= Q.min_mu && njs >= Q.min_jet && (!has_bt || nb >= Q.min_b);
+                            if (pass) fill3(sink, Q, edges, v, ht, lead, njs, w);
+                        }
+                    }
+                }
+                wave_sync();
+            }
+        }
+        // merge the LDS histograms when the next chunk is another dataset (or none)
+        if (LDSH) {
+            const int nci = ci + static_cast<int>(gridDim.x);
+            if (nci >= P.n_chunks || as_const(P.chunks)[nci].d != CH.d) {
+                __syncthreads();
+                const int64_t h0 = D.hist0;
+                for (int i = tid; i < P.ds_slots; i += 64 * WAVES) {
+                    const uint32_t c = c_s[i];
+                    if (c) {
+                        atomic_add_u64(&P.counts[h0 + i], c);
+                        atomic_add_f64(&P.sumw[h0 + i], sw_s[i]);
+                        c_s[i] = 0u;
+                        sw_s[i] = 0.0;
+                    }
+                }
+                __syncthreads();
+            }
         }
     }
-    flush(d);
 }
 
 using KernelFn = void (*)(PipeArgs);
 
-template <typename T, bool EXT, int BLOCK, int EVPT, bool LDSH>
+template <typename T, bool EXT, int WAVES, int EVPL, bool LDSH>
 static KernelFn kfn() {
-    return reinterpret_cast<KernelFn>(&pipeline_kernel<T, EXT, BLOCK, EVPT, LDSH>);
+    return reinterpret_cast<KernelFn>(&pipeline_kernel<T, EXT, WAVES, EVPL, LDSH>);
 }
 
-template <typename T, bool EXT, int BLOCK, int EVPT>
+template <typename T, bool EXT, int WAVES, int EVPL>
 static KernelFn pick_h(bool ldsh) {
-    return ldsh ? kfn<T, EXT, BLOCK, EVPT, true>() : kfn<T, EXT, BLOCK, EVPT, false>();
+    return ldsh ? kfn<T, EXT, WAVES, EVPL, true>() : kfn<T, EXT, WAVES, EVPL, false>();
 }
 
 template <typename T, bool EXT>
 static KernelFn pick_shape(int block, int evpt, bool ldsh) {
-    if (block == 512) return evpt == 2 ? pick_h<T, EXT, 512, 2>(ldsh) : pick_h<T, EXT, 512, 1>(ldsh);
-    return evpt == 2 ? pick_h<T, EXT, 256, 2>(ldsh) : pick_h<T, EXT, 256, 1>(ldsh);
+    if (block == 512) return evpt == 2 ? pick_h<T, EXT, 8, 2>(ldsh) : pick_h<T, EXT, 8, 1>(ldsh);
+    return evpt == 2 ? pick_h<T, EXT, 4, 2>(ldsh) : pick_h<T, EXT, 4, 1>(ldsh);
 }
 
 static KernelFn pick_kernel(int dtype, bool ext, int block, int evpt, bool ldsh) {
@@ -458,7 +464,8 @@ static KernelFn pick_kernel(int dtype, bool ext, int block, int evpt, bool ldsh)
     return ext ? pick_shape<float, true>(block, evpt, ldsh) : pick_shape<float, false>(block, evpt, ldsh);
 }
 
-constexpr int kMaxLdsHistBytes = 48 * 1024;
+constexpr int kMaxLdsHistBytes = 32 * 1024;
+constexpr int kMaxLdsEdgeBytes = 4 * 1024;
 
 }  // namespace hepk
 
@@ -542,9 +549,30 @@ extern "C" int hepk_plan_create(const hepk_dataset *ds, int32_t n_ds, const hepk
     p->dtype = dtype;
     p->ext = ext;
 
+    // Bin edges are copied into the plan's own table (one device-to-host copy
+    // for the bin-guess start values, one device-to-device copy per array).
+    std::vector<std::vector<float>> eh(static_cast<size_t>(n_query) * 3);
+    int64_t n_edges = 0;
+    for (int i = 0; i < n_query; ++i)
+        for (int h = 0; h < 3; ++h) {
+            auto &v = eh[i * 3 + h];
+            v.resize(q[i].nbins[h] + 1);
+            if (hipMemcpy(v.data(), q[i].edges[h], v.size() * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) {
+                set_error("hepk_plan_create: reading query %d edges %d failed", i, h);
+                return plan_fail(p, HEPK_EHIP);
+            }
+            for (size_t k = 0; k + 1 < v.size(); ++k)
+                if (!(v[k] < v[k + 1])) {
+                    set_error("hepk_plan_create: query %d edges %d not strictly increasing at %zu", i, h, k);
+                    return plan_fail(p, HEPK_EINVAL);
+                }
+            n_edges += static_cast<int64_t>(v.size());
+        }
+
     // histogram layout: per dataset, per query, per scale, (H_T, lead, nJet)
     std::vector<QDev> qd(n_query);
     std::vector<float> scales;
+    std::vector<float> edge_table;
     int64_t ds_slots = 0;
     for (int i = 0; i < n_query; ++i) {
         const hepk_query &Q = q[i];
@@ -566,16 +594,21 @@ extern "C" int hepk_plan_create(const hepk_dataset *ds, int32_t n_ds, const hepk
         for (int v = 0; v < Q.n_scale; ++v) scales.push_back(Q.scales[v]);
         int32_t acc = 0;
         for (int h = 0; h < 3; ++h) {
+            const auto &v = eh[i * 3 + h];
             o.nbins[h] = Q.nbins[h];
-            o.edges[h] = Q.edges[h];
             o.hoff[h] = acc;
+            o.ebase[h] = static_cast<int32_t>(edge_table.size());
+            edge_table.insert(edge_table.end(), v.begin(), v.end());
+            const float span = v.back() - v.front();
+            o.lo[h] = v.front();
+            o.inv_w[h] = (span > 0.0f && std::isfinite(span)) ? static_cast<float>(Q.nbins[h]) / span : 0.0f;
             acc += Q.nbins[h] + 2;
         }
         o.per_scale = acc;
         o.slot0 = static_cast<int32_t>(ds_slots);
         ds_slots += static_cast<int64_t>(acc) * Q.n_scale;
     }
-    if (ds_slots >= (int64_t(1) << 30)) {
+    if (ds_slots >= (int64_t(1) << 30) || n_edges >= (int64_t(1) << 30)) {
         set_error("hepk_plan_create: %lld histogram slots per dataset is too many", (long long)ds_slots);
         return plan_fail(p, HEPK_EINVAL);
     }
@@ -596,10 +629,13 @@ extern "C" int hepk_plan_create(const hepk_dataset *ds, int32_t n_ds, const hepk
     const size_t hist_bytes = static_cast<size_t>(ds_slots) * (sizeof(double) + sizeof(uint32_t));
     const bool ldsh = (t.hist_mode == 0) && hist_bytes <= static_cast<size_t>(kMaxLdsHistBytes);
     if (!ldsh) t.hist_mode = 1;
-    const int tile = t.block * t.ev_per_thread;
+    const bool edges_lds = n_edges * sizeof(float) <= static_cast<size_t>(kMaxLdsEdgeBytes);
+    const int waves = t.block / 64;
+    const int tw = 64 * t.ev_per_thread;
 
     std::vector<DsDev> dd(n_ds);
-    std::vector<int64_t> prefix(n_ds + 1, 0);
+    int64_t total_tiles = 0;
+    std::vector<int64_t> tiles(n_ds);
     for (int d = 0; d < n_ds; ++d) {
         const hepk_dataset &D = ds[d];
         DsDev &o = dd[d];
@@ -620,56 +656,67 @@ extern "C" int hepk_plan_create(const hepk_dataset *ds, int32_t n_ds, const hepk
         o.ephi = D.electrons.phi;
         o.w = D.weights;
         o.hist0 = d * ds_slots;
-        prefix[d + 1] = prefix[d] + ceil_div(D.n_events, tile);
-    }
-    const int64_t n_items = prefix[n_ds];
-
-    // one device allocation for the tables
-    const size_t sz_ds = sizeof(DsDev) * n_ds, sz_pre = sizeof(int64_t) * (n_ds + 1);
-    const size_t sz_q = sizeof(QDev) * n_query, sz_sc = sizeof(float) * scales.size();
-    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    const size_t total = al(sz_ds) + al(sz_pre) + al(sz_q) + al(sz_sc);
-    if (hipMalloc(&p->dev_mem, total) != hipSuccess) {
-        set_error("hepk_plan_create: hipMalloc of %zu bytes failed", total);
-        return plan_fail(p, HEPK_ENOMEM);
-    }
-    char *base = static_cast<char *>(p->dev_mem);
-    std::vector<char> host(total, 0);
-    size_t o_ds = 0, o_pre = al(sz_ds), o_q = o_pre + al(sz_pre), o_sc = o_q + al(sz_q);
-    std::memcpy(host.data() + o_ds, dd.data(), sz_ds);
-    std::memcpy(host.data() + o_pre, prefix.data(), sz_pre);
-    std::memcpy(host.data() + o_q, qd.data(), sz_q);
-    if (sz_sc) std::memcpy(host.data() + o_sc, scales.data(), sz_sc);
-    if (hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
-        set_error("hepk_plan_create: table upload failed");
-        return plan_fail(p, HEPK_EHIP);
+        tiles[d] = ceil_div(D.n_events, tw);
+        total_tiles += tiles[d];
     }
 
     p->fn = pick_kernel(dtype, ext, t.block, t.ev_per_thread, ldsh);
-    p->lds_bytes = ldsh ? hist_bytes : 0;
+    p->lds_bytes = (ldsh ? hist_bytes : 0) + (edges_lds ? n_edges * sizeof(float) : 0);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(p->fn), t.block,
                                                      p->lds_bytes) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     int64_t grid = t.grid > 0 ? t.grid : static_cast<int64_t>(per_cu) * device_cus();
-    grid = std::max<int64_t>(1, std::min<int64_t>(grid, std::max<int64_t>(1, n_items)));
-    const int64_t ipw = std::max<int64_t>(1, ceil_div(n_items, grid));
-    grid = std::max<int64_t>(1, ceil_div(n_items, ipw));
+
+    // Chunks: runs of tiles of one dataset, a multiple of the wavefronts per
+    // workgroup long, about total/grid tiles each, so that every workgroup
+    // gets one chunk (plus the few split off at dataset ends).
+    const int64_t per = std::max<int64_t>(waves, ceil_div(ceil_div(total_tiles, std::max<int64_t>(1, grid)), waves) * waves);
+    std::vector<Chunk> chunks;
+    for (int d = 0; d < n_ds; ++d)
+        for (int64_t t0 = 0; t0 < tiles[d]; t0 += per) chunks.push_back(Chunk{d, 0, t0, std::min(tiles[d], t0 + per)});
+    const int64_t n_chunks = static_cast<int64_t>(chunks.size());
+    HEPK_REQUIRE(n_chunks < (int64_t(1) << 31), "hepk_plan_create: too many work chunks");
+    grid = std::max<int64_t>(1, std::min<int64_t>(grid, n_chunks));
     t.grid = static_cast<int32_t>(grid);
     p->tune = t;
     p->grid = static_cast<int>(grid);
 
+    // one device allocation for the tables
+    const size_t sz_ds = sizeof(DsDev) * n_ds, sz_ch = sizeof(Chunk) * std::max<int64_t>(1, n_chunks);
+    const size_t sz_q = sizeof(QDev) * n_query, sz_sc = sizeof(float) * scales.size();
+    const size_t sz_e = sizeof(float) * edge_table.size();
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t o_ds = 0, o_ch = al(sz_ds), o_q = o_ch + al(sz_ch), o_sc = o_q + al(sz_q), o_e = o_sc + al(sz_sc);
+    const size_t total = o_e + al(sz_e);
+    if (hipMalloc(&p->dev_mem, total) != hipSuccess) {
+        set_error("hepk_plan_create: hipMalloc of %zu bytes failed", total);
+        return plan_fail(p, HEPK_ENOMEM);
+    }
+    char *base = static_cast<char *>(p->dev_mem);
+    std::vector<char> host(total, 0);
+    std::memcpy(host.data() + o_ds, dd.data(), sz_ds);
+    if (n_chunks) std::memcpy(host.data() + o_ch, chunks.data(), sizeof(Chunk) * n_chunks);
+    std::memcpy(host.data() + o_q, qd.data(), sz_q);
+    if (sz_sc) std::memcpy(host.data() + o_sc, scales.data(), sz_sc);
+    if (sz_e) std::memcpy(host.data() + o_e, edge_table.data(), sz_e);
+    if (hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("hepk_plan_create: table upload failed");
+        return plan_fail(p, HEPK_EHIP);
+    }
+
     PipeArgs &A = p->args;
     A.ds = reinterpret_cast<const DsDev *>(base + o_ds);
-    A.item_prefix = reinterpret_cast<const int64_t *>(base + o_pre);
     A.qs = reinterpret_cast<const QDev *>(base + o_q);
     A.scales = reinterpret_cast<const float *>(base + o_sc);
-    A.n_items = n_items;
-    A.items_per_wg = ipw;
-    A.n_ds = n_ds;
+    A.chunks = reinterpret_cast<const Chunk *>(base + o_ch);
+    A.edges = reinterpret_cast<const float *>(base + o_e);
+    A.n_chunks = static_cast<int32_t>(n_chunks);
     A.n_q = n_query;
     A.ds_slots = static_cast<int32_t>(ds_slots);
+    A.n_edges = static_cast<int32_t>(n_edges);
+    A.edges_in_lds = edges_lds ? 1 : 0;
     *out = p;
     return HEPK_OK;
 }
@@ -706,7 +753,7 @@ extern "C" int hepk_pipeline(hepk_plan p, double *sumw, uint64_t *counts, hipStr
     clear_error();
     HEPK_REQUIRE(p, "hepk_pipeline: plan is NULL");
     HEPK_REQUIRE(sumw && counts, "hepk_pipeline: histogram buffers are NULL");
-    if (p->args.n_items == 0) return HEPK_OK;
+    if (p->args.n_chunks == 0) return HEPK_OK;
     int dev = 0;
     HEPK_HIP(hipGetDevice(&dev));
     HEPK_REQUIRE(dev == p->device, "hepk_pipeline: plan made on device %d, current device %d", p->device, dev);
