@@ -145,6 +145,26 @@ __device__ __forceinline__ const_ptr<T> as_const(const T *p) {
     return reinterpret_cast<const_ptr<T>>(reinterpret_cast<uintptr_t>(p));
 }
 
+// hist_slot with the end edges already at hand (lo == E[0], hi == E[nbins]).
+__device__ __forceinline__ int hist_slot_lohi(float x, const float *E, int nbins, float lo, float hi, float inv_w) {
+    if (!(x >= lo)) return 0;
+    if (x >= hi) return nbins + 1;
+    float g = (x - lo) * inv_w;
+    int s = (g >= 0.0f) ? ((g < static_cast<float>(nbins)) ? static_cast<int>(g) + 1 : nbins) : 1;
+    if (x < E[s - 1] || x >= E[s]) {
+        int a = 0, b = nbins;  // E[a] <= x < E[b]
+        while (b - a > 1) {
+            int m = (a + b) >> 1;
+            if (E[m] <= x)
+                a = m;
+            else
+                b = m;
+        }
+        s = a + 1;
+    }
+    return s;
+}
+
 __device__ __forceinline__ void atomic_add_f64(double *p, double v) {
     unsafeAtomicAdd(p, v);  // global_atomic_add_f64 / ds_add_f64 on gfx950
 }

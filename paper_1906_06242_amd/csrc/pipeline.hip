@@ -66,7 +66,8 @@ struct QDev {
     int32_t slot0;      // first slot of this query within a dataset block
     int32_t per_scale;  // slots per scale
     int32_t ebase[3];   // first edge of each observable in the plan's edge table
-    float lo[3], inv_w[3];  // start values of the bin guess (verified against the edges)
+    float lo[3], hi[3];     // first and last edge of each observable
+    float inv_w[3];         // nbins / (hi - lo): start value of the bin search
 };
 
 struct Chunk {
@@ -112,7 +113,7 @@ __device__ __forceinline__ void fill3(const HistSink<LDSH> &sink, const QDev &Q,
     for (int h = 0; h < 3; ++h) {
         const float x = xs[h];
         if (x != x) continue;
-        const int s = hist_slot(x, edges + Q.ebase[h], Q.nbins[h], Q.lo[h], Q.inv_w[h]);
+        const int s = hist_slot_lohi(x, edges + Q.ebase[h], Q.nbins[h], Q.lo[h], Q.hi[h], Q.inv_w[h]);
         sink.add(base + Q.hoff[h] + s, w);
     }
 }
@@ -187,17 +188,63 @@ struct Caps {
     static constexpr int JC = 64 * JK, MC = 64 * MK, EC = 64 * EK;
 };
 
+// One wavefront's LDS.  jr holds, per jet, its event's range of selected
+// muons (first | count << 16) until the cone test reads it; the same word
+// then holds the jet's pt (or NaN) for the per-event walk.
 template <int EVPL, bool EXT>
 struct WaveLds {
     using C = Caps<EVPL, EXT>;
-    int32_t joff[C::TW + 1], moff[C::TW + 1];
-    int32_t eoff[EXT ? C::TW + 1 : 1];
-    float ptc[C::JC];
-    float meta[C::MC], mphi[C::MC];
-    float eeta[EXT ? C::EC : 1], ephi[EXT ? C::EC : 1];
-    uint8_t jev[C::JC];
+    union {
+        uint32_t rng;
+        float pt;
+    } jr[C::JC];
+    uint32_t jre[EXT ? C::JC : 1];   // same for selected electrons
+    float seta[C::MC], sphi[C::MC];  // selected muons, compacted in tile order
+    float sea[EXT ? C::EC : 1], sep[EXT ? C::EC : 1];
+    uint16_t mpre[C::MC + 1];        // selected muons before muon m
+    uint16_t epre[EXT ? C::EC + 1 : 1];
     uint8_t bt[EXT ? C::JC : 1];
 };
+
+struct TileBounds {
+    int64_t J0, J1, M0, M1, L0, L1;
+};
+
+template <bool EXT>
+__device__ __forceinline__ TileBounds tile_bounds(const DsDev &D, bool has_el, int64_t e0, int ne) {
+    TileBounds b;
+    b.J0 = as_const(D.joff)[e0];
+    b.J1 = as_const(D.joff)[e0 + ne];
+    b.M0 = as_const(D.moff)[e0];
+    b.M1 = as_const(D.moff)[e0 + ne];
+    b.L0 = (EXT && has_el) ? as_const(D.eoff)[e0] : 0;
+    b.L1 = (EXT && has_el) ? as_const(D.eoff)[e0 + ne] : 0;
+    return b;
+}
+
+// Compacts the selected objects of a tile (sel per slot k of this lane) into
+// (eta, phi) arrays in tile order; pre[m] = number of selected objects before
+// object m, pre[n] = total.
+template <int K>
+__device__ __forceinline__ void compact(const bool (&sel)[K], const float (&eta)[K], const float (&phi)[K], int n,
+                                        int lane, float *oeta, float *ophi, uint16_t *pre) {
+    int run = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int m = lane + 64 * k;
+        const uint64_t bal = __ballot(sel[k]);
+        const int before = run + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+                                     static_cast<uint32_t>(bal >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bal), 0u)));
+        if (m < n) pre[m] = static_cast<uint16_t>(before);
+        if (sel[k]) {
+            oeta[before] = eta[k];
+            ophi[before] = phi[k];
+        }
+        run += __popcll(bal);
+    }
+    if (lane == 0) pre[n] = static_cast<uint16_t>(run);
+}
 
 template <typename T, bool EXT, int WAVES, int EVPL, bool LDSH>
 __global__ __launch_bounds__(64 * WAVES) void pipeline_kernel(PipeArgs P) {
@@ -242,13 +289,23 @@ __global__ __launch_bounds__(64 * WAVES) void pipeline_kernel(PipeArgs P) {
         const bool has_el = EXT && D.eoff != nullptr;
         const bool has_bt = EXT && D.jbt != nullptr;
 
-        for (int64_t t = CH.t0 + wave; t < CH.t1; t += WAVES) {
+        // tile bounds are fetched one tile ahead (scalar loads that overlap
+        // the current tile's vector loads)
+        int64_t t = CH.t0 + wave;
+        TileBounds nb{};
+        if (t < CH.t1) {
+            const int64_t e0 = t * TW;
+            nb = tile_bounds<EXT>(D, has_el, e0, static_cast<int>(min<int64_t>(TW, D.n_events - e0)));
+        }
+        for (; t < CH.t1; t += WAVES) {
             const int64_t e0 = t * TW;
             const int ne = static_cast<int>(min<int64_t>(TW, D.n_events - e0));
-            const int64_t J0 = as_const(D.joff)[e0], J1 = as_const(D.joff)[e0 + ne];
-            const int64_t M0 = as_const(D.moff)[e0], M1 = as_const(D.moff)[e0 + ne];
-            const int64_t L0 = has_el ? as_const(D.eoff)[e0] : 0, L1 = has_el ? as_const(D.eoff)[e0 + ne] : 0;
-            if (J1 - J0 > C::JC || M1 - M0 > C::MC || L1 - L0 > C::EC) {
+            const TileBounds B = nb;
+            if (t + WAVES < CH.t1) {
+                const int64_t e1 = (t + WAVES) * TW;
+                nb = tile_bounds<EXT>(D, has_el, e1, static_cast<int>(min<int64_t>(TW, D.n_events - e1)));
+            }
+            if (B.J1 - B.J0 > C::JC || B.M1 - B.M0 > C::MC || B.L1 - B.L0 > C::EC) {
 #pragma unroll
                 for (int r = 0; r < EVPL; ++r) {
                     const int ev = lane + 64 * r;
@@ -256,21 +313,28 @@ __global__ __launch_bounds__(64 * WAVES) void pipeline_kernel(PipeArgs P) {
                 }
                 continue;
             }
-            const int nj = static_cast<int>(J1 - J0), nm = static_cast<int>(M1 - M0);
-            const int nl = static_cast<int>(L1 - L0);
+            const int nj = static_cast<int>(B.J1 - B.J0), nm = static_cast<int>(B.M1 - B.M0);
+            const int nl = static_cast<int>(B.L1 - B.L0);
 
-            // ---- 1. all of the tile's loads in flight at once
-            int32_t jo[EVPL], mo[EVPL], lo_[EVPL];
+            // ---- 1. all of the tile's loads in flight at once: both offsets of
+            // each event lane's event (tile-relative), its weight, and up to JK
+            // jets, MK muons and EK electrons per lane
+            int32_t jb[EVPL], je[EVPL], mb[EVPL], me[EVPL], lb[EVPL], le[EVPL];
             float wv[EVPL];
 #pragma unroll
             for (int r = 0; r < EVPL; ++r) {
                 const int ev = lane + 64 * r;
-                jo[r] = mo[r] = lo_[r] = 0;
+                jb[r] = je[r] = mb[r] = me[r] = lb[r] = le[r] = 0;
                 wv[r] = 1.0f;
                 if (ev < ne) {
-                    jo[r] = static_cast<int32_t>(D.joff[e0 + ev] - J0);
-                    mo[r] = static_cast<int32_t>(D.moff[e0 + ev] - M0);
-                    if (has_el) lo_[r] = static_cast<int32_t>(D.eoff[e0 + ev] - L0);
+                    jb[r] = static_cast<int32_t>(D.joff[e0 + ev] - B.J0);
+                    je[r] = static_cast<int32_t>(D.joff[e0 + ev + 1] - B.J0);
+                    mb[r] = static_cast<int32_t>(D.moff[e0 + ev] - B.M0);
+                    me[r] = static_cast<int32_t>(D.moff[e0 + ev + 1] - B.M0);
+                    if (has_el) {
+                        lb[r] = static_cast<int32_t>(D.eoff[e0 + ev] - B.L0);
+                        le[r] = static_cast<int32_t>(D.eoff[e0 + ev + 1] - B.L0);
+                    }
                     if (D.w) wv[r] = D.w[e0 + ev];
                 }
             }
@@ -279,10 +343,10 @@ __global__ __launch_bounds__(64 * WAVES) void pipeline_kernel(PipeArgs P) {
             for (int k = 0; k < JK; ++k) {
                 const int j = lane + 64 * k;
                 if (j < nj) {
-                    jpt[k] = ldf(static_cast<const T *>(D.jpt), J0 + j);
-                    jeta[k] = ldf(static_cast<const T *>(D.jeta), J0 + j);
-                    jphi[k] = ldf(static_cast<const T *>(D.jphi), J0 + j);
-                    if (EXT && has_bt) jbt[EXT ? k : 0] = ldf(static_cast<const T *>(D.jbt), J0 + j);
+                    jpt[k] = ldf(static_cast<const T *>(D.jpt), B.J0 + j);
+                    jeta[k] = ldf(static_cast<const T *>(D.jeta), B.J0 + j);
+                    jphi[k] = ldf(static_cast<const T *>(D.jphi), B.J0 + j);
+                    if (EXT && has_bt) jbt[EXT ? k : 0] = ldf(static_cast<const T *>(D.jbt), B.J0 + j);
                 }
             }
             float mpt[MK] = {}, meta[MK] = {}, mphi[MK] = {}, miso[MK] = {};
@@ -290,10 +354,10 @@ __global__ __launch_bounds__(64 * WAVES) void pipeline_kernel(PipeArgs P) {
             for (int k = 0; k < MK; ++k) {
                 const int m = lane + 64 * k;
                 if (m < nm) {
-                    mpt[k] = ldf(static_cast<const T *>(D.mpt), M0 + m);
-                    meta[k] = ldf(static_cast<const T *>(D.meta), M0 + m);
-                    mphi[k] = ldf(static_cast<const T *>(D.mphi), M0 + m);
-                    if (has_iso) miso[k] = ldf(static_cast<const T *>(D.miso), M0 + m);
+                    mpt[k] = ldf(static_cast<const T *>(D.mpt), B.M0 + m);
+                    meta[k] = ldf(static_cast<const T *>(D.meta), B.M0 + m);
+                    mphi[k] = ldf(static_cast<const T *>(D.mphi), B.M0 + m);
+                    if (has_iso) miso[k] = ldf(static_cast<const T *>(D.miso), B.M0 + m);
                 }
             }
             float lpt[EK] = {}, leta[EK] = {}, lphi[EK] = {};
@@ -302,9 +366,9 @@ __global__ __launch_bounds__(64 * WAVES) void pipeline_kernel(PipeArgs P) {
                 for (int k = 0; k < EK; ++k) {
                     const int m = lane + 64 * k;
                     if (m < nl) {
-                        lpt[k] = ldf(static_cast<const T *>(D.ept), L0 + m);
-                        leta[k] = ldf(static_cast<const T *>(D.eeta), L0 + m);
-                        lphi[k] = ldf(static_cast<const T *>(D.ephi), L0 + m);
+                        lpt[k] = ldf(static_cast<const T *>(D.ept), B.L0 + m);
+                        leta[k] = ldf(static_cast<const T *>(D.eeta), B.L0 + m);
+                        lphi[k] = ldf(static_cast<const T *>(D.ephi), B.L0 + m);
                     }
                 }
             }
@@ -312,78 +376,78 @@ __global__ __launch_bounds__(64 * WAVES) void pipeline_kernel(PipeArgs P) {
             // tile's loads before this point and waits once, instead of sinking
             // each load to its first use (one HBM round trip per tile).
 #pragma unroll
+            for (int r = 0; r < EVPL; ++r)
+                asm volatile("" ::"v"(jb[r]), "v"(je[r]), "v"(mb[r]), "v"(me[r]), "v"(wv[r]));
+#pragma unroll
             for (int k = 0; k < JK; ++k) asm volatile("" ::"v"(jpt[k]), "v"(jeta[k]), "v"(jphi[k]));
 #pragma unroll
             for (int k = 0; k < MK; ++k) asm volatile("" ::"v"(mpt[k]), "v"(meta[k]), "v"(mphi[k]), "v"(miso[k]));
             if (EXT) {
+#pragma unroll
+                for (int r = 0; r < EVPL; ++r) asm volatile("" ::"v"(lb[r]), "v"(le[r]));
 #pragma unroll
                 for (int k = 0; k < JK; ++k) asm volatile("" ::"v"(jbt[EXT ? k : 0]));
 #pragma unroll
                 for (int k = 0; k < EK; ++k) asm volatile("" ::"v"(lpt[k]), "v"(leta[k]), "v"(lphi[k]));
             }
 
-            // ---- 2. offsets and the jet -> event map
-#pragma unroll
-            for (int r = 0; r < EVPL; ++r) {
-                const int ev = lane + 64 * r;
-                if (ev < ne) {
-                    L.joff[ev] = jo[r];
-                    L.moff[ev] = mo[r];
-                    if (EXT) L.eoff[ev] = lo_[r];
-                }
-            }
-            if (lane == 0) {
-                L.joff[ne] = nj;
-                L.moff[ne] = nm;
-                if (EXT) L.eoff[ne] = nl;
-            }
-            wave_sync();
-#pragma unroll
-            for (int r = 0; r < EVPL; ++r) {
-                const int ev = lane + 64 * r;
-                if (ev < ne)
-                    for (int k = L.joff[ev]; k < L.joff[ev + 1]; ++k) L.jev[k] = static_cast<uint8_t>(ev);
-            }
-
             for (int q = 0; q < P.n_q; ++q) {
                 const QDev Q = as_const(P.qs)[q];
-                // ---- 3. lepton selection, staged in LDS
+                // ---- 2. lepton selection; selected leptons compacted into LDS
+                {
+                    bool sel[MK];
 #pragma unroll
-                for (int k = 0; k < MK; ++k) {
-                    const int m = lane + 64 * k;
-                    if (m < nm) {
-                        const bool sel = mpt[k] > Q.mu_pt && fabsf(meta[k]) < Q.mu_abseta &&
-                                         (!has_iso || miso[k] < Q.mu_iso);
-                        L.meta[m] = sel ? meta[k] : __builtin_nanf("");
-                        L.mphi[m] = mphi[k];
-                    }
+                    for (int k = 0; k < MK; ++k)
+                        sel[k] = (lane + 64 * k < nm) && mpt[k] > Q.mu_pt && fabsf(meta[k]) < Q.mu_abseta &&
+                                 (!has_iso || miso[k] < Q.mu_iso);
+                    compact<MK>(sel, meta, mphi, nm, lane, L.seta, L.sphi, L.mpre);
                 }
                 if (EXT) {
+                    bool sel[EK];
 #pragma unroll
-                    for (int k = 0; k < EK; ++k) {
-                        const int m = lane + 64 * k;
-                        if (m < nl) {
-                            const bool sel = lpt[k] > Q.el_pt && fabsf(leta[k]) < Q.el_abseta;
-                            L.eeta[m] = sel ? leta[k] : __builtin_nanf("");
-                            L.ephi[m] = lphi[k];
+                    for (int k = 0; k < EK; ++k)
+                        sel[k] = (lane + 64 * k < nl) && lpt[k] > Q.el_pt && fabsf(leta[k]) < Q.el_abseta;
+                    compact<EK>(sel, leta, lphi, nl, lane, L.sea, L.sep, L.epre);
+                }
+                wave_sync();
+                // ---- 3. each event lane writes its selected-lepton range over its jets
+                int nmu[EVPL];
+#pragma unroll
+                for (int r = 0; r < EVPL; ++r) {
+                    nmu[r] = 0;
+                    const int ev = lane + 64 * r;
+                    if (ev < ne) {
+                        const int s0 = L.mpre[mb[r]];
+                        nmu[r] = L.mpre[me[r]] - s0;
+                        const uint32_t pk = static_cast<uint32_t>(s0) | (static_cast<uint32_t>(nmu[r]) << 16);
+                        uint32_t pke = 0;
+                        if (EXT) {
+                            const int u0 = L.epre[lb[r]];
+                            pke = static_cast<uint32_t>(u0) | (static_cast<uint32_t>(L.epre[le[r]] - u0) << 16);
+                        }
+                        for (int k = jb[r]; k < je[r]; ++k) {
+                            L.jr[k].rng = pk;
+                            if (EXT) L.jre[k] = pke;
                         }
                     }
                 }
                 wave_sync();
-                // ---- 4. cone test per jet
+                // ---- 4. cone test per jet against its event's selected leptons
 #pragma unroll
                 for (int k = 0; k < JK; ++k) {
                     const int j = lane + 64 * k;
                     if (j < nj) {
-                        const int ev = L.jev[j];
+                        const uint32_t pk = L.jr[j].rng;
+                        const int c0 = static_cast<int>(pk & 0xffffu), c1 = c0 + static_cast<int>(pk >> 16);
                         bool hit = false;
-                        for (int m = L.moff[ev]; m < L.moff[ev + 1]; ++m)
-                            hit |= delta_r2(jeta[k], jphi[k], L.meta[m], L.mphi[m]) <= Q.thr2;
-                        if (EXT)
-                            for (int m = L.eoff[ev]; m < L.eoff[ev + 1]; ++m)
-                                hit |= delta_r2(jeta[k], jphi[k], L.eeta[m], L.ephi[m]) <= Q.thr2;
+                        for (int i = c0; i < c1; ++i) hit |= delta_r2(jeta[k], jphi[k], L.seta[i], L.sphi[i]) <= Q.thr2;
+                        if (EXT) {
+                            const uint32_t pe = L.jre[j];
+                            const int u0 = static_cast<int>(pe & 0xffffu), u1 = u0 + static_cast<int>(pe >> 16);
+                            for (int i = u0; i < u1; ++i) hit |= delta_r2(jeta[k], jphi[k], L.sea[i], L.sep[i]) <= Q.thr2;
+                        }
                         const bool ok = !hit && fabsf(jeta[k]) < Q.jet_abseta;
-                        L.ptc[j] = ok ? jpt[k] : __builtin_nanf("");
+                        L.jr[j].pt = ok ? jpt[k] : __builtin_nanf("");
                         if (EXT) L.bt[j] = (has_bt && jbt[EXT ? k : 0] > Q.btag) ? 1 : 0;
                     }
                 }
@@ -393,25 +457,22 @@ __global__ __launch_bounds__(64 * WAVES) void pipeline_kernel(PipeArgs P) {
                 for (int r = 0; r < EVPL; ++r) {
                     const int ev = lane + 64 * r;
                     if (ev < ne) {
-                        int nmu = 0;
-                        for (int m = L.moff[ev]; m < L.moff[ev + 1]; ++m) nmu += (L.meta[m] == L.meta[m]) ? 1 : 0;
-                        const int j0 = L.joff[ev], j1 = L.joff[ev + 1];
                         const double w = static_cast<double>(wv[r]);
                         for (int v = 0; v < Q.n_scale; ++v) {
                             const float s = as_const(P.scales)[Q.scale0 + v];
-                            int njs = 0, nb = 0;
+                            int njs = 0, nbt = 0;
                             float ht = 0.0f, lead = -INFINITY;
-                            for (int k = j0; k < j1; ++k) {
-                                const float x = L.ptc[k] * s;
+                            for (int k = jb[r]; k < je[r]; ++k) {
+                                const float x = L.jr[k].pt * s;
                                 if (x > Q.jet_pt) {
                                     if (njs == 0 || x > lead) lead = x;
                                     ++njs;
                                     ht = ht + x;
-                                    if (EXT) nb += L.bt[k];
+                                    if (EXT) nbt += L.bt[k];
                                 }
                             }
                             const bool pass =
-                                nmu >= Q.min_mu && njs >= Q.min_jet && (!has_bt || nb >= Q.min_b);
+                                nmu[r] >= Q.min_mu && njs >= Q.min_jet && (!has_bt || nbt >= Q.min_b);
                             if (pass) fill3(sink, Q, edges, v, ht, lead, njs, w);
                         }
                     }
@@ -601,6 +662,7 @@ extern "C" int hepk_plan_create(const hepk_dataset *ds, int32_t n_ds, const hepk
             edge_table.insert(edge_table.end(), v.begin(), v.end());
             const float span = v.back() - v.front();
             o.lo[h] = v.front();
+            o.hi[h] = v.back();
             o.inv_w[h] = (span > 0.0f && std::isfinite(span)) ? static_cast<float>(Q.nbins[h]) / span : 0.0f;
             acc += Q.nbins[h] + 2;
         }
