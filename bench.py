@@ -37,6 +37,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_1906_06242_amd/csrc/pipeline.hip", "paper_1906_06242_amd/csrc/common.hpp"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def kernel_traffic(events: int):
+    """HBM bytes per fused launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    passes (scaled by a plain copy of known size), or None when they were taken
+    for another workload or an older version of the kernel."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        tr = json.load(f)
+    if tr.get("events") != events or tr.get("source_sha256") != kernel_sources_sha256():
+        return None
+    return tr.get("bytes_per_launch")
+
+
 def cpu_baseline(ds, q, reps: int):
     """The oracle (one thread, as it stands) on the same events; median pass time."""
     from oracle import ref
@@ -79,6 +101,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-reps", type=int, default=4)
     ap.add_argument("--tune", type=str, default="", help="JSON launch configuration")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device-to-device copy (scale for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -111,12 +135,7 @@ def main():
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     log(f"fused: {ms_step:.3f} ms/step wall, {kern_ms:.3f} ms/launch, {achieved:.0f} GB/s")
 
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
-            tr = json.load(f)
-        if tr.get("events") == args.events and tr.get("tune") == plan.tune:
-            traffic = tr.get("bytes_per_launch")
+    traffic = kernel_traffic(args.events)
 
     out = {
         "metric": "events/s and % HBM roofline, fused vs plain pipeline; query p50/p99 latency",
@@ -148,8 +167,14 @@ def main():
         out["fused_over_plain"] = p_step / ms_step
         log(f"plain: {p_step:.3f} ms/step")
 
-    # parity of the timed run: the accumulated histograms equal (steps+warmup) x one oracle pass
     plan.close()
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(ds, q, args.cpu_reps)
         out["cpu_baseline"]["host_nproc"] = os.cpu_count()

@@ -54,8 +54,8 @@ __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + 
 constexpr float kPi = 0x1.921fb6p+1f;
 constexpr float kTwoPi = 0x1.921fb6p+2f;
 
-template <typename T>
-__device__ __forceinline__ float ldf(const T *p, int64_t i) {
+template <typename T, typename I>
+__device__ __forceinline__ float ldf(const T *p, I i) {
     return static_cast<float>(p[i]);  // _Float16 -> float is v_cvt_f32_f16: exact
 }
 
@@ -90,15 +90,19 @@ __device__ __forceinline__ bool cmp_i(int32_t v, int32_t op, int32_t t) {
 // dR^2 = deta^2 + dphi^2 with dphi brought into [-pi, pi] by one step of 2*pi.
 // Written as separate rounded float32 operations; -ffp-contract=off keeps
 // the compiler from fusing the square and the sum.
+//
+// Only |dphi| enters the square, and the wrapped magnitude is |dphi| - 2*pi
+// whenever |dphi| > pi: for dphi > pi that is dphi - 2*pi itself, for
+// dphi < -pi it is -(dphi + 2*pi), and negation is exact (round-to-nearest
+// is symmetric in sign).  So the square equals that of the two-sided wrap
+// bit for bit, in three instructions (sub with |.| modifier, cmp, cndmask).
 __device__ __forceinline__ float delta_r2(float eta_a, float phi_a, float eta_b, float phi_b) {
-    float deta = eta_a - eta_b;
-    float dphi = phi_a - phi_b;
-    if (dphi > kPi)
-        dphi = dphi - kTwoPi;
-    else if (dphi < -kPi)
-        dphi = dphi + kTwoPi;
-    float a = deta * deta;
-    float b = dphi * dphi;
+    const float deta = eta_a - eta_b;
+    const float adphi = fabsf(phi_a - phi_b);
+    const float wrapped = adphi - kTwoPi;
+    const float dphi = (adphi > kPi) ? wrapped : adphi;
+    const float a = deta * deta;
+    const float b = dphi * dphi;
     return a + b;
 }
 

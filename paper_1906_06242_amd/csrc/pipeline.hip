@@ -246,8 +246,10 @@ __device__ __forceinline__ void compact(const bool (&sel)[K], const float (&eta)
     if (lane == 0) pre[n] = static_cast<uint16_t>(run);
 }
 
+// Six wavefronts per SIMD (at most 80 VGPRs): measured the best trade
+// between latency hiding and the registers that hold a tile in flight.
 template <typename T, bool EXT, int WAVES, int EVPL, bool LDSH>
-__global__ __launch_bounds__(64 * WAVES) void pipeline_kernel(PipeArgs P) {
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6))) void pipeline_kernel(PipeArgs P) {
     using C = Caps<EVPL, EXT>;
     constexpr int TW = C::TW, JK = C::JK, MK = C::MK, EK = C::EK;
     __shared__ WaveLds<EVPL, EXT> wl[WAVES];
@@ -319,6 +321,15 @@ __global__ __launch_bounds__(64 * WAVES) void pipeline_kernel(PipeArgs P) {
             // ---- 1. all of the tile's loads in flight at once: both offsets of
             // each event lane's event (tile-relative), its weight, and up to JK
             // jets, MK muons and EK electrons per lane
+            // tile-base pointers (scalar) and 32-bit lane offsets
+            const int64_t *jo = D.joff + e0, *mo = D.moff + e0, *lo = has_el ? D.eoff + e0 : nullptr;
+            const float *wp = D.w ? D.w + e0 : nullptr;
+            const T *cjpt = static_cast<const T *>(D.jpt) + B.J0, *cjeta = static_cast<const T *>(D.jeta) + B.J0;
+            const T *cjphi = static_cast<const T *>(D.jphi) + B.J0;
+            const T *cjbt = has_bt ? static_cast<const T *>(D.jbt) + B.J0 : nullptr;
+            const T *cmpt = static_cast<const T *>(D.mpt) + B.M0, *cmeta = static_cast<const T *>(D.meta) + B.M0;
+            const T *cmphi = static_cast<const T *>(D.mphi) + B.M0;
+            const T *cmiso = has_iso ? static_cast<const T *>(D.miso) + B.M0 : nullptr;
             int32_t jb[EVPL], je[EVPL], mb[EVPL], me[EVPL], lb[EVPL], le[EVPL];
             float wv[EVPL];
 #pragma unroll
@@ -327,15 +338,15 @@ __global__ __launch_bounds__(64 * WAVES) void pipeline_kernel(PipeArgs P) {
                 jb[r] = je[r] = mb[r] = me[r] = lb[r] = le[r] = 0;
                 wv[r] = 1.0f;
                 if (ev < ne) {
-                    jb[r] = static_cast<int32_t>(D.joff[e0 + ev] - B.J0);
-                    je[r] = static_cast<int32_t>(D.joff[e0 + ev + 1] - B.J0);
-                    mb[r] = static_cast<int32_t>(D.moff[e0 + ev] - B.M0);
-                    me[r] = static_cast<int32_t>(D.moff[e0 + ev + 1] - B.M0);
-                    if (has_el) {
-                        lb[r] = static_cast<int32_t>(D.eoff[e0 + ev] - B.L0);
-                        le[r] = static_cast<int32_t>(D.eoff[e0 + ev + 1] - B.L0);
+                    jb[r] = static_cast<int32_t>(jo[ev] - B.J0);
+                    je[r] = static_cast<int32_t>(jo[ev + 1] - B.J0);
+                    mb[r] = static_cast<int32_t>(mo[ev] - B.M0);
+                    me[r] = static_cast<int32_t>(mo[ev + 1] - B.M0);
+                    if (EXT && has_el) {
+                        lb[r] = static_cast<int32_t>(lo[ev] - B.L0);
+                        le[r] = static_cast<int32_t>(lo[ev + 1] - B.L0);
                     }
-                    if (D.w) wv[r] = D.w[e0 + ev];
+                    if (wp) wv[r] = wp[ev];
                 }
             }
             float jpt[JK] = {}, jeta[JK] = {}, jphi[JK] = {}, jbt[EXT ? JK : 1] = {};
@@ -343,10 +354,10 @@ __global__ __launch_bounds__(64 * WAVES) void pipeline_kernel(PipeArgs P) {
             for (int k = 0; k < JK; ++k) {
                 const int j = lane + 64 * k;
                 if (j < nj) {
-                    jpt[k] = ldf(static_cast<const T *>(D.jpt), B.J0 + j);
-                    jeta[k] = ldf(static_cast<const T *>(D.jeta), B.J0 + j);
-                    jphi[k] = ldf(static_cast<const T *>(D.jphi), B.J0 + j);
-                    if (EXT && has_bt) jbt[EXT ? k : 0] = ldf(static_cast<const T *>(D.jbt), B.J0 + j);
+                    jpt[k] = ldf(cjpt, j);
+                    jeta[k] = ldf(cjeta, j);
+                    jphi[k] = ldf(cjphi, j);
+                    if (EXT && has_bt) jbt[EXT ? k : 0] = ldf(cjbt, j);
                 }
             }
             float mpt[MK] = {}, meta[MK] = {}, mphi[MK] = {}, miso[MK] = {};
@@ -354,21 +365,23 @@ __global__ __launch_bounds__(64 * WAVES) void pipeline_kernel(PipeArgs P) {
             for (int k = 0; k < MK; ++k) {
                 const int m = lane + 64 * k;
                 if (m < nm) {
-                    mpt[k] = ldf(static_cast<const T *>(D.mpt), B.M0 + m);
-                    meta[k] = ldf(static_cast<const T *>(D.meta), B.M0 + m);
-                    mphi[k] = ldf(static_cast<const T *>(D.mphi), B.M0 + m);
-                    if (has_iso) miso[k] = ldf(static_cast<const T *>(D.miso), B.M0 + m);
+                    mpt[k] = ldf(cmpt, m);
+                    meta[k] = ldf(cmeta, m);
+                    mphi[k] = ldf(cmphi, m);
+                    if (has_iso) miso[k] = ldf(cmiso, m);
                 }
             }
             float lpt[EK] = {}, leta[EK] = {}, lphi[EK] = {};
-            if (EXT) {
+            if (EXT && has_el) {
+                const T *cept = static_cast<const T *>(D.ept) + B.L0, *ceeta = static_cast<const T *>(D.eeta) + B.L0;
+                const T *cephi = static_cast<const T *>(D.ephi) + B.L0;
 #pragma unroll
                 for (int k = 0; k < EK; ++k) {
                     const int m = lane + 64 * k;
                     if (m < nl) {
-                        lpt[k] = ldf(static_cast<const T *>(D.ept), B.L0 + m);
-                        leta[k] = ldf(static_cast<const T *>(D.eeta), B.L0 + m);
-                        lphi[k] = ldf(static_cast<const T *>(D.ephi), B.L0 + m);
+                        lpt[k] = ldf(cept, m);
+                        leta[k] = ldf(ceeta, m);
+                        lphi[k] = ldf(cephi, m);
                     }
                 }
             }
@@ -473,7 +486,14 @@ __global__ __launch_bounds__(64 * WAVES) void pipeline_kernel(PipeArgs P) {
                             }
                             const bool pass =
                                 nmu[r] >= Q.min_mu && njs >= Q.min_jet && (!has_bt || nbt >= Q.min_b);
-                            if (pass) fill3(sink, Q, edges, v, ht, lead, njs, w);
+                            if (pass) {
+                                // separate calls so each knows its address space (LDS or
+                                // global) and reads the edges without flat loads
+                                if (P.edges_in_lds)
+                                    fill3(sink, Q, e_s, v, ht, lead, njs, w);
+                                else
+                                    fill3(sink, Q, P.edges, v, ht, lead, njs, w);
+                            }
                         }
                     }
                 }
@@ -595,7 +615,7 @@ extern "C" int hepk_plan_create(const hepk_dataset *ds, int32_t n_ds, const hepk
         }
         n_scale_total += Q.n_scale;
     }
-    hepk_tune t{256, 1, 0, 0};
+    hepk_tune t{512, 1, 0, 0};
     if (tune) t = *tune;
     HEPK_REQUIRE(t.block == 256 || t.block == 512, "hepk_plan_create: block %d not 256 or 512", t.block);
     HEPK_REQUIRE(t.ev_per_thread == 1 || t.ev_per_thread == 2, "hepk_plan_create: ev_per_thread %d not 1 or 2",
