@@ -194,7 +194,8 @@ typedef struct hepk_query {
     int32_t min_mu, min_jet, min_b;
     int32_t n_scale;                 /* >= 1 */
     const float *scales;             /* (host) n_scale jet-energy-scale factors */
-    const float *edges[3];           /* H_T, lead, nJet bin edges (device, nbins+1) */
+    const float *edges[3];           /* (host) H_T, lead, nJet bin edges, nbins+1 each,
+                                        strictly increasing; copied into the plan */
     int32_t nbins[3];
 } hepk_query;
 
@@ -212,14 +213,40 @@ typedef struct hepk_tune {
 typedef struct hepk_plan_s *hepk_plan;
 
 /* Builds a plan for datasets ds[0..n_ds) and queries q[0..n_query): uploads
- * the dataset and query tables to device memory and fixes the launch
- * configuration (tune NULL: a default for the device).  Histogram layout in
- * the sumw/counts buffers given to hepk_pipeline: one block of nbins+2 slots
- * per (dataset, query, scale, observable), blocks ordered dataset-major, then
- * query, then scale, then observable (H_T, lead, nJet). */
+ * the dataset and query tables (with a copy of every query's bin edges) to
+ * device memory and fixes the launch configuration (tune NULL: a default for
+ * the device).  Histogram layout in the sumw/counts buffers given to
+ * hepk_pipeline: one block of nbins+2 slots per (dataset, query, scale,
+ * observable), blocks ordered dataset-major, then query, then scale, then
+ * observable (H_T, lead, nJet); hepk_plan_hist_offset gives each block. */
 int hepk_plan_create(const hepk_dataset *ds /* host, n_ds */, int32_t n_ds,
                      const hepk_query *q /* host, n_query */, int32_t n_query,
                      const hepk_tune *tune /* host, nullable */, hepk_plan *out /* host */);
+
+/* Options of hepk_plan_create_ex (zero-initialised: hepk_plan_create). */
+typedef struct hepk_plan_opts {
+    hepk_tune tune;          /* block == 0: the default launch configuration */
+    int32_t shared_hist;     /* 1: all datasets accumulate into one set of histograms
+                                (the layout of dataset 0), e.g. the chunks of one sample */
+    int32_t reserve_bins;    /* > 0: every query slot reserves reserve_bins bins per
+                                histogram so hepk_plan_set_query can later install any query
+                                with nbins <= reserve_bins (and n_scale <= the slot's) */
+} hepk_plan_opts;
+
+int hepk_plan_create_ex(const hepk_dataset *ds /* host, n_ds */, int32_t n_ds,
+                        const hepk_query *q /* host, n_query */, int32_t n_query,
+                        const hepk_plan_opts *opts /* host, nullable */, hepk_plan *out /* host */);
+
+/* Replaces the query in slot `slot` (q NULL: the slot goes idle and is
+ * skipped).  The new thresholds and edges are staged in the plan's pinned
+ * host memory and copied on `stream`, so launches enqueued on that stream
+ * afterwards see the new query and earlier ones the old.  The slot's
+ * histogram blocks stay where they are; with reserve_bins > 0 the blocks have
+ * reserve_bins + 2 slots of which the first nbins + 2 are used.  A slot must
+ * not be set again before the previous update of that slot has executed (the
+ * staging area is per slot). */
+int hepk_plan_set_query(hepk_plan p, int32_t slot, const hepk_query *q /* host, nullable */,
+                        hipStream_t stream);
 
 /* Total histogram slots of the plan (length of sumw and counts). */
 int hepk_plan_hist_slots(hepk_plan p, int64_t *n_slots /* host */);
@@ -234,6 +261,27 @@ int hepk_plan_get_tune(hepk_plan p, hepk_tune *tune /* host */);
 /* Runs the fused pass, accumulating into sumw/counts (hepk_plan_hist_slots
  * entries each). */
 int hepk_pipeline(hepk_plan p, double *sumw, uint64_t *counts, hipStream_t stream);
+
+/* Same, over datasets [d0, d0 + nd) only. */
+int hepk_pipeline_range(hepk_plan p, int32_t d0, int32_t nd, double *sumw, uint64_t *counts,
+                        hipStream_t stream);
+
+/* Same as hepk_pipeline, launched as a HIP graph owned by the plan: the
+ * graph (one kernel node) is built on the first call and its arguments are
+ * updated in place when sumw/counts change, so repeated passes cost one
+ * graph launch each. */
+int hepk_pipeline_graph(hepk_plan p, double *sumw, uint64_t *counts, hipStream_t stream);
+
+/* Launch-configuration search (Sec. IV: kernel scheduling was the bottleneck
+ * of the paper's GPU runs).  Times the fused pass over ds/q for every
+ * candidate -- block 256/512, 1 or 2 events per thread, LDS or global-atomic
+ * histograms -- with `reps` timed runs each (after one warm-up) and returns
+ * the fastest in *best and its median time in *best_ms (host).  sumw/counts
+ * are scratch histogram buffers of hepk_plan_hist_slots entries for this
+ * ds/q (their contents are garbage afterwards).  Synchronises `stream`. */
+int hepk_autotune(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_t n_query,
+                  double *sumw, uint64_t *counts, int32_t reps, hepk_tune *best /* host */,
+                  float *best_ms /* host, nullable */, hipStream_t stream);
 
 int hepk_plan_destroy(hepk_plan p);
 

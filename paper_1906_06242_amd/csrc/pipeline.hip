@@ -61,13 +61,16 @@ struct QDev {
     float mu_pt, mu_abseta, mu_iso, el_pt, el_abseta, jet_pt, jet_abseta, thr2, btag;
     int32_t min_mu, min_jet, min_b;
     int32_t n_scale, scale0;
+    int32_t active;      // 0: idle query slot, skipped
     int32_t nbins[3];
-    int32_t hoff[3];    // slot offset of each observable within one scale's block
-    int32_t slot0;      // first slot of this query within a dataset block
-    int32_t per_scale;  // slots per scale
-    int32_t ebase[3];   // first edge of each observable in the plan's edge table
-    float lo[3], hi[3];     // first and last edge of each observable
-    float inv_w[3];         // nbins / (hi - lo): start value of the bin search
+    int32_t ebase[3];    // first edge of each observable in the plan's edge table
+    float lo[3], hi[3];  // first and last edge of each observable
+    float inv_w[3];      // nbins / (hi - lo): start value of the bin search
+    // Histogram of (scale v, observable h) starts at slot0 + v * per_scale +
+    // hoff[h]: in the workgroup's LDS copy (compact over the active queries)
+    // and in the dataset's block in HBM (fixed per query slot).
+    int32_t lslot0, lper_scale, lhoff[3];
+    int32_t gslot0, gper_scale, ghoff[3];
 };
 
 struct Chunk {
@@ -81,7 +84,8 @@ struct PipeArgs {
     const float *scales;
     const Chunk *chunks;
     const float *edges;  // all queries' bin edges, concatenated
-    int32_t n_chunks, n_q, ds_slots, n_edges, edges_in_lds;
+    int32_t chunk_begin, chunk_end;  // chunks [chunk_begin, chunk_end) of `chunks`
+    int32_t n_q, ds_slots, n_edges, edges_in_lds;  // ds_slots: LDS histogram slots
     double *sumw;
     uint64_t *counts;
 };
@@ -107,14 +111,14 @@ struct HistSink {
 template <bool LDSH>
 __device__ __forceinline__ void fill3(const HistSink<LDSH> &sink, const QDev &Q, const float *edges, int v,
                                       float ht, float lead, int nj, double w) {
-    const int base = Q.slot0 + v * Q.per_scale;
+    const int base = LDSH ? Q.lslot0 + v * Q.lper_scale : Q.gslot0 + v * Q.gper_scale;
     const float xs[3] = {ht, lead, static_cast<float>(nj)};
 #pragma unroll
     for (int h = 0; h < 3; ++h) {
         const float x = xs[h];
         if (x != x) continue;
         const int s = hist_slot_lohi(x, edges + Q.ebase[h], Q.nbins[h], Q.lo[h], Q.hi[h], Q.inv_w[h]);
-        sink.add(base + Q.hoff[h] + s, w);
+        sink.add(base + (LDSH ? Q.lhoff[h] : Q.ghoff[h]) + s, w);
     }
 }
 
@@ -146,6 +150,7 @@ __device__ void event_direct(const PipeArgs &P, const DsDev &D, int64_t e, const
     const T *ephi = static_cast<const T *>(D.ephi);
     for (int q = 0; q < P.n_q; ++q) {
         const QDev Q = as_const(P.qs)[q];
+        if (!Q.active) continue;
         auto mu_sel = [&](int64_t m) {
             return ldf(mpt, m) > Q.mu_pt && fabsf(ldf(meta, m)) < Q.mu_abseta &&
                    (!has_iso || ldf(miso, m) < Q.mu_iso);
@@ -276,7 +281,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
     }
     __syncthreads();
 
-    for (int ci = blockIdx.x; ci < P.n_chunks; ci += gridDim.x) {
+    for (int ci = P.chunk_begin + blockIdx.x; ci < P.chunk_end; ci += gridDim.x) {
         const Chunk CH = as_const(P.chunks)[ci];
         const DsDev D = as_const(P.ds)[CH.d];
         HistSink<LDSH> sink;
@@ -406,6 +411,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
 
             for (int q = 0; q < P.n_q; ++q) {
                 const QDev Q = as_const(P.qs)[q];
+                if (!Q.active) continue;
                 // ---- 2. lepton selection; selected leptons compacted into LDS
                 {
                     bool sel[MK];
@@ -453,7 +459,14 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
                         const uint32_t pk = L.jr[j].rng;
                         const int c0 = static_cast<int>(pk & 0xffffu), c1 = c0 + static_cast<int>(pk >> 16);
                         bool hit = false;
-                        for (int i = c0; i < c1; ++i) hit |= delta_r2(jeta[k], jphi[k], L.seta[i], L.sphi[i]) <= Q.thr2;
+                        int i = c0;
+                        // two leptons per step: both LDS reads in flight before the math
+                        for (; i + 2 <= c1; i += 2) {
+                            const float e0 = L.seta[i], p0 = L.sphi[i], e1 = L.seta[i + 1], p1 = L.sphi[i + 1];
+                            hit |= delta_r2(jeta[k], jphi[k], e0, p0) <= Q.thr2;
+                            hit |= delta_r2(jeta[k], jphi[k], e1, p1) <= Q.thr2;
+                        }
+                        if (i < c1) hit |= delta_r2(jeta[k], jphi[k], L.seta[i], L.sphi[i]) <= Q.thr2;
                         if (EXT) {
                             const uint32_t pe = L.jre[j];
                             const int u0 = static_cast<int>(pe & 0xffffu), u1 = u0 + static_cast<int>(pe >> 16);
@@ -473,17 +486,29 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
                         const double w = static_cast<double>(wv[r]);
                         for (int v = 0; v < Q.n_scale; ++v) {
                             const float s = as_const(P.scales)[Q.scale0 + v];
+                            // Walk the event's jets in order: left-to-right float32 H_T
+                            // over the selected ones, their count and maximum.  Written
+                            // branch-free, two jets per step (both LDS reads in flight);
+                            // adding only selected x keeps the sum order of the
+                            // definition.  The maximum is updated on a strict '>', which keeps the
+                            // first of equal values, as the definition does.
                             int njs = 0, nbt = 0;
                             float ht = 0.0f, lead = -INFINITY;
-                            for (int k = jb[r]; k < je[r]; ++k) {
-                                const float x = L.jr[k].pt * s;
-                                if (x > Q.jet_pt) {
-                                    if (njs == 0 || x > lead) lead = x;
-                                    ++njs;
-                                    ht = ht + x;
-                                    if (EXT) nbt += L.bt[k];
-                                }
+                            auto step = [&](float x, int k) {
+                                const bool sel = x > Q.jet_pt;
+                                const float hs = ht + x;
+                                ht = sel ? hs : ht;
+                                lead = (sel && x > lead) ? x : lead;
+                                njs += sel ? 1 : 0;
+                                if (EXT) nbt += sel ? L.bt[k] : 0;
+                            };
+                            int k = jb[r];
+                            for (; k + 2 <= je[r]; k += 2) {
+                                const float x0 = L.jr[k].pt * s, x1 = L.jr[k + 1].pt * s;
+                                step(x0, k);
+                                step(x1, k + 1);
                             }
+                            if (k < je[r]) step(L.jr[k].pt * s, k);
                             const bool pass =
                                 nmu[r] >= Q.min_mu && njs >= Q.min_jet && (!has_bt || nbt >= Q.min_b);
                             if (pass) {
@@ -503,17 +528,25 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
         // merge the LDS histograms when the next chunk is another dataset (or none)
         if (LDSH) {
             const int nci = ci + static_cast<int>(gridDim.x);
-            if (nci >= P.n_chunks || as_const(P.chunks)[nci].d != CH.d) {
+            if (nci >= P.chunk_end || as_const(P.chunks)[nci].d != CH.d) {
                 __syncthreads();
-                const int64_t h0 = D.hist0;
-                for (int i = tid; i < P.ds_slots; i += 64 * WAVES) {
-                    const uint32_t c = c_s[i];
-                    if (c) {
-                        atomic_add_u64(&P.counts[h0 + i], c);
-                        atomic_add_f64(&P.sumw[h0 + i], sw_s[i]);
-                        c_s[i] = 0u;
-                        sw_s[i] = 0.0;
-                    }
+                for (int q = 0; q < P.n_q; ++q) {
+                    const QDev Q = as_const(P.qs)[q];
+                    if (!Q.active) continue;
+                    for (int v = 0; v < Q.n_scale; ++v)
+                        for (int h = 0; h < 3; ++h) {
+                            const int ls = Q.lslot0 + v * Q.lper_scale + Q.lhoff[h];
+                            const int64_t gs = D.hist0 + Q.gslot0 + v * Q.gper_scale + Q.ghoff[h];
+                            for (int i = tid; i < Q.nbins[h] + 2; i += 64 * WAVES) {
+                                const uint32_t c = c_s[ls + i];
+                                if (c) {
+                                    atomic_add_u64(&P.counts[gs + i], c);
+                                    atomic_add_f64(&P.sumw[gs + i], sw_s[ls + i]);
+                                    c_s[ls + i] = 0u;
+                                    sw_s[ls + i] = 0.0;
+                                }
+                            }
+                        }
                 }
                 __syncthreads();
             }
@@ -555,29 +588,162 @@ struct hepk_plan_s {
     int32_t n_ds = 0, n_q = 0;
     int dtype = HEPK_F32;
     bool ext = false;
+    bool shared = false;
     hepk_tune tune{};
     int grid = 0;
-    size_t lds_bytes = 0;
-    hepk::KernelFn fn = nullptr;
-    hepk::PipeArgs args{};
+    hepk::KernelFn fn_lds = nullptr, fn_glob = nullptr;
+    hepk::PipeArgs args{};             // table pointers; chunk range and histograms set per launch
+    int32_t n_chunks_all = 0;          // balanced chunks of the full pass: [0, n_chunks_all)
+    std::vector<int32_t> full_begin;   // n_ds + 1: first chunk of each dataset in the full list
+    std::vector<int32_t> own_begin;    // n_ds + 1: each dataset's own balanced chunk list
+    int64_t ds_block = 0;              // histogram slots per dataset block
     int64_t n_slots = 0;
-    std::vector<int64_t> hoff;   // per (d, q, v, h)
-    std::vector<int32_t> hnb;
-    std::vector<int32_t> q_scale0, q_nscale;
-    int64_t entries_per_ds = 0;  // 3 * total scales over queries
+    std::vector<hepk::QDev> qd;        // host copy of the query table
+    std::vector<int32_t> cap_bins;     // (slot, h): reserved bins
+    std::vector<int32_t> cap_scales;   // slot: reserved scales
+    int32_t lds_slots = 0;             // LDS histogram slots of the active queries
+    int32_t n_edges = 0;
+    bool edges_lds = false;
     void *dev_mem = nullptr;
+    hepk::QDev *d_q = nullptr;
+    float *d_scales = nullptr, *d_edges = nullptr;
+    // pinned staging ring for hepk_plan_set_query
+    char *pinned = nullptr;
+    size_t stage_bytes = 0;
+    int ring_pos = 0;
+    std::vector<hipEvent_t> ring_ev;
+    std::vector<bool> ring_used;
+    // graph launch
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipGraphNode_t gnode = nullptr;
+    hepk::KernelFn gfn = nullptr;
+    hepk::PipeArgs gargs{};
+    size_t glds = 0;
+    int ggrid = 0;
 };
 
-static int plan_fail(hepk_plan p, int rc) {
-    if (p) {
-        if (p->dev_mem) (void)hipFree(p->dev_mem);
-        delete p;
+namespace hepk {
+
+constexpr int kStageRing = 32;
+
+// LDS layout of the active queries (compact) and whether it fits in LDS.
+static void relayout(hepk_plan p) {
+    int32_t acc = 0;
+    for (auto &o : p->qd) {
+        o.lslot0 = acc;
+        int32_t per = 0;
+        for (int h = 0; h < 3; ++h) {
+            o.lhoff[h] = per;
+            per += o.nbins[h] + 2;
+        }
+        o.lper_scale = per;
+        if (o.active) acc += per * o.n_scale;
     }
+    p->lds_slots = acc;
+}
+
+static bool use_lds_hist(hepk_plan p) {
+    return p->tune.hist_mode == 0 &&
+           static_cast<size_t>(p->lds_slots) * (sizeof(double) + sizeof(uint32_t)) <= static_cast<size_t>(kMaxLdsHistBytes);
+}
+
+// Fills the query-dependent fields of a table entry; the caller has checked q.
+static void set_qdev(QDev &o, const hepk_query &Q, const float *const edges[3]) {
+    o.mu_pt = Q.mu_pt;
+    o.mu_abseta = Q.mu_abseta;
+    o.mu_iso = Q.mu_iso;
+    o.el_pt = Q.el_pt;
+    o.el_abseta = Q.el_abseta;
+    o.jet_pt = Q.jet_pt;
+    o.jet_abseta = Q.jet_abseta;
+    o.thr2 = Q.dr * Q.dr;  // rounded once to float32
+    o.btag = Q.btag;
+    o.min_mu = Q.min_mu;
+    o.min_jet = Q.min_jet;
+    o.min_b = Q.min_b;
+    o.n_scale = Q.n_scale;
+    o.active = 1;
+    for (int h = 0; h < 3; ++h) {
+        const int nb = Q.nbins[h];
+        const float *e = edges[h];
+        o.nbins[h] = nb;
+        const float span = e[nb] - e[0];
+        o.lo[h] = e[0];
+        o.hi[h] = e[nb];
+        o.inv_w[h] = (span > 0.0f && std::isfinite(span)) ? static_cast<float>(nb) / span : 0.0f;
+    }
+}
+
+static int check_query(const hepk_query &Q, int i) {
+    HEPK_REQUIRE(Q.n_scale >= 1 && Q.scales, "query %d needs >= 1 scale", i);
+    for (int h = 0; h < 3; ++h) {
+        HEPK_REQUIRE(Q.nbins[h] >= 1 && Q.edges[h], "query %d histogram %d invalid", i, h);
+        for (int k = 0; k < Q.nbins[h]; ++k)
+            HEPK_REQUIRE(Q.edges[h][k] < Q.edges[h][k + 1], "query %d edges %d not strictly increasing at %d", i,
+                         h, k);
+    }
+    return HEPK_OK;
+}
+
+static int64_t hist_base(hepk_plan p, int d) { return p->shared ? 0 : d * p->ds_block; }
+
+struct Launch {
+    KernelFn fn;
+    int grid, block;
+    size_t lds;
+    PipeArgs a;
+};
+
+static Launch make_launch(hepk_plan p, int32_t c0, int32_t c1, double *sumw, uint64_t *counts) {
+    Launch L{};
+    const bool ldsh = use_lds_hist(p);
+    L.fn = ldsh ? p->fn_lds : p->fn_glob;
+    L.block = p->tune.block;
+    L.grid = std::max(1, std::min(p->grid, c1 - c0));
+    L.lds = (ldsh ? static_cast<size_t>(p->lds_slots) * (sizeof(double) + sizeof(uint32_t)) : 0) +
+            (p->edges_lds ? static_cast<size_t>(p->n_edges) * sizeof(float) : 0);
+    L.a = p->args;
+    L.a.chunk_begin = c0;
+    L.a.chunk_end = c1;
+    L.a.ds_slots = ldsh ? p->lds_slots : 0;
+    L.a.sumw = sumw;
+    L.a.counts = counts;
+    return L;
+}
+
+static int run_launch(const Launch &L, hipStream_t stream) {
+    void *kargs[] = {const_cast<PipeArgs *>(&L.a)};
+    HEPK_HIP(hipLaunchKernel(reinterpret_cast<const void *>(L.fn), dim3(L.grid), dim3(L.block), kargs, L.lds,
+                             stream));
+    return check_launch("hepk_pipeline");
+}
+
+static bool any_active(hepk_plan p) {
+    for (const auto &o : p->qd)
+        if (o.active) return true;
+    return false;
+}
+
+static void free_plan(hepk_plan p) {
+    if (!p) return;
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    for (auto e : p->ring_ev) (void)hipEventDestroy(e);
+    if (p->pinned) (void)hipHostFree(p->pinned);
+    if (p->dev_mem) (void)hipFree(p->dev_mem);
+    delete p;
+}
+
+}  // namespace hepk
+
+static int plan_fail(hepk_plan p, int rc) {
+    hepk::free_plan(p);
     return rc;
 }
 
-extern "C" int hepk_plan_create(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_t n_query,
-                                const hepk_tune *tune, hepk_plan *out) {
+extern "C" int hepk_plan_create_ex(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_t n_query,
+                                   const hepk_plan_opts *opts, hepk_plan *out) {
     using namespace hepk;
     clear_error();
     HEPK_REQUIRE(out, "hepk_plan_create: out is NULL");
@@ -606,167 +772,147 @@ extern "C" int hepk_plan_create(const hepk_dataset *ds, int32_t n_ds, const hepk
         }
         if (D.jets.extra) ext = true;
     }
-    int64_t n_scale_total = 0;
     for (int i = 0; i < n_query; ++i) {
-        const hepk_query &Q = q[i];
-        HEPK_REQUIRE(Q.n_scale >= 1 && Q.scales, "hepk_plan_create: query %d needs >= 1 scale", i);
-        for (int h = 0; h < 3; ++h) {
-            HEPK_REQUIRE(Q.nbins[h] >= 1 && Q.edges[h], "hepk_plan_create: query %d histogram %d invalid", i, h);
-        }
-        n_scale_total += Q.n_scale;
+        int rc = check_query(q[i], i);
+        if (rc) return rc;
     }
-    hepk_tune t{512, 1, 0, 0};
-    if (tune) t = *tune;
+    hepk_plan_opts o{};
+    if (opts) o = *opts;
+    hepk_tune t = o.tune;
+    if (t.block == 0) t = hepk_tune{512, 1, 0, 0};
     HEPK_REQUIRE(t.block == 256 || t.block == 512, "hepk_plan_create: block %d not 256 or 512", t.block);
     HEPK_REQUIRE(t.ev_per_thread == 1 || t.ev_per_thread == 2, "hepk_plan_create: ev_per_thread %d not 1 or 2",
                  t.ev_per_thread);
     HEPK_REQUIRE(t.hist_mode == 0 || t.hist_mode == 1, "hepk_plan_create: hist_mode %d not 0 or 1", t.hist_mode);
     HEPK_REQUIRE(t.grid >= 0, "hepk_plan_create: grid < 0");
+    HEPK_REQUIRE(o.reserve_bins >= 0 && o.reserve_bins < (1 << 20), "hepk_plan_create: reserve_bins out of range");
 
     hepk_plan p = new hepk_plan_s();
-    HEPK_HIP(hipGetDevice(&p->device));
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        set_error("hepk_plan_create: no current HIP device");
+        return plan_fail(p, HEPK_EHIP);
+    }
     p->n_ds = n_ds;
     p->n_q = n_query;
     p->dtype = dtype;
     p->ext = ext;
+    p->shared = o.shared_hist != 0;
 
-    // Bin edges are copied into the plan's own table (one device-to-host copy
-    // for the bin-guess start values, one device-to-device copy per array).
-    std::vector<std::vector<float>> eh(static_cast<size_t>(n_query) * 3);
-    int64_t n_edges = 0;
-    for (int i = 0; i < n_query; ++i)
-        for (int h = 0; h < 3; ++h) {
-            auto &v = eh[i * 3 + h];
-            v.resize(q[i].nbins[h] + 1);
-            if (hipMemcpy(v.data(), q[i].edges[h], v.size() * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) {
-                set_error("hepk_plan_create: reading query %d edges %d failed", i, h);
-                return plan_fail(p, HEPK_EHIP);
-            }
-            for (size_t k = 0; k + 1 < v.size(); ++k)
-                if (!(v[k] < v[k + 1])) {
-                    set_error("hepk_plan_create: query %d edges %d not strictly increasing at %zu", i, h, k);
-                    return plan_fail(p, HEPK_EINVAL);
-                }
-            n_edges += static_cast<int64_t>(v.size());
-        }
-
-    // histogram layout: per dataset, per query, per scale, (H_T, lead, nJet)
-    std::vector<QDev> qd(n_query);
-    std::vector<float> scales;
-    std::vector<float> edge_table;
-    int64_t ds_slots = 0;
+    // query slots: reserved bins/scales, global histogram blocks, edge and scale regions
+    p->qd.assign(n_query, QDev{});
+    p->cap_bins.assign(3 * n_query, 0);
+    p->cap_scales.assign(n_query, 0);
+    std::vector<float> edge_table, scales;
+    int64_t gacc = 0;
+    int32_t max_cap = 0, max_sc = 0;
     for (int i = 0; i < n_query; ++i) {
-        const hepk_query &Q = q[i];
-        QDev &o = qd[i];
-        o.mu_pt = Q.mu_pt;
-        o.mu_abseta = Q.mu_abseta;
-        o.mu_iso = Q.mu_iso;
-        o.el_pt = Q.el_pt;
-        o.el_abseta = Q.el_abseta;
-        o.jet_pt = Q.jet_pt;
-        o.jet_abseta = Q.jet_abseta;
-        o.thr2 = Q.dr * Q.dr;  // rounded once to float32
-        o.btag = Q.btag;
-        o.min_mu = Q.min_mu;
-        o.min_jet = Q.min_jet;
-        o.min_b = Q.min_b;
-        o.n_scale = Q.n_scale;
-        o.scale0 = static_cast<int32_t>(scales.size());
-        for (int v = 0; v < Q.n_scale; ++v) scales.push_back(Q.scales[v]);
-        int32_t acc = 0;
+        QDev &e = p->qd[i];
+        set_qdev(e, q[i], q[i].edges);
+        p->cap_scales[i] = q[i].n_scale;
+        max_sc = std::max(max_sc, q[i].n_scale);
+        e.scale0 = static_cast<int32_t>(scales.size());
+        for (int v = 0; v < q[i].n_scale; ++v) scales.push_back(q[i].scales[v]);
+        int32_t per = 0;
         for (int h = 0; h < 3; ++h) {
-            const auto &v = eh[i * 3 + h];
-            o.nbins[h] = Q.nbins[h];
-            o.hoff[h] = acc;
-            o.ebase[h] = static_cast<int32_t>(edge_table.size());
-            edge_table.insert(edge_table.end(), v.begin(), v.end());
-            const float span = v.back() - v.front();
-            o.lo[h] = v.front();
-            o.hi[h] = v.back();
-            o.inv_w[h] = (span > 0.0f && std::isfinite(span)) ? static_cast<float>(Q.nbins[h]) / span : 0.0f;
-            acc += Q.nbins[h] + 2;
+            const int cap = std::max(q[i].nbins[h], o.reserve_bins);
+            p->cap_bins[3 * i + h] = cap;
+            max_cap = std::max(max_cap, cap);
+            e.ghoff[h] = per;
+            per += cap + 2;
+            e.ebase[h] = static_cast<int32_t>(edge_table.size());
+            edge_table.insert(edge_table.end(), q[i].edges[h], q[i].edges[h] + q[i].nbins[h] + 1);
+            edge_table.resize(e.ebase[h] + cap + 1, 0.0f);
         }
-        o.per_scale = acc;
-        o.slot0 = static_cast<int32_t>(ds_slots);
-        ds_slots += static_cast<int64_t>(acc) * Q.n_scale;
+        e.gper_scale = per;
+        e.gslot0 = static_cast<int32_t>(gacc);
+        gacc += static_cast<int64_t>(per) * q[i].n_scale;
     }
-    if (ds_slots >= (int64_t(1) << 30) || n_edges >= (int64_t(1) << 30)) {
-        set_error("hepk_plan_create: %lld histogram slots per dataset is too many", (long long)ds_slots);
+    if (gacc >= (int64_t(1) << 30) || edge_table.size() >= (size_t(1) << 30)) {
+        set_error("hepk_plan_create: %lld histogram slots per dataset is too many", (long long)gacc);
         return plan_fail(p, HEPK_EINVAL);
     }
-    p->n_slots = ds_slots * n_ds;
-    for (int d = 0; d < n_ds; ++d)
-        for (int i = 0; i < n_query; ++i)
-            for (int v = 0; v < q[i].n_scale; ++v)
-                for (int h = 0; h < 3; ++h) {
-                    p->hoff.push_back(d * ds_slots + qd[i].slot0 + v * qd[i].per_scale + qd[i].hoff[h]);
-                    p->hnb.push_back(q[i].nbins[h]);
-                }
-    for (int i = 0; i < n_query; ++i) {
-        p->q_scale0.push_back(qd[i].scale0);
-        p->q_nscale.push_back(q[i].n_scale);
-    }
-    p->entries_per_ds = 3 * n_scale_total;
+    p->ds_block = gacc;
+    p->n_slots = p->shared ? gacc : gacc * n_ds;
+    p->n_edges = static_cast<int32_t>(edge_table.size());
+    p->edges_lds = static_cast<size_t>(p->n_edges) * sizeof(float) <= static_cast<size_t>(kMaxLdsEdgeBytes);
+    p->tune = t;
+    relayout(p);
 
-    const size_t hist_bytes = static_cast<size_t>(ds_slots) * (sizeof(double) + sizeof(uint32_t));
-    const bool ldsh = (t.hist_mode == 0) && hist_bytes <= static_cast<size_t>(kMaxLdsHistBytes);
-    if (!ldsh) t.hist_mode = 1;
-    const bool edges_lds = n_edges * sizeof(float) <= static_cast<size_t>(kMaxLdsEdgeBytes);
     const int waves = t.block / 64;
     const int tw = 64 * t.ev_per_thread;
-
     std::vector<DsDev> dd(n_ds);
-    int64_t total_tiles = 0;
     std::vector<int64_t> tiles(n_ds);
+    int64_t total_tiles = 0;
     for (int d = 0; d < n_ds; ++d) {
         const hepk_dataset &D = ds[d];
-        DsDev &o = dd[d];
-        o.n_events = D.n_events;
-        o.joff = D.jets.offsets;
-        o.moff = D.muons.offsets;
-        o.eoff = D.electrons.offsets;
-        o.jpt = D.jets.pt;
-        o.jeta = D.jets.eta;
-        o.jphi = D.jets.phi;
-        o.jbt = D.jets.extra;
-        o.mpt = D.muons.pt;
-        o.meta = D.muons.eta;
-        o.mphi = D.muons.phi;
-        o.miso = D.muons.extra;
-        o.ept = D.electrons.pt;
-        o.eeta = D.electrons.eta;
-        o.ephi = D.electrons.phi;
-        o.w = D.weights;
-        o.hist0 = d * ds_slots;
+        DsDev &e = dd[d];
+        e.n_events = D.n_events;
+        e.joff = D.jets.offsets;
+        e.moff = D.muons.offsets;
+        e.eoff = D.electrons.offsets;
+        e.jpt = D.jets.pt;
+        e.jeta = D.jets.eta;
+        e.jphi = D.jets.phi;
+        e.jbt = D.jets.extra;
+        e.mpt = D.muons.pt;
+        e.meta = D.muons.eta;
+        e.mphi = D.muons.phi;
+        e.miso = D.muons.extra;
+        e.ept = D.electrons.pt;
+        e.eeta = D.electrons.eta;
+        e.ephi = D.electrons.phi;
+        e.w = D.weights;
+        e.hist0 = hist_base(p, d);
         tiles[d] = ceil_div(D.n_events, tw);
         total_tiles += tiles[d];
     }
 
-    p->fn = pick_kernel(dtype, ext, t.block, t.ev_per_thread, ldsh);
-    p->lds_bytes = (ldsh ? hist_bytes : 0) + (edges_lds ? n_edges * sizeof(float) : 0);
+    p->fn_lds = pick_kernel(dtype, ext, t.block, t.ev_per_thread, true);
+    p->fn_glob = pick_kernel(dtype, ext, t.block, t.ev_per_thread, false);
+    const size_t lds_hist = use_lds_hist(p) ? static_cast<size_t>(p->lds_slots) * 12 : 0;
+    const size_t lds_bytes = lds_hist + (p->edges_lds ? p->n_edges * sizeof(float) : 0);
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(p->fn), t.block,
-                                                     p->lds_bytes) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(use_lds_hist(p) ? p->fn_lds : p->fn_glob), t.block,
+            lds_bytes) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     int64_t grid = t.grid > 0 ? t.grid : static_cast<int64_t>(per_cu) * device_cus();
 
-    // Chunks: runs of tiles of one dataset, a multiple of the wavefronts per
-    // workgroup long, about total/grid tiles each, so that every workgroup
-    // gets one chunk (plus the few split off at dataset ends).
-    const int64_t per = std::max<int64_t>(waves, ceil_div(ceil_div(total_tiles, std::max<int64_t>(1, grid)), waves) * waves);
+    // Work chunks: runs of tiles of one dataset, a multiple of the
+    // wavefronts per workgroup long.  The full pass uses chunks of about
+    // total/grid tiles (one per workgroup, plus those split at dataset ends);
+    // each dataset also has its own list of about tiles/grid-sized chunks so
+    // that a pass over that dataset alone fills the device.
+    auto chunk_len = [&](int64_t n) {
+        return std::max<int64_t>(waves, ceil_div(ceil_div(n, std::max<int64_t>(1, grid)), waves) * waves);
+    };
     std::vector<Chunk> chunks;
-    for (int d = 0; d < n_ds; ++d)
+    const int64_t per_all = chunk_len(total_tiles);
+    p->full_begin.assign(n_ds + 1, 0);
+    for (int d = 0; d < n_ds; ++d) {
+        p->full_begin[d] = static_cast<int32_t>(chunks.size());
+        for (int64_t t0 = 0; t0 < tiles[d]; t0 += per_all)
+            chunks.push_back(Chunk{d, 0, t0, std::min(tiles[d], t0 + per_all)});
+    }
+    p->full_begin[n_ds] = static_cast<int32_t>(chunks.size());
+    p->n_chunks_all = static_cast<int32_t>(chunks.size());
+    p->own_begin.assign(n_ds + 1, 0);
+    for (int d = 0; d < n_ds; ++d) {
+        p->own_begin[d] = static_cast<int32_t>(chunks.size());
+        const int64_t per = chunk_len(tiles[d]);
         for (int64_t t0 = 0; t0 < tiles[d]; t0 += per) chunks.push_back(Chunk{d, 0, t0, std::min(tiles[d], t0 + per)});
-    const int64_t n_chunks = static_cast<int64_t>(chunks.size());
-    HEPK_REQUIRE(n_chunks < (int64_t(1) << 31), "hepk_plan_create: too many work chunks");
-    grid = std::max<int64_t>(1, std::min<int64_t>(grid, n_chunks));
-    t.grid = static_cast<int32_t>(grid);
-    p->tune = t;
-    p->grid = static_cast<int>(grid);
+    }
+    p->own_begin[n_ds] = static_cast<int32_t>(chunks.size());
+    if (chunks.size() >= (size_t(1) << 31)) {
+        set_error("hepk_plan_create: too many work chunks");
+        return plan_fail(p, HEPK_EINVAL);
+    }
+    p->grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(grid, std::max(1, p->n_chunks_all))));
+    p->tune.grid = p->grid;
 
     // one device allocation for the tables
-    const size_t sz_ds = sizeof(DsDev) * n_ds, sz_ch = sizeof(Chunk) * std::max<int64_t>(1, n_chunks);
+    const size_t sz_ds = sizeof(DsDev) * n_ds, sz_ch = sizeof(Chunk) * std::max<size_t>(1, chunks.size());
     const size_t sz_q = sizeof(QDev) * n_query, sz_sc = sizeof(float) * scales.size();
     const size_t sz_e = sizeof(float) * edge_table.size();
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -779,27 +925,100 @@ extern "C" int hepk_plan_create(const hepk_dataset *ds, int32_t n_ds, const hepk
     char *base = static_cast<char *>(p->dev_mem);
     std::vector<char> host(total, 0);
     std::memcpy(host.data() + o_ds, dd.data(), sz_ds);
-    if (n_chunks) std::memcpy(host.data() + o_ch, chunks.data(), sizeof(Chunk) * n_chunks);
-    std::memcpy(host.data() + o_q, qd.data(), sz_q);
+    if (!chunks.empty()) std::memcpy(host.data() + o_ch, chunks.data(), sizeof(Chunk) * chunks.size());
+    std::memcpy(host.data() + o_q, p->qd.data(), sz_q);
     if (sz_sc) std::memcpy(host.data() + o_sc, scales.data(), sz_sc);
     if (sz_e) std::memcpy(host.data() + o_e, edge_table.data(), sz_e);
     if (hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
         set_error("hepk_plan_create: table upload failed");
         return plan_fail(p, HEPK_EHIP);
     }
+    p->d_q = reinterpret_cast<QDev *>(base + o_q);
+    p->d_scales = reinterpret_cast<float *>(base + o_sc);
+    p->d_edges = reinterpret_cast<float *>(base + o_e);
+
+    // staging ring: a full query table plus one slot's edges and scales per entry
+    p->stage_bytes = al(sz_q) + al(sizeof(float) * 3 * (max_cap + 1)) + al(sizeof(float) * max_sc);
+    if (hipHostMalloc(reinterpret_cast<void **>(&p->pinned), p->stage_bytes * kStageRing, hipHostMallocDefault) !=
+        hipSuccess) {
+        set_error("hepk_plan_create: pinned staging allocation failed");
+        return plan_fail(p, HEPK_ENOMEM);
+    }
+    p->ring_ev.assign(kStageRing, nullptr);
+    p->ring_used.assign(kStageRing, false);
+    for (int r = 0; r < kStageRing; ++r)
+        if (hipEventCreateWithFlags(&p->ring_ev[r], hipEventDisableTiming) != hipSuccess) {
+            set_error("hepk_plan_create: event creation failed");
+            return plan_fail(p, HEPK_EHIP);
+        }
 
     PipeArgs &A = p->args;
     A.ds = reinterpret_cast<const DsDev *>(base + o_ds);
-    A.qs = reinterpret_cast<const QDev *>(base + o_q);
-    A.scales = reinterpret_cast<const float *>(base + o_sc);
+    A.qs = p->d_q;
+    A.scales = p->d_scales;
     A.chunks = reinterpret_cast<const Chunk *>(base + o_ch);
-    A.edges = reinterpret_cast<const float *>(base + o_e);
-    A.n_chunks = static_cast<int32_t>(n_chunks);
+    A.edges = p->d_edges;
     A.n_q = n_query;
-    A.ds_slots = static_cast<int32_t>(ds_slots);
-    A.n_edges = static_cast<int32_t>(n_edges);
-    A.edges_in_lds = edges_lds ? 1 : 0;
+    A.n_edges = p->n_edges;
+    A.edges_in_lds = p->edges_lds ? 1 : 0;
     *out = p;
+    return HEPK_OK;
+}
+
+extern "C" int hepk_plan_create(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_t n_query,
+                                const hepk_tune *tune, hepk_plan *out) {
+    hepk_plan_opts o{};
+    if (tune) o.tune = *tune;
+    if (tune && tune->block == 0) {
+        hepk::set_error("hepk_plan_create: block 0 not 256 or 512");
+        return HEPK_EINVAL;
+    }
+    return hepk_plan_create_ex(ds, n_ds, q, n_query, &o, out);
+}
+
+extern "C" int hepk_plan_set_query(hepk_plan p, int32_t slot, const hepk_query *q, hipStream_t stream) {
+    using namespace hepk;
+    clear_error();
+    HEPK_REQUIRE(p, "hepk_plan_set_query: plan is NULL");
+    HEPK_REQUIRE(slot >= 0 && slot < p->n_q, "hepk_plan_set_query: slot %d out of [0, %d)", slot, p->n_q);
+    if (q) {
+        int rc = check_query(*q, slot);
+        if (rc) return rc;
+        HEPK_REQUIRE(q->n_scale <= p->cap_scales[slot], "hepk_plan_set_query: %d scales, slot holds %d", q->n_scale,
+                     p->cap_scales[slot]);
+        for (int h = 0; h < 3; ++h)
+            HEPK_REQUIRE(q->nbins[h] <= p->cap_bins[3 * slot + h], "hepk_plan_set_query: %d bins, slot holds %d",
+                         q->nbins[h], p->cap_bins[3 * slot + h]);
+    }
+    const int r = p->ring_pos;
+    p->ring_pos = (p->ring_pos + 1) % kStageRing;
+    if (p->ring_used[r]) HEPK_HIP(hipEventSynchronize(p->ring_ev[r]));
+    char *st = p->pinned + r * p->stage_bytes;
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t sz_q = sizeof(QDev) * p->n_q;
+    QDev &e = p->qd[slot];
+    const int max_cap = *std::max_element(p->cap_bins.begin(), p->cap_bins.end());
+    float *st_e = reinterpret_cast<float *>(st + al(sz_q));
+    float *st_s = reinterpret_cast<float *>(st + al(sz_q) + al(sizeof(float) * 3 * (max_cap + 1)));
+    if (q) {
+        set_qdev(e, *q, q->edges);
+        for (int h = 0; h < 3; ++h) std::memcpy(st_e + h * (max_cap + 1), q->edges[h], sizeof(float) * (q->nbins[h] + 1));
+        std::memcpy(st_s, q->scales, sizeof(float) * q->n_scale);
+    } else {
+        e.active = 0;
+    }
+    relayout(p);
+    std::memcpy(st, p->qd.data(), sz_q);
+    if (q) {
+        for (int h = 0; h < 3; ++h)
+            HEPK_HIP(hipMemcpyAsync(p->d_edges + e.ebase[h], st_e + h * (max_cap + 1), sizeof(float) * (q->nbins[h] + 1),
+                                    hipMemcpyHostToDevice, stream));
+        HEPK_HIP(hipMemcpyAsync(p->d_scales + e.scale0, st_s, sizeof(float) * q->n_scale, hipMemcpyHostToDevice,
+                                stream));
+    }
+    HEPK_HIP(hipMemcpyAsync(p->d_q, st, sz_q, hipMemcpyHostToDevice, stream));
+    HEPK_HIP(hipEventRecord(p->ring_ev[r], stream));
+    p->ring_used[r] = true;
     return HEPK_OK;
 }
 
@@ -816,10 +1035,10 @@ extern "C" int hepk_plan_hist_offset(hepk_plan p, int32_t d, int32_t iq, int32_t
     HEPK_REQUIRE(p && offset && nbins, "hepk_plan_hist_offset: NULL argument");
     HEPK_REQUIRE(d >= 0 && d < p->n_ds && iq >= 0 && iq < p->n_q && h >= 0 && h < 3,
                  "hepk_plan_hist_offset: index out of range");
-    HEPK_REQUIRE(v >= 0 && v < p->q_nscale[iq], "hepk_plan_hist_offset: scale index out of range");
-    const int64_t k = d * p->entries_per_ds + 3 * (p->q_scale0[iq] + v) + h;
-    *offset = p->hoff[k];
-    *nbins = p->hnb[k];
+    const hepk::QDev &e = p->qd[iq];
+    HEPK_REQUIRE(v >= 0 && v < p->cap_scales[iq], "hepk_plan_hist_offset: scale index out of range");
+    *offset = hepk::hist_base(p, d) + e.gslot0 + static_cast<int64_t>(v) * e.gper_scale + e.ghoff[h];
+    *nbins = e.nbins[h];
     return HEPK_OK;
 }
 
@@ -827,31 +1046,139 @@ extern "C" int hepk_plan_get_tune(hepk_plan p, hepk_tune *tune) {
     hepk::clear_error();
     HEPK_REQUIRE(p && tune, "hepk_plan_get_tune: NULL argument");
     *tune = p->tune;
+    tune->hist_mode = hepk::use_lds_hist(p) ? 0 : 1;
     return HEPK_OK;
 }
 
-extern "C" int hepk_pipeline(hepk_plan p, double *sumw, uint64_t *counts, hipStream_t stream) {
+static int pipeline_chunks(hepk_plan p, int32_t c0, int32_t c1, double *sumw, uint64_t *counts, hipStream_t stream) {
     using namespace hepk;
-    clear_error();
-    HEPK_REQUIRE(p, "hepk_pipeline: plan is NULL");
-    HEPK_REQUIRE(sumw && counts, "hepk_pipeline: histogram buffers are NULL");
-    if (p->args.n_chunks == 0) return HEPK_OK;
+    if (c1 <= c0 || !any_active(p)) return HEPK_OK;
     int dev = 0;
     HEPK_HIP(hipGetDevice(&dev));
     HEPK_REQUIRE(dev == p->device, "hepk_pipeline: plan made on device %d, current device %d", p->device, dev);
-    PipeArgs a = p->args;
-    a.sumw = sumw;
-    a.counts = counts;
+    return run_launch(make_launch(p, c0, c1, sumw, counts), stream);
+}
+
+extern "C" int hepk_pipeline(hepk_plan p, double *sumw, uint64_t *counts, hipStream_t stream) {
+    hepk::clear_error();
+    HEPK_REQUIRE(p, "hepk_pipeline: plan is NULL");
+    HEPK_REQUIRE(sumw && counts, "hepk_pipeline: histogram buffers are NULL");
+    return pipeline_chunks(p, 0, p->n_chunks_all, sumw, counts, stream);
+}
+
+extern "C" int hepk_pipeline_range(hepk_plan p, int32_t d0, int32_t nd, double *sumw, uint64_t *counts,
+                                   hipStream_t stream) {
+    hepk::clear_error();
+    HEPK_REQUIRE(p, "hepk_pipeline_range: plan is NULL");
+    HEPK_REQUIRE(sumw && counts, "hepk_pipeline_range: histogram buffers are NULL");
+    HEPK_REQUIRE(d0 >= 0 && nd >= 0 && d0 + nd <= p->n_ds, "hepk_pipeline_range: datasets [%d, %d) out of [0, %d)",
+                 d0, d0 + nd, p->n_ds);
+    if (nd == 1) return pipeline_chunks(p, p->own_begin[d0], p->own_begin[d0 + 1], sumw, counts, stream);
+    return pipeline_chunks(p, p->full_begin[d0], p->full_begin[d0 + nd], sumw, counts, stream);
+}
+
+extern "C" int hepk_pipeline_graph(hepk_plan p, double *sumw, uint64_t *counts, hipStream_t stream) {
+    using namespace hepk;
+    clear_error();
+    HEPK_REQUIRE(p, "hepk_pipeline_graph: plan is NULL");
+    HEPK_REQUIRE(sumw && counts, "hepk_pipeline_graph: histogram buffers are NULL");
+    if (p->n_chunks_all == 0 || !any_active(p)) return HEPK_OK;
+    int dev = 0;
+    HEPK_HIP(hipGetDevice(&dev));
+    HEPK_REQUIRE(dev == p->device, "hepk_pipeline_graph: plan made on device %d, current device %d", p->device, dev);
+    const Launch L = make_launch(p, 0, p->n_chunks_all, sumw, counts);
+    hipKernelNodeParams kp{};
+    kp.func = reinterpret_cast<void *>(L.fn);
+    kp.gridDim = dim3(L.grid);
+    kp.blockDim = dim3(L.block);
+    kp.sharedMemBytes = static_cast<unsigned int>(L.lds);
+    PipeArgs a = L.a;
     void *kargs[] = {&a};
-    HEPK_HIP(hipLaunchKernel(reinterpret_cast<const void *>(p->fn), dim3(p->grid), dim3(p->tune.block), kargs,
-                             p->lds_bytes, stream));
-    return check_launch("hepk_pipeline");
+    kp.kernelParams = kargs;
+    if (!p->gexec || p->gfn != L.fn || p->ggrid != L.grid) {
+        if (p->gexec) HEPK_HIP(hipGraphExecDestroy(p->gexec));
+        if (p->graph) HEPK_HIP(hipGraphDestroy(p->graph));
+        p->gexec = nullptr;
+        p->graph = nullptr;
+        HEPK_HIP(hipGraphCreate(&p->graph, 0));
+        HEPK_HIP(hipGraphAddKernelNode(&p->gnode, p->graph, nullptr, 0, &kp));
+        HEPK_HIP(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+    } else if (std::memcmp(&p->gargs, &a, sizeof(a)) != 0 || p->glds != L.lds) {
+        HEPK_HIP(hipGraphExecKernelNodeSetParams(p->gexec, p->gnode, &kp));
+    }
+    p->gfn = L.fn;
+    p->ggrid = L.grid;
+    p->gargs = a;
+    p->glds = L.lds;
+    HEPK_HIP(hipGraphLaunch(p->gexec, stream));
+    return HEPK_OK;
 }
 
 extern "C" int hepk_plan_destroy(hepk_plan p) {
     hepk::clear_error();
     if (!p) return HEPK_OK;
-    if (p->dev_mem) HEPK_HIP(hipFree(p->dev_mem));
-    delete p;
+    if (!p->ring_ev.empty())
+        for (size_t r = 0; r < p->ring_ev.size(); ++r)
+            if (p->ring_used[r]) (void)hipEventSynchronize(p->ring_ev[r]);
+    hepk::free_plan(p);
+    return HEPK_OK;
+}
+
+extern "C" int hepk_autotune(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_t n_query,
+                             double *sumw, uint64_t *counts, int32_t reps, hepk_tune *best, float *best_ms,
+                             hipStream_t stream) {
+    using namespace hepk;
+    clear_error();
+    HEPK_REQUIRE(best && sumw && counts, "hepk_autotune: NULL argument");
+    HEPK_REQUIRE(reps >= 1 && reps <= 1000, "hepk_autotune: reps %d out of [1, 1000]", reps);
+    const hepk_tune cands[] = {{256, 1, 0, 0}, {512, 1, 0, 0}, {256, 2, 0, 0}, {512, 2, 0, 0},
+                               {256, 1, 1, 0}, {512, 1, 1, 0}, {256, 2, 1, 0}, {512, 2, 1, 0}};
+    hipEvent_t e0, e1;
+    HEPK_HIP(hipEventCreate(&e0));
+    HEPK_HIP(hipEventCreate(&e1));
+    float best_t = INFINITY;
+    hepk_tune best_c{};
+    std::vector<hepk_tune> seen;
+    int rc = HEPK_OK;
+    for (const hepk_tune &c : cands) {
+        hepk_plan p = nullptr;
+        rc = hepk_plan_create(ds, n_ds, q, n_query, &c, &p);
+        if (rc) break;
+        hepk_tune eff{};
+        hepk_plan_get_tune(p, &eff);
+        bool dup = false;
+        for (const auto &s : seen)
+            dup |= s.block == eff.block && s.ev_per_thread == eff.ev_per_thread && s.hist_mode == eff.hist_mode;
+        if (dup) {
+            hepk_plan_destroy(p);
+            continue;
+        }
+        seen.push_back(eff);
+        std::vector<float> ts;
+        rc = hepk_pipeline(p, sumw, counts, stream);  // warm-up
+        for (int r = 0; rc == HEPK_OK && r < reps; ++r) {
+            if (hipEventRecord(e0, stream) != hipSuccess) rc = HEPK_EHIP;
+            if (rc == HEPK_OK) rc = hepk_pipeline(p, sumw, counts, stream);
+            if (rc == HEPK_OK && hipEventRecord(e1, stream) != hipSuccess) rc = HEPK_EHIP;
+            float ms = 0.0f;
+            if (rc == HEPK_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = HEPK_EHIP;
+            ts.push_back(ms);
+        }
+        hepk_plan_destroy(p);
+        if (rc) break;
+        std::sort(ts.begin(), ts.end());
+        const float med = ts[ts.size() / 2];
+        if (med < best_t) {
+            best_t = med;
+            best_c = eff;
+            best_c.grid = 0;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *best = best_c;
+    if (best_ms) *best_ms = best_t;
     return HEPK_OK;
 }

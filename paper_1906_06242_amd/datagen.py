@@ -181,7 +181,9 @@ def make_dataset(seed: int, n_events: int, extended: bool = False,
     """The whole dataset in host memory.
 
     jobs > 1 draws the chunks in that many processes (same result: every
-    chunk has its own seed).  jobs = 0 picks min(8, cpus) for large datasets.
+    chunk has its own seed).  jobs = 0 picks min(8, cpus) for large datasets,
+    or HEPK_GEN_JOBS if set (1 for processes that must not fork, e.g. under a
+    profiler that has already opened the GPU).
     """
     if n_events == 0:
         z = np.zeros(1, np.int64)
@@ -192,7 +194,7 @@ def make_dataset(seed: int, n_events: int, extended: bool = False,
                        mk(EL_COLS) if extended else None, content_dtype, seed)
     sizes = _chunk_sizes(n_events)
     if jobs == 0:
-        jobs = min(8, os.cpu_count() or 1) if len(sizes) > 2 else 1
+        jobs = int(os.environ.get("HEPK_GEN_JOBS", "0")) or (min(8, os.cpu_count() or 1) if len(sizes) > 2 else 1)
     if jobs <= 1 or len(sizes) == 1:
         return concat(list(iter_chunks(seed, n_events, extended, content_dtype)))
     import multiprocessing as mp

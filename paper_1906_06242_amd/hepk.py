@@ -22,8 +22,9 @@ MAX_CUTS = 8
 
 EXPORTS = (
     "hepk_select", "hepk_reduce", "hepk_match_dr", "hepk_hist_fill", "hepk_validate_offsets",
-    "hepk_plan_create", "hepk_plan_hist_slots", "hepk_plan_hist_offset", "hepk_plan_get_tune",
-    "hepk_pipeline", "hepk_plan_destroy", "hepk_last_error", "hepk_abi_version",
+    "hepk_plan_create", "hepk_plan_create_ex", "hepk_plan_set_query", "hepk_plan_hist_slots",
+    "hepk_plan_hist_offset", "hepk_plan_get_tune", "hepk_pipeline", "hepk_pipeline_range",
+    "hepk_pipeline_graph", "hepk_autotune", "hepk_plan_destroy", "hepk_last_error", "hepk_abi_version",
 )
 
 
@@ -72,6 +73,15 @@ class Tune(C.Structure):
         return {"block": self.block, "ev_per_thread": self.ev_per_thread,
                 "hist_mode": self.hist_mode, "grid": self.grid}
 
+    @classmethod
+    def of(cls, d: Optional[dict]) -> "Tune":
+        d = d or {}
+        return cls(d.get("block", 512), d.get("ev_per_thread", 1), d.get("hist_mode", 0), d.get("grid", 0))
+
+
+class PlanOpts(C.Structure):
+    _fields_ = [("tune", Tune), ("shared_hist", C.c_int32), ("reserve_bins", C.c_int32)]
+
 
 _lib = None
 
@@ -93,6 +103,13 @@ def load(path: str = LIB_PATH):
     lib.hepk_validate_offsets.argtypes = [vp, i64, i64, vp, vp]
     lib.hepk_plan_create.argtypes = [C.POINTER(DatasetS), i32, C.POINTER(QueryS), i32,
                                      C.POINTER(Tune), C.POINTER(vp)]
+    lib.hepk_plan_create_ex.argtypes = [C.POINTER(DatasetS), i32, C.POINTER(QueryS), i32,
+                                        C.POINTER(PlanOpts), C.POINTER(vp)]
+    lib.hepk_plan_set_query.argtypes = [vp, i32, C.POINTER(QueryS), vp]
+    lib.hepk_pipeline_range.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.hepk_pipeline_graph.argtypes = [vp, vp, vp, vp]
+    lib.hepk_autotune.argtypes = [C.POINTER(DatasetS), i32, C.POINTER(QueryS), i32, vp, vp, i32,
+                                  C.POINTER(Tune), C.POINTER(C.c_float), vp]
     lib.hepk_plan_hist_slots.argtypes = [vp, C.POINTER(i64)]
     lib.hepk_plan_hist_offset.argtypes = [vp, i32, i32, i32, i32, C.POINTER(i64), C.POINTER(i32)]
     lib.hepk_plan_get_tune.argtypes = [vp, C.POINTER(Tune)]
@@ -240,43 +257,54 @@ class DeviceDataset:
 
 
 
-class Plan:
-    """hepk_plan over device datasets and datagen.Query objects."""
+def query_struct(q, keep: list) -> QueryS:
+    """A datagen.Query as the C struct; host arrays it points to go into keep."""
+    import numpy as np
+    sc = np.ascontiguousarray(q.scales, np.float32)
+    eds = [np.ascontiguousarray(e, np.float32) for e in q.edges()]
+    keep += [sc] + eds
+    qs = QueryS(q.mu_pt, q.mu_abseta, q.mu_iso, q.el_pt, q.el_abseta, q.jet_pt, q.jet_abseta,
+                q.dr, q.btag, q.min_mu, q.min_jet, q.min_b, len(sc), sc.ctypes.data)
+    for h in range(3):
+        qs.edges[h] = eds[h].ctypes.data
+        qs.nbins[h] = len(eds[h]) - 1
+    return qs
 
-    def __init__(self, datasets: List[DeviceDataset], queries, tune: Optional[dict] = None):
-        import torch
-        self._keep = []
+
+class Plan:
+    """hepk_plan over device datasets and datagen.Query objects.
+
+    shared_hist: all datasets accumulate into one set of histograms.
+    reserve_bins: every query slot can later take (set_query) any query with
+    at most that many bins per histogram.
+    """
+
+    def __init__(self, datasets: List[DeviceDataset], queries, tune: Optional[dict] = None,
+                 shared_hist: bool = False, reserve_bins: int = 0):
+        keep = []
         dsa = (DatasetS * len(datasets))(*[d.struct() for d in datasets])
-        qa = (QueryS * len(queries))()
-        self.edges = []
-        for i, q in enumerate(queries):
-            sc = (C.c_float * q.n_scale)(*[float(x) for x in q.scales])
-            self._keep.append(sc)
-            eds = [torch.from_numpy(e.astype("float32")).to("cuda") for e in q.edges()]
-            self.edges.append(eds)
-            qs = QueryS(q.mu_pt, q.mu_abseta, q.mu_iso, q.el_pt, q.el_abseta, q.jet_pt, q.jet_abseta,
-                        q.dr, q.btag, q.min_mu, q.min_jet, q.min_b, q.n_scale,
-                        C.cast(sc, C.c_void_p))
-            for h in range(3):
-                qs.edges[h] = _ptr(eds[h])
-                qs.nbins[h] = eds[h].numel() - 1
-            qa[i] = qs
-        tn = None
-        if tune is not None:
-            tn = Tune(tune.get("block", 256), tune.get("ev_per_thread", 1),
-                      tune.get("hist_mode", 0), tune.get("grid", 0))
+        qa = (QueryS * len(queries))(*[query_struct(q, keep) for q in queries])
+        opts = PlanOpts(Tune.of(tune) if tune is not None else Tune(0, 0, 0, 0),
+                        1 if shared_hist else 0, reserve_bins)
         h = C.c_void_p()
-        _call("hepk_plan_create", dsa, len(datasets), qa, len(queries),
-              C.byref(tn) if tn is not None else None, C.byref(h))
+        _call("hepk_plan_create_ex", dsa, len(datasets), qa, len(queries), C.byref(opts), C.byref(h))
         self.handle = h
         self.datasets = datasets
-        self.queries = queries
+        self.queries = list(queries)
+        self.shared = shared_hist
         n = C.c_int64()
         _call("hepk_plan_hist_slots", h, C.byref(n))
         self.n_slots = n.value
         t = Tune()
         _call("hepk_plan_get_tune", h, C.byref(t))
         self.tune = t.as_dict()
+
+    def set_query(self, slot: int, q, stream=None):
+        """Install query q (None: idle) in a slot, ordered on the stream."""
+        keep = []
+        qs = C.byref(query_struct(q, keep)) if q is not None else None
+        _call("hepk_plan_set_query", self.handle, slot, qs, _stream(stream))
+        self.queries[slot] = q
 
     def hist_offset(self, d: int, q: int, v: int, h: int):
         off, nb = C.c_int64(), C.c_int32()
@@ -291,14 +319,23 @@ class Plan:
     def run(self, sumw, counts, stream=None):
         _call("hepk_pipeline", self.handle, _ptr(sumw), _ptr(counts), _stream(stream))
 
+    def run_range(self, d0: int, nd: int, sumw, counts, stream=None):
+        _call("hepk_pipeline_range", self.handle, d0, nd, _ptr(sumw), _ptr(counts), _stream(stream))
+
+    def run_graph(self, sumw, counts, stream=None):
+        _call("hepk_pipeline_graph", self.handle, _ptr(sumw), _ptr(counts), _stream(stream))
+
     def split(self, sumw, counts):
         """Host copies as hists[d][q][v][h] = (sumw, counts) numpy arrays."""
         s = sumw.cpu().numpy()
         c = counts.cpu().numpy().view("uint64")
         out = []
-        for d in range(len(self.datasets)):
+        for d in range(1 if self.shared else len(self.datasets)):
             per_d = []
             for qi, q in enumerate(self.queries):
+                if q is None:
+                    per_d.append(None)
+                    continue
                 per_q = []
                 for v in range(q.n_scale):
                     per_v = []
@@ -320,3 +357,20 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def autotune(datasets: List[DeviceDataset], queries, reps: int = 5, stream=None):
+    """Fastest launch configuration for these datasets and queries (hepk_autotune)."""
+    import torch
+    keep = []
+    dsa = (DatasetS * len(datasets))(*[d.struct() for d in datasets])
+    qa = (QueryS * len(queries))(*[query_struct(q, keep) for q in queries])
+    probe = Plan(datasets, queries)
+    s = torch.zeros(probe.n_slots, dtype=torch.float64, device="cuda")
+    c = torch.zeros(probe.n_slots, dtype=torch.int64, device="cuda")
+    probe.close()
+    best = Tune()
+    ms = C.c_float()
+    _call("hepk_autotune", dsa, len(datasets), qa, len(queries), _ptr(s), _ptr(c), reps,
+          C.byref(best), C.byref(ms), _stream(stream))
+    return best.as_dict(), ms.value

@@ -122,8 +122,9 @@ def test_plan_create_rejects_bad_arguments(lib):
     q[0].n_scale = 1
     q[0].scales = C.cast(sc, C.c_void_p)
     assert _rc("hepk_plan_create", ds, 1, q, 1, None, C.byref(out)) == H.EINVAL  # nbins 0
+    edges = (C.c_float * 11)(*range(11))
     for h in range(3):
-        q[0].edges[h] = 8
+        q[0].edges[h] = C.cast(edges, C.c_void_p)
         q[0].nbins[h] = 10
     bad = H.Tune(384, 1, 0, 0)
     assert _rc("hepk_plan_create", ds, 1, q, 1, C.byref(bad), C.byref(out)) == H.EINVAL
@@ -141,3 +142,33 @@ def test_pipeline_and_queries_reject_null(lib):
     assert _rc("hepk_plan_hist_slots", None, C.byref(n)) == H.EINVAL
     assert _rc("hepk_plan_destroy", None) == H.OK
     assert _rc("hepk_validate_offsets", None, 1, 1, 8, None) == H.EINVAL
+
+
+def test_slot_range_graph_autotune_reject_bad_arguments(lib):
+    assert _rc("hepk_plan_set_query", None, 0, None, None) == H.EINVAL
+    assert _rc("hepk_pipeline_range", None, 0, 1, 8, 8, None) == H.EINVAL
+    assert _rc("hepk_pipeline_graph", None, 8, 8, None) == H.EINVAL
+    best = H.Tune()
+    ds = (H.DatasetS * 1)()
+    q = (H.QueryS * 1)()
+    assert _rc("hepk_autotune", ds, 1, q, 1, 8, 8, 0, C.byref(best), None, None) == H.EINVAL
+    assert "reps" in H.last_error()
+    assert _rc("hepk_autotune", ds, 1, q, 1, None, 8, 3, C.byref(best), None, None) == H.EINVAL
+    out = C.c_void_p()
+    opts = H.PlanOpts(H.Tune(0, 0, 0, 0), 0, -5)
+    ds[0] = H.DatasetS(0, H.F32, H.Collection(8, 8, 8, 8, None), H.Collection(8, 8, 8, 8, 8),
+                       H.Collection(None, None, None, None, None), None)
+    sc = (C.c_float * 1)(1.0)
+    e = (C.c_float * 3)(0.0, 1.0, 2.0)
+    q[0].n_scale = 1
+    q[0].scales = C.cast(sc, C.c_void_p)
+    for h in range(3):
+        q[0].edges[h] = C.cast(e, C.c_void_p)
+        q[0].nbins[h] = 2
+    assert _rc("hepk_plan_create_ex", ds, 1, q, 1, C.byref(opts), C.byref(out)) == H.EINVAL
+    assert "reserve_bins" in H.last_error()
+    bad = (C.c_float * 3)(0.0, 2.0, 1.0)
+    q[0].edges[1] = C.cast(bad, C.c_void_p)
+    opts = H.PlanOpts(H.Tune(0, 0, 0, 0), 0, 0)
+    assert _rc("hepk_plan_create_ex", ds, 1, q, 1, C.byref(opts), C.byref(out)) == H.EINVAL
+    assert "increasing" in H.last_error()

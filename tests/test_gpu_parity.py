@@ -426,3 +426,113 @@ def test_pipeline_full_size_1e7():
     q = datagen.Query()
     got = fused([ds], [q])[0]
     check_against_oracle(ds, [q], got, "1e7")
+
+
+# ------------------------------------------------------------------ plan features
+
+def _sum_hists(hs):
+    return [(sum(h[k][0] for h in hs), sum(h[k][1] for h in hs)) for k in range(3)]
+
+
+def test_pipeline_range_per_dataset():
+    say("pipeline range")
+    sizes = [3000, 70000, 1, 20000]
+    dss = [datagen.make_dataset(2000 + i, n) for i, n in enumerate(sizes)]
+    q = datagen.Query()
+    plan = H.Plan([H.DeviceDataset(d) for d in dss], [q])
+    for d in range(len(dss)):
+        s, c = plan.new_hists()
+        plan.run_range(d, 1, s, c)
+        got = plan.split(s, c)
+        check_against_oracle(dss[d], [q], got[d][:1], f"range d={d}")
+        for other in range(len(dss)):
+            if other != d:
+                assert all(int(got[other][0][0][h][1].sum()) == 0 for h in range(3))
+    s, c = plan.new_hists()
+    plan.run_range(1, 3, s, c)
+    got = plan.split(s, c)
+    for d in (1, 2, 3):
+        check_against_oracle(dss[d], [q], got[d], f"range 1..3 d={d}")
+    plan.close()
+
+
+def test_pipeline_shared_hist_sums_datasets():
+    say("pipeline shared hist")
+    dss = [datagen.make_dataset(3000 + i, n) for i, n in enumerate([40000, 12345, 0, 777])]
+    q = datagen.Query()
+    plan = H.Plan([H.DeviceDataset(d) for d in dss], [q], shared_hist=True)
+    s, c = plan.new_hists()
+    plan.run(s, c)
+    got = plan.split(s, c)[0][0][0]
+    want = _sum_hists([ref.pipeline(d, [q])[0][0] for d in dss])
+    for h in range(3):
+        assert_hist(got[h], want[h], f"shared h{h}")
+    plan.close()
+
+
+def test_set_query_replaces_and_idles_slots():
+    say("set_query")
+    ds = datagen.make_dataset(12, 60000)
+    qs = datagen.draw_queries(5, 6)
+    plan = H.Plan([H.DeviceDataset(ds)], [datagen.Query()] * 3, reserve_bins=200)
+    for slot in range(3):
+        plan.set_query(slot, qs[slot])
+    s, c = plan.new_hists()
+    plan.run(s, c)
+    got = plan.split(s, c)[0]
+    check_against_oracle(ds, qs[:3], got, "slots 0..2")
+    # replace slot 1, idle slot 0; fresh histograms
+    plan.set_query(1, qs[4])
+    plan.set_query(0, None)
+    s, c = plan.new_hists()
+    plan.run(s, c)
+    got = plan.split(s, c)[0]
+    assert got[0] is None
+    check_against_oracle(ds, [qs[4], qs[2]], [got[1], got[2]], "after replace")
+    off, nb = plan.hist_offset(0, 0, 0, 0)
+    assert int(host(c)[off:off + nb + 2].sum()) == 0
+    plan.close()
+
+
+def test_graph_replays_match_eager():
+    import torch
+    say("graph replays")
+    ds = datagen.make_dataset(13, 50000)
+    q = datagen.Query()
+    want = ref.pipeline(ds, [q])[0][0]
+    plan = H.Plan([H.DeviceDataset(ds)], [q])
+    s, c = plan.new_hists()
+    for k in range(1, 4):
+        plan.run_graph(s, c)
+        torch.cuda.synchronize()
+        got = plan.split(s, c)[0][0][0]
+        for h in range(3):
+            assert_hist(got[h], (k * want[h][0], k * want[h][1]), f"replay {k} h{h}")
+        # eager work between replays
+        s2, c2 = plan.new_hists()
+        plan.run(s2, c2)
+        torch.cuda.synchronize()
+    # new histogram buffers: the graph node is updated in place
+    s3, c3 = plan.new_hists()
+    plan.run_graph(s3, c3)
+    got = plan.split(s3, c3)[0][0][0]
+    for h in range(3):
+        assert_hist(got[h], want[h], f"new buffers h{h}")
+    plan.close()
+
+
+def test_autotune_picks_a_valid_configuration():
+    say("autotune")
+    dss = [datagen.make_dataset(4000 + i, n) for i, n in enumerate([30000, 5000, 60000])]
+    q = datagen.Query()
+    dds = [H.DeviceDataset(d) for d in dss]
+    best, ms = H.autotune(dds, [q], reps=3)
+    assert best["block"] in (256, 512) and best["ev_per_thread"] in (1, 2) and best["hist_mode"] in (0, 1)
+    assert ms > 0
+    plan = H.Plan(dds, [q], best)
+    s, c = plan.new_hists()
+    plan.run(s, c)
+    got = plan.split(s, c)
+    for d, ds in enumerate(dss):
+        check_against_oracle(ds, [q], got[d], f"autotuned d={d}")
+    plan.close()
