@@ -14,6 +14,18 @@ kernel's achieved HBM bandwidth from its algorithmic bytes (the input columns
 the pass must read, mass columns excluded) over its average launch time,
 measured with HIP events on the launch stream; `cpu_baseline` is the CPU
 oracle on one host core over a bounded sample of the same workload.
+
+Further sections on the same line (each skippable):
+  extended  5e7 events, float16 content widened in registers, electrons,
+            jet b-tag, 20 jet-energy-scale variations -> 60 histograms/pass;
+  batch     64 datasets of log-uniform sizes in [1e4, 5e6] in one persistent
+            launch replayed from a HIP graph, with the launch-configuration
+            sweep (block, events per thread, LDS vs global histograms);
+  serving   2e8 events resident, Poisson stream of queries at 50/s with
+            random cuts and binnings, continuous batching over a circular
+            chunk scan: p50/p99 latency and query-events/s, plus closed-loop
+            throughput of the fused server vs the per-kernel pipeline.
+Those large inputs are drawn on the GPU (datagen.make_dataset_device).
 """
 from __future__ import annotations
 
@@ -91,6 +103,163 @@ def time_steps(fn, steps: int, warmup: int, stream):
     return [a.elapsed_time(b) for a, b in ev], wall
 
 
+def dev_bytes_read(t: dict) -> int:
+    """Algorithmic bytes of one pass over an on-device dataset (mass columns excluded)."""
+    b = 0
+    for k, v in t.items():
+        if hasattr(v, "element_size") and not k.endswith(".mass"):
+            b += v.numel() * v.element_size()
+    return b
+
+
+def time_plan(run, steps: int, warmup: int = 2):
+    import torch
+    ms, wall = time_steps(run, steps, warmup, torch.cuda.current_stream())
+    return statistics.median(ms), wall / steps
+
+
+def spot_check(dd_all: dict, e0: int, e1: int, queries, tune=None) -> bool:
+    """Fused pass over events [e0, e1) of a device dataset vs the oracle on a host copy."""
+    import numpy as np
+    from oracle import ref
+    from paper_1906_06242_amd import datagen
+    from paper_1906_06242_amd import hepk as H
+    view = H.DeviceDataset.from_tensors(dd_all).view(e0, e1)
+    plan = H.Plan([view], queries, tune)
+    s, c = plan.new_hists()
+    plan.run(s, c)
+    got = plan.split(s, c)[0]
+    plan.close()
+    want = ref.pipeline(datagen.host_slice(dd_all, e0, e1), queries)
+    ok = True
+    for qi, qq in enumerate(queries):
+        for v in range(qq.n_scale):
+            for h in range(3):
+                gs, gc = got[qi][v][h]
+                ws, wc = want[qi][v][h]
+                ok &= bool(np.array_equal(gc, wc) and np.all(np.abs(gs - ws) <= 1e-5 * np.abs(ws)))
+    return ok
+
+
+def section_extended(args) -> dict:
+    import torch
+    from paper_1906_06242_amd import datagen
+    from paper_1906_06242_amd import hepk as H
+    n = 50_000_000
+    t0 = time.time()
+    t = datagen.make_dataset_device(0, n, extended=True, content_dtype="f16")
+    torch.cuda.synchronize()
+    log(f"extended: generated {n} events on device in {time.time() - t0:.1f} s")
+    q = datagen.extended_query()
+    dd = H.DeviceDataset.from_tensors(t)
+    plan = H.Plan([dd], [q])
+    s, c = plan.new_hists()
+    kern_ms, step_ms = time_plan(lambda: plan.run(s, c), 10)
+    alg = dev_bytes_read(t)
+    res = {"workload": "5e7 events, f16 content, jets+muons+electrons, b-tag, 20 JES scales, 60 histograms",
+           "events_per_s": n / (step_ms * 1e-3), "ms_per_step": step_ms, "kernel_ms": kern_ms,
+           "bytes_read_per_pass": alg, "bytes_per_event": alg / n,
+           "achieved_GBps": alg / (kern_ms * 1e-3) / 1e9, "hbm_frac": alg / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "tune": plan.tune, "histograms": 60}
+    plan.close()
+    res["parity_spot_check"] = spot_check(t, 1_234_567, 1_264_567, [q])
+    log(f"extended: {step_ms:.3f} ms/step, {res['achieved_GBps']:.0f} GB/s, parity {res['parity_spot_check']}")
+    del t, dd
+    torch.cuda.empty_cache()
+    return res
+
+
+def section_batch(args) -> dict:
+    import torch
+    from paper_1906_06242_amd import datagen
+    from paper_1906_06242_amd import hepk as H
+    sizes = datagen.batch_sizes(0)
+    t0 = time.time()
+    ts = [datagen.make_dataset_device(1000 + d, int(n)) for d, n in enumerate(sizes)]
+    torch.cuda.synchronize()
+    n_all = int(sizes.sum())
+    log(f"batch: generated {len(sizes)} datasets, {n_all} events, in {time.time() - t0:.1f} s")
+    dds = [H.DeviceDataset.from_tensors(t) for t in ts]
+    q = datagen.Query()
+    alg = sum(dev_bytes_read(t) for t in ts)
+    sweep = []
+    for blk in (256, 512):
+        for evpt in (1, 2):
+            for hm in (0, 1):
+                tn = {"block": blk, "ev_per_thread": evpt, "hist_mode": hm}
+                plan = H.Plan(dds, [q], tn)
+                s, c = plan.new_hists()
+                kern_ms, _ = time_plan(lambda: plan.run(s, c), 5, 1)
+                sweep.append({"tune": tn, "kernel_ms": kern_ms})
+                plan.close()
+    best, best_ms = H.autotune(dds, [q], reps=5)
+    plan = H.Plan(dds, [q], best)
+    s, c = plan.new_hists()
+    kern_ms, step_ms = time_plan(lambda: plan.run_graph(s, c), 10)
+    res = {"workload": f"{len(sizes)} datasets, log-uniform sizes in [1e4, 5e6], {n_all} events, one graph launch",
+           "events": n_all, "events_per_s": n_all / (step_ms * 1e-3), "ms_per_step": step_ms,
+           "kernel_ms": kern_ms, "bytes_read_per_pass": alg,
+           "achieved_GBps": alg / (kern_ms * 1e-3) / 1e9, "hbm_frac": alg / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "autotuned": best, "autotune_ms": best_ms, "sweep": sweep}
+    plan.close()
+    res["parity_spot_check"] = spot_check(ts[5], 0, min(40000, int(sizes[5])), [q])
+    log(f"batch: {step_ms:.3f} ms/step, {res['achieved_GBps']:.0f} GB/s, best {best}")
+    del ts, dds
+    torch.cuda.empty_cache()
+    return res
+
+
+def section_serving(args) -> dict:
+    import torch
+    from paper_1906_06242_amd import datagen
+    from paper_1906_06242_amd import hepk as H
+    from paper_1906_06242_amd import plain
+    from paper_1906_06242_amd.serve import GpuBackend, Server, percentile
+    n = 200_000_000
+    t0 = time.time()
+    t = datagen.make_dataset_device(0, n)
+    torch.cuda.synchronize()
+    log(f"serving: generated {n} events on device in {time.time() - t0:.1f} s")
+    dd = H.DeviceDataset.from_tensors(t)
+    stored = sum(v.numel() * v.element_size() for v in t.values() if hasattr(v, "numel"))
+    qs = datagen.draw_queries(1, args.serve_queries, qps=50.0)
+    be = GpuBackend(dd, n_chunks=16, n_slots=8)
+    # warm-up: a few queries closed loop
+    Server(be).run_closed(datagen.draw_queries(2, 4))
+    srv = Server(be)
+    w0 = time.perf_counter()
+    done = srv.run_stream(qs)
+    wall = time.perf_counter() - w0
+    lat = [x.latency * 1e3 for x in done]
+    res = {"workload": f"{n:.0e} events resident ({stored / 1e9:.1f} GB), {len(qs)} queries, Poisson 50/s, "
+                       "16 chunks, 8 query slots",
+           "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99), "max_ms": max(lat),
+           "queries": len(done), "wall_s": wall, "query_events_per_s": len(done) * n / wall,
+           "launches": srv.launches}
+    # closed loop: all queries waiting, fused co-batched server vs per-kernel pipeline per query
+    qc = datagen.draw_queries(3, 32)
+    srv = Server(be)
+    w0 = time.perf_counter()
+    srv.run_closed(qc)
+    torch.cuda.synchronize()
+    res["saturated_query_events_per_s"] = len(qc) * n / (time.perf_counter() - w0)
+    be.close()
+    qp = qc[:3]
+    plain.run(dd, qp[0])
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for x in qp:
+        plain.run(dd, x)
+    torch.cuda.synchronize()
+    res["plain_query_events_per_s"] = len(qp) * n / (time.perf_counter() - w0)
+    res["served_over_plain"] = res["saturated_query_events_per_s"] / res["plain_query_events_per_s"]
+    log(f"serving: p50 {res['p50_ms']:.2f} ms, p99 {res['p99_ms']:.2f} ms, "
+        f"saturated {res['saturated_query_events_per_s']:.3e} vs plain {res['plain_query_events_per_s']:.3e}")
+    del t, dd
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +270,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-reps", type=int, default=4)
     ap.add_argument("--tune", type=str, default="", help="JSON launch configuration")
+    ap.add_argument("--sections", type=str, default="extended,batch,serving",
+                    help="comma list of extra sections to run (extended, batch, serving) or 'none'")
+    ap.add_argument("--serve-queries", type=int, default=1000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -179,6 +351,15 @@ def main():
         out["cpu_baseline"] = cpu_baseline(ds, q, args.cpu_reps)
         out["cpu_baseline"]["host_nproc"] = os.cpu_count()
         log(f"cpu oracle: {out['cpu_baseline']['value']:.3e} events/s")
+    del dd, ds
+    torch.cuda.empty_cache()
+    sections = [x for x in args.sections.split(",") if x and x != "none"]
+    if "extended" in sections:
+        out["extended"] = section_extended(args)
+    if "batch" in sections:
+        out["batch"] = section_batch(args)
+    if "serving" in sections:
+        out["serving"] = section_serving(args)
     print(json.dumps(out), flush=True)
 
 

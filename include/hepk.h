@@ -239,12 +239,12 @@ int hepk_plan_create_ex(const hepk_dataset *ds /* host, n_ds */, int32_t n_ds,
 
 /* Replaces the query in slot `slot` (q NULL: the slot goes idle and is
  * skipped).  The new thresholds and edges are staged in the plan's pinned
- * host memory and copied on `stream`, so launches enqueued on that stream
- * afterwards see the new query and earlier ones the old.  The slot's
- * histogram blocks stay where they are; with reserve_bins > 0 the blocks have
- * reserve_bins + 2 slots of which the first nbins + 2 are used.  A slot must
- * not be set again before the previous update of that slot has executed (the
- * staging area is per slot). */
+ * host memory (a ring of 32 staging areas, each reused only after its
+ * previous copy has executed) and copied on `stream`, so launches enqueued on
+ * that stream afterwards see the new query and earlier ones the old.  The
+ * slot's histogram blocks stay where they are; with reserve_bins > 0 the
+ * blocks have reserve_bins + 2 slots of which the first nbins + 2 are used.
+ * Updates and launches of one plan must go to one stream. */
 int hepk_plan_set_query(hepk_plan p, int32_t slot, const hepk_query *q /* host, nullable */,
                         hipStream_t stream);
 

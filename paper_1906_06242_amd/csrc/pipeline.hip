@@ -209,6 +209,11 @@ struct WaveLds {
     uint16_t mpre[C::MC + 1];        // selected muons before muon m
     uint16_t epre[EXT ? C::EC + 1 : 1];
     uint8_t bt[EXT ? C::JC : 1];
+    // per event, for queries with several jet-energy scales: jet range
+    // (first | end << 16), selected muons, weight
+    uint32_t evjr[C::TW];
+    uint16_t evnmu[C::TW];
+    float evw[C::TW];
 };
 
 struct TileBounds {
@@ -479,46 +484,85 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
                 }
                 wave_sync();
                 // ---- 5. per-event reductions, event cut, fills
+                // Walk an event's jets in order for one scale s: left-to-right
+                // float32 H_T over the selected ones, their count and maximum.
+                // Branch-free, two jets per step (both LDS reads in flight);
+                // adding only selected x keeps the sum order of the definition,
+                // and the maximum is updated on a strict '>', which keeps the
+                // first of equal values, as the definition does.
+                auto walk = [&](int j0, int j1, float s, float &ht, float &lead, int &njs, int &nbt) {
+                    njs = 0;
+                    nbt = 0;
+                    ht = 0.0f;
+                    lead = -INFINITY;
+                    auto step = [&](float x, int k) {
+                        const bool sel = x > Q.jet_pt;
+                        const float hs = ht + x;
+                        ht = sel ? hs : ht;
+                        lead = (sel && x > lead) ? x : lead;
+                        njs += sel ? 1 : 0;
+                        if (EXT) nbt += sel ? L.bt[k] : 0;
+                    };
+                    int k = j0;
+                    for (; k + 2 <= j1; k += 2) {
+                        const float x0 = L.jr[k].pt * s, x1 = L.jr[k + 1].pt * s;
+                        step(x0, k);
+                        step(x1, k + 1);
+                    }
+                    if (k < j1) step(L.jr[k].pt * s, k);
+                };
+                auto fill = [&](int v, float ht, float lead, int njs, double w) {
+                    // separate calls so each knows its address space (LDS or
+                    // global) and reads the edges without flat loads
+                    if (P.edges_in_lds)
+                        fill3(sink, Q, e_s, v, ht, lead, njs, w);
+                    else
+                        fill3(sink, Q, P.edges, v, ht, lead, njs, w);
+                };
+                if (Q.n_scale == 1) {
+                    const float s = as_const(P.scales)[Q.scale0];
 #pragma unroll
-                for (int r = 0; r < EVPL; ++r) {
-                    const int ev = lane + 64 * r;
-                    if (ev < ne) {
-                        const double w = static_cast<double>(wv[r]);
-                        for (int v = 0; v < Q.n_scale; ++v) {
-                            const float s = as_const(P.scales)[Q.scale0 + v];
-                            // Walk the event's jets in order: left-to-right float32 H_T
-                            // over the selected ones, their count and maximum.  Written
-                            // branch-free, two jets per step (both LDS reads in flight);
-                            // adding only selected x keeps the sum order of the
-                            // definition.  The maximum is updated on a strict '>', which keeps the
-                            // first of equal values, as the definition does.
-                            int njs = 0, nbt = 0;
-                            float ht = 0.0f, lead = -INFINITY;
-                            auto step = [&](float x, int k) {
-                                const bool sel = x > Q.jet_pt;
-                                const float hs = ht + x;
-                                ht = sel ? hs : ht;
-                                lead = (sel && x > lead) ? x : lead;
-                                njs += sel ? 1 : 0;
-                                if (EXT) nbt += sel ? L.bt[k] : 0;
-                            };
-                            int k = jb[r];
-                            for (; k + 2 <= je[r]; k += 2) {
-                                const float x0 = L.jr[k].pt * s, x1 = L.jr[k + 1].pt * s;
-                                step(x0, k);
-                                step(x1, k + 1);
-                            }
-                            if (k < je[r]) step(L.jr[k].pt * s, k);
-                            const bool pass =
-                                nmu[r] >= Q.min_mu && njs >= Q.min_jet && (!has_bt || nbt >= Q.min_b);
-                            if (pass) {
-                                // separate calls so each knows its address space (LDS or
-                                // global) and reads the edges without flat loads
-                                if (P.edges_in_lds)
-                                    fill3(sink, Q, e_s, v, ht, lead, njs, w);
-                                else
-                                    fill3(sink, Q, P.edges, v, ht, lead, njs, w);
-                            }
+                    for (int r = 0; r < EVPL; ++r) {
+                        const int ev = lane + 64 * r;
+                        if (ev < ne) {
+                            float ht, lead;
+                            int njs, nbt;
+                            walk(jb[r], je[r], s, ht, lead, njs, nbt);
+                            if (nmu[r] >= Q.min_mu && njs >= Q.min_jet && (!has_bt || nbt >= Q.min_b))
+                                fill(0, ht, lead, njs, static_cast<double>(wv[r]));
+                        }
+                    }
+                } else {
+                    // Several scales: lanes take (event, scale) pairs, event-major,
+                    // so one round covers a few events (shorter divergent walks)
+                    // and its fills spread over different histograms.
+#pragma unroll
+                    for (int r = 0; r < EVPL; ++r) {
+                        const int ev = lane + 64 * r;
+                        if (ev < ne) {
+                            L.evjr[ev] = static_cast<uint32_t>(jb[r]) | (static_cast<uint32_t>(je[r]) << 16);
+                            L.evnmu[ev] = static_cast<uint16_t>(nmu[r]);
+                            L.evw[ev] = wv[r];
+                        }
+                    }
+                    wave_sync();
+                    const int V = Q.n_scale;
+                    const int npairs = ne * V;
+                    int e = lane / V, v = lane - (lane / V) * V;
+                    const int de = 64 / V, dv = 64 - (64 / V) * V;
+                    for (int i = lane; i < npairs; i += 64) {
+                        const uint32_t jr = L.evjr[e];
+                        float ht, lead;
+                        int njs, nbt;
+                        walk(static_cast<int>(jr & 0xffffu), static_cast<int>(jr >> 16), P.scales[Q.scale0 + v], ht,
+                             lead, njs, nbt);
+                        if (L.evnmu[e] >= Q.min_mu && njs >= Q.min_jet && (!has_bt || nbt >= Q.min_b))
+                            fill(v, ht, lead, njs, static_cast<double>(L.evw[e]));
+                        e += de;
+                        v += dv;
+                        if (v >= V) {
+                            v -= V;
+                            e += 1;
                         }
                     }
                 }
@@ -578,7 +622,10 @@ static KernelFn pick_kernel(int dtype, bool ext, int block, int evpt, bool ldsh)
     return ext ? pick_shape<float, true>(block, evpt, ldsh) : pick_shape<float, false>(block, evpt, ldsh);
 }
 
-constexpr int kMaxLdsHistBytes = 32 * 1024;
+// LDS for the workgroup's private histograms: up to 64 KiB (60 histograms of
+// 100 bins fit); larger sets go to global atomics.  More LDS lowers occupancy,
+// which the launch-configuration search weighs against atomic contention.
+constexpr int kMaxLdsHistBytes = 64 * 1024;
 constexpr int kMaxLdsEdgeBytes = 4 * 1024;
 
 }  // namespace hepk

@@ -286,3 +286,89 @@ def draw_queries(seed: int, n: int, qps: float = 50.0) -> List[Query]:
                          edges_lead=uniform_edges(int(nb_lead[i]), 0.0, 1000.0),
                          arrival=float(t[i])))
     return out
+
+
+# ---------------------------------------------------------------------------
+# on-device generation for the large workloads
+# ---------------------------------------------------------------------------
+
+DEVICE_CHUNK = 1 << 22  # events per independently seeded device chunk
+
+
+def make_dataset_device(seed: int, n_events: int, extended: bool = False,
+                        content_dtype: str = "f32", device: str = "cuda"):
+    """The same distributions drawn on the GPU (torch Philox streams).
+
+    Chunk c of seed s uses generator seed s * 1_000_003 + c; draws are float64,
+    cast once to the storage dtype.  Returns a dict of device tensors with the
+    keys of paper_1906_06242_amd.hepk.DeviceDataset ("jets.offsets",
+    "jets.pt", ..., "weight") plus "n_events".  A different random stream
+    from make_dataset (which draws on the host), so the two generators give
+    different events with the same distributions.
+    """
+    import torch
+    dev = device
+    cdt = torch.float16 if content_dtype == "f16" else torch.float32
+    parts = {}
+    bases = {"jets": 0, "muons": 0, "electrons": 0}
+    names = {"jets": ["pt", "eta", "phi", "mass"] + (["btag"] if extended else []),
+             "muons": ["pt", "eta", "phi", "mass", "iso"],
+             "electrons": ["pt", "eta", "phi", "mass"]}
+    colls = ["jets", "muons"] + (["electrons"] if extended else [])
+    rates = {"jets": (5.0, 20), "muons": (1.5, 8), "electrons": (0.8, 8)}
+    for c in range((n_events + DEVICE_CHUNK - 1) // DEVICE_CHUNK):
+        n = min(DEVICE_CHUNK, n_events - c * DEVICE_CHUNK)
+        g = torch.Generator(device=dev)
+        g.manual_seed(seed * 1_000_003 + c)
+        counts = {}
+        for name in colls:
+            lam, cap = rates[name]
+            k = torch.poisson(torch.full((n,), lam, dtype=torch.float64, device=dev), generator=g)
+            counts[name] = torch.clamp(k, max=cap).to(torch.int64)
+        w = torch.empty(n, dtype=torch.float64, device=dev).normal_(1.0, 0.1, generator=g)
+        parts.setdefault("weight", []).append(w.to(torch.float32))
+        for name in colls:
+            m = int(counts[name].sum())
+            off = torch.cumsum(counts[name], 0) + bases[name]
+            parts.setdefault(f"{name}.offsets", []).append(off)
+            bases[name] += m
+            pt = 20.0 + torch.empty(m, dtype=torch.float64, device=dev).exponential_(1.0 / 30.0, generator=g)
+            eta = torch.clamp(torch.empty(m, dtype=torch.float64, device=dev).normal_(0.0, 1.5, generator=g), -4.7, 4.7)
+            phi = torch.empty(m, dtype=torch.float64, device=dev).uniform_(-math.pi, math.pi, generator=g)
+            mass = torch.empty(m, dtype=torch.float64, device=dev).uniform_(0.0, 20.0, generator=g)
+            cols = {"pt": pt, "eta": eta, "phi": phi, "mass": mass}
+            if name == "muons":
+                cols["iso"] = torch.empty(m, dtype=torch.float64, device=dev).exponential_(1.0 / 0.1, generator=g)
+            if name == "jets" and extended:
+                a = torch._standard_gamma(torch.full((m,), 0.5, dtype=torch.float64, device=dev), generator=g)
+                b = torch._standard_gamma(torch.full((m,), 2.0, dtype=torch.float64, device=dev), generator=g)
+                cols["btag"] = a / (a + b)
+            for k in names[name]:
+                parts.setdefault(f"{name}.{k}", []).append(cols[k].to(cdt))
+    out = {"n_events": n_events, "content_dtype": content_dtype}
+    for key, lst in parts.items():
+        if key.endswith(".offsets"):
+            out[key] = torch.cat([torch.zeros(1, dtype=torch.int64, device=dev)] + lst)
+        else:
+            out[key] = torch.cat(lst) if lst else torch.zeros(0, device=dev)
+    if n_events == 0:
+        for name in colls:
+            out[f"{name}.offsets"] = torch.zeros(1, dtype=torch.int64, device=dev)
+    return out
+
+
+def host_slice(dev_ds: dict, e0: int, e1: int) -> Dataset:
+    """Host copy of events [e0, e1) of an on-device dataset (offsets rebased)."""
+    colls = [c for c in ("jets", "muons", "electrons") if f"{c}.offsets" in dev_ds]
+    built = {}
+    for name in colls:
+        off = dev_ds[f"{name}.offsets"][e0:e1 + 1].cpu().numpy()
+        a, b = int(off[0]), int(off[-1])
+        cols = {}
+        for key, t in dev_ds.items():
+            if isinstance(key, str) and key.startswith(name + ".") and not key.endswith(".offsets"):
+                cols[key.split(".", 1)[1]] = t[a:b].cpu().numpy()
+        built[name] = Collection(off - a, cols)
+    w = dev_ds["weight"][e0:e1].cpu().numpy()
+    return Dataset(e1 - e0, built["jets"], built["muons"], w, built.get("electrons"),
+                   dev_ds.get("content_dtype", "f32"))

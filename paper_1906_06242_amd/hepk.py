@@ -221,14 +221,23 @@ def validate_offsets(offsets, n_objects: int, stream=None) -> int:
 # ---------------------------------------------------------------- fused pass
 
 class DeviceDataset:
-    """A datagen.Dataset with every column resident in device memory."""
+    """Event columns resident in device memory.
 
-    def __init__(self, ds, device="cuda"):
+    Built from a datagen.Dataset (host arrays are uploaded) or, with
+    from_tensors, from device tensors keyed "jets.offsets", "jets.pt", ...,
+    "weight".  view(e0, e1) is events [e0, e1) without copying: the offsets
+    pointers move by e0 and still index the full content arrays.
+    """
+
+    def __init__(self, ds=None, device="cuda"):
         import numpy as np
         import torch
+        self.tensors: Dict[str, "torch.Tensor"] = {}
+        self.e0 = 0
+        if ds is None:
+            return
         self.n_events = ds.n_events
         self.content_dtype = ds.content_dtype
-        self.tensors: Dict[str, "torch.Tensor"] = {}
         for cname, coll in ds.collections():
             self.tensors[f"{cname}.offsets"] = torch.from_numpy(coll.offsets).to(device)
             for k, v in coll.cols.items():
@@ -239,22 +248,48 @@ class DeviceDataset:
                 self.tensors[f"{cname}.{k}"] = torch.from_numpy(v).to(device)
         w = ds.weight if ds.weight.size else np.ones(1, np.float32)
         self.tensors["weight"] = torch.from_numpy(w).to(device)
-        self.has_electrons = ds.electrons is not None
+
+    @classmethod
+    def from_tensors(cls, t: dict) -> "DeviceDataset":
+        import torch
+        d = cls()
+        d.n_events = int(t["n_events"])
+        d.content_dtype = t.get("content_dtype", "f32")
+        for k, v in t.items():
+            if isinstance(v, torch.Tensor):
+                if v.numel() == 0:
+                    v = torch.zeros(1, dtype=v.dtype, device=v.device)
+                d.tensors[k] = v
+        return d
+
+    def view(self, e0: int, e1: int) -> "DeviceDataset":
+        d = DeviceDataset()
+        d.tensors = self.tensors
+        d.content_dtype = self.content_dtype
+        d.n_events = e1 - e0
+        d.e0 = self.e0 + e0
+        return d
+
+    @property
+    def has_electrons(self) -> bool:
+        return "electrons.offsets" in self.tensors
 
     def t(self, key):
         return self.tensors.get(key)
 
     def struct(self) -> DatasetS:
         def coll(name, extra):
-            if self.t(f"{name}.offsets") is None:
+            off = self.t(f"{name}.offsets")
+            if off is None:
                 return Collection(None, None, None, None, None)
-            return Collection(_ptr(self.t(f"{name}.offsets")), _ptr(self.t(f"{name}.pt")),
+            return Collection(_ptr(off) + 8 * self.e0, _ptr(self.t(f"{name}.pt")),
                               _ptr(self.t(f"{name}.eta")), _ptr(self.t(f"{name}.phi")),
                               _ptr(self.t(f"{name}.{extra}")) if extra else None)
+        w = self.t("weight")
         return DatasetS(self.n_events, F16 if self.content_dtype == "f16" else F32,
                         coll("jets", "btag" if self.t("jets.btag") is not None else None),
-                        coll("muons", "iso"), coll("electrons", None), _ptr(self.t("weight")))
-
+                        coll("muons", "iso"), coll("electrons", None),
+                        _ptr(w) + 4 * self.e0 if w is not None else None)
 
 
 def query_struct(q, keep: list) -> QueryS:
