@@ -2,19 +2,20 @@
 // kernel), accumulating into the caller's histogram.
 //
 // Each workgroup keeps a private copy of the histogram in LDS (float64 sums
-// via ds_add_f64, uint32 counts via ds_add_u32), walks a grid-stride range of
-// rows, and merges its non-empty slots into HBM with global atomics at the
-// end.  Histograms too large for LDS go straight to global atomics.  Sums of
-// float64 weights are exact in any order while every partial sum is a
-// multiple of the smallest weight's ulp below 2^53 of it, which holds for the
-// float32 weights of this analysis; otherwise the order changes only the
-// last bits.
+// via ds_add_f64, uint32 counts via ds_add_u32) together with the bin edges,
+// walks a grid-stride range of rows four at a time (loads of the four rows in
+// flight together), and merges its non-empty slots into HBM with global
+// atomics at the end.  Histograms too large for LDS go straight to global
+// atomics with the edges read from HBM.  Sums of float64 weights are exact in
+// any order while every partial sum is a multiple of the smallest weight's ulp
+// below 2^53 of it, which holds for the float32 weights of this analysis;
+// otherwise the order changes only the last bits.
 #include "common.hpp"
 
 namespace hepk {
 
 constexpr int HB = 256;
-constexpr int kMaxLdsSlots = 4096;  // 48 KiB of LDS per workgroup
+constexpr int kMaxLdsSlots = 3000;  // 36 KiB of histogram + 12 KiB of edges
 
 template <typename X, bool LDS>
 __global__ __launch_bounds__(HB) void hist_kernel(const X *__restrict__ x, const float *__restrict__ w,
@@ -22,42 +23,64 @@ __global__ __launch_bounds__(HB) void hist_kernel(const X *__restrict__ x, const
                                                   const float *__restrict__ edges, int nbins,
                                                   double *__restrict__ sumw, uint64_t *__restrict__ counts) {
     extern __shared__ double hist_lds[];
-    // start values of the bin guess (verified against the edges in hist_slot)
-    const float lo = edges[0];
-    const float span = edges[nbins] - lo;
-    const float inv_w = (span > 0.0f && span < INFINITY) ? static_cast<float>(nbins) / span : 0.0f;
     const int nslots = nbins + 2;
     double *sw_s = hist_lds;
     uint32_t *c_s = reinterpret_cast<uint32_t *>(hist_lds + (LDS ? nslots : 0));
+    float *e_s = reinterpret_cast<float *>(c_s + (LDS ? nslots : 0));
+    // end edges and the bin-guess start values (the guess is verified against the edges)
+    const float lo = as_const(edges)[0];
+    const float hi = as_const(edges)[nbins];
+    const float span = hi - lo;
+    const float inv_w = (span > 0.0f && span < INFINITY) ? static_cast<float>(nbins) / span : 0.0f;
     if (LDS) {
         for (int i = threadIdx.x; i < nslots; i += HB) {
             sw_s[i] = 0.0;
             c_s[i] = 0u;
         }
+        for (int i = threadIdx.x; i <= nbins; i += HB) e_s[i] = edges[i];
         __syncthreads();
     }
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * HB;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * HB + threadIdx.x; i < n; i += stride) {
-        if (m && !m[i]) continue;
-        const float v = static_cast<float>(x[i]);
-        if (v != v) continue;
-        const int s = hist_slot(v, edges, nbins, lo, inv_w);
-        const double wt = w ? static_cast<double>(w[i]) : 1.0;
+    auto one = [&](float v, double wt) {
+        if (v != v) return;
         if (LDS) {
+            const int s = hist_slot_lohi(v, e_s, nbins, lo, hi, inv_w);
             atomic_add_f64(&sw_s[s], wt);
             atomicAdd(&c_s[s], 1u);
         } else {
+            const int s = hist_slot_lohi(v, edges, nbins, lo, hi, inv_w);
             atomic_add_f64(&sumw[s], wt);
             atomic_add_u64(&counts[s], 1u);
         }
+    };
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * HB;
+    int64_t i = static_cast<int64_t>(blockIdx.x) * HB + threadIdx.x;
+    // four rows per step, loads first
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        float v[4];
+        double wt[4];
+        bool keep[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t r = i + u * stride;
+            keep[u] = !m || m[r] != 0;
+            v[u] = static_cast<float>(x[r]);
+            wt[u] = w ? static_cast<double>(w[r]) : 1.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (keep[u]) one(v[u], wt[u]);
+    }
+    for (; i < n; i += stride) {
+        if (m && !m[i]) continue;
+        one(static_cast<float>(x[i]), w ? static_cast<double>(w[i]) : 1.0);
     }
     if (LDS) {
         __syncthreads();
-        for (int i = threadIdx.x; i < nslots; i += HB) {
-            const uint32_t c = c_s[i];
+        for (int k = threadIdx.x; k < nslots; k += HB) {
+            const uint32_t c = c_s[k];
             if (c) {
-                atomic_add_u64(&counts[i], c);
-                atomic_add_f64(&sumw[i], sw_s[i]);
+                atomic_add_u64(&counts[k], c);
+                atomic_add_f64(&sumw[k], sw_s[k]);
             }
         }
     }
@@ -69,9 +92,11 @@ static int launch_hist(const void *x, const float *w, const uint8_t *m, int64_t 
     const int nslots = h->nbins + 2;
     const bool lds = nslots <= kMaxLdsSlots;
     const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n, HB * 16), 4 * device_cus()));
+    const size_t lds_bytes = static_cast<size_t>(nslots) * (sizeof(double) + sizeof(uint32_t)) +
+                             static_cast<size_t>(h->nbins + 1) * sizeof(float);
     if (lds)
-        hist_kernel<X, true><<<grid, HB, nslots * (sizeof(double) + sizeof(uint32_t)), stream>>>(
-            static_cast<const X *>(x), w, m, n, h->edges, h->nbins, h->sumw, h->counts);
+        hist_kernel<X, true><<<grid, HB, lds_bytes, stream>>>(static_cast<const X *>(x), w, m, n, h->edges,
+                                                              h->nbins, h->sumw, h->counts);
     else
         hist_kernel<X, false><<<grid, HB, 0, stream>>>(static_cast<const X *>(x), w, m, n, h->edges, h->nbins,
                                                        h->sumw, h->counts);

@@ -107,9 +107,10 @@ struct HistSink {
     }
 };
 
-// Fills H_T, lead and nJet of one passing event for scale v of query Q.
-template <bool LDSH>
-__device__ __forceinline__ void fill3(const HistSink<LDSH> &sink, const QDev &Q, const float *edges, int v,
+// Fills H_T, lead and nJet of one passing event for scale v of query Q (a
+// table entry read in place, so its fields are fetched where they are used).
+template <bool LDSH, typename QT>
+__device__ __forceinline__ void fill3(const HistSink<LDSH> &sink, const QT &Q, const float *edges, int v,
                                       float ht, float lead, int nj, double w) {
     const int base = LDSH ? Q.lslot0 + v * Q.lper_scale : Q.gslot0 + v * Q.gper_scale;
     const float xs[3] = {ht, lead, static_cast<float>(nj)};
@@ -220,8 +221,8 @@ struct TileBounds {
     int64_t J0, J1, M0, M1, L0, L1;
 };
 
-template <bool EXT>
-__device__ __forceinline__ TileBounds tile_bounds(const DsDev &D, bool has_el, int64_t e0, int ne) {
+template <bool EXT, typename DT>
+__device__ __forceinline__ TileBounds tile_bounds(const DT &D, bool has_el, int64_t e0, int ne) {
     TileBounds b;
     b.J0 = as_const(D.joff)[e0];
     b.J1 = as_const(D.joff)[e0 + ne];
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
 
     for (int ci = P.chunk_begin + blockIdx.x; ci < P.chunk_end; ci += gridDim.x) {
         const Chunk CH = as_const(P.chunks)[ci];
-        const DsDev D = as_const(P.ds)[CH.d];
+        const auto &D = as_const(P.ds)[CH.d];  // read in place, like the query table
         HistSink<LDSH> sink;
         if (LDSH) {
             sink.sw = sw_s;
@@ -318,10 +319,11 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
                 nb = tile_bounds<EXT>(D, has_el, e1, static_cast<int>(min<int64_t>(TW, D.n_events - e1)));
             }
             if (B.J1 - B.J0 > C::JC || B.M1 - B.M0 > C::MC || B.L1 - B.L0 > C::EC) {
+                const DsDev Dc = D;
 #pragma unroll
                 for (int r = 0; r < EVPL; ++r) {
                     const int ev = lane + 64 * r;
-                    if (ev < ne) event_direct<T, EXT, LDSH>(P, D, e0 + ev, edges, sink);
+                    if (ev < ne) event_direct<T, EXT, LDSH>(P, Dc, e0 + ev, edges, sink);
                 }
                 continue;
             }
@@ -415,7 +417,10 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(6)))
             }
 
             for (int q = 0; q < P.n_q; ++q) {
-                const QDev Q = as_const(P.qs)[q];
+                // the query's fields are read in place (scalar loads near their
+                // uses) rather than copied: a copy would hold ~45 SGPRs for the
+                // whole query and spill
+                const auto &Q = as_const(P.qs)[q];
                 if (!Q.active) continue;
                 // ---- 2. lepton selection; selected leptons compacted into LDS
                 {
