@@ -193,7 +193,8 @@ typedef struct hepk_query {
     float dr, btag;
     int32_t min_mu, min_jet, min_b;
     int32_t n_scale;                 /* >= 1 */
-    const float *scales;             /* (host) n_scale jet-energy-scale factors */
+    const float *scales;             /* (host) n_scale jet-energy-scale factors, each
+                                        positive and finite (else HEPK_EINVAL) */
     const float *edges[3];           /* (host) H_T, lead, nJet bin edges, nbins+1 each,
                                         strictly increasing; copied into the plan */
     int32_t nbins[3];

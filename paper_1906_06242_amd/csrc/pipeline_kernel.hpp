@@ -1,0 +1,801 @@
+// The fused analysis kernel of hepk_pipeline and its launch-shape table,
+// shared by the translation units that instantiate it.
+//
+// The whole analysis pass of Sec. IV (object selection,
+// lepton-jet Delta-R cleaning, per-event reductions, event selection,
+// weighted histograms, jet-energy-scale variations) fused into one
+// persistent kernel, for any number of datasets and queries at once.
+//
+// Sec. IV observes that hundreds of small kernel calls per pass left the GPU
+// half idle and names fusion as the fix; here every intermediate (object
+// masks, per-event counts and sums, event masks) lives in registers and LDS,
+// so a pass reads each input column from HBM once and writes only the
+// histograms.
+//
+// Work decomposition.  Each wavefront owns tiles of TW = 64 * EVPL
+// consecutive events and works through them without waiting for the other
+// wavefronts of its workgroup (no workgroup barrier inside a tile: the four
+// or eight wavefronts of a workgroup only share the LDS histograms, updated
+// with atomics).  The host cuts every dataset's tiles into chunks; a
+// workgroup takes whole chunks, so a chunk never mixes datasets and the LDS
+// histograms are merged into HBM only when the workgroup moves to another
+// dataset.  For one tile a wavefront
+//   1. reads the tile's object ranges with scalar loads, then issues all of
+//      its loads at once -- offsets and weight of its events, up to JK jets,
+//      MK muons and EK electrons per lane (consecutive lanes, consecutive
+//      objects: coalesced) -- into registers, and waits once;
+//   2. puts the offsets in LDS (tile-relative int32) and lets each event lane
+//      write its event index over its jets (the jet -> event map);
+//   3. per query: muon lanes evaluate the muon cuts and stage eta/phi in LDS,
+//      eta = NaN for muons that fail (a NaN dR^2 never passes the cone test,
+//      which is the same as skipping them); electrons likewise;
+//   4. jet lanes test the cone against their event's staged leptons and store
+//      pt (or NaN when removed or outside |eta|) in LDS;
+//   5. event lanes walk their jets in order: ptv = pt * s, the jet cut, the
+//      count, the left-to-right float32 H_T, the maximum, the b-tag count;
+//      then the event cut and three fills into the workgroup's LDS
+//      histograms (float64 sums, uint32 counts).  With several jet-energy
+//      scales a lane takes an (event, group of kG scales) pair instead and
+//      one walk serves the group.  The bins of all of a lane's fills are
+//      found together (guesses, then every edge read, then the check).
+// Steps 2-5 exchange data through the wavefront's own LDS region; a
+// wavefront's LDS operations complete in issue order, so only compiler
+// ordering fences are needed between them.  A tile whose objects exceed the
+// register capacity (a 5-sigma fluctuation for the paper's multiplicities,
+// always possible for arbitrary input) is processed one lane per event
+// straight from HBM with the same arithmetic.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+#include <vector>
+
+#include "common.hpp"
+
+namespace hepk {
+
+struct DsDev {
+    int64_t n_events;
+    const int64_t *joff, *moff, *eoff;
+    const void *jpt, *jeta, *jphi, *jbt;
+    const void *mpt, *meta, *mphi, *miso;
+    const void *ept, *eeta, *ephi;
+    const float *w;
+    int64_t hist0;  // first slot of this dataset's block of histograms
+};
+
+struct QDev {
+    float mu_pt, mu_abseta, mu_iso, el_pt, el_abseta, jet_pt, jet_abseta, thr2, btag;
+    int32_t min_mu, min_jet, min_b;
+    int32_t n_scale, scale0;
+    int32_t active;      // 0: idle query slot, skipped
+    int32_t nbins[3];
+    int32_t ebase[3];    // first edge of each observable in the plan's edge table
+    float lo[3], hi[3];  // first and last edge of each observable
+    float inv_w[3];      // nbins / (hi - lo): start value of the bin search
+    // Histogram of (scale v, observable h) starts at slot0 + v * per_scale +
+    // hoff[h]: in the workgroup's LDS copy (compact over the active queries)
+    // and in the dataset's block in HBM (fixed per query slot).
+    int32_t lslot0, lper_scale, lhoff[3];
+    int32_t gslot0, gper_scale, ghoff[3];
+};
+
+struct Chunk {
+    int32_t d, pad;
+    int64_t t0, t1;  // tiles [t0, t1) of dataset d
+};
+
+struct PipeArgs {
+    const DsDev *ds;
+    const QDev *qs;
+    const float *scales;
+    const Chunk *chunks;
+    const float *edges;  // all queries' bin edges, concatenated
+    int32_t chunk_begin, chunk_end;  // chunks [chunk_begin, chunk_end) of `chunks`
+    int32_t n_q, ds_slots, n_edges, edges_in_lds;  // ds_slots: LDS histogram slots
+    int32_t n_scales, scales_in_lds;               // the scale table, copied to LDS when small
+    double *sumw;
+    uint64_t *counts;
+};
+
+template <bool LDSH>
+struct HistSink {
+    double *sw;        // LDS (LDSH) or the dataset's block in HBM
+    uint32_t *c32;     // LDS (LDSH)
+    uint64_t *c64;     // HBM (!LDSH)
+
+    __device__ __forceinline__ void add(int slot, double w) const {
+        if (LDSH) {
+            atomic_add_f64(&sw[slot], w);
+            atomicAdd(&c32[slot], 1u);
+        } else {
+            atomic_add_f64(&sw[slot], w);
+            atomic_add_u64(&c64[slot], 1u);
+        }
+    }
+};
+
+// Histogram constants of one query, read once per query and held in
+// registers: they are uniform, and without the pin the compiler reloads each
+// field from memory (and waits for it) next to every use.
+struct FillC {
+    int32_t base, per;       // first slot of scale 0, slots per scale (LDS or global layout)
+    int32_t nb[3], eb[3], off[3];
+    float lo[3], hi[3], iw[3];
+};
+
+template <typename X>
+__device__ __forceinline__ X pin(X x) {
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
+template <bool LDSH, typename QT>
+__device__ __forceinline__ FillC fill_consts(const QT &Q) {
+    FillC F;
+    F.base = pin<int32_t>(LDSH ? Q.lslot0 : Q.gslot0);
+    F.per = pin<int32_t>(LDSH ? Q.lper_scale : Q.gper_scale);
+#pragma unroll
+    for (int h = 0; h < 3; ++h) {
+        F.nb[h] = pin<int32_t>(Q.nbins[h]);
+        F.eb[h] = pin<int32_t>(Q.ebase[h]);
+        F.off[h] = pin<int32_t>(LDSH ? Q.lhoff[h] : Q.ghoff[h]);
+        F.lo[h] = pin<float>(Q.lo[h]);
+        F.hi[h] = pin<float>(Q.hi[h]);
+        F.iw[h] = pin<float>(Q.inv_w[h]);
+    }
+    return F;
+}
+
+// Edges E[0..nbins] strictly increasing, E[0] <= x < E[nbins]: the slot of x.
+__device__ __forceinline__ int bin_search(const float *E, int nbins, float x) {
+    int a = 0, b = nbins;  // E[a] <= x < E[b]
+    while (b - a > 1) {
+        const int m = (a + b) >> 1;
+        if (E[m] <= x)
+            a = m;
+        else
+            b = m;
+    }
+    return a + 1;
+}
+
+// Slots of N values, x[n] going to observable n % 3 (H_T, lead, nJet): the
+// same slot as hist_slot_lohi, computed for all N at once -- every guess,
+// then every edge pair read (one LDS round trip for all of them), then the
+// check, with a binary search only where the guess was off (rounding at an
+// edge, or non-uniform edges).
+template <int N>
+__device__ __forceinline__ void find_bins(const FillC &F, const float *edges, const float (&x)[N], int (&s)[N]) {
+    int k[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const int h = n % 3;
+        const float g = (x[n] - F.lo[h]) * F.iw[h];
+        const int gi = g >= 0.0f ? (g < static_cast<float>(F.nb[h]) ? static_cast<int>(g) + 1 : F.nb[h]) : 1;
+        s[n] = !(x[n] >= F.lo[h]) ? 0 : (x[n] >= F.hi[h] ? F.nb[h] + 1 : gi);
+        k[n] = F.eb[h] + ((s[n] >= 1 && s[n] <= F.nb[h]) ? s[n] : 1);
+    }
+    float a[N], b[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        a[n] = edges[k[n] - 1];
+        b[n] = edges[k[n]];
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const int h = n % 3;
+        if (s[n] >= 1 && s[n] <= F.nb[h] && (x[n] < a[n] || x[n] >= b[n]))
+            s[n] = bin_search(edges + F.eb[h], F.nb[h], x[n]);
+    }
+}
+
+// Fills H_T, lead and nJet of one passing event for scale v of query Q (a
+// table entry read in place, so its fields are fetched where they are used).
+template <bool LDSH, typename QT>
+__device__ __forceinline__ void fill3(const HistSink<LDSH> &sink, const QT &Q, const float *edges, int v,
+                                      float ht, float lead, int nj, double w) {
+    const int base = LDSH ? Q.lslot0 + v * Q.lper_scale : Q.gslot0 + v * Q.gper_scale;
+    const float xs[3] = {ht, lead, static_cast<float>(nj)};
+#pragma unroll
+    for (int h = 0; h < 3; ++h) {
+        const float x = xs[h];
+        if (x != x) continue;
+        const int s = hist_slot_lohi(x, edges + Q.ebase[h], Q.nbins[h], Q.lo[h], Q.hi[h], Q.inv_w[h]);
+        sink.add(base + (LDSH ? Q.lhoff[h] : Q.ghoff[h]) + s, w);
+    }
+}
+
+// Orders this wavefront's LDS accesses around the point (LDS executes one
+// wavefront's operations in issue order, so no wait is needed, only that the
+// compiler keeps the order).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One event, one lane, columns read straight from HBM.
+template <typename T, bool EXT, bool LDSH>
+__device__ void event_direct(const PipeArgs &P, const DsDev &D, int64_t e, const float *edges,
+                             const HistSink<LDSH> &sink) {
+    const bool has_iso = D.miso != nullptr;
+    const bool has_el = EXT && D.eoff != nullptr;
+    const bool has_bt = EXT && D.jbt != nullptr;
+    const double w = D.w ? static_cast<double>(D.w[e]) : 1.0;
+    const int64_t j0 = D.joff[e], j1 = D.joff[e + 1];
+    const int64_t m0 = D.moff[e], m1 = D.moff[e + 1];
+    const int64_t l0 = has_el ? D.eoff[e] : 0, l1 = has_el ? D.eoff[e + 1] : 0;
+    const T *jpt = static_cast<const T *>(D.jpt), *jeta = static_cast<const T *>(D.jeta);
+    const T *jphi = static_cast<const T *>(D.jphi), *jbt = static_cast<const T *>(D.jbt);
+    const T *mpt = static_cast<const T *>(D.mpt), *meta = static_cast<const T *>(D.meta);
+    const T *mphi = static_cast<const T *>(D.mphi), *miso = static_cast<const T *>(D.miso);
+    const T *ept = static_cast<const T *>(D.ept), *eeta = static_cast<const T *>(D.eeta);
+    const T *ephi = static_cast<const T *>(D.ephi);
+    for (int q = 0; q < P.n_q; ++q) {
+        const QDev Q = as_const(P.qs)[q];
+        if (!Q.active) continue;
+        auto mu_sel = [&](int64_t m) {
+            return ldf(mpt, m) > Q.mu_pt && fabsf(ldf(meta, m)) < Q.mu_abseta &&
+                   (!has_iso || ldf(miso, m) < Q.mu_iso);
+        };
+        auto el_sel = [&](int64_t m) { return ldf(ept, m) > Q.el_pt && fabsf(ldf(eeta, m)) < Q.el_abseta; };
+        int nmu = 0;
+        for (int64_t m = m0; m < m1; ++m) nmu += mu_sel(m) ? 1 : 0;
+        for (int v = 0; v < Q.n_scale; ++v) {
+            const float s = as_const(P.scales)[Q.scale0 + v];
+            int nj = 0, nb = 0;
+            float ht = 0.0f, lead = -INFINITY;
+            for (int64_t j = j0; j < j1; ++j) {
+                const float x = ldf(jpt, j) * s;
+                const float eta = ldf(jeta, j);
+                if (!(x > Q.jet_pt && fabsf(eta) < Q.jet_abseta)) continue;
+                const float phi = ldf(jphi, j);
+                bool hit = false;
+                for (int64_t m = m0; m < m1 && !hit; ++m)
+                    hit = mu_sel(m) && delta_r2(eta, phi, ldf(meta, m), ldf(mphi, m)) <= Q.thr2;
+                for (int64_t m = l0; m < l1 && !hit; ++m)
+                    hit = el_sel(m) && delta_r2(eta, phi, ldf(eeta, m), ldf(ephi, m)) <= Q.thr2;
+                if (hit) continue;
+                if (nj == 0 || x > lead) lead = x;
+                ++nj;
+                ht = ht + x;
+                if (has_bt && ldf(jbt, j) > Q.btag) ++nb;
+            }
+            const bool pass = nmu >= Q.min_mu && nj >= Q.min_jet && (!has_bt || nb >= Q.min_b);
+            if (pass) fill3(sink, Q, edges, v, ht, lead, nj, w);
+        }
+    }
+}
+
+template <int EVPL, bool EXT>
+struct Caps {
+    static constexpr int TW = 64 * EVPL;             // events per wavefront tile
+    static constexpr int JK = 6 * EVPL + 1;          // jet slots per lane
+    static constexpr int MK = 2 * EVPL + 1;          // muon slots per lane
+    static constexpr int EK = EXT ? 2 * EVPL : 1;    // electron slots per lane
+    static constexpr int JC = 64 * JK, MC = 64 * MK, EC = 64 * EK;
+};
+
+// One wavefront's LDS.  jr holds, per jet, its event's range of selected
+// muons (first | count << 16) until the cone test reads it; the same word
+// then holds the jet's pt (or NaN) for the per-event walk.
+template <int EVPL, bool EXT>
+struct WaveLds {
+    using C = Caps<EVPL, EXT>;
+    union {
+        uint32_t rng;
+        float pt;
+    } jr[C::JC];
+    uint32_t jre[EXT ? C::JC : 1];   // same for selected electrons
+    float seta[C::MC], sphi[C::MC];  // selected muons, compacted in tile order
+    float sea[EXT ? C::EC : 1], sep[EXT ? C::EC : 1];
+    uint16_t mpre[C::MC + 1];        // selected muons before muon m
+    uint16_t epre[EXT ? C::EC + 1 : 1];
+    uint8_t bt[EXT ? C::JC : 1];
+    // eligible events (compacted), for queries with several jet-energy
+    // scales: jet range (first | end << 16) and weight
+    uint32_t evjr[C::TW];
+    float evw[C::TW];
+};
+
+// Adds weight w to the histograms of scales v0 + n / 3 (observable n % 3)
+// of the lanes whose pass[n / 3] is set; NaN values are not filled.
+template <int N, bool LDSH>
+__device__ __forceinline__ void fill_bins(const HistSink<LDSH> &sink, const FillC &F, const float *edges,
+                                          const float (&xs)[N], const bool (&pass)[N / 3], int v0, double w) {
+    int sl[N];
+    find_bins<N>(F, edges, xs, sl);
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+        if (pass[n / 3] && xs[n] == xs[n]) sink.add(F.base + (v0 + n / 3) * F.per + F.off[n % 3] + sl[n], w);
+}
+
+// Scales per lane in the walk over an event's jets when a query has several.
+constexpr int kG = 4;
+
+// Walks the jets [j0, j1) of one event in order (pt of each in LDS, NaN when
+// removed by the cone or |eta| cut) for G scales at once: per scale the
+// left-to-right float32 H_T of the selected jets (pt * s > jet_pt), their
+// count, b-tag count and maximum.  Adding only selected values keeps the sum
+// order of the definition.  The maximum needs no per-scale work: for s > 0,
+// rounding pt * s is monotone in pt, so the selected jets are those above a
+// pt bound and the largest selected pt * s is the largest cleaned pt times s
+// (rounded once), whenever any jet is selected.  Branch-free, two jets per
+// step (both LDS reads in flight).
+template <int G, bool EXT, typename WL>
+__device__ __forceinline__ void walk_jets(const WL &L, int j0, int j1, const float (&sc)[G], float jet_pt,
+                                          float (&ht)[G], float (&lead)[G], int (&nj)[G], int (&nb)[G]) {
+    float pmax = -INFINITY;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        ht[g] = 0.0f;
+        nj[g] = 0;
+        nb[g] = 0;
+    }
+    auto step = [&](float p, int bt) {
+        pmax = fmaxf(pmax, p);  // NaN (removed jet) leaves it unchanged
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const float x = p * sc[g];
+            const bool sel = x > jet_pt;
+            const float hs = ht[g] + x;
+            ht[g] = sel ? hs : ht[g];
+            nj[g] += sel ? 1 : 0;
+            if (EXT) nb[g] += sel ? bt : 0;
+        }
+    };
+    int k = j0;
+    for (; k + 2 <= j1; k += 2) {
+        const float p0 = L.jr[k].pt, p1 = L.jr[k + 1].pt;
+        const int b0 = EXT ? L.bt[k] : 0, b1 = EXT ? L.bt[k + 1] : 0;
+        step(p0, b0);
+        step(p1, b1);
+    }
+    if (k < j1) step(L.jr[k].pt, EXT ? static_cast<int>(L.bt[k]) : 0);
+#pragma unroll
+    for (int g = 0; g < G; ++g) lead[g] = nj[g] > 0 ? pmax * sc[g] : -INFINITY;
+}
+
+struct TileBounds {
+    int64_t J0, J1, M0, M1, L0, L1;
+};
+
+template <bool EXT, typename DT>
+__device__ __forceinline__ TileBounds tile_bounds(const DT &D, bool has_el, int64_t e0, int ne) {
+    TileBounds b;
+    b.J0 = as_const(D.joff)[e0];
+    b.J1 = as_const(D.joff)[e0 + ne];
+    b.M0 = as_const(D.moff)[e0];
+    b.M1 = as_const(D.moff)[e0 + ne];
+    b.L0 = (EXT && has_el) ? as_const(D.eoff)[e0] : 0;
+    b.L1 = (EXT && has_el) ? as_const(D.eoff)[e0 + ne] : 0;
+    return b;
+}
+
+// Compacts the selected objects of a tile (sel per slot k of this lane) into
+// (eta, phi) arrays in tile order; pre[m] = number of selected objects before
+// object m, pre[n] = total.
+template <int K>
+__device__ __forceinline__ void compact(const bool (&sel)[K], const float (&eta)[K], const float (&phi)[K], int n,
+                                        int lane, float *oeta, float *ophi, uint16_t *pre) {
+    int run = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int m = lane + 64 * k;
+        const uint64_t bal = __ballot(sel[k]);
+        const int before = run + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+                                     static_cast<uint32_t>(bal >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bal), 0u)));
+        if (m < n) pre[m] = static_cast<uint16_t>(before);
+        if (sel[k]) {
+            oeta[before] = eta[k];
+            ophi[before] = phi[k];
+        }
+        run += __popcll(bal);
+    }
+    if (lane == 0) pre[n] = static_cast<uint16_t>(run);
+}
+
+// MS: the plan has queries with several jet-energy scales (every query then
+// takes the scale-group walk of step 5; otherwise every query has one scale).
+// Occupancy targets: base schema, one scale: six wavefronts per SIMD (at most
+// 80 VGPRs), measured the best trade between latency hiding and the
+// registers that hold a tile in flight; extended schema: four (its
+// wavefronts need twice the LDS); several scales: two, which is what LDS
+// allows next to the histograms of 20 scales, so the walk and the fills
+// may use the registers for instruction-level parallelism instead.
+template <typename T, bool EXT, int WAVES, int EVPL, bool LDSH, bool MS>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(MS ? 2 : (EXT ? 4 : 6)))) void
+pipeline_kernel(PipeArgs P) {
+    using C = Caps<EVPL, EXT>;
+    constexpr int TW = C::TW, JK = C::JK, MK = C::MK, EK = C::EK;
+    __shared__ WaveLds<EVPL, EXT> wl[WAVES];
+    extern __shared__ double dyn[];  // [sumw | counts (u32) | edges | scales] per workgroup
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    auto &L = wl[wave];
+
+    double *sw_s = dyn;
+    uint32_t *c_s = reinterpret_cast<uint32_t *>(dyn + (LDSH ? P.ds_slots : 0));
+    float *e_s = reinterpret_cast<float *>(c_s + (LDSH ? P.ds_slots : 0));
+    if (LDSH) {
+        for (int i = tid; i < P.ds_slots; i += 64 * WAVES) {
+            sw_s[i] = 0.0;
+            c_s[i] = 0u;
+        }
+    }
+    float *s_s = e_s + (P.edges_in_lds ? P.n_edges : 0);
+    const float *edges = P.edges;
+    if (P.edges_in_lds) {
+        for (int i = tid; i < P.n_edges; i += 64 * WAVES) e_s[i] = as_const(P.edges)[i];
+        edges = e_s;
+    }
+    if (P.scales_in_lds)
+        for (int i = tid; i < P.n_scales; i += 64 * WAVES) s_s[i] = as_const(P.scales)[i];
+    __syncthreads();
+
+    for (int ci = P.chunk_begin + blockIdx.x; ci < P.chunk_end; ci += gridDim.x) {
+        const Chunk CH = as_const(P.chunks)[ci];
+        const auto &D = as_const(P.ds)[CH.d];  // read in place, like the query table
+        HistSink<LDSH> sink;
+        if (LDSH) {
+            sink.sw = sw_s;
+            sink.c32 = c_s;
+        } else {
+            sink.sw = P.sumw + D.hist0;
+            sink.c64 = P.counts + D.hist0;
+        }
+        const bool has_iso = D.miso != nullptr;
+        const bool has_el = EXT && D.eoff != nullptr;
+        const bool has_bt = EXT && D.jbt != nullptr;
+
+        // tile bounds are fetched one tile ahead (scalar loads that overlap
+        // the current tile's vector loads)
+        int64_t t = CH.t0 + wave;
+        TileBounds nb{};
+        if (t < CH.t1) {
+            const int64_t e0 = t * TW;
+            nb = tile_bounds<EXT>(D, has_el, e0, static_cast<int>(min<int64_t>(TW, D.n_events - e0)));
+        }
+        for (; t < CH.t1; t += WAVES) {
+            const int64_t e0 = t * TW;
+            const int ne = static_cast<int>(min<int64_t>(TW, D.n_events - e0));
+            const TileBounds B = nb;
+            if (t + WAVES < CH.t1) {
+                const int64_t e1 = (t + WAVES) * TW;
+                nb = tile_bounds<EXT>(D, has_el, e1, static_cast<int>(min<int64_t>(TW, D.n_events - e1)));
+            }
+            if (B.J1 - B.J0 > C::JC || B.M1 - B.M0 > C::MC || B.L1 - B.L0 > C::EC) {
+                const DsDev Dc = D;
+#pragma unroll
+                for (int r = 0; r < EVPL; ++r) {
+                    const int ev = lane + 64 * r;
+                    if (ev < ne) event_direct<T, EXT, LDSH>(P, Dc, e0 + ev, edges, sink);
+                }
+                continue;
+            }
+            const int nj = static_cast<int>(B.J1 - B.J0), nm = static_cast<int>(B.M1 - B.M0);
+            const int nl = static_cast<int>(B.L1 - B.L0);
+
+            // ---- 1. all of the tile's loads in flight at once: both offsets of
+            // each event lane's event (tile-relative), its weight, and up to JK
+            // jets, MK muons and EK electrons per lane
+            // tile-base pointers (scalar) and 32-bit lane offsets
+            const int64_t *jo = D.joff + e0, *mo = D.moff + e0, *lo = has_el ? D.eoff + e0 : nullptr;
+            const float *wp = D.w ? D.w + e0 : nullptr;
+            const T *cjpt = static_cast<const T *>(D.jpt) + B.J0, *cjeta = static_cast<const T *>(D.jeta) + B.J0;
+            const T *cjphi = static_cast<const T *>(D.jphi) + B.J0;
+            const T *cjbt = has_bt ? static_cast<const T *>(D.jbt) + B.J0 : nullptr;
+            const T *cmpt = static_cast<const T *>(D.mpt) + B.M0, *cmeta = static_cast<const T *>(D.meta) + B.M0;
+            const T *cmphi = static_cast<const T *>(D.mphi) + B.M0;
+            const T *cmiso = has_iso ? static_cast<const T *>(D.miso) + B.M0 : nullptr;
+            int32_t jb[EVPL], je[EVPL], mb[EVPL], me[EVPL], lb[EVPL], le[EVPL];
+            float wv[EVPL];
+#pragma unroll
+            for (int r = 0; r < EVPL; ++r) {
+                const int ev = lane + 64 * r;
+                jb[r] = je[r] = mb[r] = me[r] = lb[r] = le[r] = 0;
+                wv[r] = 1.0f;
+                if (ev < ne) {
+                    jb[r] = static_cast<int32_t>(jo[ev] - B.J0);
+                    je[r] = static_cast<int32_t>(jo[ev + 1] - B.J0);
+                    mb[r] = static_cast<int32_t>(mo[ev] - B.M0);
+                    me[r] = static_cast<int32_t>(mo[ev + 1] - B.M0);
+                    if (EXT && has_el) {
+                        lb[r] = static_cast<int32_t>(lo[ev] - B.L0);
+                        le[r] = static_cast<int32_t>(lo[ev + 1] - B.L0);
+                    }
+                    if (wp) wv[r] = wp[ev];
+                }
+            }
+            float jpt[JK] = {}, jeta[JK] = {}, jphi[JK] = {}, jbt[EXT ? JK : 1] = {};
+#pragma unroll
+            for (int k = 0; k < JK; ++k) {
+                const int j = lane + 64 * k;
+                if (j < nj) {
+                    jpt[k] = ldf(cjpt, j);
+                    jeta[k] = ldf(cjeta, j);
+                    jphi[k] = ldf(cjphi, j);
+                    if (EXT && has_bt) jbt[EXT ? k : 0] = ldf(cjbt, j);
+                }
+            }
+            float mpt[MK] = {}, meta[MK] = {}, mphi[MK] = {}, miso[MK] = {};
+#pragma unroll
+            for (int k = 0; k < MK; ++k) {
+                const int m = lane + 64 * k;
+                if (m < nm) {
+                    mpt[k] = ldf(cmpt, m);
+                    meta[k] = ldf(cmeta, m);
+                    mphi[k] = ldf(cmphi, m);
+                    if (has_iso) miso[k] = ldf(cmiso, m);
+                }
+            }
+            float lpt[EK] = {}, leta[EK] = {}, lphi[EK] = {};
+            if (EXT && has_el) {
+                const T *cept = static_cast<const T *>(D.ept) + B.L0, *ceeta = static_cast<const T *>(D.eeta) + B.L0;
+                const T *cephi = static_cast<const T *>(D.ephi) + B.L0;
+#pragma unroll
+                for (int k = 0; k < EK; ++k) {
+                    const int m = lane + 64 * k;
+                    if (m < nl) {
+                        lpt[k] = ldf(cept, m);
+                        leta[k] = ldf(ceeta, m);
+                        lphi[k] = ldf(cephi, m);
+                    }
+                }
+            }
+            // Every value above is used here, so the compiler issues all of the
+            // tile's loads before this point and waits once, instead of sinking
+            // each load to its first use (one HBM round trip per tile).
+#pragma unroll
+            for (int r = 0; r < EVPL; ++r)
+                asm volatile("" ::"v"(jb[r]), "v"(je[r]), "v"(mb[r]), "v"(me[r]), "v"(wv[r]));
+#pragma unroll
+            for (int k = 0; k < JK; ++k) asm volatile("" ::"v"(jpt[k]), "v"(jeta[k]), "v"(jphi[k]));
+#pragma unroll
+            for (int k = 0; k < MK; ++k) asm volatile("" ::"v"(mpt[k]), "v"(meta[k]), "v"(mphi[k]), "v"(miso[k]));
+            if (EXT) {
+#pragma unroll
+                for (int r = 0; r < EVPL; ++r) asm volatile("" ::"v"(lb[r]), "v"(le[r]));
+#pragma unroll
+                for (int k = 0; k < JK; ++k) asm volatile("" ::"v"(jbt[EXT ? k : 0]));
+#pragma unroll
+                for (int k = 0; k < EK; ++k) asm volatile("" ::"v"(lpt[k]), "v"(leta[k]), "v"(lphi[k]));
+            }
+
+            for (int q = 0; q < P.n_q; ++q) {
+                // the query's fields are read in place (scalar loads near their
+                // uses) rather than copied: a copy would hold ~45 SGPRs for the
+                // whole query and spill
+                const auto &Q = as_const(P.qs)[q];
+                if (!Q.active) continue;
+                // ---- 2. lepton selection; selected leptons compacted into LDS
+                {
+                    bool sel[MK];
+#pragma unroll
+                    for (int k = 0; k < MK; ++k)
+                        sel[k] = (lane + 64 * k < nm) && mpt[k] > Q.mu_pt && fabsf(meta[k]) < Q.mu_abseta &&
+                                 (!has_iso || miso[k] < Q.mu_iso);
+                    compact<MK>(sel, meta, mphi, nm, lane, L.seta, L.sphi, L.mpre);
+                }
+                if (EXT) {
+                    bool sel[EK];
+#pragma unroll
+                    for (int k = 0; k < EK; ++k)
+                        sel[k] = (lane + 64 * k < nl) && lpt[k] > Q.el_pt && fabsf(leta[k]) < Q.el_abseta;
+                    compact<EK>(sel, leta, lphi, nl, lane, L.sea, L.sep, L.epre);
+                }
+                wave_sync();
+                // ---- 3. each event lane writes its selected-lepton range over its jets
+                int nmu[EVPL];
+#pragma unroll
+                for (int r = 0; r < EVPL; ++r) {
+                    nmu[r] = 0;
+                    const int ev = lane + 64 * r;
+                    if (ev < ne) {
+                        const int s0 = L.mpre[mb[r]];
+                        nmu[r] = L.mpre[me[r]] - s0;
+                        const uint32_t pk = static_cast<uint32_t>(s0) | (static_cast<uint32_t>(nmu[r]) << 16);
+                        uint32_t pke = 0;
+                        if (EXT) {
+                            const int u0 = L.epre[lb[r]];
+                            pke = static_cast<uint32_t>(u0) | (static_cast<uint32_t>(L.epre[le[r]] - u0) << 16);
+                        }
+                        for (int k = jb[r]; k < je[r]; ++k) {
+                            L.jr[k].rng = pk;
+                            if (EXT) L.jre[k] = pke;
+                        }
+                    }
+                }
+                wave_sync();
+                // ---- 4. cone test per jet against its event's selected leptons
+#pragma unroll
+                for (int k = 0; k < JK; ++k) {
+                    const int j = lane + 64 * k;
+                    if (j < nj) {
+                        const uint32_t pk = L.jr[j].rng;
+                        const int c0 = static_cast<int>(pk & 0xffffu), c1 = c0 + static_cast<int>(pk >> 16);
+                        bool hit = false;
+                        int i = c0;
+                        // two leptons per step: both LDS reads in flight before the math
+                        for (; i + 2 <= c1; i += 2) {
+                            const float e0 = L.seta[i], p0 = L.sphi[i], e1 = L.seta[i + 1], p1 = L.sphi[i + 1];
+                            hit |= delta_r2(jeta[k], jphi[k], e0, p0) <= Q.thr2;
+                            hit |= delta_r2(jeta[k], jphi[k], e1, p1) <= Q.thr2;
+                        }
+                        if (i < c1) hit |= delta_r2(jeta[k], jphi[k], L.seta[i], L.sphi[i]) <= Q.thr2;
+                        if (EXT) {
+                            const uint32_t pe = L.jre[j];
+                            const int u0 = static_cast<int>(pe & 0xffffu), u1 = u0 + static_cast<int>(pe >> 16);
+                            for (int i = u0; i < u1; ++i) hit |= delta_r2(jeta[k], jphi[k], L.sea[i], L.sep[i]) <= Q.thr2;
+                        }
+                        const bool ok = !hit && fabsf(jeta[k]) < Q.jet_abseta;
+                        L.jr[j].pt = ok ? jpt[k] : __builtin_nanf("");
+                        if (EXT) L.bt[j] = (has_bt && jbt[EXT ? k : 0] > Q.btag) ? 1 : 0;
+                    }
+                }
+                wave_sync();
+                // ---- 5. per-event reductions, event cut, fills
+                const float jet_pt = pin<float>(Q.jet_pt);
+                const int min_mu = pin<int32_t>(Q.min_mu), min_jet = pin<int32_t>(Q.min_jet);
+                const int min_b = pin<int32_t>(has_bt ? Q.min_b : 0);
+                const FillC F = fill_consts<LDSH>(Q);
+                // separate calls for the two places the edges live, so each
+                // knows its address space (no flat loads)
+                auto fill = [&](const auto &xs, const auto &pass, int v0, double w) {
+                    constexpr int N = std::extent<std::remove_reference_t<decltype(xs)>>::value;
+                    if (P.edges_in_lds)
+                        fill_bins<N>(sink, F, e_s, xs, pass, v0, w);
+                    else
+                        fill_bins<N>(sink, F, P.edges, xs, pass, v0, w);
+                };
+                if (!MS) {
+                    const float sc[1] = {pin<float>(as_const(P.scales)[Q.scale0])};
+#pragma unroll
+                    for (int r = 0; r < EVPL; ++r) {
+                        // an event short of muons or of jets before any cut
+                        // cannot pass: its walk is skipped
+                        const bool elig = lane + 64 * r < ne && nmu[r] >= min_mu && je[r] - jb[r] >= min_jet;
+                        float ht[1], lead[1];
+                        int njs[1], nbt[1];
+                        walk_jets<1, EXT>(L, jb[r], elig ? je[r] : jb[r], sc, jet_pt, ht, lead, njs, nbt);
+                        const bool pass[1] = {elig && njs[0] >= min_jet && nbt[0] >= min_b};
+                        if (pass[0]) {
+                            const float xs[3] = {ht[0], lead[0], static_cast<float>(njs[0])};
+                            fill(xs, pass, 0, static_cast<double>(wv[r]));
+                        }
+                    }
+                } else {
+                    // Several scales: the events that can pass at all (enough
+                    // muons, enough jets before any cut; the cuts only remove
+                    // jets) are compacted, and lanes take (event, group of kG
+                    // scales) pairs of them, event-major.  One walk over an
+                    // event's jets serves the kG scales of its group (kG
+                    // independent chains), and a round covers a few events, so
+                    // the walks diverge little.
+                    int nel = 0;
+#pragma unroll
+                    for (int r = 0; r < EVPL; ++r) {
+                        const bool elig = lane + 64 * r < ne && nmu[r] >= min_mu && je[r] - jb[r] >= min_jet;
+                        const uint64_t bal = __ballot(elig);
+                        const int at = nel + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+                                                 static_cast<uint32_t>(bal >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bal), 0u)));
+                        if (elig) {
+                            L.evjr[at] = static_cast<uint32_t>(jb[r]) | (static_cast<uint32_t>(je[r]) << 16);
+                            L.evw[at] = wv[r];
+                        }
+                        nel += __popcll(bal);
+                    }
+                    wave_sync();
+                    const int V = pin<int32_t>(Q.n_scale);
+                    const float *scl = (P.scales_in_lds ? s_s : P.scales) + pin<int32_t>(Q.scale0);
+                    const int NG = (V + kG - 1) / kG;
+                    const int npairs = nel * NG;
+                    int e = lane / NG, g = lane - (lane / NG) * NG;
+                    const int de = 64 / NG, dg = 64 - (64 / NG) * NG;
+                    for (int i = lane; i < npairs; i += 64) {
+                        const uint32_t jr = L.evjr[e];
+                        float sc[kG];
+#pragma unroll
+                        for (int u = 0; u < kG; ++u) sc[u] = scl[min(g * kG + u, V - 1)];
+                        float ht[kG], lead[kG];
+                        int njs[kG], nbt[kG];
+                        walk_jets<kG, EXT>(L, static_cast<int>(jr & 0xffffu), static_cast<int>(jr >> 16), sc, jet_pt,
+                                           ht, lead, njs, nbt);
+                        bool pass[kG], any = false;
+#pragma unroll
+                        for (int u = 0; u < kG; ++u) {
+                            pass[u] = g * kG + u < V && njs[u] >= min_jet && nbt[u] >= min_b;
+                            any |= pass[u];
+                        }
+                        if (any) {
+                            float xs[3 * kG];
+#pragma unroll
+                            for (int u = 0; u < kG; ++u) {
+                                xs[3 * u] = ht[u];
+                                xs[3 * u + 1] = lead[u];
+                                xs[3 * u + 2] = static_cast<float>(njs[u]);
+                            }
+                            fill(xs, pass, g * kG, static_cast<double>(L.evw[e]));
+                        }
+                        e += de;
+                        g += dg;
+                        if (g >= NG) {
+                            g -= NG;
+                            e += 1;
+                        }
+                    }
+                }
+                wave_sync();
+            }
+        }
+        // merge the LDS histograms when the next chunk is another dataset (or none)
+        if (LDSH) {
+            const int nci = ci + static_cast<int>(gridDim.x);
+            if (nci >= P.chunk_end || as_const(P.chunks)[nci].d != CH.d) {
+                __syncthreads();
+                for (int q = 0; q < P.n_q; ++q) {
+                    const QDev Q = as_const(P.qs)[q];
+                    if (!Q.active) continue;
+                    for (int v = 0; v < Q.n_scale; ++v)
+                        for (int h = 0; h < 3; ++h) {
+                            const int ls = Q.lslot0 + v * Q.lper_scale + Q.lhoff[h];
+                            const int64_t gs = D.hist0 + Q.gslot0 + v * Q.gper_scale + Q.ghoff[h];
+                            for (int i = tid; i < Q.nbins[h] + 2; i += 64 * WAVES) {
+                                const uint32_t c = c_s[ls + i];
+                                if (c) {
+                                    atomic_add_u64(&P.counts[gs + i], c);
+                                    atomic_add_f64(&P.sumw[gs + i], sw_s[ls + i]);
+                                    c_s[ls + i] = 0u;
+                                    sw_s[ls + i] = 0.0;
+                                }
+                            }
+                        }
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
+using KernelFn = void (*)(PipeArgs);
+
+template <typename T, bool EXT, int WAVES, int EVPL, bool LDSH, bool MS>
+static KernelFn kfn() {
+    return reinterpret_cast<KernelFn>(&pipeline_kernel<T, EXT, WAVES, EVPL, LDSH, MS>);
+}
+
+template <typename T, bool EXT, int WAVES, int EVPL, bool MS>
+static KernelFn pick_h(bool ldsh) {
+    return ldsh ? kfn<T, EXT, WAVES, EVPL, true, MS>() : kfn<T, EXT, WAVES, EVPL, false, MS>();
+}
+
+template <typename T, bool EXT, bool MS>
+static KernelFn pick_shape(int block, int evpt, bool ldsh) {
+    if (block == 512) return evpt == 2 ? pick_h<T, EXT, 8, 2, MS>(ldsh) : pick_h<T, EXT, 8, 1, MS>(ldsh);
+    return evpt == 2 ? pick_h<T, EXT, 4, 2, MS>(ldsh) : pick_h<T, EXT, 4, 1, MS>(ldsh);
+}
+
+// The kernel for a launch shape; each value of MS is instantiated in its own
+// translation unit (they compile in parallel).
+template <bool MS>
+KernelFn pick_kernel(int dtype, bool ext, int block, int evpt, bool ldsh) {
+    if (dtype == HEPK_F16) return ext ? pick_shape<_Float16, true, MS>(block, evpt, ldsh)
+                                      : pick_shape<_Float16, false, MS>(block, evpt, ldsh);
+    return ext ? pick_shape<float, true, MS>(block, evpt, ldsh) : pick_shape<float, false, MS>(block, evpt, ldsh);
+}
+
+// LDS for the workgroup's private histograms: up to 64 KiB (60 histograms of
+// 100 bins fit); larger sets go to global atomics.  More LDS lowers occupancy,
+// which the launch-configuration search weighs against atomic contention.
+constexpr int kMaxLdsHistBytes = 64 * 1024;
+constexpr int kMaxLdsEdgeBytes = 4 * 1024;
+constexpr int kMaxLdsScaleBytes = 1024;
+
+}  // namespace hepk

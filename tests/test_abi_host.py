@@ -167,6 +167,11 @@ def test_slot_range_graph_autotune_reject_bad_arguments(lib):
         q[0].nbins[h] = 2
     assert _rc("hepk_plan_create_ex", ds, 1, q, 1, C.byref(opts), C.byref(out)) == H.EINVAL
     assert "reserve_bins" in H.last_error()
+    for v in (0.0, -1.0, float("inf"), float("nan")):
+        sc[0] = v
+        assert _rc("hepk_plan_create_ex", ds, 1, q, 1, C.byref(opts), C.byref(out)) == H.EINVAL
+        assert "positive" in H.last_error()
+    sc[0] = 1.0
     bad = (C.c_float * 3)(0.0, 2.0, 1.0)
     q[0].edges[1] = C.cast(bad, C.c_void_p)
     opts = H.PlanOpts(H.Tune(0, 0, 0, 0), 0, 0)

@@ -330,6 +330,49 @@ def test_pipeline_extended_schema_jes(dtype):
     assert len(got[0]) == 20
 
 
+MS_TUNES = [None, dict(block=256), dict(ev_per_thread=2), dict(block=256, ev_per_thread=2), dict(hist_mode=1)]
+
+
+@pytest.mark.parametrize("extended", [False, True])
+@pytest.mark.parametrize("tune", MS_TUNES, ids=[str(t) for t in MS_TUNES])
+def test_pipeline_mixed_scale_counts(extended, tune):
+    """Queries with 1, 3, 5 and 20 jet-energy scales in one plan (scale groups
+    full, partly used and single), uniform and log-spaced bin edges."""
+    say(f"pipeline mixed scales extended={extended} tune={tune}")
+    ds = datagen.make_dataset(6, 30000, extended=extended)
+    sc = datagen.jes_scales()
+    log_ht = np.geomspace(10.0, 3000.0, 41).astype(np.float32)
+    log_lead = np.geomspace(5.0, 1500.0, 33).astype(np.float32)
+    qs = [datagen.Query(),
+          datagen.Query(min_b=1 if extended else 0, scales=sc[:3], edges_ht=log_ht),
+          datagen.Query(jet_pt=25.0, min_jet=2, scales=sc[:5], edges_lead=log_lead),
+          datagen.Query(min_b=1 if extended else 0, scales=sc)]
+    got = fused([ds], qs, tune)[0]
+    check_against_oracle(ds, qs, got, f"mixed tune={tune}")
+    assert [len(g) for g in got] == [1, 3, 5, 20]
+
+
+def test_pipeline_lds_beyond_device_limit_uses_global_hist():
+    """The 60 histograms of the extended query fit in LDS beside 64-event
+    tiles, not beside the 128-event tiles of 512-thread workgroups: that plan
+    must take global histograms instead of asking for more LDS than a
+    workgroup has."""
+    say("pipeline LDS limit")
+    ds = datagen.make_dataset(8, 20000, extended=True, content_dtype="f16")
+    q = datagen.extended_query()
+    dd = H.DeviceDataset(ds)
+    small = H.Plan([dd], [q], dict(block=512, ev_per_thread=1, hist_mode=0))
+    assert small.tune["hist_mode"] == 0
+    small.close()
+    plan = H.Plan([dd], [q], dict(block=512, ev_per_thread=2, hist_mode=0))
+    assert plan.tune["hist_mode"] == 1
+    s, c = plan.new_hists()
+    plan.run(s, c)
+    got = plan.split(s, c)[0]
+    plan.close()
+    check_against_oracle(ds, [q], got, "LDS limit")
+
+
 def test_pipeline_batch_uneven():
     say("pipeline batch")
     sizes = [0, 1, 255, 256, 257, 30000, 5, 12345]
