@@ -109,6 +109,8 @@ static void set_qdev(QDev &o, const hepk_query &Q, const float *const edges[3]) 
     o.min_jet = Q.min_jet;
     o.min_b = Q.min_b;
     o.n_scale = Q.n_scale;
+    o.smax = Q.scales[0];
+    for (int v = 1; v < Q.n_scale; ++v) o.smax = std::max(o.smax, Q.scales[v]);
     o.active = 1;
     for (int h = 0; h < 3; ++h) {
         const int nb = Q.nbins[h];

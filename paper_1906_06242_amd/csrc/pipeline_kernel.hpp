@@ -70,6 +70,7 @@ struct QDev {
     float mu_pt, mu_abseta, mu_iso, el_pt, el_abseta, jet_pt, jet_abseta, thr2, btag;
     int32_t min_mu, min_jet, min_b;
     int32_t n_scale, scale0;
+    float smax;          // largest scale; used only when jet_pt >= 0
     int32_t active;      // 0: idle query slot, skipped
     int32_t nbins[3];
     int32_t ebase[3];    // first edge of each observable in the plan's edge table
@@ -671,17 +672,31 @@ pipeline_kernel(PipeArgs P) {
                         }
                     }
                 } else {
-                    // Several scales: the events that can pass at all (enough
-                    // muons, enough jets before any cut; the cuts only remove
-                    // jets) are compacted, and lanes take (event, group of kG
-                    // scales) pairs of them, event-major.  One walk over an
-                    // event's jets serves the kG scales of its group (kG
-                    // independent chains), and a round covers a few events, so
-                    // the walks diverge little.
+                    // Several scales: the events that can pass at some scale are
+                    // compacted, and lanes take (event, group of kG scales)
+                    // pairs of them, event-major.  One walk over an event's
+                    // jets serves the kG scales of its group (kG independent
+                    // chains), and a round covers a few events, so the walks
+                    // diverge little.  An event can pass only with enough
+                    // muons and enough jets before any cut (the cuts only
+                    // remove jets); with jet_pt >= 0 also only with enough
+                    // selected jets and b-tagged jets at the largest scale: a
+                    // jet selected at s <= smax is selected at smax (rounding
+                    // pt * s is monotone in s for pt >= 0, and pt * s <= 0 <=
+                    // jet_pt otherwise), so one walk at smax bounds both counts
+                    // at every scale.
+                    const bool prefilter = jet_pt >= 0.0f;
+                    const float smax[1] = {pin<float>(Q.smax)};
                     int nel = 0;
 #pragma unroll
                     for (int r = 0; r < EVPL; ++r) {
-                        const bool elig = lane + 64 * r < ne && nmu[r] >= min_mu && je[r] - jb[r] >= min_jet;
+                        bool elig = lane + 64 * r < ne && nmu[r] >= min_mu && je[r] - jb[r] >= min_jet;
+                        if (prefilter && elig) {
+                            float ht1[1], lead1[1];
+                            int nj1[1], nb1[1];
+                            walk_jets<1, EXT>(L, jb[r], je[r], smax, jet_pt, ht1, lead1, nj1, nb1);
+                            elig = nj1[0] >= min_jet && nb1[0] >= min_b;
+                        }
                         const uint64_t bal = __ballot(elig);
                         const int at = nel + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
                                                  static_cast<uint32_t>(bal >> 32),

@@ -336,8 +336,9 @@ MS_TUNES = [None, dict(block=256), dict(ev_per_thread=2), dict(block=256, ev_per
 @pytest.mark.parametrize("extended", [False, True])
 @pytest.mark.parametrize("tune", MS_TUNES, ids=[str(t) for t in MS_TUNES])
 def test_pipeline_mixed_scale_counts(extended, tune):
-    """Queries with 1, 3, 5 and 20 jet-energy scales in one plan (scale groups
-    full, partly used and single), uniform and log-spaced bin edges."""
+    """Queries with 1, 3, 5, 20 and 6 jet-energy scales in one plan (scale
+    groups full, partly used and single), uniform and log-spaced bin edges,
+    and a negative jet threshold (no largest-scale pre-filter)."""
     say(f"pipeline mixed scales extended={extended} tune={tune}")
     ds = datagen.make_dataset(6, 30000, extended=extended)
     sc = datagen.jes_scales()
@@ -346,10 +347,11 @@ def test_pipeline_mixed_scale_counts(extended, tune):
     qs = [datagen.Query(),
           datagen.Query(min_b=1 if extended else 0, scales=sc[:3], edges_ht=log_ht),
           datagen.Query(jet_pt=25.0, min_jet=2, scales=sc[:5], edges_lead=log_lead),
-          datagen.Query(min_b=1 if extended else 0, scales=sc)]
+          datagen.Query(min_b=1 if extended else 0, scales=sc),
+          datagen.Query(jet_pt=-1.0, min_jet=6, scales=sc[5:11])]  # no largest-scale pre-filter
     got = fused([ds], qs, tune)[0]
     check_against_oracle(ds, qs, got, f"mixed tune={tune}")
-    assert [len(g) for g in got] == [1, 3, 5, 20]
+    assert [len(g) for g in got] == [1, 3, 5, 20, 6]
 
 
 def test_pipeline_lds_beyond_device_limit_uses_global_hist():
