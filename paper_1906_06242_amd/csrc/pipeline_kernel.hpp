@@ -592,7 +592,15 @@ pipeline_kernel(PipeArgs P) {
                     compact<EK>(sel, leta, lphi, nl, lane, L.sea, L.sep, L.epre);
                 }
                 wave_sync();
-                // ---- 3. each event lane writes its selected-lepton range over its jets
+                // query fields used from here on, read once (pinned: reloading
+                // them inside the loops below costs a wait each time)
+                const float jet_pt = pin<float>(Q.jet_pt);
+                const int min_mu = pin<int32_t>(Q.min_mu), min_jet = pin<int32_t>(Q.min_jet);
+                const int min_b = pin<int32_t>(has_bt ? Q.min_b : 0);
+                // ---- 3. each event lane writes its selected-lepton range over
+                // its jets; an event that cannot pass (too few muons, or too
+                // few jets before any cut) gets empty ranges: its jets' cone
+                // test is not needed
                 int nmu[EVPL];
 #pragma unroll
                 for (int r = 0; r < EVPL; ++r) {
@@ -601,11 +609,14 @@ pipeline_kernel(PipeArgs P) {
                     if (ev < ne) {
                         const int s0 = L.mpre[mb[r]];
                         nmu[r] = L.mpre[me[r]] - s0;
-                        const uint32_t pk = static_cast<uint32_t>(s0) | (static_cast<uint32_t>(nmu[r]) << 16);
+                        const bool elig = nmu[r] >= min_mu && je[r] - jb[r] >= min_jet;
+                        const uint32_t pk =
+                            static_cast<uint32_t>(s0) | (static_cast<uint32_t>(elig ? nmu[r] : 0) << 16);
                         uint32_t pke = 0;
                         if (EXT) {
                             const int u0 = L.epre[lb[r]];
-                            pke = static_cast<uint32_t>(u0) | (static_cast<uint32_t>(L.epre[le[r]] - u0) << 16);
+                            pke = static_cast<uint32_t>(u0) |
+                                  (static_cast<uint32_t>(elig ? L.epre[le[r]] - u0 : 0) << 16);
                         }
                         for (int k = jb[r]; k < je[r]; ++k) {
                             L.jr[k].rng = pk;
@@ -614,37 +625,45 @@ pipeline_kernel(PipeArgs P) {
                     }
                 }
                 wave_sync();
-                // ---- 4. cone test per jet against its event's selected leptons
+                // ---- 4. cone test per jet against its event's selected
+                // leptons.  A jet outside |eta| or below jet_pt at the largest
+                // scale (with jet_pt >= 0) is selected at no scale: it skips
+                // the test and is stored as NaN.  That changes no result: a
+                // selected jet of its event has a larger pt, so the maximum
+                // and the sums and counts of selected jets are the same.
+                const float thr2 = pin<float>(Q.thr2), jet_abseta = pin<float>(Q.jet_abseta);
+                const float smax = pin<float>(Q.smax);
+                const float btag = EXT ? pin<float>(Q.btag) : 0.0f;
 #pragma unroll
                 for (int k = 0; k < JK; ++k) {
                     const int j = lane + 64 * k;
                     if (j < nj) {
+                        const bool need = fabsf(jeta[k]) < jet_abseta && (jet_pt < 0.0f || jpt[k] * smax > jet_pt);
                         const uint32_t pk = L.jr[j].rng;
-                        const int c0 = static_cast<int>(pk & 0xffffu), c1 = c0 + static_cast<int>(pk >> 16);
+                        const int c0 = static_cast<int>(pk & 0xffffu);
+                        const int c1 = c0 + (need ? static_cast<int>(pk >> 16) : 0);
                         bool hit = false;
                         int i = c0;
                         // two leptons per step: both LDS reads in flight before the math
                         for (; i + 2 <= c1; i += 2) {
                             const float e0 = L.seta[i], p0 = L.sphi[i], e1 = L.seta[i + 1], p1 = L.sphi[i + 1];
-                            hit |= delta_r2(jeta[k], jphi[k], e0, p0) <= Q.thr2;
-                            hit |= delta_r2(jeta[k], jphi[k], e1, p1) <= Q.thr2;
+                            hit |= delta_r2(jeta[k], jphi[k], e0, p0) <= thr2;
+                            hit |= delta_r2(jeta[k], jphi[k], e1, p1) <= thr2;
                         }
-                        if (i < c1) hit |= delta_r2(jeta[k], jphi[k], L.seta[i], L.sphi[i]) <= Q.thr2;
+                        if (i < c1) hit |= delta_r2(jeta[k], jphi[k], L.seta[i], L.sphi[i]) <= thr2;
                         if (EXT) {
                             const uint32_t pe = L.jre[j];
-                            const int u0 = static_cast<int>(pe & 0xffffu), u1 = u0 + static_cast<int>(pe >> 16);
-                            for (int i = u0; i < u1; ++i) hit |= delta_r2(jeta[k], jphi[k], L.sea[i], L.sep[i]) <= Q.thr2;
+                            const int u0 = static_cast<int>(pe & 0xffffu);
+                            const int u1 = u0 + (need ? static_cast<int>(pe >> 16) : 0);
+                            for (int i = u0; i < u1; ++i) hit |= delta_r2(jeta[k], jphi[k], L.sea[i], L.sep[i]) <= thr2;
                         }
-                        const bool ok = !hit && fabsf(jeta[k]) < Q.jet_abseta;
+                        const bool ok = need && !hit;
                         L.jr[j].pt = ok ? jpt[k] : __builtin_nanf("");
-                        if (EXT) L.bt[j] = (has_bt && jbt[EXT ? k : 0] > Q.btag) ? 1 : 0;
+                        if (EXT) L.bt[j] = (has_bt && jbt[EXT ? k : 0] > btag) ? 1 : 0;
                     }
                 }
                 wave_sync();
                 // ---- 5. per-event reductions, event cut, fills
-                const float jet_pt = pin<float>(Q.jet_pt);
-                const int min_mu = pin<int32_t>(Q.min_mu), min_jet = pin<int32_t>(Q.min_jet);
-                const int min_b = pin<int32_t>(has_bt ? Q.min_b : 0);
                 const FillC F = fill_consts<LDSH>(Q);
                 // separate calls for the two places the edges live, so each
                 // knows its address space (no flat loads)
@@ -686,7 +705,7 @@ pipeline_kernel(PipeArgs P) {
                     // jet_pt otherwise), so one walk at smax bounds both counts
                     // at every scale.
                     const bool prefilter = jet_pt >= 0.0f;
-                    const float smax[1] = {pin<float>(Q.smax)};
+                    const float smaxa[1] = {smax};
                     int nel = 0;
 #pragma unroll
                     for (int r = 0; r < EVPL; ++r) {
@@ -694,7 +713,7 @@ pipeline_kernel(PipeArgs P) {
                         if (prefilter && elig) {
                             float ht1[1], lead1[1];
                             int nj1[1], nb1[1];
-                            walk_jets<1, EXT>(L, jb[r], je[r], smax, jet_pt, ht1, lead1, nj1, nb1);
+                            walk_jets<1, EXT>(L, jb[r], je[r], smaxa, jet_pt, ht1, lead1, nj1, nb1);
                             elig = nj1[0] >= min_jet && nb1[0] >= min_b;
                         }
                         const uint64_t bal = __ballot(elig);
