@@ -16,6 +16,9 @@ measured with HIP events on the launch stream; `cpu_baseline` is the CPU
 oracle on one host core over a bounded sample of the same workload.
 
 Further sections on the same line (each skippable):
+  primitives  each single-purpose entry point of the per-kernel chain timed
+            alone on the same 1e7 events: algorithmic bytes / HIP-event time
+            against the HBM peak;
   extended  5e7 events, float16 content widened in registers, electrons,
             jet b-tag, 20 jet-energy-scale variations -> 60 histograms/pass;
   batch     64 datasets of log-uniform sizes in [1e4, 5e6] in one persistent
@@ -140,6 +143,61 @@ def spot_check(dd_all: dict, e0: int, e1: int, queries, tune=None) -> bool:
                 ws, wc = want[qi][v][h]
                 ok &= bool(np.array_equal(gc, wc) and np.all(np.abs(gs - ws) <= 1e-5 * np.abs(ws)))
     return ok
+
+
+def section_primitives(dd, q, stream, reps: int = 10) -> dict:
+    """Each entry point of the per-kernel chain alone: median HIP-event time,
+    algorithmic bytes (inputs read + outputs written), fraction of HBM peak."""
+    import torch
+    from paper_1906_06242_amd import hepk as H
+    t = dd.t
+    n, mm, mj = dd.n_events, t("muons.pt").numel(), t("jets.pt").numel()
+    ob = 8 * (n + 1)  # one offsets array
+    msel = H.select([(t("muons.pt"), H.GT, q.mu_pt), (t("muons.eta"), H.ABS_LT, q.mu_abseta),
+                     (t("muons.iso"), H.LT, q.mu_iso)], mm)
+    _, _, clean = H.match_dr(t("jets.offsets"), t("jets.eta"), t("jets.phi"), t("muons.offsets"),
+                             t("muons.eta"), t("muons.phi"), q.dr, mask_b=msel, want=("clean",))
+    jsel = H.select([(t("jets.pt"), H.GT, q.jet_pt), (t("jets.eta"), H.ABS_LT, q.jet_abseta)], mj,
+                    mask_in=clean)
+    nmu = H.reduce(H.COUNT, t("muons.offsets"), obj_mask=msel)
+    njet = H.reduce(H.COUNT, t("jets.offsets"), obj_mask=jsel)
+    ht = H.reduce(H.SUM, t("jets.offsets"), t("jets.pt"), obj_mask=jsel)
+    passed = H.select([(nmu, H.GE, q.min_mu), (njet, H.GE, q.min_jet)], n)
+    e = torch.from_numpy(q.edges_ht.astype("float32")).to("cuda")
+    hs = torch.zeros(len(e) + 1, dtype=torch.float64, device="cuda")
+    hc = torch.zeros(len(e) + 1, dtype=torch.int64, device="cuda")
+    o_mask, o_i32 = torch.empty(mj, dtype=torch.uint8, device="cuda"), torch.empty(n, dtype=torch.int32, device="cuda")
+    o_f32 = torch.empty(n, dtype=torch.float32, device="cuda")
+    cases = {
+        "select (muons, 3 cuts)": (lambda: H.select([(t("muons.pt"), H.GT, q.mu_pt),
+                                                     (t("muons.eta"), H.ABS_LT, q.mu_abseta),
+                                                     (t("muons.iso"), H.LT, q.mu_iso)], mm, out=o_mask[:mm]),
+                                   13 * mm),
+        "select (jets, 2 cuts + mask)": (lambda: H.select([(t("jets.pt"), H.GT, q.jet_pt),
+                                                           (t("jets.eta"), H.ABS_LT, q.jet_abseta)], mj,
+                                                          mask_in=clean, out=o_mask), 10 * mj),
+        "select (events, 2 int32 cuts)": (lambda: H.select([(nmu, H.GE, q.min_mu), (njet, H.GE, q.min_jet)], n,
+                                                           out=o_mask[:n]), 9 * n),
+        "match_dr (jets vs selected muons, clean mask)": (
+            lambda: H.match_dr(t("jets.offsets"), t("jets.eta"), t("jets.phi"), t("muons.offsets"),
+                               t("muons.eta"), t("muons.phi"), q.dr, mask_b=msel, want=("clean",)),
+            2 * ob + 8 * mj + 9 * mm + mj),
+        "reduce COUNT (jets, mask)": (lambda: H.reduce(H.COUNT, t("jets.offsets"), obj_mask=jsel, out=o_i32),
+                                      ob + mj + 4 * n),
+        "reduce SUM (jet pt, mask)": (lambda: H.reduce(H.SUM, t("jets.offsets"), t("jets.pt"), obj_mask=jsel,
+                                                       out=o_f32), ob + 5 * mj + 4 * n),
+        "reduce MAX (jet pt, mask)": (lambda: H.reduce(H.MAX, t("jets.offsets"), t("jets.pt"), obj_mask=jsel,
+                                                       out=o_f32), ob + 5 * mj + 4 * n),
+        "hist_fill (H_T, weights, event mask)": (lambda: H.hist_fill(ht, e, hs, hc, w=t("weight"),
+                                                                      evt_mask=passed), 9 * n),
+    }
+    res = {}
+    for name, (fn, nbytes) in cases.items():
+        ms = statistics.median(time_steps(fn, reps, 2, stream)[0])
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        res[name] = {"ms": ms, "bytes": int(nbytes), "GBps": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+        log(f"primitive {name}: {ms * 1e3:.1f} us, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.0f}% of HBM peak)")
+    return res
 
 
 def section_extended(args) -> dict:
@@ -271,8 +329,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-reps", type=int, default=4)
     ap.add_argument("--tune", type=str, default="", help="JSON launch configuration")
-    ap.add_argument("--sections", type=str, default="extended,batch,serving",
-                    help="comma list of extra sections to run (extended, batch, serving) or 'none'")
+    ap.add_argument("--sections", type=str, default="primitives,extended,batch,serving",
+                    help="comma list of extra sections to run (primitives, extended, batch, serving) or 'none'")
     ap.add_argument("--serve-queries", type=int, default=1000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (scale for HBM byte counters)")
@@ -341,6 +399,9 @@ def main():
         log(f"plain: {p_step:.3f} ms/step")
 
     plan.close()
+    sections = [x for x in args.sections.split(",") if x and x != "none"]
+    if "primitives" in sections:
+        out["primitives"] = section_primitives(dd, q, stream)
     if args.calib_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -354,7 +415,6 @@ def main():
         log(f"cpu oracle: {out['cpu_baseline']['value']:.3e} events/s")
     del dd, ds
     torch.cuda.empty_cache()
-    sections = [x for x in args.sections.split(",") if x and x != "none"]
     if "extended" in sections:
         out["extended"] = section_extended(args)
     if "batch" in sections:

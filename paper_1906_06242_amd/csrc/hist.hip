@@ -1,11 +1,12 @@
 // hepk_hist_fill: weighted 1-D histogram fill (Sec. III fill-histogram
 // kernel), accumulating into the caller's histogram.
 //
-// Each workgroup keeps a private copy of the histogram in LDS (float64 sums
-// via ds_add_f64, uint32 counts via ds_add_u32) together with the bin edges,
-// walks a grid-stride range of rows four at a time (loads of the four rows in
-// flight together), and merges its non-empty slots into HBM with global
-// atomics at the end.  Histograms too large for LDS go straight to global
+// Each workgroup (1024 threads, one per CU) keeps a private copy of the
+// histogram in LDS (float64 sums via ds_add_f64, uint32 counts via
+// ds_add_u32) together with the bin edges, walks a grid-stride range of rows
+// eight at a time per thread (loads of the eight rows in flight together),
+// and merges its non-empty slots into HBM with global atomics at the end (one
+// merge per CU keeps the atomics on each slot few).  Histograms too large for LDS go straight to global
 // atomics with the edges read from HBM.  Sums of float64 weights are exact in
 // any order while every partial sum is a multiple of the smallest weight's ulp
 // below 2^53 of it, which holds for the float32 weights of this analysis;
@@ -14,7 +15,8 @@
 
 namespace hepk {
 
-constexpr int HB = 256;
+constexpr int HB = 1024;
+constexpr int HR = 8;  // rows per thread in flight
 constexpr int kMaxLdsSlots = 3000;  // 36 KiB of histogram + 12 KiB of edges
 
 template <typename X, bool LDS>
@@ -54,21 +56,21 @@ __global__ __launch_bounds__(HB) void hist_kernel(const X *__restrict__ x, const
     };
     const int64_t stride = static_cast<int64_t>(gridDim.x) * HB;
     int64_t i = static_cast<int64_t>(blockIdx.x) * HB + threadIdx.x;
-    // four rows per step, loads first
-    for (; i + 3 * stride < n; i += 4 * stride) {
-        float v[4];
-        double wt[4];
-        bool keep[4];
+    // HR rows per step, loads first
+    for (; i + (HR - 1) * stride < n; i += HR * stride) {
+        float v[HR];
+        float wt[HR];
+        bool keep[HR];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < HR; ++u) {
             const int64_t r = i + u * stride;
             keep[u] = !m || m[r] != 0;
             v[u] = static_cast<float>(x[r]);
-            wt[u] = w ? static_cast<double>(w[r]) : 1.0;
+            wt[u] = w ? w[r] : 1.0f;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (keep[u]) one(v[u], wt[u]);
+        for (int u = 0; u < HR; ++u)
+            if (keep[u]) one(v[u], static_cast<double>(wt[u]));
     }
     for (; i < n; i += stride) {
         if (m && !m[i]) continue;
@@ -91,7 +93,7 @@ static int launch_hist(const void *x, const float *w, const uint8_t *m, int64_t 
                        hipStream_t stream) {
     const int nslots = h->nbins + 2;
     const bool lds = nslots <= kMaxLdsSlots;
-    const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n, HB * 16), 4 * device_cus()));
+    const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n, HB * HR), device_cus()));
     const size_t lds_bytes = static_cast<size_t>(nslots) * (sizeof(double) + sizeof(uint32_t)) +
                              static_cast<size_t>(h->nbins + 1) * sizeof(float);
     if (lds)

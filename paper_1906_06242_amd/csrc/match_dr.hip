@@ -3,42 +3,55 @@
 // within a Delta-R cone of an object of a second collection; Sec. IV:
 // jet-lepton matching).
 //
-// A workgroup takes a tile of MB consecutive events.  The tile's b objects
-// (a few per event) are staged once into LDS, with eta replaced by NaN for
-// masked-out b so that their dR^2 is NaN and never becomes the minimum
-// (exactly as skipping them).  Then one lane per a object -- coalesced reads
-// of a's columns -- scans the b objects of its event in ascending order with
-// a strict '<', which keeps the lowest index on ties.  Tiles whose objects
-// exceed the LDS capacity fall back to one lane per event reading HBM
-// directly; the arithmetic is the same.
+// Each wavefront owns tiles of 64 consecutive events and works through them
+// without waiting for the rest of its workgroup.  For one tile it reads the
+// two object ranges with scalar loads, then issues every load of the tile at
+// once: both offsets of each event lane's event in a and b, up to MKA a
+// objects and MKB b objects per lane (consecutive lanes, consecutive
+// objects).  The b objects go to the wavefront's LDS with eta replaced by NaN
+// for masked-out b, so that their dR^2 is NaN and never becomes the minimum
+// (exactly as skipping them); each event lane writes its event's b range over
+// its a objects; then each a lane scans the b objects of its event in
+// ascending order with a strict '<', which keeps the lowest index on ties.
+// Tiles whose objects exceed the register capacity fall back to one lane per
+// event reading HBM directly; the arithmetic is the same.
 #include "common.hpp"
 
 namespace hepk {
 
-constexpr int MB = 256;          // events per tile == threads per workgroup
-constexpr int MACAP = 16 * MB;   // a objects per tile held in the event map
-constexpr int MBCAP = 8 * MB;    // b objects per tile staged in LDS
+constexpr int MW = 4;    // wavefronts per workgroup
+constexpr int MKA = 8;   // a objects per lane: 512 per tile
+constexpr int MKB = 4;   // b objects per lane: 256 per tile
+
+__device__ __forceinline__ void wave_fence_dr() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <typename T>
-__global__ __launch_bounds__(MB) void match_dr_kernel(
+__global__ __launch_bounds__(64 * MW) void match_dr_kernel(
     const int64_t *__restrict__ off_a, const T *__restrict__ eta_a, const T *__restrict__ phi_a,
     const uint8_t *__restrict__ mask_a, const int64_t *__restrict__ off_b, const T *__restrict__ eta_b,
     const T *__restrict__ phi_b, const uint8_t *__restrict__ mask_b, int64_t n_events, float thr2,
     float *__restrict__ min_dr2, int32_t *__restrict__ idx_b, uint8_t *__restrict__ clean) {
-    __shared__ int32_t offa_s[MB + 1], offb_s[MB + 1];
-    __shared__ float beta_s[MBCAP], bphi_s[MBCAP];
-    __shared__ uint16_t aev_s[MACAP];
-    const int tid = threadIdx.x;
-    const int64_t n_tiles = ceil_div(n_events, MB);
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t e0 = tile * MB;
-        const int ne = static_cast<int>(n_events - e0 < MB ? n_events - e0 : MB);
-        const int64_t A0 = off_a[e0], A1 = off_a[e0 + ne];
-        const int64_t B0 = off_b[e0], B1 = off_b[e0 + ne];
-        if (A1 - A0 > MACAP || B1 - B0 > MBCAP) {
+    __shared__ float beta_s[MW][64 * MKB], bphi_s[MW][64 * MKB];
+    __shared__ uint32_t arng_s[MW][64 * MKA];  // per a object: its event's b range (first | count << 16)
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float *be = beta_s[wave], *bp = bphi_s[wave];
+    uint32_t *ar = arng_s[wave];
+    const int64_t n_tiles = ceil_div(n_events, 64);
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * MW + wave; t < n_tiles;
+         t += static_cast<int64_t>(gridDim.x) * MW) {
+        const int64_t e0 = t * 64;
+        const int ne = static_cast<int>(min<int64_t>(64, n_events - e0));
+        const int64_t A0 = as_const(off_a)[e0], A1 = as_const(off_a)[e0 + ne];
+        const int64_t B0 = as_const(off_b)[e0], B1 = as_const(off_b)[e0 + ne];
+        const int64_t e = e0 + lane;
+        if (A1 - A0 > 64 * MKA || B1 - B0 > 64 * MKB) {
             // direct path: one lane per event, everything from HBM
-            if (tid < ne) {
-                const int64_t e = e0 + tid;
+            if (lane < ne) {
                 const int64_t b0 = off_b[e], b1 = off_b[e + 1];
                 for (int64_t a = off_a[e]; a < off_a[e + 1]; ++a) {
                     const float ea = ldf(eta_a, a), pa = ldf(phi_a, a);
@@ -60,42 +73,75 @@ __global__ __launch_bounds__(MB) void match_dr_kernel(
             continue;
         }
         const int na = static_cast<int>(A1 - A0), nb = static_cast<int>(B1 - B0);
-        if (tid < ne) {
-            offa_s[tid] = static_cast<int32_t>(off_a[e0 + tid] - A0);
-            offb_s[tid] = static_cast<int32_t>(off_b[e0 + tid] - B0);
+        // ---- every load of the tile in flight at once
+        int32_t ab = 0, ae = 0, bb = 0, bn = 0;
+        if (lane < ne) {
+            ab = static_cast<int32_t>(off_a[e] - A0);
+            ae = static_cast<int32_t>(off_a[e + 1] - A0);
+            bb = static_cast<int32_t>(off_b[e] - B0);
+            bn = static_cast<int32_t>(off_b[e + 1] - B0) - bb;
         }
-        if (tid == 0) {
-            offa_s[ne] = na;
-            offb_s[ne] = nb;
-        }
-        for (int b = tid; b < nb; b += MB) {
-            float e = ldf(eta_b, B0 + b);
-            if (mask_b && !mask_b[B0 + b]) e = __builtin_nanf("");
-            beta_s[b] = e;
-            bphi_s[b] = ldf(phi_b, B0 + b);
-        }
-        __syncthreads();
-        if (tid < ne)
-            for (int k = offa_s[tid]; k < offa_s[tid + 1]; ++k) aev_s[k] = static_cast<uint16_t>(tid);
-        __syncthreads();
-        for (int a = tid; a < na; a += MB) {
-            const int ev = aev_s[a];
-            const float ea = ldf(eta_a, A0 + a), pa = ldf(phi_a, A0 + a);
-            const int b0 = offb_s[ev], b1 = offb_s[ev + 1];
-            float best = INFINITY;
-            int32_t bi = -1;
-            for (int b = b0; b < b1; ++b) {
-                const float d2 = delta_r2(ea, pa, beta_s[b], bphi_s[b]);
-                if (d2 < best) {
-                    best = d2;
-                    bi = b - b0;
-                }
+        float veb[MKB], vpb[MKB];
+#pragma unroll
+        for (int k = 0; k < MKB; ++k) {
+            const int i = lane + 64 * k;
+            veb[k] = vpb[k] = 0.0f;
+            if (i < nb) {
+                veb[k] = ldf(eta_b, B0 + i);
+                vpb[k] = ldf(phi_b, B0 + i);
+                if (mask_b && !mask_b[B0 + i]) veb[k] = __builtin_nanf("");
             }
-            if (min_dr2) min_dr2[A0 + a] = best;
-            if (idx_b) idx_b[A0 + a] = bi;
-            if (clean) clean[A0 + a] = ((!mask_a || mask_a[A0 + a]) && !(best <= thr2)) ? 1 : 0;
         }
-        __syncthreads();
+        float vea[MKA], vpa[MKA];
+        bool oka[MKA];
+#pragma unroll
+        for (int k = 0; k < MKA; ++k) {
+            const int i = lane + 64 * k;
+            vea[k] = vpa[k] = 0.0f;
+            oka[k] = true;
+            if (i < na) {
+                vea[k] = ldf(eta_a, A0 + i);
+                vpa[k] = ldf(phi_a, A0 + i);
+                if (mask_a) oka[k] = mask_a[A0 + i] != 0;
+            }
+        }
+        // ---- b objects and the per-a b ranges into LDS
+#pragma unroll
+        for (int k = 0; k < MKB; ++k) {
+            const int i = lane + 64 * k;
+            if (i < nb) {
+                be[i] = veb[k];
+                bp[i] = vpb[k];
+            }
+        }
+        if (lane < ne) {
+            const uint32_t pk = static_cast<uint32_t>(bb) | (static_cast<uint32_t>(bn) << 16);
+            for (int k = ab; k < ae; ++k) ar[k] = pk;
+        }
+        wave_fence_dr();
+        // ---- one lane per a object
+#pragma unroll
+        for (int k = 0; k < MKA; ++k) {
+            const int i = lane + 64 * k;
+            if (i < na) {
+                const uint32_t pk = ar[i];
+                const int b0 = static_cast<int>(pk & 0xffffu), b1 = b0 + static_cast<int>(pk >> 16);
+                float best = INFINITY;
+                int32_t bi = -1;
+                for (int b = b0; b < b1; ++b) {
+                    const float d2 = delta_r2(vea[k], vpa[k], be[b], bp[b]);
+                    if (d2 < best) {
+                        best = d2;
+                        bi = b - b0;
+                    }
+                }
+                const int64_t a = A0 + i;
+                if (min_dr2) min_dr2[a] = best;
+                if (idx_b) idx_b[a] = bi;
+                if (clean) clean[a] = (oka[k] && !(best <= thr2)) ? 1 : 0;
+            }
+        }
+        wave_fence_dr();  // the next tile overwrites the staging
     }
 }
 
@@ -116,15 +162,15 @@ extern "C" int hepk_match_dr(const int64_t *off_a, const void *eta_a, const void
     }
     if (n_events == 0 || (!min_dr2 && !idx_b && !clean_out)) return HEPK_OK;
     const float thr2 = dr * dr;  // rounded once to float32
-    const int64_t n_tiles = ceil_div(n_events, MB);
-    const int grid = static_cast<int>(std::min<int64_t>(n_tiles, 8 * device_cus()));
+    const int64_t n_tiles = ceil_div(n_events, 64);
+    const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n_tiles, MW), 16 * device_cus()));
     if (dtype == HEPK_F16)
-        match_dr_kernel<_Float16><<<grid, MB, 0, stream>>>(
+        match_dr_kernel<_Float16><<<grid, 64 * MW, 0, stream>>>(
             off_a, static_cast<const _Float16 *>(eta_a), static_cast<const _Float16 *>(phi_a), mask_a, off_b,
             static_cast<const _Float16 *>(eta_b), static_cast<const _Float16 *>(phi_b), mask_b, n_events, thr2,
             min_dr2, idx_b, clean_out);
     else
-        match_dr_kernel<float><<<grid, MB, 0, stream>>>(
+        match_dr_kernel<float><<<grid, 64 * MW, 0, stream>>>(
             off_a, static_cast<const float *>(eta_a), static_cast<const float *>(phi_a), mask_a, off_b,
             static_cast<const float *>(eta_b), static_cast<const float *>(phi_b), mask_b, n_events, thr2,
             min_dr2, idx_b, clean_out);

@@ -2,19 +2,25 @@
 // (Sec. III: the H_T kernel of Listing 1 and the count/sum/max/min-within-
 // offsets kernels).
 //
-// A workgroup takes a tile of RB consecutive events.  Their objects form one
-// contiguous content range, which is staged through LDS in chunks of RCH with
-// coalesced loads; then one lane per event walks its own objects in order.
-// Walking in order keeps the float32 sum identical to the left-to-right sum
-// of Listing 1's inner loop (a tree would round differently), and gives the
-// lowest index on max/min ties.  Counts feed an optional exclusive scan that
-// yields the offsets of the selected sub-collection.
+// Each wavefront owns tiles of 64 consecutive events and works through them
+// without waiting for the rest of its workgroup.  For one tile it reads the
+// tile's object range with two scalar loads, then issues every load of the
+// tile at once -- both offsets and the event mask of each event lane, and up
+// to RK objects (content and object mask) per lane, consecutive lanes on
+// consecutive objects -- stages the objects in its own LDS region, and lets
+// one lane per event walk its objects in order.  Walking in order keeps the
+// float32 sum identical to the left-to-right sum of Listing 1's inner loop (a
+// tree would round differently), and gives the lowest index on max/min ties.
+// A tile with more than 64 * RK objects is walked straight from HBM, one lane
+// per event, with the same arithmetic.  Counts can feed an exclusive scan
+// that yields the offsets of the selected sub-collection.
 #include "common.hpp"
 
 namespace hepk {
 
-constexpr int RB = 256;    // events per tile == threads per workgroup
-constexpr int RCH = 4096;  // objects staged per chunk
+constexpr int RB = 256;  // threads per workgroup; events per tile of the offsets scan
+constexpr int RW = RB / 64;
+constexpr int RK = 8;    // objects per lane staged for one tile (512 per tile)
 
 enum { R_COUNT = 0, R_SUM = 1, R_MAX = 2, R_MIN = 3 };
 
@@ -33,85 +39,122 @@ __device__ int64_t block_inclusive_scan(int64_t v, int64_t *buf) {
     return v;
 }
 
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Running reduction of one event.
+template <int OP>
+struct Acc {
+    int32_t cnt = 0;
+    float sum = 0.0f;
+    float best = (OP == R_MAX) ? -INFINITY : INFINITY;
+    int32_t bi = -1;
+    __device__ __forceinline__ void add(float v, bool keep, int32_t k) {
+        if (!keep) return;
+        if (OP == R_COUNT) {
+            ++cnt;
+        } else if (OP == R_SUM) {
+            sum = sum + v;
+        } else {
+            const bool better = (OP == R_MAX) ? (v > best) : (v < best);
+            if (bi < 0 || better) {
+                best = v;
+                bi = k;
+            }
+        }
+    }
+};
+
 template <typename T, int OP>
 __global__ __launch_bounds__(RB) void reduce_kernel(const int64_t *__restrict__ off, int64_t n_events,
                                                     const T *__restrict__ content,
                                                     const uint8_t *__restrict__ obj_mask,
                                                     const uint8_t *__restrict__ evt_mask, void *out,
-                                                    int32_t *out_arg, int index_only, int64_t *tile_tot) {
-    __shared__ int64_t off_s[RB + 1];
-    __shared__ float val_s[(OP == R_COUNT) ? 1 : RCH];
-    __shared__ uint8_t msk_s[RCH];
-    __shared__ int64_t scan_s[RB];
-    const int tid = threadIdx.x;
-    const int64_t n_tiles = ceil_div(n_events, RB);
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t e0 = tile * RB;
-        const int ne = static_cast<int>(n_events - e0 < RB ? n_events - e0 : RB);
-        const int64_t A = off[e0];
-        const int64_t B = off[e0 + ne];
-        if (tid < ne) off_s[tid] = off[e0 + tid] - A;
-        if (tid == 0) off_s[ne] = B - A;
-        __syncthreads();
-        const bool act = tid < ne;
-        const int64_t e = e0 + tid;
-        const bool take = act && (!evt_mask || evt_mask[e] != 0);
-        const int64_t a0 = act ? off_s[tid] : 0;
-        const int64_t a1 = act ? off_s[tid + 1] : 0;
-        int32_t cnt = 0;
-        float acc = 0.0f;
-        float best = (OP == R_MAX) ? -INFINITY : INFINITY;
-        int32_t bi = -1;
-        if (OP == R_COUNT && !obj_mask) {
-            cnt = take ? static_cast<int32_t>(a1 - a0) : 0;
-        } else {
-            const int64_t tot = B - A;
-            for (int64_t c0 = 0; c0 < tot; c0 += RCH) {
-                const int clen = static_cast<int>(tot - c0 < RCH ? tot - c0 : RCH);
-                for (int i = tid; i < clen; i += RB) {
-                    if (OP != R_COUNT) val_s[i] = ldf(content, A + c0 + i);
-                    msk_s[i] = obj_mask ? obj_mask[A + c0 + i] : 1;
+                                                    int32_t *out_arg, int index_only) {
+    __shared__ float val_s[RW][(OP == R_COUNT) ? 1 : 64 * RK];
+    __shared__ uint8_t msk_s[RW][64 * RK];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float *vs = val_s[wave];
+    uint8_t *ms = msk_s[wave];
+    const int64_t n_tiles = ceil_div(n_events, 64);
+    const bool walk_objects = !(OP == R_COUNT && !obj_mask);
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * RW + wave; t < n_tiles;
+         t += static_cast<int64_t>(gridDim.x) * RW) {
+        const int64_t e0 = t * 64;
+        const int ne = static_cast<int>(min<int64_t>(64, n_events - e0));
+        const int64_t A = as_const(off)[e0];
+        const int64_t tot = as_const(off)[e0 + ne] - A;
+        const int64_t e = e0 + lane;
+        const bool act = lane < ne;
+        int64_t a0 = 0, a1 = 0;  // the event's objects, relative to the tile's first
+        bool take = false;
+        if (act) {
+            a0 = off[e] - A;
+            a1 = off[e + 1] - A;
+            take = !evt_mask || evt_mask[e] != 0;
+        }
+        Acc<OP> r;
+        if (!walk_objects) {
+            r.cnt = take ? static_cast<int32_t>(a1 - a0) : 0;
+        } else if (tot <= 64 * RK) {
+            const int n = static_cast<int>(tot);
+            float v[RK];
+            uint8_t mk[RK];
+#pragma unroll
+            for (int k = 0; k < RK; ++k) {
+                const int i = lane + 64 * k;
+                v[k] = 0.0f;
+                mk[k] = 1;
+                if (i < n) {
+                    if (OP != R_COUNT) v[k] = ldf(content, A + i);
+                    if (obj_mask) mk[k] = obj_mask[A + i];
                 }
-                __syncthreads();
-                if (take) {
-                    const int64_t k0 = a0 > c0 ? a0 : c0;
-                    const int64_t k1 = a1 < c0 + clen ? a1 : c0 + clen;
-                    for (int64_t k = k0; k < k1; ++k) {
-                        const int kk = static_cast<int>(k - c0);
-                        if (!msk_s[kk]) continue;
-                        if (OP == R_COUNT) {
-                            ++cnt;
-                        } else if (OP == R_SUM) {
-                            acc = acc + val_s[kk];
-                        } else {
-                            const float v = val_s[kk];
-                            const bool better = (OP == R_MAX) ? (v > best) : (v < best);
-                            if (bi < 0 || better) {
-                                best = v;
-                                bi = static_cast<int32_t>(k - a0);
-                            }
-                        }
-                    }
-                }
-                __syncthreads();
             }
+#pragma unroll
+            for (int k = 0; k < RK; ++k) {
+                const int i = lane + 64 * k;
+                if (i < n) {
+                    if (OP != R_COUNT) vs[i] = v[k];
+                    ms[i] = mk[k];
+                }
+            }
+            wave_fence();
+            const int b0 = static_cast<int>(a0), b1 = static_cast<int>(a1);  // within the tile's 512
+            if (take)
+                for (int k = b0; k < b1; ++k) r.add(OP != R_COUNT ? vs[k] : 0.0f, ms[k] != 0, k - b0);
+            wave_fence();  // the next tile overwrites the staging
+        } else if (take) {
+            for (int64_t k = a0; k < a1; ++k)
+                r.add(OP != R_COUNT ? ldf(content, A + k) : 0.0f, !obj_mask || obj_mask[A + k] != 0,
+                      static_cast<int32_t>(k - a0));
         }
         if (act) {
             if (OP == R_COUNT) {
-                static_cast<int32_t *>(out)[e] = cnt;
+                static_cast<int32_t *>(out)[e] = r.cnt;
             } else if (OP == R_SUM) {
-                static_cast<float *>(out)[e] = acc;
+                static_cast<float *>(out)[e] = r.sum;
             } else if (index_only) {
-                static_cast<int32_t *>(out)[e] = bi;
+                static_cast<int32_t *>(out)[e] = r.bi;
             } else {
-                static_cast<float *>(out)[e] = best;
-                if (out_arg) out_arg[e] = bi;
+                static_cast<float *>(out)[e] = r.best;
+                if (out_arg) out_arg[e] = r.bi;
             }
         }
-        if (OP == R_COUNT && tile_tot) {
-            int64_t incl = block_inclusive_scan(act ? cnt : 0, scan_s);
-            if (tid == RB - 1) tile_tot[tile] = incl;
-        }
+    }
+}
+
+// tile_tot[tile] = sum of the counts of events [tile * RB, tile * RB + RB).
+__global__ __launch_bounds__(RB) void tile_sums_kernel(const int32_t *counts, int64_t n_events, int64_t *tile_tot) {
+    __shared__ int64_t scan_s[RB];
+    const int64_t n_tiles = ceil_div(n_events, RB);
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t e = tile * RB + threadIdx.x;
+        const int64_t incl = block_inclusive_scan(e < n_events ? counts[e] : 0, scan_s);
+        if (threadIdx.x == RB - 1) tile_tot[tile] = incl;
         __syncthreads();
     }
 }
@@ -161,11 +204,17 @@ template <typename T, int OP>
 static int launch_reduce(const int64_t *off, int64_t n, const void *content, const uint8_t *om,
                          const uint8_t *em, void *out, int32_t *out_arg, int index_only, int64_t *tile_tot,
                          hipStream_t stream) {
-    const int64_t n_tiles = ceil_div(n, RB);
-    const int grid = static_cast<int>(std::min<int64_t>(n_tiles, 8 * device_cus()));
+    const int64_t n_wave_tiles = ceil_div(n, 64);
+    const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n_wave_tiles, RW), 16 * device_cus()));
     reduce_kernel<T, OP><<<grid, RB, 0, stream>>>(off, n, static_cast<const T *>(content), om, em, out,
-                                                  out_arg, index_only, tile_tot);
-    return check_launch("hepk_reduce");
+                                                  out_arg, index_only);
+    int rc = check_launch("hepk_reduce");
+    if (rc == HEPK_OK && tile_tot) {
+        const int g = static_cast<int>(std::min<int64_t>(ceil_div(n, RB), 8 * device_cus()));
+        tile_sums_kernel<<<g, RB, 0, stream>>>(static_cast<const int32_t *>(out), n, tile_tot);
+        rc = check_launch("hepk_reduce tile sums");
+    }
+    return rc;
 }
 
 }  // namespace hepk
