@@ -42,12 +42,24 @@ __global__ __launch_bounds__(64 * MW) void match_dr_kernel(
     float *be = beta_s[wave], *bp = bphi_s[wave];
     uint32_t *ar = arng_s[wave];
     const int64_t n_tiles = ceil_div(n_events, 64);
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * MW + wave; t < n_tiles;
-         t += static_cast<int64_t>(gridDim.x) * MW) {
+    const int64_t step = static_cast<int64_t>(gridDim.x) * MW;
+    // the object ranges of a tile are fetched one tile ahead (scalar loads
+    // that overlap the current tile's work)
+    int64_t nb4[4] = {0, 0, 0, 0};
+    auto bounds = [&](int64_t t) {
+        const int64_t e0 = t * 64, e1 = e0 + min<int64_t>(64, n_events - e0);
+        nb4[0] = as_const(off_a)[e0];
+        nb4[1] = as_const(off_a)[e1];
+        nb4[2] = as_const(off_b)[e0];
+        nb4[3] = as_const(off_b)[e1];
+    };
+    int64_t t = static_cast<int64_t>(blockIdx.x) * MW + wave;
+    if (t < n_tiles) bounds(t);
+    for (; t < n_tiles; t += step) {
         const int64_t e0 = t * 64;
         const int ne = static_cast<int>(min<int64_t>(64, n_events - e0));
-        const int64_t A0 = as_const(off_a)[e0], A1 = as_const(off_a)[e0 + ne];
-        const int64_t B0 = as_const(off_b)[e0], B1 = as_const(off_b)[e0 + ne];
+        const int64_t A0 = nb4[0], A1 = nb4[1], B0 = nb4[2], B1 = nb4[3];
+        if (t + step < n_tiles) bounds(t + step);
         const int64_t e = e0 + lane;
         if (A1 - A0 > 64 * MKA || B1 - B0 > 64 * MKB) {
             // direct path: one lane per event, everything from HBM

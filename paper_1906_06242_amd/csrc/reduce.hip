@@ -82,12 +82,23 @@ __global__ __launch_bounds__(RB) void reduce_kernel(const int64_t *__restrict__ 
     uint8_t *ms = msk_s[wave];
     const int64_t n_tiles = ceil_div(n_events, 64);
     const bool walk_objects = !(OP == R_COUNT && !obj_mask);
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * RW + wave; t < n_tiles;
-         t += static_cast<int64_t>(gridDim.x) * RW) {
+    const int64_t step = static_cast<int64_t>(gridDim.x) * RW;
+    // the object range of a tile is fetched one tile ahead (scalar loads that
+    // overlap the current tile's work)
+    auto bounds = [&](int64_t t, int64_t &lo, int64_t &hi) {
+        const int64_t e0 = t * 64;
+        lo = as_const(off)[e0];
+        hi = as_const(off)[e0 + min<int64_t>(64, n_events - e0)];
+    };
+    int64_t t = static_cast<int64_t>(blockIdx.x) * RW + wave;
+    int64_t nA = 0, nB = 0;
+    if (t < n_tiles) bounds(t, nA, nB);
+    for (; t < n_tiles; t += step) {
         const int64_t e0 = t * 64;
         const int ne = static_cast<int>(min<int64_t>(64, n_events - e0));
-        const int64_t A = as_const(off)[e0];
-        const int64_t tot = as_const(off)[e0 + ne] - A;
+        const int64_t A = nA;
+        const int64_t tot = nB - nA;
+        if (t + step < n_tiles) bounds(t + step, nA, nB);
         const int64_t e = e0 + lane;
         const bool act = lane < ne;
         int64_t a0 = 0, a1 = 0;  // the event's objects, relative to the tile's first

@@ -2,9 +2,10 @@
 // (Sec. III object/event masks; Sec. IV object selection on pt and eta,
 // event selection on event variables).
 //
-// Elementwise and HBM-bound: each thread owns 4 consecutive rows, so the
-// mask is written as one 32-bit store per thread and every column read is a
-// fully used 1 KiB span per wavefront instruction.
+// Elementwise and HBM-bound: each thread owns 4 consecutive rows, reads them
+// from every cut's column with one 16-byte (float32, int32) or 8-byte
+// (float16) load -- all cuts' loads issued before any compare -- and writes
+// the 4 mask bytes as one 32-bit store.
 #include "common.hpp"
 
 namespace hepk {
@@ -38,17 +39,48 @@ __device__ __forceinline__ bool row_passes(const SelectArgs &a, int64_t i) {
     return ok;
 }
 
-// Rows [0, 4*n4) in groups of four; mask_in/mask_out 4-byte aligned.
-__global__ void select_vec4_kernel(SelectArgs a, int64_t n4, const uint32_t *mask_in, uint32_t *mask_out) {
+// Rows [0, 4*n4) in groups of four; mask_in/mask_out 4-byte aligned, columns
+// 16-byte (float32, int32) or 8-byte (float16) aligned.
+__global__ __launch_bounds__(256) void select_vec4_kernel(SelectArgs a, int64_t n4, const uint32_t *mask_in,
+                                                          uint32_t *mask_out) {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n4; g += stride) {
-        uint32_t m = mask_in ? mask_in[g] : 0x01010101u;
+        uint4 raw[HEPK_MAX_CUTS];
+#pragma unroll
+        for (int k = 0; k < HEPK_MAX_CUTS; ++k) {
+            if (k < a.n_cuts) {
+                const CutDev &c = a.cut[k];
+                if (c.dtype == HEPK_F16) {
+                    const uint2 h = static_cast<const uint2 *>(c.col)[g];
+                    raw[k] = make_uint4(h.x, h.y, 0u, 0u);
+                } else {
+                    raw[k] = static_cast<const uint4 *>(c.col)[g];
+                }
+            }
+        }
+        const uint32_t m = mask_in ? mask_in[g] : 0x01010101u;
         uint32_t out = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            bool in = ((m >> (8 * k)) & 0xffu) != 0;
-            bool p = in && row_passes(a, 4 * g + k);
-            out |= (p ? 1u : 0u) << (8 * k);
+        for (int r = 0; r < 4; ++r) {
+            bool p = ((m >> (8 * r)) & 0xffu) != 0;
+#pragma unroll
+            for (int k = 0; k < HEPK_MAX_CUTS; ++k) {
+                if (k < a.n_cuts) {
+                    const CutDev &c = a.cut[k];
+                    const uint32_t w[4] = {raw[k].x, raw[k].y, raw[k].z, raw[k].w};
+                    bool q;
+                    if (c.dtype == HEPK_I32) {
+                        q = cmp_i(static_cast<int32_t>(w[r]), c.op, c.ithr);
+                    } else if (c.dtype == HEPK_F16) {
+                        const uint16_t bits16 = static_cast<uint16_t>(w[r >> 1] >> (16 * (r & 1)));
+                        q = cmp_f(static_cast<float>(__builtin_bit_cast(_Float16, bits16)), c.op, c.thr);
+                    } else {
+                        q = cmp_f(__builtin_bit_cast(float, w[r]), c.op, c.thr);
+                    }
+                    p = p && q;
+                }
+            }
+            out |= (p ? 1u : 0u) << (8 * r);
         }
         mask_out[g] = out;
     }
@@ -87,9 +119,11 @@ extern "C" int hepk_select(const hepk_cut *cuts, int32_t n_cuts, int64_t n, cons
     }
     if (n == 0) return HEPK_OK;
     const int block = 256;
-    const int max_grid = 8 * device_cus();
-    const bool aligned = (reinterpret_cast<uintptr_t>(mask_out) % 4 == 0) &&
-                         (!mask_in || reinterpret_cast<uintptr_t>(mask_in) % 4 == 0);
+    const int max_grid = 64 * device_cus();
+    bool aligned = (reinterpret_cast<uintptr_t>(mask_out) % 4 == 0) &&
+                   (!mask_in || reinterpret_cast<uintptr_t>(mask_in) % 4 == 0);
+    for (int k = 0; k < n_cuts; ++k)
+        aligned = aligned && reinterpret_cast<uintptr_t>(cuts[k].col) % (cuts[k].dtype == HEPK_F16 ? 8 : 16) == 0;
     int64_t done = 0;
     if (aligned && n >= 4) {
         const int64_t n4 = n / 4;
