@@ -201,7 +201,9 @@ typedef struct hepk_query {
 } hepk_query;
 
 /* Launch configuration of the fused kernel.  block: threads per workgroup
- * (256 or 512); ev_per_thread: events per thread in a tile (1 or 2); hist_mode:
+ * (256, 512 or 1024; 1024 with ev_per_thread 1 only: the workgroups that
+ * share one LDS copy of many histograms); ev_per_thread: events per thread in
+ * a tile (1 or 2); hist_mode:
  * 0 = per-workgroup LDS histograms merged with global atomics, 1 = global
  * atomics only; grid: workgroups (0: enough to fill the device). */
 typedef struct hepk_tune {
@@ -226,7 +228,9 @@ int hepk_plan_create(const hepk_dataset *ds /* host, n_ds */, int32_t n_ds,
 
 /* Options of hepk_plan_create_ex (zero-initialised: hepk_plan_create). */
 typedef struct hepk_plan_opts {
-    hepk_tune tune;          /* block == 0: the default launch configuration */
+    hepk_tune tune;          /* block == 0: the default launch configuration
+                                (block 512, or 1024 when a query has several
+                                scales; one event per thread; LDS histograms) */
     int32_t shared_hist;     /* 1: all datasets accumulate into one set of histograms
                                 (the layout of dataset 0), e.g. the chunks of one sample */
     int32_t reserve_bins;    /* > 0: every query slot reserves reserve_bins bins per
@@ -275,7 +279,8 @@ int hepk_pipeline_graph(hepk_plan p, double *sumw, uint64_t *counts, hipStream_t
 
 /* Launch-configuration search (Sec. IV: kernel scheduling was the bottleneck
  * of the paper's GPU runs).  Times the fused pass over ds/q for every
- * candidate -- block 256/512, 1 or 2 events per thread, LDS or global-atomic
+ * candidate -- block 256/512 with 1 or 2 events per thread, block 1024 with
+ * one, LDS or global-atomic
  * histograms -- with `reps` timed runs each (after one warm-up) and returns
  * the fastest in *best and its median time in *best_ms (host).  sumw/counts
  * are scratch histogram buffers of hepk_plan_hist_slots entries for this

@@ -241,11 +241,18 @@ extern "C" int hepk_plan_create_ex(const hepk_dataset *ds, int32_t n_ds, const h
     }
     hepk_plan_opts o{};
     if (opts) o = *opts;
+    // default launch shape: 512 threads; 1024 when a query has several
+    // jet-energy scales (one LDS copy of their many histograms shared by 16
+    // wavefronts instead of 8)
+    int32_t q_scales = 1;
+    for (int i = 0; i < n_query; ++i) q_scales = std::max(q_scales, q[i].n_scale);
     hepk_tune t = o.tune;
-    if (t.block == 0) t = hepk_tune{512, 1, 0, 0};
-    HEPK_REQUIRE(t.block == 256 || t.block == 512, "hepk_plan_create: block %d not 256 or 512", t.block);
+    if (t.block == 0) t = hepk_tune{q_scales > 1 ? 1024 : 512, 1, 0, 0};
+    HEPK_REQUIRE(t.block == 256 || t.block == 512 || t.block == 1024,
+                 "hepk_plan_create: block %d not 256, 512 or 1024", t.block);
     HEPK_REQUIRE(t.ev_per_thread == 1 || t.ev_per_thread == 2, "hepk_plan_create: ev_per_thread %d not 1 or 2",
                  t.ev_per_thread);
+    HEPK_REQUIRE(t.block < 1024 || t.ev_per_thread == 1, "hepk_plan_create: block 1024 takes ev_per_thread 1");
     HEPK_REQUIRE(t.hist_mode == 0 || t.hist_mode == 1, "hepk_plan_create: hist_mode %d not 0 or 1", t.hist_mode);
     HEPK_REQUIRE(t.grid >= 0, "hepk_plan_create: grid < 0");
     HEPK_REQUIRE(o.reserve_bins >= 0 && o.reserve_bins < (1 << 20), "hepk_plan_create: reserve_bins out of range");
@@ -621,8 +628,8 @@ extern "C" int hepk_autotune(const hepk_dataset *ds, int32_t n_ds, const hepk_qu
     clear_error();
     HEPK_REQUIRE(best && sumw && counts, "hepk_autotune: NULL argument");
     HEPK_REQUIRE(reps >= 1 && reps <= 1000, "hepk_autotune: reps %d out of [1, 1000]", reps);
-    const hepk_tune cands[] = {{256, 1, 0, 0}, {512, 1, 0, 0}, {256, 2, 0, 0}, {512, 2, 0, 0},
-                               {256, 1, 1, 0}, {512, 1, 1, 0}, {256, 2, 1, 0}, {512, 2, 1, 0}};
+    const hepk_tune cands[] = {{256, 1, 0, 0}, {512, 1, 0, 0}, {1024, 1, 0, 0}, {256, 2, 0, 0}, {512, 2, 0, 0},
+                               {256, 1, 1, 0}, {512, 1, 1, 0}, {1024, 1, 1, 0}, {256, 2, 1, 0}, {512, 2, 1, 0}};
     hipEvent_t e0, e1;
     HEPK_HIP(hipEventCreate(&e0));
     HEPK_HIP(hipEventCreate(&e1));

@@ -278,11 +278,15 @@ struct Caps {
     static constexpr int MK = 2 * EVPL + 1;          // muon slots per lane
     static constexpr int EK = EXT ? 2 * EVPL : 1;    // electron slots per lane
     static constexpr int JC = 64 * JK, MC = 64 * MK, EC = 64 * EK;
+    // both lepton ranges of a jet in one word (8-bit first and count each)
+    // when the tile caps allow it
+    static constexpr bool PACK = EXT && MC <= 255 && EC <= 255;
 };
 
 // One wavefront's LDS.  jr holds, per jet, its event's range of selected
-// muons (first | count << 16) until the cone test reads it; the same word
-// then holds the jet's pt (or NaN) for the per-event walk.
+// muons (first | count << 16; with PACK, muons in the low and electrons in
+// the high 16 bits, first | count << 8 each) until the cone test reads it;
+// the same word then holds the jet's pt (or NaN) for the per-event walk.
 template <int EVPL, bool EXT>
 struct WaveLds {
     using C = Caps<EVPL, EXT>;
@@ -290,16 +294,21 @@ struct WaveLds {
         uint32_t rng;
         float pt;
     } jr[C::JC];
-    uint32_t jre[EXT ? C::JC : 1];   // same for selected electrons
-    float seta[C::MC], sphi[C::MC];  // selected muons, compacted in tile order
+    uint32_t jre[(EXT && !C::PACK) ? C::JC : 1];  // electron ranges when not packed
+    float seta[C::MC], sphi[C::MC];                // selected muons, compacted in tile order
     float sea[EXT ? C::EC : 1], sep[EXT ? C::EC : 1];
-    uint16_t mpre[C::MC + 1];        // selected muons before muon m
-    uint16_t epre[EXT ? C::EC + 1 : 1];
     uint8_t bt[EXT ? C::JC : 1];
-    // eligible events (compacted), for queries with several jet-energy
-    // scales: jet range (first | end << 16) and weight
-    uint32_t evjr[C::TW];
-    float evw[C::TW];
+    union {
+        struct {  // steps 2-3: selected leptons before lepton m
+            uint16_t mpre[C::MC + 1];
+            uint16_t epre[EXT ? C::EC + 1 : 1];
+        } p;
+        struct {  // step 5, several scales: eligible events (compacted),
+                  // jet range (first | end << 16) and weight
+            uint32_t evjr[C::TW];
+            float evw[C::TW];
+        } w;
+    } u;
 };
 
 // Adds weight w to the histograms of scales v0 + n / 3 (observable n % 3)
@@ -314,7 +323,8 @@ __device__ __forceinline__ void fill_bins(const HistSink<LDSH> &sink, const Fill
         if (pass[n / 3] && xs[n] == xs[n]) sink.add(F.base + (v0 + n / 3) * F.per + F.off[n % 3] + sl[n], w);
 }
 
-// Scales per lane in the walk over an event's jets when a query has several.
+// Scales per lane in the walk over an event's jets when a query has several
+// (even: the fills take them two at a time).
 constexpr int kG = 4;
 
 // Walks the jets [j0, j1) of one event in order (pt of each in LDS, NaN when
@@ -582,14 +592,14 @@ pipeline_kernel(PipeArgs P) {
                     for (int k = 0; k < MK; ++k)
                         sel[k] = (lane + 64 * k < nm) && mpt[k] > Q.mu_pt && fabsf(meta[k]) < Q.mu_abseta &&
                                  (!has_iso || miso[k] < Q.mu_iso);
-                    compact<MK>(sel, meta, mphi, nm, lane, L.seta, L.sphi, L.mpre);
+                    compact<MK>(sel, meta, mphi, nm, lane, L.seta, L.sphi, L.u.p.mpre);
                 }
                 if (EXT) {
                     bool sel[EK];
 #pragma unroll
                     for (int k = 0; k < EK; ++k)
                         sel[k] = (lane + 64 * k < nl) && lpt[k] > Q.el_pt && fabsf(leta[k]) < Q.el_abseta;
-                    compact<EK>(sel, leta, lphi, nl, lane, L.sea, L.sep, L.epre);
+                    compact<EK>(sel, leta, lphi, nl, lane, L.sea, L.sep, L.u.p.epre);
                 }
                 wave_sync();
                 // query fields used from here on, read once (pinned: reloading
@@ -607,20 +617,21 @@ pipeline_kernel(PipeArgs P) {
                     nmu[r] = 0;
                     const int ev = lane + 64 * r;
                     if (ev < ne) {
-                        const int s0 = L.mpre[mb[r]];
-                        nmu[r] = L.mpre[me[r]] - s0;
+                        const int s0 = L.u.p.mpre[mb[r]];
+                        nmu[r] = L.u.p.mpre[me[r]] - s0;
                         const bool elig = nmu[r] >= min_mu && je[r] - jb[r] >= min_jet;
-                        const uint32_t pk =
-                            static_cast<uint32_t>(s0) | (static_cast<uint32_t>(elig ? nmu[r] : 0) << 16);
+                        constexpr int CS = C::PACK ? 8 : 16;  // count shift
+                        uint32_t pk = static_cast<uint32_t>(s0) | (static_cast<uint32_t>(elig ? nmu[r] : 0) << CS);
                         uint32_t pke = 0;
                         if (EXT) {
-                            const int u0 = L.epre[lb[r]];
+                            const int u0 = L.u.p.epre[lb[r]];
                             pke = static_cast<uint32_t>(u0) |
-                                  (static_cast<uint32_t>(elig ? L.epre[le[r]] - u0 : 0) << 16);
+                                  (static_cast<uint32_t>(elig ? L.u.p.epre[le[r]] - u0 : 0) << CS);
+                            if (C::PACK) pk |= pke << 16;
                         }
                         for (int k = jb[r]; k < je[r]; ++k) {
                             L.jr[k].rng = pk;
-                            if (EXT) L.jre[k] = pke;
+                            if (EXT && !C::PACK) L.jre[C::PACK ? 0 : k] = pke;
                         }
                     }
                 }
@@ -640,8 +651,8 @@ pipeline_kernel(PipeArgs P) {
                     if (j < nj) {
                         const bool need = fabsf(jeta[k]) < jet_abseta && (jet_pt < 0.0f || jpt[k] * smax > jet_pt);
                         const uint32_t pk = L.jr[j].rng;
-                        const int c0 = static_cast<int>(pk & 0xffffu);
-                        const int c1 = c0 + (need ? static_cast<int>(pk >> 16) : 0);
+                        const int c0 = static_cast<int>(C::PACK ? (pk & 0xffu) : (pk & 0xffffu));
+                        const int c1 = c0 + (need ? static_cast<int>(C::PACK ? ((pk >> 8) & 0xffu) : (pk >> 16)) : 0);
                         bool hit = false;
                         int i = c0;
                         // two leptons per step: both LDS reads in flight before the math
@@ -652,9 +663,10 @@ pipeline_kernel(PipeArgs P) {
                         }
                         if (i < c1) hit |= delta_r2(jeta[k], jphi[k], L.seta[i], L.sphi[i]) <= thr2;
                         if (EXT) {
-                            const uint32_t pe = L.jre[j];
-                            const int u0 = static_cast<int>(pe & 0xffffu);
-                            const int u1 = u0 + (need ? static_cast<int>(pe >> 16) : 0);
+                            const uint32_t pe = C::PACK ? (pk >> 16) : L.jre[C::PACK ? 0 : j];
+                            const int u0 = static_cast<int>(C::PACK ? (pe & 0xffu) : (pe & 0xffffu));
+                            const int u1 =
+                                u0 + (need ? static_cast<int>(C::PACK ? ((pe >> 8) & 0xffu) : (pe >> 16)) : 0);
                             for (int i = u0; i < u1; ++i) hit |= delta_r2(jeta[k], jphi[k], L.sea[i], L.sep[i]) <= thr2;
                         }
                         const bool ok = need && !hit;
@@ -721,8 +733,8 @@ pipeline_kernel(PipeArgs P) {
                                                  static_cast<uint32_t>(bal >> 32),
                                                  __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bal), 0u)));
                         if (elig) {
-                            L.evjr[at] = static_cast<uint32_t>(jb[r]) | (static_cast<uint32_t>(je[r]) << 16);
-                            L.evw[at] = wv[r];
+                            L.u.w.evjr[at] = static_cast<uint32_t>(jb[r]) | (static_cast<uint32_t>(je[r]) << 16);
+                            L.u.w.evw[at] = wv[r];
                         }
                         nel += __popcll(bal);
                     }
@@ -734,7 +746,7 @@ pipeline_kernel(PipeArgs P) {
                     int e = lane / NG, g = lane - (lane / NG) * NG;
                     const int de = 64 / NG, dg = 64 - (64 / NG) * NG;
                     for (int i = lane; i < npairs; i += 64) {
-                        const uint32_t jr = L.evjr[e];
+                        const uint32_t jr = L.u.w.evjr[e];
                         float sc[kG];
 #pragma unroll
                         for (int u = 0; u < kG; ++u) sc[u] = scl[min(g * kG + u, V - 1)];
@@ -749,14 +761,16 @@ pipeline_kernel(PipeArgs P) {
                             any |= pass[u];
                         }
                         if (any) {
-                            float xs[3 * kG];
+                            // two scales' bins per search: the batch that fits the
+                            // registers of 1024-thread workgroups without spilling
+                            const double w = static_cast<double>(L.u.w.evw[e]);
 #pragma unroll
-                            for (int u = 0; u < kG; ++u) {
-                                xs[3 * u] = ht[u];
-                                xs[3 * u + 1] = lead[u];
-                                xs[3 * u + 2] = static_cast<float>(njs[u]);
+                            for (int u = 0; u < kG; u += 2) {
+                                const float xs[6] = {ht[u], lead[u], static_cast<float>(njs[u]),
+                                                     ht[u + 1], lead[u + 1], static_cast<float>(njs[u + 1])};
+                                const bool pu[2] = {pass[u], pass[u + 1]};
+                                if (pu[0] || pu[1]) fill(xs, pu, g * kG + u, w);
                             }
-                            fill(xs, pass, g * kG, static_cast<double>(L.evw[e]));
                         }
                         e += de;
                         g += dg;
@@ -812,6 +826,7 @@ static KernelFn pick_h(bool ldsh) {
 
 template <typename T, bool EXT, bool MS>
 static KernelFn pick_shape(int block, int evpt, bool ldsh) {
+    if (block == 1024) return pick_h<T, EXT, 16, 1, MS>(ldsh);  // one event per thread only
     if (block == 512) return evpt == 2 ? pick_h<T, EXT, 8, 2, MS>(ldsh) : pick_h<T, EXT, 8, 1, MS>(ldsh);
     return evpt == 2 ? pick_h<T, EXT, 4, 2, MS>(ldsh) : pick_h<T, EXT, 4, 1, MS>(ldsh);
 }

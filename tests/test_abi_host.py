@@ -131,6 +131,9 @@ def test_plan_create_rejects_bad_arguments(lib):
     assert "block" in H.last_error()
     bad = H.Tune(256, 3, 0, 0)
     assert _rc("hepk_plan_create", ds, 1, q, 1, C.byref(bad), C.byref(out)) == H.EINVAL
+    bad = H.Tune(1024, 2, 0, 0)
+    assert _rc("hepk_plan_create", ds, 1, q, 1, C.byref(bad), C.byref(out)) == H.EINVAL
+    assert "1024" in H.last_error()
     ds[0].n_events = 1 << 31
     assert _rc("hepk_plan_create", ds, 1, q, 1, None, C.byref(out)) == H.EINVAL
     assert not out.value

@@ -299,7 +299,7 @@ def test_pipeline_golden_hand_values():
 
 
 TUNES = [None, dict(block=512), dict(ev_per_thread=2), dict(block=512, ev_per_thread=2),
-         dict(hist_mode=1), dict(grid=7)]
+         dict(hist_mode=1), dict(grid=7), dict(block=1024), dict(block=1024, hist_mode=1, grid=3)]
 
 
 @pytest.mark.parametrize("tune", TUNES, ids=[str(t) for t in TUNES])
@@ -330,7 +330,8 @@ def test_pipeline_extended_schema_jes(dtype):
     assert len(got[0]) == 20
 
 
-MS_TUNES = [None, dict(block=256), dict(ev_per_thread=2), dict(block=256, ev_per_thread=2), dict(hist_mode=1)]
+MS_TUNES = [None, dict(block=256), dict(ev_per_thread=2), dict(block=256, ev_per_thread=2), dict(hist_mode=1),
+            dict(block=1024), dict(block=1024, hist_mode=1)]
 
 
 @pytest.mark.parametrize("extended", [False, True])
@@ -355,13 +356,13 @@ def test_pipeline_mixed_scale_counts(extended, tune):
 
 
 def test_pipeline_lds_beyond_device_limit_uses_global_hist():
-    """The 60 histograms of the extended query fit in LDS beside 64-event
-    tiles, not beside the 128-event tiles of 512-thread workgroups: that plan
-    must take global histograms instead of asking for more LDS than a
-    workgroup has."""
+    """60 histograms (20 scales, 130 H_T bins: 62 KB) fit in LDS beside
+    64-event tiles, not beside the 128-event tiles of 512-thread workgroups:
+    that plan must take global histograms instead of asking for more LDS than
+    a workgroup has."""
     say("pipeline LDS limit")
     ds = datagen.make_dataset(8, 20000, extended=True, content_dtype="f16")
-    q = datagen.extended_query()
+    q = datagen.Query(min_b=1, scales=datagen.jes_scales(), edges_ht=datagen.uniform_edges(130, 0.0, 2000.0))
     dd = H.DeviceDataset(ds)
     small = H.Plan([dd], [q], dict(block=512, ev_per_thread=1, hist_mode=0))
     assert small.tune["hist_mode"] == 0
