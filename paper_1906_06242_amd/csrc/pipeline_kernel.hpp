@@ -465,120 +465,145 @@ pipeline_kernel(PipeArgs P) {
         const bool has_el = EXT && D.eoff != nullptr;
         const bool has_bt = EXT && D.jbt != nullptr;
 
-        // tile bounds are fetched one tile ahead (scalar loads that overlap
-        // the current tile's vector loads)
-        int64_t t = CH.t0 + wave;
-        TileBounds nb{};
-        if (t < CH.t1) {
-            const int64_t e0 = t * TW;
-            nb = tile_bounds<EXT>(D, has_el, e0, static_cast<int>(min<int64_t>(TW, D.n_events - e0)));
-        }
-        for (; t < CH.t1; t += WAVES) {
-            const int64_t e0 = t * TW;
+        // The raw loads of one tile (the offsets as their low 32-bit words:
+        // tile-relative differences are exact modulo 2^32).
+        struct Raw {
+            uint32_t j0[EVPL], j1[EVPL], m0[EVPL], m1[EVPL], l0[EVPL], l1[EVPL];
+            float w[EVPL];
+            float jpt[JK], jeta[JK], jphi[JK], jbt[EXT ? JK : 1];
+            float mpt[MK], meta[MK], mphi[MK], miso[MK];
+            float lpt[EK], leta[EK], lphi[EK];
+        };
+        auto lo32 = [](const int64_t *p) { return *reinterpret_cast<const uint32_t *>(p); };
+        auto bounds_of = [&](int64_t tt) {
+            const int64_t e = tt * TW;
+            return tile_bounds<EXT>(D, has_el, e, static_cast<int>(min<int64_t>(TW, D.n_events - e)));
+        };
+        auto oversize = [&](const TileBounds &b) {
+            return b.J1 - b.J0 > C::JC || b.M1 - b.M0 > C::MC || b.L1 - b.L0 > C::EC;
+        };
+        // ---- 1. all of a tile's loads, without waiting: both offsets of each
+        // event lane's event, its weight, and up to JK jets, MK muons and EK
+        // electrons per lane (consecutive lanes, consecutive objects)
+        auto issue = [&](int64_t tt, const TileBounds &b, Raw &R) {
+            const int64_t e0 = tt * TW;
             const int ne = static_cast<int>(min<int64_t>(TW, D.n_events - e0));
-            const TileBounds B = nb;
-            if (t + WAVES < CH.t1) {
-                const int64_t e1 = (t + WAVES) * TW;
-                nb = tile_bounds<EXT>(D, has_el, e1, static_cast<int>(min<int64_t>(TW, D.n_events - e1)));
-            }
-            if (B.J1 - B.J0 > C::JC || B.M1 - B.M0 > C::MC || B.L1 - B.L0 > C::EC) {
-                const DsDev Dc = D;
-#pragma unroll
-                for (int r = 0; r < EVPL; ++r) {
-                    const int ev = lane + 64 * r;
-                    if (ev < ne) event_direct<T, EXT, LDSH>(P, Dc, e0 + ev, edges, sink);
-                }
-                continue;
-            }
-            const int nj = static_cast<int>(B.J1 - B.J0), nm = static_cast<int>(B.M1 - B.M0);
-            const int nl = static_cast<int>(B.L1 - B.L0);
-
-            // ---- 1. all of the tile's loads in flight at once: both offsets of
-            // each event lane's event (tile-relative), its weight, and up to JK
-            // jets, MK muons and EK electrons per lane
-            // tile-base pointers (scalar) and 32-bit lane offsets
-            const int64_t *jo = D.joff + e0, *mo = D.moff + e0, *lo = has_el ? D.eoff + e0 : nullptr;
+            const int nj = static_cast<int>(b.J1 - b.J0), nm = static_cast<int>(b.M1 - b.M0);
+            const int nl = static_cast<int>(b.L1 - b.L0);
             const float *wp = D.w ? D.w + e0 : nullptr;
-            const T *cjpt = static_cast<const T *>(D.jpt) + B.J0, *cjeta = static_cast<const T *>(D.jeta) + B.J0;
-            const T *cjphi = static_cast<const T *>(D.jphi) + B.J0;
-            const T *cjbt = has_bt ? static_cast<const T *>(D.jbt) + B.J0 : nullptr;
-            const T *cmpt = static_cast<const T *>(D.mpt) + B.M0, *cmeta = static_cast<const T *>(D.meta) + B.M0;
-            const T *cmphi = static_cast<const T *>(D.mphi) + B.M0;
-            const T *cmiso = has_iso ? static_cast<const T *>(D.miso) + B.M0 : nullptr;
-            int32_t jb[EVPL], je[EVPL], mb[EVPL], me[EVPL], lb[EVPL], le[EVPL];
-            float wv[EVPL];
 #pragma unroll
             for (int r = 0; r < EVPL; ++r) {
                 const int ev = lane + 64 * r;
-                jb[r] = je[r] = mb[r] = me[r] = lb[r] = le[r] = 0;
-                wv[r] = 1.0f;
+                R.j0[r] = R.j1[r] = R.m0[r] = R.m1[r] = R.l0[r] = R.l1[r] = 0;
+                R.w[r] = 1.0f;
                 if (ev < ne) {
-                    jb[r] = static_cast<int32_t>(jo[ev] - B.J0);
-                    je[r] = static_cast<int32_t>(jo[ev + 1] - B.J0);
-                    mb[r] = static_cast<int32_t>(mo[ev] - B.M0);
-                    me[r] = static_cast<int32_t>(mo[ev + 1] - B.M0);
+                    R.j0[r] = lo32(D.joff + e0 + ev);
+                    R.j1[r] = lo32(D.joff + e0 + ev + 1);
+                    R.m0[r] = lo32(D.moff + e0 + ev);
+                    R.m1[r] = lo32(D.moff + e0 + ev + 1);
                     if (EXT && has_el) {
-                        lb[r] = static_cast<int32_t>(lo[ev] - B.L0);
-                        le[r] = static_cast<int32_t>(lo[ev + 1] - B.L0);
+                        R.l0[r] = lo32(D.eoff + e0 + ev);
+                        R.l1[r] = lo32(D.eoff + e0 + ev + 1);
                     }
-                    if (wp) wv[r] = wp[ev];
+                    if (wp) R.w[r] = wp[ev];
                 }
             }
-            float jpt[JK] = {}, jeta[JK] = {}, jphi[JK] = {}, jbt[EXT ? JK : 1] = {};
+            const T *cjpt = static_cast<const T *>(D.jpt) + b.J0, *cjeta = static_cast<const T *>(D.jeta) + b.J0;
+            const T *cjphi = static_cast<const T *>(D.jphi) + b.J0;
+            const T *cjbt = has_bt ? static_cast<const T *>(D.jbt) + b.J0 : nullptr;
 #pragma unroll
             for (int k = 0; k < JK; ++k) {
                 const int j = lane + 64 * k;
+                R.jpt[k] = R.jeta[k] = R.jphi[k] = 0.0f;
+                if (EXT) R.jbt[EXT ? k : 0] = 0.0f;
                 if (j < nj) {
-                    jpt[k] = ldf(cjpt, j);
-                    jeta[k] = ldf(cjeta, j);
-                    jphi[k] = ldf(cjphi, j);
-                    if (EXT && has_bt) jbt[EXT ? k : 0] = ldf(cjbt, j);
+                    R.jpt[k] = ldf(cjpt, j);
+                    R.jeta[k] = ldf(cjeta, j);
+                    R.jphi[k] = ldf(cjphi, j);
+                    if (EXT && has_bt) R.jbt[EXT ? k : 0] = ldf(cjbt, j);
                 }
             }
-            float mpt[MK] = {}, meta[MK] = {}, mphi[MK] = {}, miso[MK] = {};
+            const T *cmpt = static_cast<const T *>(D.mpt) + b.M0, *cmeta = static_cast<const T *>(D.meta) + b.M0;
+            const T *cmphi = static_cast<const T *>(D.mphi) + b.M0;
+            const T *cmiso = has_iso ? static_cast<const T *>(D.miso) + b.M0 : nullptr;
 #pragma unroll
             for (int k = 0; k < MK; ++k) {
                 const int m = lane + 64 * k;
+                R.mpt[k] = R.meta[k] = R.mphi[k] = R.miso[k] = 0.0f;
                 if (m < nm) {
-                    mpt[k] = ldf(cmpt, m);
-                    meta[k] = ldf(cmeta, m);
-                    mphi[k] = ldf(cmphi, m);
-                    if (has_iso) miso[k] = ldf(cmiso, m);
+                    R.mpt[k] = ldf(cmpt, m);
+                    R.meta[k] = ldf(cmeta, m);
+                    R.mphi[k] = ldf(cmphi, m);
+                    if (has_iso) R.miso[k] = ldf(cmiso, m);
                 }
             }
-            float lpt[EK] = {}, leta[EK] = {}, lphi[EK] = {};
+#pragma unroll
+            for (int k = 0; k < EK; ++k) R.lpt[k] = R.leta[k] = R.lphi[k] = 0.0f;
             if (EXT && has_el) {
-                const T *cept = static_cast<const T *>(D.ept) + B.L0, *ceeta = static_cast<const T *>(D.eeta) + B.L0;
-                const T *cephi = static_cast<const T *>(D.ephi) + B.L0;
+                const T *cept = static_cast<const T *>(D.ept) + b.L0, *ceeta = static_cast<const T *>(D.eeta) + b.L0;
+                const T *cephi = static_cast<const T *>(D.ephi) + b.L0;
 #pragma unroll
                 for (int k = 0; k < EK; ++k) {
                     const int m = lane + 64 * k;
                     if (m < nl) {
-                        lpt[k] = ldf(cept, m);
-                        leta[k] = ldf(ceeta, m);
-                        lphi[k] = ldf(cephi, m);
+                        R.lpt[k] = ldf(cept, m);
+                        R.leta[k] = ldf(ceeta, m);
+                        R.lphi[k] = ldf(cephi, m);
                     }
                 }
             }
-            // Every value above is used here, so the compiler issues all of the
-            // tile's loads before this point and waits once, instead of sinking
-            // each load to its first use (one HBM round trip per tile).
+        };
+        // Every value of R is used here, so the compiler waits for the tile's
+        // loads at this point (once), not at each value's first use.
+        auto settle = [&](Raw &R) {
 #pragma unroll
             for (int r = 0; r < EVPL; ++r)
-                asm volatile("" ::"v"(jb[r]), "v"(je[r]), "v"(mb[r]), "v"(me[r]), "v"(wv[r]));
+                asm volatile("" ::"v"(R.j0[r]), "v"(R.j1[r]), "v"(R.m0[r]), "v"(R.m1[r]), "v"(R.w[r]));
 #pragma unroll
-            for (int k = 0; k < JK; ++k) asm volatile("" ::"v"(jpt[k]), "v"(jeta[k]), "v"(jphi[k]));
+            for (int k = 0; k < JK; ++k) asm volatile("" ::"v"(R.jpt[k]), "v"(R.jeta[k]), "v"(R.jphi[k]));
 #pragma unroll
-            for (int k = 0; k < MK; ++k) asm volatile("" ::"v"(mpt[k]), "v"(meta[k]), "v"(mphi[k]), "v"(miso[k]));
+            for (int k = 0; k < MK; ++k)
+                asm volatile("" ::"v"(R.mpt[k]), "v"(R.meta[k]), "v"(R.mphi[k]), "v"(R.miso[k]));
             if (EXT) {
 #pragma unroll
-                for (int r = 0; r < EVPL; ++r) asm volatile("" ::"v"(lb[r]), "v"(le[r]));
+                for (int r = 0; r < EVPL; ++r) asm volatile("" ::"v"(R.l0[r]), "v"(R.l1[r]));
 #pragma unroll
-                for (int k = 0; k < JK; ++k) asm volatile("" ::"v"(jbt[EXT ? k : 0]));
+                for (int k = 0; k < JK; ++k) asm volatile("" ::"v"(R.jbt[EXT ? k : 0]));
 #pragma unroll
-                for (int k = 0; k < EK; ++k) asm volatile("" ::"v"(lpt[k]), "v"(leta[k]), "v"(lphi[k]));
+                for (int k = 0; k < EK; ++k) asm volatile("" ::"v"(R.lpt[k]), "v"(R.leta[k]), "v"(R.lphi[k]));
             }
-
+        };
+        // Steps 2-5 for every query on a settled tile.
+        auto work = [&](int64_t e0, const TileBounds &B, Raw &R) {
+            const int ne = static_cast<int>(min<int64_t>(TW, D.n_events - e0));
+            const int nj = static_cast<int>(B.J1 - B.J0), nm = static_cast<int>(B.M1 - B.M0);
+            const int nl = static_cast<int>(B.L1 - B.L0);
+            int32_t jb[EVPL], je[EVPL], mb[EVPL], me[EVPL], lb[EVPL], le[EVPL];
+            float wv[EVPL];
+#pragma unroll
+            for (int r = 0; r < EVPL; ++r) {
+                const bool in = lane + 64 * r < ne;
+                jb[r] = in ? static_cast<int32_t>(R.j0[r] - static_cast<uint32_t>(B.J0)) : 0;
+                je[r] = in ? static_cast<int32_t>(R.j1[r] - static_cast<uint32_t>(B.J0)) : 0;
+                mb[r] = in ? static_cast<int32_t>(R.m0[r] - static_cast<uint32_t>(B.M0)) : 0;
+                me[r] = in ? static_cast<int32_t>(R.m1[r] - static_cast<uint32_t>(B.M0)) : 0;
+                lb[r] = (in && EXT && has_el) ? static_cast<int32_t>(R.l0[r] - static_cast<uint32_t>(B.L0)) : 0;
+                le[r] = (in && EXT && has_el) ? static_cast<int32_t>(R.l1[r] - static_cast<uint32_t>(B.L0)) : 0;
+                wv[r] = R.w[r];
+            }
+            float(&jpt)[JK] = R.jpt;
+            float(&jeta)[JK] = R.jeta;
+            float(&jphi)[JK] = R.jphi;
+            float(&jbt)[EXT ? JK : 1] = R.jbt;
+            float(&mpt)[MK] = R.mpt;
+            float(&meta)[MK] = R.meta;
+            float(&mphi)[MK] = R.mphi;
+            float(&miso)[MK] = R.miso;
+            float(&lpt)[EK] = R.lpt;
+            float(&leta)[EK] = R.leta;
+            float(&lphi)[EK] = R.lphi;
+            (void)jbt;
+            (void)lpt;
             for (int q = 0; q < P.n_q; ++q) {
                 // the query's fields are read in place (scalar loads near their
                 // uses) rather than copied: a copy would hold ~45 SGPRs for the
@@ -782,6 +807,33 @@ pipeline_kernel(PipeArgs P) {
                 }
                 wave_sync();
             }
+        };
+        auto direct = [&](int64_t e0) {
+            const int ne = static_cast<int>(min<int64_t>(TW, D.n_events - e0));
+            const DsDev Dc = D;
+#pragma unroll
+            for (int r = 0; r < EVPL; ++r) {
+                const int ev = lane + 64 * r;
+                if (ev < ne) event_direct<T, EXT, LDSH>(P, Dc, e0 + ev, edges, sink);
+            }
+        };
+
+        // tile bounds are fetched one tile ahead (scalar loads that overlap
+        // the current tile's vector loads)
+        int64_t t = CH.t0 + wave;
+        TileBounds nb{};
+        if (t < CH.t1) nb = bounds_of(t);
+        for (; t < CH.t1; t += WAVES) {
+            const TileBounds B = nb;
+            if (t + WAVES < CH.t1) nb = bounds_of(t + WAVES);
+            if (oversize(B)) {
+                direct(t * TW);
+                continue;
+            }
+            Raw R;
+            issue(t, B, R);
+            settle(R);
+            work(t * TW, B, R);
         }
         // merge the LDS histograms when the next chunk is another dataset (or none)
         if (LDSH) {
