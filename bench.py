@@ -75,18 +75,76 @@ def kernel_traffic(events: int):
     return tr.get("bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(ds, q, reps: int):
-    """The oracle (one thread, as it stands) on the same events; median pass time."""
+    """The oracle (one thread, as it stands) on the same events, pinned to one
+    host core; median pass time."""
     from oracle import ref
-    times = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        ref.pipeline(ds, [q])
-        times.append(time.perf_counter() - t0)
+    old = os.sched_getaffinity(0)
+    core = min(old)
+    os.sched_setaffinity(0, {core})
+    try:
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            ref.pipeline(ds, [q])
+            times.append(time.perf_counter() - t0)
+    finally:
+        os.sched_setaffinity(0, old)
     med = statistics.median(times)
     return {"value": ds.n_events / med, "unit": "events/s", "cores": 1, "kind": "oracle",
             "sample": f"{reps} passes over the full {ds.n_events:.0e}-event workload, median "
-                      f"{med:.2f} s/pass (single-threaded C, host core of the GPU box)"}
+                      f"{med:.2f} s/pass (single-threaded C pinned to host core {core} of the GPU box)",
+            "cpu_model": cpu_model()}
+
+
+def time_flushed(fn, reps: int, stream, flush):
+    """Median HIP-event duration (ms) of fn, the last-level cache refilled by a
+    read of `flush` (>= 512 MB, clean lines: nothing to write back during the
+    timed launch) before each repetition."""
+    import torch
+    fn()
+    ms = []
+    sink = torch.empty((), dtype=flush.dtype, device=flush.device)
+    for _ in range(reps):
+        torch.sum(flush, dim=0, out=sink)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    return statistics.median(ms)
+
+
+def streaming_ceiling(stream, flush) -> dict:
+    """What plain streaming reaches on this GPU: hepk_stream_read (16-byte
+    loads, nothing else) and torch's sum over 1 GiB (read only), and a 1 GiB
+    device copy (read + write)."""
+    import torch
+    from paper_1906_06242_amd import hepk as H
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nb = x.numel() * 4
+    h_ms = time_flushed(lambda: H.stream_read(x, sink), 10, stream, flush)
+    r_ms = time_flushed(lambda: x.sum(), 10, stream, flush)
+    c_ms = time_flushed(lambda: y.copy_(x), 10, stream, flush)
+    del x, y
+    return {"read_GBps": nb / (h_ms * 1e-3) / 1e9, "torch_sum_GBps": nb / (r_ms * 1e-3) / 1e9,
+            "copy_GBps": 2 * nb / (c_ms * 1e-3) / 1e9,
+            "what": "hepk_stream_read and torch sum over 1 GiB float32 (read), 1 GiB device copy (read + write), "
+                    "median of 10, last-level cache refilled by a 512 MB read before each"}
 
 
 def time_steps(fn, steps: int, warmup: int, stream):
@@ -327,7 +385,7 @@ def main():
     ap.add_argument("--events", type=int, default=10_000_000)
     ap.add_argument("--no-plain", action="store_true", help="skip the per-kernel pipeline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--cpu-reps", type=int, default=4)
+    ap.add_argument("--cpu-reps", type=int, default=7)
     ap.add_argument("--tune", type=str, default="", help="JSON launch configuration")
     ap.add_argument("--sections", type=str, default="primitives,extended,batch,serving",
                     help="comma list of extra sections to run (primitives, extended, batch, serving) or 'none'")
@@ -367,6 +425,14 @@ def main():
     log(f"fused: {ms_step:.3f} ms/step wall, {kern_ms:.3f} ms/launch, {achieved:.0f} GB/s")
 
     traffic = kernel_traffic(args.events)
+    # the same launch with the 256 MB last-level cache refilled by other data
+    # before each of 10 repetitions (median), and what plain streaming reaches
+    flush = torch.ones(1 << 27, dtype=torch.float32, device="cuda")  # 512 MB
+    flushed_ms = time_flushed(lambda: plan.run(sumw, counts), 10, stream, flush)
+    ceiling = streaming_ceiling(stream, flush)
+    del flush
+    log(f"fused, cache flushed: {flushed_ms:.3f} ms/launch, {alg_bytes / (flushed_ms * 1e-3) / 1e9:.0f} GB/s; "
+        f"streaming read {ceiling['read_GBps']:.0f} GB/s, copy {ceiling['copy_GBps']:.0f} GB/s")
 
     out = {
         "metric": "events/s and % HBM roofline, fused vs plain pipeline; query p50/p99 latency",
@@ -387,6 +453,10 @@ def main():
                    "bytes_read_per_pass": alg_bytes, "bytes_per_event": alg_bytes / args.events},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "roofline_cache_flushed": {"ms_per_launch": flushed_ms,
+                                   "achieved": alg_bytes / (flushed_ms * 1e-3) / 1e9, "unit": "GB/s",
+                                   "frac": alg_bytes / (flushed_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "streaming_ceiling": ceiling,
     }
 
     if not args.no_plain:
@@ -412,6 +482,7 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(ds, q, args.cpu_reps)
         out["cpu_baseline"]["host_nproc"] = os.cpu_count()
+        out["cpu_baseline"]["gpu_over_one_core"] = value / out["cpu_baseline"]["value"]
         log(f"cpu oracle: {out['cpu_baseline']['value']:.3e} events/s")
     del dd, ds
     torch.cuda.empty_cache()

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define HEPK_ABI_VERSION 1
+#define HEPK_ABI_VERSION 2
 #define HEPK_MAX_CUTS 8
 
 typedef enum hepk_status {
@@ -148,6 +148,13 @@ int hepk_hist_fill(const void *x, int32_t dtype, const float *w /* nullable, n *
  * n_objects; writes the number of violations to *bad (device int64). */
 int hepk_validate_offsets(const int64_t *offsets, int64_t n_events, int64_t n_objects,
                           int64_t *bad /* device, 1 */, hipStream_t stream);
+
+/* Measurement helper, not a step of the method: reads nbytes (a multiple of
+ * 16, p 16-byte aligned) with 16-byte loads, several in flight per thread,
+ * and nothing else -- the streaming rate the HBM-bound kernels above are
+ * compared with.  *sink (device, 1) may receive a value derived from the
+ * data (a data-dependent store keeps the loads); its content is meaningless. */
+int hepk_stream_read(const void *p, int64_t nbytes, uint32_t *sink /* device, 1 */, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * The fused analysis pass.

@@ -60,6 +60,28 @@ __global__ void validate_offsets_kernel(const int64_t *off, int64_t n, int64_t m
 
 __global__ void zero_i64_kernel(int64_t *p) { *p = 0; }
 
+// Grid-stride read of n16 16-byte words, four loads in flight per thread.
+__global__ __launch_bounds__(256) void stream_read_kernel(const uint4 *__restrict__ p, int64_t n16, uint32_t key,
+                                                          uint32_t *sink) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+    int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    uint32_t acc = 0;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        uint4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = p[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+    }
+    for (; i < n16; i += stride) {
+        const uint4 v = p[i];
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
+    // data-dependent (the compiler cannot drop the loads); a match, should the
+    // data ever give one, only writes the caller's sink
+    if (acc == key) *sink = acc;
+}
+
 }  // namespace hepk
 
 extern "C" const char *hepk_last_error(void) { return hepk::g_err; }
@@ -77,4 +99,18 @@ extern "C" int hepk_validate_offsets(const int64_t *offsets, int64_t n_events, i
     validate_offsets_kernel<<<grid, 256, 0, stream>>>(offsets, n_events, n_objects,
                                                       reinterpret_cast<unsigned long long *>(bad));
     return check_launch("hepk_validate_offsets");
+}
+
+extern "C" int hepk_stream_read(const void *p, int64_t nbytes, uint32_t *sink, hipStream_t stream) {
+    using namespace hepk;
+    clear_error();
+    HEPK_REQUIRE(p && sink, "hepk_stream_read: null pointer");
+    HEPK_REQUIRE(nbytes >= 0 && nbytes % 16 == 0, "hepk_stream_read: nbytes %lld not a multiple of 16",
+                 (long long)nbytes);
+    HEPK_REQUIRE(reinterpret_cast<uintptr_t>(p) % 16 == 0, "hepk_stream_read: p not 16-byte aligned");
+    if (nbytes == 0) return HEPK_OK;
+    const int64_t n16 = nbytes / 16;
+    const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n16, 256 * 4), 8 * device_cus()));
+    stream_read_kernel<<<grid, 256, 0, stream>>>(static_cast<const uint4 *>(p), n16, 0x9e3779b9u, sink);
+    return check_launch("hepk_stream_read");
 }

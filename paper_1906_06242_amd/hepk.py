@@ -21,7 +21,7 @@ COUNT, SUM, MAX, MIN, ARGMAX, ARGMIN = range(6)
 MAX_CUTS = 8
 
 EXPORTS = (
-    "hepk_select", "hepk_reduce", "hepk_match_dr", "hepk_hist_fill", "hepk_validate_offsets",
+    "hepk_select", "hepk_reduce", "hepk_match_dr", "hepk_hist_fill", "hepk_validate_offsets", "hepk_stream_read",
     "hepk_plan_create", "hepk_plan_create_ex", "hepk_plan_set_query", "hepk_plan_hist_slots",
     "hepk_plan_hist_offset", "hepk_plan_get_tune", "hepk_pipeline", "hepk_pipeline_range",
     "hepk_pipeline_graph", "hepk_autotune", "hepk_plan_destroy", "hepk_last_error", "hepk_abi_version",
@@ -101,6 +101,7 @@ def load(path: str = LIB_PATH):
     lib.hepk_match_dr.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i32, i64, C.c_float, vp, vp, vp, vp]
     lib.hepk_hist_fill.argtypes = [vp, i32, vp, vp, i64, C.POINTER(Hist), vp]
     lib.hepk_validate_offsets.argtypes = [vp, i64, i64, vp, vp]
+    lib.hepk_stream_read.argtypes = [vp, i64, vp, vp]
     lib.hepk_plan_create.argtypes = [C.POINTER(DatasetS), i32, C.POINTER(QueryS), i32,
                                      C.POINTER(Tune), C.POINTER(vp)]
     lib.hepk_plan_create_ex.argtypes = [C.POINTER(DatasetS), i32, C.POINTER(QueryS), i32,
@@ -216,6 +217,11 @@ def validate_offsets(offsets, n_objects: int, stream=None) -> int:
     _call("hepk_validate_offsets", _ptr(offsets), offsets.numel() - 1, n_objects, _ptr(bad),
           _stream(stream))
     return int(bad.item())
+
+
+def stream_read(t, sink, stream=None):
+    """Reads all of device tensor t (measurement helper; see hepk_stream_read)."""
+    _call("hepk_stream_read", _ptr(t), t.numel() * t.element_size(), _ptr(sink), _stream(stream))
 
 
 # ---------------------------------------------------------------- fused pass

@@ -139,6 +139,15 @@ def test_plan_create_rejects_bad_arguments(lib):
     assert not out.value
 
 
+def test_stream_read_rejects_bad_arguments(lib):
+    assert _rc("hepk_stream_read", None, 16, 8, None) == H.EINVAL
+    assert _rc("hepk_stream_read", 16, 15, 8, None) == H.EINVAL
+    assert "multiple of 16" in H.last_error()
+    assert _rc("hepk_stream_read", 8, 16, 8, None) == H.EINVAL
+    assert "aligned" in H.last_error()
+    assert _rc("hepk_stream_read", 16, 0, 8, None) == H.OK
+
+
 def test_pipeline_and_queries_reject_null(lib):
     assert _rc("hepk_pipeline", None, 8, 8, None) == H.EINVAL
     n = C.c_int64()
