@@ -133,20 +133,27 @@ __device__ __forceinline__ X pin(X x) {
     return x;
 }
 
+// All fields are read first and pinned by one statement, so their loads are
+// issued together and waited for once.
 template <bool LDSH, typename QT>
 __device__ __forceinline__ FillC fill_consts(const QT &Q) {
     FillC F;
-    F.base = pin<int32_t>(LDSH ? Q.lslot0 : Q.gslot0);
-    F.per = pin<int32_t>(LDSH ? Q.lper_scale : Q.gper_scale);
+    F.base = LDSH ? Q.lslot0 : Q.gslot0;
+    F.per = LDSH ? Q.lper_scale : Q.gper_scale;
 #pragma unroll
     for (int h = 0; h < 3; ++h) {
-        F.nb[h] = pin<int32_t>(Q.nbins[h]);
-        F.eb[h] = pin<int32_t>(Q.ebase[h]);
-        F.off[h] = pin<int32_t>(LDSH ? Q.lhoff[h] : Q.ghoff[h]);
-        F.lo[h] = pin<float>(Q.lo[h]);
-        F.hi[h] = pin<float>(Q.hi[h]);
-        F.iw[h] = pin<float>(Q.inv_w[h]);
+        F.nb[h] = Q.nbins[h];
+        F.eb[h] = Q.ebase[h];
+        F.off[h] = LDSH ? Q.lhoff[h] : Q.ghoff[h];
+        F.lo[h] = Q.lo[h];
+        F.hi[h] = Q.hi[h];
+        F.iw[h] = Q.inv_w[h];
     }
+    asm volatile(""
+                 : "+s"(F.base), "+s"(F.per), "+s"(F.nb[0]), "+s"(F.nb[1]), "+s"(F.nb[2]), "+s"(F.eb[0]),
+                   "+s"(F.eb[1]), "+s"(F.eb[2]), "+s"(F.off[0]), "+s"(F.off[1]), "+s"(F.off[2]), "+s"(F.lo[0]),
+                   "+s"(F.lo[1]), "+s"(F.lo[2]), "+s"(F.hi[0]), "+s"(F.hi[1]), "+s"(F.hi[2]), "+s"(F.iw[0]),
+                   "+s"(F.iw[1]), "+s"(F.iw[2]));
     return F;
 }
 
@@ -610,28 +617,36 @@ pipeline_kernel(PipeArgs P) {
                 // whole query and spill
                 const auto &Q = as_const(P.qs)[q];
                 if (!Q.active) continue;
+                // the query's cut constants, read once and pinned by one
+                // statement (loads issued together, one wait; unpinned, the
+                // compiler reloads them inside the loops below, a wait each)
+                float mu_pt = Q.mu_pt, mu_abseta = Q.mu_abseta, mu_iso = Q.mu_iso;
+                float el_pt = EXT ? Q.el_pt : 0.0f, el_abseta = EXT ? Q.el_abseta : 0.0f;
+                float jet_pt = Q.jet_pt, thr2 = Q.thr2, jet_abseta = Q.jet_abseta, smax = Q.smax;
+                float btag = EXT ? Q.btag : 0.0f;
+                int min_mu = Q.min_mu, min_jet = Q.min_jet, min_b = has_bt ? Q.min_b : 0;
+                asm volatile(""
+                             : "+s"(mu_pt), "+s"(mu_abseta), "+s"(mu_iso), "+s"(el_pt), "+s"(el_abseta),
+                               "+s"(jet_pt), "+s"(thr2), "+s"(jet_abseta), "+s"(smax), "+s"(btag), "+s"(min_mu),
+                               "+s"(min_jet), "+s"(min_b));
                 // ---- 2. lepton selection; selected leptons compacted into LDS
+                // (all compares evaluated: no branches per slot)
                 {
                     bool sel[MK];
 #pragma unroll
                     for (int k = 0; k < MK; ++k)
-                        sel[k] = (lane + 64 * k < nm) && mpt[k] > Q.mu_pt && fabsf(meta[k]) < Q.mu_abseta &&
-                                 (!has_iso || miso[k] < Q.mu_iso);
+                        sel[k] = (lane + 64 * k < nm) & (mpt[k] > mu_pt) & (fabsf(meta[k]) < mu_abseta) &
+                                 (!has_iso | (miso[k] < mu_iso));
                     compact<MK>(sel, meta, mphi, nm, lane, L.seta, L.sphi, L.u.p.mpre);
                 }
                 if (EXT) {
                     bool sel[EK];
 #pragma unroll
                     for (int k = 0; k < EK; ++k)
-                        sel[k] = (lane + 64 * k < nl) && lpt[k] > Q.el_pt && fabsf(leta[k]) < Q.el_abseta;
+                        sel[k] = (lane + 64 * k < nl) & (lpt[k] > el_pt) & (fabsf(leta[k]) < el_abseta);
                     compact<EK>(sel, leta, lphi, nl, lane, L.sea, L.sep, L.u.p.epre);
                 }
                 wave_sync();
-                // query fields used from here on, read once (pinned: reloading
-                // them inside the loops below costs a wait each time)
-                const float jet_pt = pin<float>(Q.jet_pt);
-                const int min_mu = pin<int32_t>(Q.min_mu), min_jet = pin<int32_t>(Q.min_jet);
-                const int min_b = pin<int32_t>(has_bt ? Q.min_b : 0);
                 // ---- 3. each event lane writes its selected-lepton range over
                 // its jets; an event that cannot pass (too few muons, or too
                 // few jets before any cut) gets empty ranges: its jets' cone
@@ -667,9 +682,6 @@ pipeline_kernel(PipeArgs P) {
                 // the test and is stored as NaN.  That changes no result: a
                 // selected jet of its event has a larger pt, so the maximum
                 // and the sums and counts of selected jets are the same.
-                const float thr2 = pin<float>(Q.thr2), jet_abseta = pin<float>(Q.jet_abseta);
-                const float smax = pin<float>(Q.smax);
-                const float btag = EXT ? pin<float>(Q.btag) : 0.0f;
 #pragma unroll
                 for (int k = 0; k < JK; ++k) {
                     const int j = lane + 64 * k;
@@ -764,8 +776,9 @@ pipeline_kernel(PipeArgs P) {
                         nel += __popcll(bal);
                     }
                     wave_sync();
-                    const int V = pin<int32_t>(Q.n_scale);
-                    const float *scl = (P.scales_in_lds ? s_s : P.scales) + pin<int32_t>(Q.scale0);
+                    int V = Q.n_scale, scale0 = Q.scale0;
+                    asm volatile("" : "+s"(V), "+s"(scale0));
+                    const float *scl = (P.scales_in_lds ? s_s : P.scales) + scale0;
                     const int NG = (V + kG - 1) / kG;
                     const int npairs = nel * NG;
                     int e = lane / NG, g = lane - (lane / NG) * NG;
