@@ -27,9 +27,7 @@ struct hepk_plan_s {
     size_t lds_static_lds = 0, lds_static_glob = 0;  // static LDS of the two kernels
     size_t lds_max = 0;                              // the device's LDS per workgroup
     hepk::PipeArgs args{};             // table pointers; chunk range and histograms set per launch
-    int32_t n_chunks_all = 0;          // balanced chunks of the full pass: [0, n_chunks_all)
-    std::vector<int32_t> full_begin;   // n_ds + 1: first chunk of each dataset in the full list
-    std::vector<int32_t> own_begin;    // n_ds + 1: each dataset's own balanced chunk list
+    std::vector<int64_t> tile_pre;     // n_ds + 1: tiles of the datasets before each (chunk d = dataset d)
     int64_t ds_block = 0;              // histogram slots per dataset block
     int64_t n_slots = 0;
     std::vector<hepk::QDev> qd;        // host copy of the query table
@@ -153,7 +151,9 @@ static Launch make_launch(hepk_plan p, int32_t c0, int32_t c1, double *sumw, uin
     const bool ldsh = use_lds_hist(p);
     L.fn = ldsh ? p->fn_lds : p->fn_glob;
     L.block = p->tune.block;
-    L.grid = std::max(1, std::min(p->grid, c1 - c0));
+    // workgroups: as many as fit, but at least one tile per wavefront each
+    const int64_t n_tiles = p->tile_pre[c1] - p->tile_pre[c0];
+    L.grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(p->grid, ceil_div(n_tiles, p->tune.block / 64))));
     L.lds = (ldsh ? hist_lds_bytes(p) : 0) + table_lds_bytes(p);
     L.lds_static = ldsh ? p->lds_static_lds : p->lds_static_glob;
     L.lds_max = p->lds_max;
@@ -373,36 +373,16 @@ extern "C" int hepk_plan_create_ex(const hepk_dataset *ds, int32_t n_ds, const h
         per_cu = 1;
     int64_t grid = t.grid > 0 ? t.grid : static_cast<int64_t>(per_cu) * device_cus();
 
-    // Work chunks: runs of tiles of one dataset, a multiple of the
-    // wavefronts per workgroup long.  The full pass uses chunks of about
-    // total/grid tiles (one per workgroup, plus those split at dataset ends);
-    // each dataset also has its own list of about tiles/grid-sized chunks so
-    // that a pass over that dataset alone fills the device.
-    auto chunk_len = [&](int64_t n) {
-        return std::max<int64_t>(waves, ceil_div(ceil_div(n, std::max<int64_t>(1, grid)), waves) * waves);
-    };
-    std::vector<Chunk> chunks;
-    const int64_t per_all = chunk_len(total_tiles);
-    p->full_begin.assign(n_ds + 1, 0);
+    // Work: one chunk per dataset (its tiles), with the tiles of the datasets
+    // before it; a launch over chunks [c0, c1) gives each workgroup an equal
+    // slice of their concatenated tiles (the kernel finds its slice).
+    std::vector<Chunk> chunks(n_ds);
+    p->tile_pre.assign(n_ds + 1, 0);
     for (int d = 0; d < n_ds; ++d) {
-        p->full_begin[d] = static_cast<int32_t>(chunks.size());
-        for (int64_t t0 = 0; t0 < tiles[d]; t0 += per_all)
-            chunks.push_back(Chunk{d, 0, t0, std::min(tiles[d], t0 + per_all)});
+        chunks[d] = Chunk{d, 0, 0, tiles[d], p->tile_pre[d]};
+        p->tile_pre[d + 1] = p->tile_pre[d] + tiles[d];
     }
-    p->full_begin[n_ds] = static_cast<int32_t>(chunks.size());
-    p->n_chunks_all = static_cast<int32_t>(chunks.size());
-    p->own_begin.assign(n_ds + 1, 0);
-    for (int d = 0; d < n_ds; ++d) {
-        p->own_begin[d] = static_cast<int32_t>(chunks.size());
-        const int64_t per = chunk_len(tiles[d]);
-        for (int64_t t0 = 0; t0 < tiles[d]; t0 += per) chunks.push_back(Chunk{d, 0, t0, std::min(tiles[d], t0 + per)});
-    }
-    p->own_begin[n_ds] = static_cast<int32_t>(chunks.size());
-    if (chunks.size() >= (size_t(1) << 31)) {
-        set_error("hepk_plan_create: too many work chunks");
-        return plan_fail(p, HEPK_EINVAL);
-    }
-    p->grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(grid, std::max(1, p->n_chunks_all))));
+    p->grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(grid, 1 << 20)));
     p->tune.grid = p->grid;
 
     // one device allocation for the tables
@@ -548,7 +528,7 @@ extern "C" int hepk_plan_get_tune(hepk_plan p, hepk_tune *tune) {
 
 static int pipeline_chunks(hepk_plan p, int32_t c0, int32_t c1, double *sumw, uint64_t *counts, hipStream_t stream) {
     using namespace hepk;
-    if (c1 <= c0 || !any_active(p)) return HEPK_OK;
+    if (c1 <= c0 || p->tile_pre[c1] == p->tile_pre[c0] || !any_active(p)) return HEPK_OK;
     int dev = 0;
     HEPK_HIP(hipGetDevice(&dev));
     HEPK_REQUIRE(dev == p->device, "hepk_pipeline: plan made on device %d, current device %d", p->device, dev);
@@ -559,7 +539,7 @@ extern "C" int hepk_pipeline(hepk_plan p, double *sumw, uint64_t *counts, hipStr
     hepk::clear_error();
     HEPK_REQUIRE(p, "hepk_pipeline: plan is NULL");
     HEPK_REQUIRE(sumw && counts, "hepk_pipeline: histogram buffers are NULL");
-    return pipeline_chunks(p, 0, p->n_chunks_all, sumw, counts, stream);
+    return pipeline_chunks(p, 0, p->n_ds, sumw, counts, stream);
 }
 
 extern "C" int hepk_pipeline_range(hepk_plan p, int32_t d0, int32_t nd, double *sumw, uint64_t *counts,
@@ -569,8 +549,7 @@ extern "C" int hepk_pipeline_range(hepk_plan p, int32_t d0, int32_t nd, double *
     HEPK_REQUIRE(sumw && counts, "hepk_pipeline_range: histogram buffers are NULL");
     HEPK_REQUIRE(d0 >= 0 && nd >= 0 && d0 + nd <= p->n_ds, "hepk_pipeline_range: datasets [%d, %d) out of [0, %d)",
                  d0, d0 + nd, p->n_ds);
-    if (nd == 1) return pipeline_chunks(p, p->own_begin[d0], p->own_begin[d0 + 1], sumw, counts, stream);
-    return pipeline_chunks(p, p->full_begin[d0], p->full_begin[d0 + nd], sumw, counts, stream);
+    return pipeline_chunks(p, d0, d0 + nd, sumw, counts, stream);
 }
 
 extern "C" int hepk_pipeline_graph(hepk_plan p, double *sumw, uint64_t *counts, hipStream_t stream) {
@@ -578,11 +557,11 @@ extern "C" int hepk_pipeline_graph(hepk_plan p, double *sumw, uint64_t *counts, 
     clear_error();
     HEPK_REQUIRE(p, "hepk_pipeline_graph: plan is NULL");
     HEPK_REQUIRE(sumw && counts, "hepk_pipeline_graph: histogram buffers are NULL");
-    if (p->n_chunks_all == 0 || !any_active(p)) return HEPK_OK;
+    if (p->tile_pre[p->n_ds] == 0 || !any_active(p)) return HEPK_OK;
     int dev = 0;
     HEPK_HIP(hipGetDevice(&dev));
     HEPK_REQUIRE(dev == p->device, "hepk_pipeline_graph: plan made on device %d, current device %d", p->device, dev);
-    const Launch L = make_launch(p, 0, p->n_chunks_all, sumw, counts);
+    const Launch L = make_launch(p, 0, p->n_ds, sumw, counts);
     if (int rc = check_lds(L)) return rc;
     hipKernelNodeParams kp{};
     kp.func = reinterpret_cast<void *>(L.fn);

@@ -16,10 +16,10 @@
 // consecutive events and works through them without waiting for the other
 // wavefronts of its workgroup (no workgroup barrier inside a tile: the four
 // or eight wavefronts of a workgroup only share the LDS histograms, updated
-// with atomics).  The host cuts every dataset's tiles into chunks; a
-// workgroup takes whole chunks, so a chunk never mixes datasets and the LDS
-// histograms are merged into HBM only when the workgroup moves to another
-// dataset.  For one tile a wavefront
+// with atomics).  A launch covers whole datasets (one chunk each); every
+// workgroup takes an equal slice of their concatenated tiles, so uneven
+// datasets never unbalance the launch, and merges its LDS histograms into
+// HBM when its slice leaves a dataset.  For one tile a wavefront
 //   1. reads the tile's object ranges with scalar loads, then issues all of
 //      its loads at once -- offsets and weight of its events, up to JK jets,
 //      MK muons and EK electrons per lane (consecutive lanes, consecutive
@@ -86,6 +86,7 @@ struct QDev {
 struct Chunk {
     int32_t d, pad;
     int64_t t0, t1;  // tiles [t0, t1) of dataset d
+    int64_t pre;     // tiles of the chunks before this one
 };
 
 struct PipeArgs {
@@ -457,8 +458,29 @@ pipeline_kernel(PipeArgs P) {
         for (int i = tid; i < P.n_scales; i += 64 * WAVES) s_s[i] = as_const(P.scales)[i];
     __syncthreads();
 
-    for (int ci = P.chunk_begin + blockIdx.x; ci < P.chunk_end; ci += gridDim.x) {
-        const Chunk CH = as_const(P.chunks)[ci];
+    // This workgroup's work: an equal slice [my0, my1) of the concatenated
+    // tiles of chunks [chunk_begin, chunk_end); its first chunk is found by a
+    // binary search over the chunks' tile prefixes (uniform, scalar loads).
+    const auto chs = as_const(P.chunks);
+    const int64_t T0 = chs[P.chunk_begin].pre;
+    const int64_t nT = chs[P.chunk_end - 1].pre + (chs[P.chunk_end - 1].t1 - chs[P.chunk_end - 1].t0) - T0;
+    const int64_t my0 = T0 + nT * blockIdx.x / gridDim.x;
+    const int64_t my1 = T0 + nT * (blockIdx.x + 1) / gridDim.x;
+    int cfirst = P.chunk_begin;
+    for (int hi = P.chunk_end - 1; cfirst < hi;) {  // last chunk with pre <= my0
+        const int mid = (cfirst + hi + 1) >> 1;
+        if (chs[mid].pre <= my0)
+            cfirst = mid;
+        else
+            hi = mid - 1;
+    }
+    for (int ci = cfirst; ci < P.chunk_end && my0 < my1; ++ci) {
+        const Chunk CH = chs[ci];
+        if (CH.pre >= my1) break;
+        // this workgroup's tiles of the chunk
+        const int64_t c_t0 = CH.t0 + max<int64_t>(my0 - CH.pre, 0);
+        const int64_t c_t1 = CH.t0 + min<int64_t>(my1 - CH.pre, CH.t1 - CH.t0);
+        if (c_t1 <= c_t0) continue;
         const auto &D = as_const(P.ds)[CH.d];  // read in place, like the query table
         HistSink<LDSH> sink;
         if (LDSH) {
@@ -833,12 +855,12 @@ pipeline_kernel(PipeArgs P) {
 
         // tile bounds are fetched one tile ahead (scalar loads that overlap
         // the current tile's vector loads)
-        int64_t t = CH.t0 + wave;
+        int64_t t = c_t0 + wave;
         TileBounds nb{};
-        if (t < CH.t1) nb = bounds_of(t);
-        for (; t < CH.t1; t += WAVES) {
+        if (t < c_t1) nb = bounds_of(t);
+        for (; t < c_t1; t += WAVES) {
             const TileBounds B = nb;
-            if (t + WAVES < CH.t1) nb = bounds_of(t + WAVES);
+            if (t + WAVES < c_t1) nb = bounds_of(t + WAVES);
             if (oversize(B)) {
                 direct(t * TW);
                 continue;
@@ -848,31 +870,29 @@ pipeline_kernel(PipeArgs P) {
             settle(R);
             work(t * TW, B, R);
         }
-        // merge the LDS histograms when the next chunk is another dataset (or none)
+        // merge the LDS histograms into the dataset's block in HBM (the next
+        // chunk, if any, is another dataset)
         if (LDSH) {
-            const int nci = ci + static_cast<int>(gridDim.x);
-            if (nci >= P.chunk_end || as_const(P.chunks)[nci].d != CH.d) {
-                __syncthreads();
-                for (int q = 0; q < P.n_q; ++q) {
-                    const QDev Q = as_const(P.qs)[q];
-                    if (!Q.active) continue;
-                    for (int v = 0; v < Q.n_scale; ++v)
-                        for (int h = 0; h < 3; ++h) {
-                            const int ls = Q.lslot0 + v * Q.lper_scale + Q.lhoff[h];
-                            const int64_t gs = D.hist0 + Q.gslot0 + v * Q.gper_scale + Q.ghoff[h];
-                            for (int i = tid; i < Q.nbins[h] + 2; i += 64 * WAVES) {
-                                const uint32_t c = c_s[ls + i];
-                                if (c) {
-                                    atomic_add_u64(&P.counts[gs + i], c);
-                                    atomic_add_f64(&P.sumw[gs + i], sw_s[ls + i]);
-                                    c_s[ls + i] = 0u;
-                                    sw_s[ls + i] = 0.0;
-                                }
+            __syncthreads();
+            for (int q = 0; q < P.n_q; ++q) {
+                const QDev Q = as_const(P.qs)[q];
+                if (!Q.active) continue;
+                for (int v = 0; v < Q.n_scale; ++v)
+                    for (int h = 0; h < 3; ++h) {
+                        const int ls = Q.lslot0 + v * Q.lper_scale + Q.lhoff[h];
+                        const int64_t gs = D.hist0 + Q.gslot0 + v * Q.gper_scale + Q.ghoff[h];
+                        for (int i = tid; i < Q.nbins[h] + 2; i += 64 * WAVES) {
+                            const uint32_t c = c_s[ls + i];
+                            if (c) {
+                                atomic_add_u64(&P.counts[gs + i], c);
+                                atomic_add_f64(&P.sumw[gs + i], sw_s[ls + i]);
+                                c_s[ls + i] = 0u;
+                                sw_s[ls + i] = 0.0;
                             }
                         }
-                }
-                __syncthreads();
+                    }
             }
+            __syncthreads();
         }
     }
 }
