@@ -1,13 +1,13 @@
 // hepk_hist_fill: weighted 1-D histogram fill (Sec. III fill-histogram
 // kernel), accumulating into the caller's histogram.
 //
-// Each workgroup (1024 threads, one per CU) keeps a private copy of the
+// Each workgroup (1024 threads, two per CU) keeps a private copy of the
 // histogram in LDS (float64 sums via ds_add_f64, uint32 counts via
 // ds_add_u32) together with the bin edges, walks a grid-stride range of rows
 // eight at a time per thread (loads of the eight rows in flight together),
-// and merges its non-empty slots into HBM with global atomics at the end (one
-// merge per CU keeps the atomics on each slot few).  Histograms too large for LDS go straight to global
-// atomics with the edges read from HBM.  Sums of float64 weights are exact in
+// and merges its non-empty slots into HBM with global atomics at the end
+// (few workgroups: few atomics on each slot).  Histograms too large for LDS
+// go straight to global atomics with the edges read from HBM.  Sums of float64 weights are exact in
 // any order while every partial sum is a multiple of the smallest weight's ulp
 // below 2^53 of it, which holds for the float32 weights of this analysis;
 // otherwise the order changes only the last bits.
@@ -93,7 +93,7 @@ static int launch_hist(const void *x, const float *w, const uint8_t *m, int64_t 
                        hipStream_t stream) {
     const int nslots = h->nbins + 2;
     const bool lds = nslots <= kMaxLdsSlots;
-    const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n, HB * HR), device_cus()));
+    const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n, HB * HR), 2 * device_cus()));
     const size_t lds_bytes = static_cast<size_t>(nslots) * (sizeof(double) + sizeof(uint32_t)) +
                              static_cast<size_t>(h->nbins + 1) * sizeof(float);
     if (lds)
