@@ -128,7 +128,12 @@ __global__ __launch_bounds__(64 * MW) void match_dr_kernel(
         }
         if (lane < ne) {
             const uint32_t pk = static_cast<uint32_t>(bb) | (static_cast<uint32_t>(bn) << 16);
-            for (int k = ab; k < ae; ++k) ar[k] = pk;
+            int k = ab;
+            for (; k + 2 <= ae; k += 2) {  // two per step: a divergent loop
+                ar[k] = pk;
+                ar[k + 1] = pk;
+            }
+            if (k < ae) ar[k] = pk;
         }
         wave_fence_dr();
         // ---- one lane per a object

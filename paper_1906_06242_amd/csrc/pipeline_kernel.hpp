@@ -691,7 +691,18 @@ pipeline_kernel(PipeArgs P) {
                                   (static_cast<uint32_t>(elig ? L.u.p.epre[le[r]] - u0 : 0) << CS);
                             if (C::PACK) pk |= pke << 16;
                         }
-                        for (int k = jb[r]; k < je[r]; ++k) {
+                        // two jets per step (a divergent loop: its trip count
+                        // is the largest jet count of the wavefront)
+                        int k = jb[r];
+                        for (; k + 2 <= je[r]; k += 2) {
+                            L.jr[k].rng = pk;
+                            L.jr[k + 1].rng = pk;
+                            if (EXT && !C::PACK) {
+                                L.jre[C::PACK ? 0 : k] = pke;
+                                L.jre[C::PACK ? 0 : k + 1] = pke;
+                            }
+                        }
+                        if (k < je[r]) {
                             L.jr[k].rng = pk;
                             if (EXT && !C::PACK) L.jre[C::PACK ? 0 : k] = pke;
                         }

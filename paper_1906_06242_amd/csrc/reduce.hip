@@ -135,8 +135,17 @@ __global__ __launch_bounds__(RB) void reduce_kernel(const int64_t *__restrict__ 
             }
             wave_fence();
             const int b0 = static_cast<int>(a0), b1 = static_cast<int>(a1);  // within the tile's 512
-            if (take)
-                for (int k = b0; k < b1; ++k) r.add(OP != R_COUNT ? vs[k] : 0.0f, ms[k] != 0, k - b0);
+            if (take) {
+                // two objects per step (both LDS reads in flight), in order
+                int k = b0;
+                for (; k + 2 <= b1; k += 2) {
+                    const float v0 = OP != R_COUNT ? vs[k] : 0.0f, v1 = OP != R_COUNT ? vs[k + 1] : 0.0f;
+                    const bool m0 = ms[k] != 0, m1 = ms[k + 1] != 0;
+                    r.add(v0, m0, k - b0);
+                    r.add(v1, m1, k + 1 - b0);
+                }
+                if (k < b1) r.add(OP != R_COUNT ? vs[k] : 0.0f, ms[k] != 0, k - b0);
+            }
             wave_fence();  // the next tile overwrites the staging
         } else if (take) {
             for (int64_t k = a0; k < a1; ++k)
