@@ -737,7 +737,13 @@ pipeline_kernel(PipeArgs P) {
                             const int u0 = static_cast<int>(C::PACK ? (pe & 0xffu) : (pe & 0xffffu));
                             const int u1 =
                                 u0 + (need ? static_cast<int>(C::PACK ? ((pe >> 8) & 0xffu) : (pe >> 16)) : 0);
-                            for (int i = u0; i < u1; ++i) hit |= delta_r2(jeta[k], jphi[k], L.sea[i], L.sep[i]) <= thr2;
+                            int i = u0;
+                            for (; i + 2 <= u1; i += 2) {
+                                const float e0 = L.sea[i], p0 = L.sep[i], e1 = L.sea[i + 1], p1 = L.sep[i + 1];
+                                hit |= delta_r2(jeta[k], jphi[k], e0, p0) <= thr2;
+                                hit |= delta_r2(jeta[k], jphi[k], e1, p1) <= thr2;
+                            }
+                            if (i < u1) hit |= delta_r2(jeta[k], jphi[k], L.sea[i], L.sep[i]) <= thr2;
                         }
                         const bool ok = need && !hit;
                         L.jr[j].pt = ok ? jpt[k] : __builtin_nanf("");

@@ -355,6 +355,35 @@ def test_pipeline_mixed_scale_counts(extended, tune):
     assert [len(g) for g in got] == [1, 3, 5, 20, 6]
 
 
+EDGE_TUNES = [None, dict(block=256, ev_per_thread=2), dict(hist_mode=1), dict(block=1024)]
+
+
+@pytest.mark.parametrize("extended", [False, True])
+@pytest.mark.parametrize("tune", EDGE_TUNES, ids=[str(t) for t in EDGE_TUNES])
+def test_pipeline_edge_queries(extended, tune):
+    """Queries at the edges of the work-skipping rules: no muon or jet
+    requirement (every event eligible, lead = -inf into underflow), a negative
+    jet threshold (no largest-scale pre-filter, no skipped cone tests), a zero
+    and a huge cone, scales all below one, thresholds equal to generated
+    values, one and several scales."""
+    say(f"pipeline edge queries extended={extended} tune={tune}")
+    ds = datagen.make_dataset(31, 20000, extended=extended)
+    pt0 = float(ds.jets.cols["pt"][17])
+    down = np.array([0.9, 0.95, 0.97], np.float32)
+    qs = [datagen.Query(min_mu=0, min_jet=0),
+          datagen.Query(min_mu=0, min_jet=0, scales=down),
+          datagen.Query(jet_pt=-5.0, min_jet=1, scales=down),
+          datagen.Query(jet_pt=-5.0, min_jet=2),
+          datagen.Query(dr=0.0, min_jet=3),
+          datagen.Query(dr=6.0, min_mu=0, min_jet=1, scales=down),
+          datagen.Query(jet_pt=pt0, min_jet=1, scales=np.array([1.0, 1.5], np.float32)),
+          datagen.Query(mu_pt=1e9, min_mu=0, min_jet=2, min_b=1 if extended else 0)]
+    got = fused([ds], qs, tune)[0]
+    check_against_oracle(ds, qs, got, f"edge tune={tune}")
+    # the first query counts every event somewhere (underflow included)
+    assert int(got[0][0][2][1].sum()) == ds.n_events
+
+
 def test_pipeline_lds_beyond_device_limit_uses_global_hist():
     """60 histograms (20 scales, 130 H_T bins: 62 KB) fit in LDS beside
     64-event tiles, not beside the 128-event tiles of 512-thread workgroups:
