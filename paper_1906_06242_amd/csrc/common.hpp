@@ -106,29 +106,6 @@ __device__ __forceinline__ float delta_r2(float eta_a, float phi_a, float eta_b,
     return a + b;
 }
 
-// Histogram slot of x (not NaN) for edges E[0..nbins]: 0 if x < E[0],
-// nbins+1 if x >= E[nbins], else s with E[s-1] <= x < E[s].  A guess from the
-// uniform-bin formula (lo, inv_w) is verified against the edges and replaced by
-// a binary search when wrong, so any increasing edges give the exact slot.
-__device__ __forceinline__ int hist_slot(float x, const float *E, int nbins, float lo, float inv_w) {
-    if (!(x >= E[0])) return 0;
-    if (x >= E[nbins]) return nbins + 1;
-    float g = (x - lo) * inv_w;
-    int s = (g >= 0.0f) ? ((g < static_cast<float>(nbins)) ? static_cast<int>(g) + 1 : nbins) : 1;
-    if (x < E[s - 1] || x >= E[s]) {
-        int a = 0, b = nbins;  // E[a] <= x < E[b]
-        while (b - a > 1) {
-            int m = (a + b) >> 1;
-            if (E[m] <= x)
-                a = m;
-            else
-                b = m;
-        }
-        s = a + 1;
-    }
-    return s;
-}
-
 // Read-only data seen through the constant address space: the compiler may then
 // fetch it with scalar loads into SGPRs when the address is uniform (a kernel
 // that also does global atomics otherwise has to assume the data may change
@@ -149,24 +126,31 @@ __device__ __forceinline__ const_ptr<T> as_const(const T *p) {
     return reinterpret_cast<const_ptr<T>>(reinterpret_cast<uintptr_t>(p));
 }
 
-// hist_slot with the end edges already at hand (lo == E[0], hi == E[nbins]).
+// Edges E[0..nbins] strictly increasing and E[0] <= x < E[nbins]: the slot
+// s of x, E[s-1] <= x < E[s] (binary search).
+__device__ __forceinline__ int bin_search(const float *E, int nbins, float x) {
+    int a = 0, b = nbins;  // E[a] <= x < E[b]
+    while (b - a > 1) {
+        const int m = (a + b) >> 1;
+        if (E[m] <= x)
+            a = m;
+        else
+            b = m;
+    }
+    return a + 1;
+}
+
+// Histogram slot of x (not NaN) for strictly increasing edges E[0..nbins],
+// lo == E[0], hi == E[nbins]: 0 if x < lo, nbins+1 if x >= hi, else s with
+// E[s-1] <= x < E[s].  A guess from the uniform-bin formula (inv_w = nbins /
+// (hi - lo)) is verified against the edges and replaced by a binary search
+// when wrong, so any increasing edges give the exact slot.
 __device__ __forceinline__ int hist_slot_lohi(float x, const float *E, int nbins, float lo, float hi, float inv_w) {
     if (!(x >= lo)) return 0;
     if (x >= hi) return nbins + 1;
-    float g = (x - lo) * inv_w;
-    int s = (g >= 0.0f) ? ((g < static_cast<float>(nbins)) ? static_cast<int>(g) + 1 : nbins) : 1;
-    if (x < E[s - 1] || x >= E[s]) {
-        int a = 0, b = nbins;  // E[a] <= x < E[b]
-        while (b - a > 1) {
-            int m = (a + b) >> 1;
-            if (E[m] <= x)
-                a = m;
-            else
-                b = m;
-        }
-        s = a + 1;
-    }
-    return s;
+    const float g = (x - lo) * inv_w;
+    const int s = (g >= 0.0f) ? ((g < static_cast<float>(nbins)) ? static_cast<int>(g) + 1 : nbins) : 1;
+    return (x < E[s - 1] || x >= E[s]) ? bin_search(E, nbins, x) : s;
 }
 
 __device__ __forceinline__ void atomic_add_f64(double *p, double v) {

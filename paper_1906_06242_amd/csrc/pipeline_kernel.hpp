@@ -20,17 +20,20 @@
 // workgroup takes an equal slice of their concatenated tiles, so uneven
 // datasets never unbalance the launch, and merges its LDS histograms into
 // HBM when its slice leaves a dataset.  For one tile a wavefront
-//   1. reads the tile's object ranges with scalar loads, then issues all of
-//      its loads at once -- offsets and weight of its events, up to JK jets,
-//      MK muons and EK electrons per lane (consecutive lanes, consecutive
-//      objects: coalesced) -- into registers, and waits once;
-//   2. puts the offsets in LDS (tile-relative int32) and lets each event lane
-//      write its event index over its jets (the jet -> event map);
-//   3. per query: muon lanes evaluate the muon cuts and stage eta/phi in LDS,
-//      eta = NaN for muons that fail (a NaN dR^2 never passes the cone test,
-//      which is the same as skipping them); electrons likewise;
-//   4. jet lanes test the cone against their event's staged leptons and store
-//      pt (or NaN when removed or outside |eta|) in LDS;
+//   1. reads the tile's object ranges with scalar loads (one tile ahead),
+//      then issues all of its loads at once -- offsets (their low 32-bit
+//      words) and weight of its events, up to JK jets, MK muons and EK
+//      electrons per lane (consecutive lanes, consecutive objects:
+//      coalesced) -- into registers, and waits once;
+//   2. per query: muon (and electron) lanes evaluate the cuts; the selected
+//      leptons are compacted by wavefront ballot into LDS in tile order,
+//      with the count of selected leptons before each lepton;
+//   3. each event lane writes its event's range of selected leptons over its
+//      jets (an empty range for an event that cannot pass: too few selected
+//      muons, or too few jets before any cut);
+//   4. jet lanes test the cone against those leptons and store pt in LDS, or
+//      NaN when removed, outside |eta|, or below jet_pt at every scale (the
+//      last two skip the test);
 //   5. event lanes walk their jets in order: ptv = pt * s, the jet cut, the
 //      count, the left-to-right float32 H_T, the maximum, the b-tag count;
 //      then the event cut and three fills into the workgroup's LDS
@@ -156,19 +159,6 @@ __device__ __forceinline__ FillC fill_consts(const QT &Q) {
                    "+s"(F.lo[1]), "+s"(F.lo[2]), "+s"(F.hi[0]), "+s"(F.hi[1]), "+s"(F.hi[2]), "+s"(F.iw[0]),
                    "+s"(F.iw[1]), "+s"(F.iw[2]));
     return F;
-}
-
-// Edges E[0..nbins] strictly increasing, E[0] <= x < E[nbins]: the slot of x.
-__device__ __forceinline__ int bin_search(const float *E, int nbins, float x) {
-    int a = 0, b = nbins;  // E[a] <= x < E[b]
-    while (b - a > 1) {
-        const int m = (a + b) >> 1;
-        if (E[m] <= x)
-            a = m;
-        else
-            b = m;
-    }
-    return a + 1;
 }
 
 // Slots of N values, x[n] going to observable n % 3 (H_T, lead, nJet): the
