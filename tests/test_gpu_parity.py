@@ -179,8 +179,8 @@ def test_match_dr_matches_oracle(case):
         rng = np.random.default_rng(5)
         ca = np.minimum(rng.poisson(5, n), 20)
         cb = np.minimum(rng.poisson(2, n), 8)
-        ca[300:310] = 900     # one tile with > 4096 a objects
-        cb[1500:1510] = 300   # one tile with > 2048 b objects
+        ca[300:310] = 900     # tiles far beyond the on-chip capacity for a objects
+        cb[1500:1510] = 300   # and for b objects (one lane per event from HBM)
         offa = np.concatenate([[0], np.cumsum(ca)]).astype(np.int64)
         offb = np.concatenate([[0], np.cumsum(cb)]).astype(np.int64)
         ea = rng.normal(0, 1.5, offa[-1]).astype(np.float32)
@@ -259,6 +259,19 @@ def test_hist_fill_int_and_half_inputs():
         c = torch.zeros(len(edges) + 1, dtype=torch.int64, device="cuda")
         H.hist_fill(dev(x), dev(edges), s, c)
         assert_hist((host(s), host(c)), (ws, wc))
+
+
+def test_stream_read_reads_and_leaves_sink():
+    """The measurement helper reads the buffer; with all-zero data its
+    data-dependent store never fires, so the sink keeps its value."""
+    import torch
+    say("stream read")
+    x = torch.zeros(1 << 20, dtype=torch.float32, device="cuda")
+    sink = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    H.stream_read(x, sink)
+    H.stream_read(x[:4], sink)   # 16 bytes: one word, tail loop only
+    torch.cuda.synchronize()
+    assert int(sink.item()) == 7
 
 
 def test_validate_offsets():
