@@ -39,12 +39,20 @@ __device__ __forceinline__ bool row_passes(const SelectArgs &a, int64_t i) {
     return ok;
 }
 
-// Rows [0, 4*n4) in groups of four; mask_in/mask_out 4-byte aligned, columns
-// 16-byte (float32, int32) or 8-byte (float16) aligned.
-__global__ __launch_bounds__(256) void select_vec4_kernel(SelectArgs a, int64_t n4, const uint32_t *mask_in,
+// Rows [0, n) in groups of four (mask_in/mask_out 4-byte aligned, columns
+// 16-byte (float32, int32) or 8-byte (float16) aligned); the last, partial
+// group row by row with byte stores.
+__global__ __launch_bounds__(256) void select_vec4_kernel(SelectArgs a, int64_t n, const uint32_t *mask_in,
                                                           uint32_t *mask_out) {
+    const int64_t n4 = n / 4;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    for (int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; g < n4; g += stride) {
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid == 0 && 4 * n4 < n) {
+        const uint8_t *mi = reinterpret_cast<const uint8_t *>(mask_in);
+        uint8_t *mo = reinterpret_cast<uint8_t *>(mask_out);
+        for (int64_t i = 4 * n4; i < n; ++i) mo[i] = ((!mi || mi[i] != 0) && row_passes(a, i)) ? 1 : 0;
+    }
+    for (int64_t g = gid; g < n4; g += stride) {
         uint4 raw[HEPK_MAX_CUTS];
 #pragma unroll
         for (int k = 0; k < HEPK_MAX_CUTS; ++k) {
@@ -86,7 +94,7 @@ __global__ __launch_bounds__(256) void select_vec4_kernel(SelectArgs a, int64_t 
     }
 }
 
-// Rows [begin, n) one per thread (tails and unaligned masks).
+// Rows [begin, n) one per thread (unaligned masks or columns).
 __global__ void select_scalar_kernel(SelectArgs a, int64_t begin, int64_t n, const uint8_t *mask_in,
                                      uint8_t *mask_out) {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
@@ -124,20 +132,13 @@ extern "C" int hepk_select(const hepk_cut *cuts, int32_t n_cuts, int64_t n, cons
                    (!mask_in || reinterpret_cast<uintptr_t>(mask_in) % 4 == 0);
     for (int k = 0; k < n_cuts; ++k)
         aligned = aligned && reinterpret_cast<uintptr_t>(cuts[k].col) % (cuts[k].dtype == HEPK_F16 ? 8 : 16) == 0;
-    int64_t done = 0;
-    if (aligned && n >= 4) {
-        const int64_t n4 = n / 4;
-        int grid = static_cast<int>(std::min<int64_t>(ceil_div(n4, block), max_grid));
-        select_vec4_kernel<<<grid, block, 0, stream>>>(a, n4, reinterpret_cast<const uint32_t *>(mask_in),
+    if (aligned) {
+        const int grid = static_cast<int>(std::min<int64_t>(std::max<int64_t>(1, ceil_div(n / 4, block)), max_grid));
+        select_vec4_kernel<<<grid, block, 0, stream>>>(a, n, reinterpret_cast<const uint32_t *>(mask_in),
                                                        reinterpret_cast<uint32_t *>(mask_out));
-        int rc = check_launch("hepk_select");
-        if (rc) return rc;
-        done = 4 * n4;
-    }
-    if (done < n) {
-        int grid = static_cast<int>(std::min<int64_t>(ceil_div(n - done, block), max_grid));
-        select_scalar_kernel<<<grid, block, 0, stream>>>(a, done, n, mask_in, mask_out);
         return check_launch("hepk_select");
     }
-    return HEPK_OK;
+    const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n, block), max_grid));
+    select_scalar_kernel<<<grid, block, 0, stream>>>(a, 0, n, mask_in, mask_out);
+    return check_launch("hepk_select");
 }
