@@ -284,7 +284,8 @@ struct Caps {
 // One wavefront's LDS.  jr holds, per jet, its event's range of selected
 // muons (first | count << 16; with PACK, muons in the low and electrons in
 // the high 16 bits, first | count << 8 each) until the cone test reads it;
-// the same word then holds the jet's pt (or NaN) for the per-event walk.
+// the same word then holds the jet's pt (or NaN) for the per-event walk
+// (with one scale and jet_pt >= 0: pt * s of a selected jet, else +0).
 template <int EVPL, bool EXT>
 struct WaveLds {
     using C = Caps<EVPL, EXT>;
@@ -366,6 +367,38 @@ __device__ __forceinline__ void walk_jets(const WL &L, int j0, int j1, const flo
     if (k < j1) step(L.jr[k].pt, EXT ? static_cast<int>(L.bt[k]) : 0);
 #pragma unroll
     for (int g = 0; g < G; ++g) lead[g] = nj[g] > 0 ? pmax * sc[g] : -INFINITY;
+}
+
+// The same reductions for one scale s when the cone test already stored
+// every selected jet as pt * s and every other jet as +0 (possible when
+// jet_pt >= 0: a selected value exceeds jet_pt >= 0, so it is positive and
+// the count is that of positive values).  Adding +0 leaves a float32 sum of
+// positive values unchanged, so summing every stored value keeps the sum
+// order of the definition.  The b-tag flag is stored already ANDed with the
+// selection.
+template <bool EXT, typename WL>
+__device__ __forceinline__ void walk_selected(const WL &L, int j0, int j1, float &ht, float &lead, int &nj,
+                                              int &nb) {
+    float h = 0.0f, m = 0.0f;
+    int n = 0, b = 0;
+    auto step = [&](float x, int bt) {
+        h += x;
+        n += x > 0.0f ? 1 : 0;
+        m = fmaxf(m, x);
+        if (EXT) b += bt;
+    };
+    int k = j0;
+    for (; k + 2 <= j1; k += 2) {
+        const float x0 = L.jr[k].pt, x1 = L.jr[k + 1].pt;
+        const int b0 = EXT ? L.bt[k] : 0, b1 = EXT ? L.bt[k + 1] : 0;
+        step(x0, b0);
+        step(x1, b1);
+    }
+    if (k < j1) step(L.jr[k].pt, EXT ? static_cast<int>(L.bt[k]) : 0);
+    ht = h;
+    nj = n;
+    nb = b;
+    lead = n > 0 ? m : -INFINITY;
 }
 
 struct TileBounds {
@@ -705,6 +738,10 @@ pipeline_kernel(PipeArgs P) {
                 // the test and is stored as NaN.  That changes no result: a
                 // selected jet of its event has a larger pt, so the maximum
                 // and the sums and counts of selected jets are the same.
+                // With one scale and jet_pt >= 0 (zsel) the test above is the
+                // whole jet selection, so a kept jet is stored as pt * s and
+                // any other as +0, for walk_selected.
+                const bool zsel = !MS && jet_pt >= 0.0f;
 #pragma unroll
                 for (int k = 0; k < JK; ++k) {
                     const int j = lane + 64 * k;
@@ -736,8 +773,14 @@ pipeline_kernel(PipeArgs P) {
                             if (i < u1) hit |= delta_r2(jeta[k], jphi[k], L.sea[i], L.sep[i]) <= thr2;
                         }
                         const bool ok = need && !hit;
-                        L.jr[j].pt = ok ? jpt[k] : __builtin_nanf("");
-                        if (EXT) L.bt[j] = (has_bt && jbt[EXT ? k : 0] > btag) ? 1 : 0;
+                        const bool tag = has_bt && jbt[EXT ? k : 0] > btag;
+                        if (zsel) {
+                            L.jr[j].pt = ok ? jpt[k] * smax : 0.0f;
+                            if (EXT) L.bt[j] = (ok && tag) ? 1 : 0;
+                        } else {
+                            L.jr[j].pt = ok ? jpt[k] : __builtin_nanf("");
+                            if (EXT) L.bt[j] = tag ? 1 : 0;
+                        }
                     }
                 }
                 wave_sync();
@@ -761,7 +804,10 @@ pipeline_kernel(PipeArgs P) {
                         const bool elig = lane + 64 * r < ne && nmu[r] >= min_mu && je[r] - jb[r] >= min_jet;
                         float ht[1], lead[1];
                         int njs[1], nbt[1];
-                        walk_jets<1, EXT>(L, jb[r], elig ? je[r] : jb[r], sc, jet_pt, ht, lead, njs, nbt);
+                        if (zsel)
+                            walk_selected<EXT>(L, jb[r], elig ? je[r] : jb[r], ht[0], lead[0], njs[0], nbt[0]);
+                        else
+                            walk_jets<1, EXT>(L, jb[r], elig ? je[r] : jb[r], sc, jet_pt, ht, lead, njs, nbt);
                         const bool pass[1] = {elig && njs[0] >= min_jet && nbt[0] >= min_b};
                         if (pass[0]) {
                             const float xs[3] = {ht[0], lead[0], static_cast<float>(njs[0])};

@@ -378,9 +378,12 @@ def test_pipeline_edge_queries(extended, tune):
     requirement (every event eligible, lead = -inf into underflow), a negative
     jet threshold (no largest-scale pre-filter, no skipped cone tests), a zero
     and a huge cone, scales all below one, thresholds equal to generated
-    values, one and several scales."""
+    values, one and several scales; single-scale thresholds of +0 and -0
+    with some jets of pt exactly 0 (the walk over values stored as pt * s or
+    +0 must count none of them)."""
     say(f"pipeline edge queries extended={extended} tune={tune}")
     ds = datagen.make_dataset(31, 20000, extended=extended)
+    ds.jets.cols["pt"][5::97] = 0.0
     pt0 = float(ds.jets.cols["pt"][17])
     down = np.array([0.9, 0.95, 0.97], np.float32)
     qs = [datagen.Query(min_mu=0, min_jet=0),
@@ -390,7 +393,10 @@ def test_pipeline_edge_queries(extended, tune):
           datagen.Query(dr=0.0, min_jet=3),
           datagen.Query(dr=6.0, min_mu=0, min_jet=1, scales=down),
           datagen.Query(jet_pt=pt0, min_jet=1, scales=np.array([1.0, 1.5], np.float32)),
-          datagen.Query(mu_pt=1e9, min_mu=0, min_jet=2, min_b=1 if extended else 0)]
+          datagen.Query(mu_pt=1e9, min_mu=0, min_jet=2, min_b=1 if extended else 0),
+          datagen.Query(jet_pt=0.0, min_jet=1, min_b=1 if extended else 0),
+          datagen.Query(jet_pt=-0.0, dr=0.0, min_mu=0, min_jet=2),
+          datagen.Query(jet_pt=pt0, min_jet=1)]
     got = fused([ds], qs, tune)[0]
     check_against_oracle(ds, qs, got, f"edge tune={tune}")
     # the first query counts every event somewhere (underflow included)
