@@ -294,7 +294,7 @@ struct WaveLds {
         float pt;
     } jr[C::JC];
     uint32_t jre[(EXT && !C::PACK) ? C::JC : 1];  // electron ranges when not packed
-    float seta[C::MC], sphi[C::MC];                // selected muons, compacted in tile order
+    float seta[C::MC + 2], sphi[C::MC + 2];        // selected muons, compacted in tile order (+2 padding)
     float sea[EXT ? C::EC : 1], sep[EXT ? C::EC : 1];
     uint8_t bt[EXT ? C::JC : 1];
     union {
@@ -738,20 +738,50 @@ pipeline_kernel(PipeArgs P) {
                 // the test and is stored as NaN.  That changes no result: a
                 // selected jet of its event has a larger pt, so the maximum
                 // and the sums and counts of selected jets are the same.
-                // With one scale and jet_pt >= 0 (zsel) the test above is the
+                // With one scale and jet_pt >= 0 (zsel) this step decides the
                 // whole jet selection, so a kept jet is stored as pt * s and
                 // any other as +0, for walk_selected.
                 const bool zsel = !MS && jet_pt >= 0.0f;
+                // Slots in pairs (CB; three at a time spills registers): the
+                // pair's packed ranges, then the first two selected muons of
+                // each slot's event, each set of reads in flight together (two
+                // LDS round trips per pair); only events with more muons loop
+                // over the rest.  A slot past the tile's jets reads a stale
+                // word: its first and count are forced to 0.  Reads past a
+                // range's end land in the next event's muons or in the two
+                // padding entries and are unused.
+                constexpr int CB = 2;
 #pragma unroll
-                for (int k = 0; k < JK; ++k) {
-                    const int j = lane + 64 * k;
-                    if (j < nj) {
-                        const bool need = fabsf(jeta[k]) < jet_abseta && (jet_pt < 0.0f || jpt[k] * smax > jet_pt);
-                        const uint32_t pk = L.jr[j].rng;
-                        const int c0 = static_cast<int>(C::PACK ? (pk & 0xffu) : (pk & 0xffffu));
-                        const int c1 = c0 + (need ? static_cast<int>(C::PACK ? ((pk >> 8) & 0xffu) : (pk >> 16)) : 0);
-                        bool hit = false;
-                        int i = c0;
+                for (int k0 = 0; k0 < JK; k0 += CB) {
+                    uint32_t pk[CB];
+#pragma unroll
+                    for (int b = 0; b < CB; ++b)
+                        if (k0 + b < JK) pk[b] = L.jr[lane + 64 * (k0 + b)].rng;
+                    float e0[CB], p0[CB], e1[CB], p1[CB];
+#pragma unroll
+                    for (int b = 0; b < CB; ++b) {
+                        if (k0 + b >= JK) continue;
+                        const int c0 = lane + 64 * (k0 + b) < nj
+                                           ? static_cast<int>(C::PACK ? (pk[b] & 0xffu) : (pk[b] & 0xffffu))
+                                           : 0;
+                        e0[b] = L.seta[c0];
+                        p0[b] = L.sphi[c0];
+                        e1[b] = L.seta[c0 + 1];
+                        p1[b] = L.sphi[c0 + 1];
+                    }
+#pragma unroll
+                    for (int b = 0; b < CB; ++b) {
+                        const int k = k0 + b;
+                        const int j = lane + 64 * k;
+                        if (k >= JK || j >= nj) continue;
+                        const bool need =
+                            fabsf(jeta[k]) < jet_abseta && (jet_pt < 0.0f || jpt[k] * smax > jet_pt);
+                        const int c0 = static_cast<int>(C::PACK ? (pk[b] & 0xffu) : (pk[b] & 0xffffu));
+                        const int cn = need ? static_cast<int>(C::PACK ? ((pk[b] >> 8) & 0xffu) : (pk[b] >> 16)) : 0;
+                        bool hit = (cn >= 1 & delta_r2(jeta[k], jphi[k], e0[b], p0[b]) <= thr2) |
+                                   (cn >= 2 & delta_r2(jeta[k], jphi[k], e1[b], p1[b]) <= thr2);
+                        const int c1 = c0 + cn;
+                        int i = c0 + 2;
                         // two leptons per step: both LDS reads in flight before the math
                         for (; i + 2 <= c1; i += 2) {
                             const float e0 = L.seta[i], p0 = L.sphi[i], e1 = L.seta[i + 1], p1 = L.sphi[i + 1];
@@ -760,7 +790,7 @@ pipeline_kernel(PipeArgs P) {
                         }
                         if (i < c1) hit |= delta_r2(jeta[k], jphi[k], L.seta[i], L.sphi[i]) <= thr2;
                         if (EXT) {
-                            const uint32_t pe = C::PACK ? (pk >> 16) : L.jre[C::PACK ? 0 : j];
+                            const uint32_t pe = C::PACK ? (pk[b] >> 16) : L.jre[C::PACK ? 0 : j];
                             const int u0 = static_cast<int>(C::PACK ? (pe & 0xffu) : (pe & 0xffffu));
                             const int u1 =
                                 u0 + (need ? static_cast<int>(C::PACK ? ((pe >> 8) & 0xffu) : (pe >> 16)) : 0);
