@@ -537,9 +537,7 @@ pipeline_kernel(PipeArgs P) {
         // ---- 1. all of a tile's loads, without waiting: both offsets of each
         // event lane's event, its weight, and up to JK jets, MK muons and EK
         // electrons per lane (consecutive lanes, consecutive objects)
-        auto issue = [&](int64_t tt, const TileBounds &b, Raw &R) {
-            const int64_t e0 = tt * TW;
-            const int ne = static_cast<int>(min<int64_t>(TW, D.n_events - e0));
+        auto issue = [&](int64_t e0, int ne, const TileBounds &b, Raw &R) {
             const int nj = static_cast<int>(b.J1 - b.J0), nm = static_cast<int>(b.M1 - b.M0);
             const int nl = static_cast<int>(b.L1 - b.L0);
             const float *wp = D.w ? D.w + e0 : nullptr;
@@ -626,8 +624,7 @@ pipeline_kernel(PipeArgs P) {
             }
         };
         // Steps 2-5 for every query on a settled tile.
-        auto work = [&](int64_t e0, const TileBounds &B, Raw &R) {
-            const int ne = static_cast<int>(min<int64_t>(TW, D.n_events - e0));
+        auto work = [&](int64_t e0, int ne, const TileBounds &B, Raw &R) {
             const int nj = static_cast<int>(B.J1 - B.J0), nm = static_cast<int>(B.M1 - B.M0);
             const int nl = static_cast<int>(B.L1 - B.L0);
             int32_t jb[EVPL], je[EVPL], mb[EVPL], me[EVPL], lb[EVPL], le[EVPL];
@@ -926,32 +923,45 @@ pipeline_kernel(PipeArgs P) {
                 wave_sync();
             }
         };
-        auto direct = [&](int64_t e0) {
-            const int ne = static_cast<int>(min<int64_t>(TW, D.n_events - e0));
-            const DsDev Dc = D;
-#pragma unroll
-            for (int r = 0; r < EVPL; ++r) {
-                const int ev = lane + 64 * r;
-                if (ev < ne) event_direct<T, EXT, LDSH>(P, Dc, e0 + ev, edges, sink);
-            }
-        };
-
-        // tile bounds are fetched one tile ahead (scalar loads that overlap
-        // the current tile's vector loads)
+        // Tile bounds are fetched one tile ahead (scalar loads that overlap
+        // the current tile's vector loads).  A tile whose objects exceed the
+        // register capacity runs as consecutive sub-tiles: from its first
+        // event not yet run, the event count is halved until the objects fit
+        // (a few scalar loads), that sub-tile runs like a tile, and the rest
+        // of the tile follows.  Only a single event beyond the capacity goes
+        // one lane, straight from HBM.
         int64_t t = c_t0 + wave;
         TileBounds nb{};
+        int64_t e = t * TW, eend = min<int64_t>(e + TW, D.n_events);  // events of tile t not yet run
         if (t < c_t1) nb = bounds_of(t);
-        for (; t < c_t1; t += WAVES) {
-            const TileBounds B = nb;
-            if (t + WAVES < c_t1) nb = bounds_of(t + WAVES);
-            if (oversize(B)) {
-                direct(t * TW);
-                continue;
+        while (t < c_t1) {
+            int n = static_cast<int>(eend - e);
+            TileBounds B;
+            if (e == t * TW) {
+                B = nb;
+                if (t + WAVES < c_t1) nb = bounds_of(t + WAVES);
+            } else {
+                B = tile_bounds<EXT>(D, has_el, e, n);
             }
-            Raw R;
-            issue(t, B, R);
-            settle(R);
-            work(t * TW, B, R);
+            while (n > 1 && oversize(B)) {
+                n = (n + 1) >> 1;
+                B = tile_bounds<EXT>(D, has_el, e, n);
+            }
+            if (oversize(B)) {
+                const DsDev Dc = D;
+                if (lane == 0) event_direct<T, EXT, LDSH>(P, Dc, e, edges, sink);
+            } else {
+                Raw R;
+                issue(e, n, B, R);
+                settle(R);
+                work(e, n, B, R);
+            }
+            e += n;
+            if (e >= eend) {
+                t += WAVES;
+                e = t * TW;
+                eend = min<int64_t>(e + TW, D.n_events);
+            }
         }
         // merge the LDS histograms into the dataset's block in HBM (the next
         // chunk, if any, is another dataset)

@@ -477,6 +477,45 @@ def test_pipeline_oversized_tiles(extended):
         check_against_oracle(ds, [q], got, f"giant tune={tune}")
 
 
+def _with_dense_runs(ds, rng):
+    """Runs of consecutive events with many objects: their tiles exceed the
+    on-chip capacity while halves or quarters of them fit (12 and 20 jets,
+    5 muons, 4 electrons per event)."""
+    jc = np.diff(ds.jets.offsets).copy()
+    mc = np.diff(ds.muons.offsets).copy()
+    jc[1000:1300] = 12
+    jc[1500:1600] = 20
+    mc[2000:2200] = 5
+    mc[1550:1580] = 4
+
+    def rebuild(coll, counts):
+        off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        return datagen.Collection(off, {k: rng.choice(v, int(off[-1])).astype(v.dtype) for k, v in coll.cols.items()})
+
+    els = None
+    if ds.electrons is not None:
+        ec = np.diff(ds.electrons.offsets).copy()
+        ec[2500:2700] = 4
+        ec[1020:1040] = 3
+        els = rebuild(ds.electrons, ec)
+    return datagen.Dataset(ds.n_events, rebuild(ds.jets, jc), rebuild(ds.muons, mc), ds.weight, els,
+                           ds.content_dtype)
+
+
+@pytest.mark.parametrize("extended", [False, True])
+def test_pipeline_dense_runs_split_tiles(extended):
+    """Tiles beyond the capacity run as fitting sub-tiles (halved event
+    counts), in every launch shape, equal to the oracle."""
+    say(f"pipeline dense runs extended={extended}")
+    base = datagen.make_dataset(12, 4000, extended=extended)
+    ds = _with_dense_runs(base, np.random.default_rng(5))
+    q = datagen.Query(min_b=1, scales=datagen.jes_scales()[:4]) if extended else datagen.Query()
+    qs = [q, datagen.Query(jet_pt=-1.0, min_mu=0, min_jet=3)]
+    for tune in (None, dict(block=512, ev_per_thread=2, hist_mode=0), dict(block=256, ev_per_thread=1, hist_mode=1)):
+        got = fused([ds], qs, tune)[0]
+        check_against_oracle(ds, qs, got, f"dense tune={tune}")
+
+
 def test_pipeline_repeated_runs_accumulate():
     say("pipeline accumulate")
     ds = datagen.make_dataset(4, 20000)
