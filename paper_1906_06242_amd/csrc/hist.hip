@@ -4,7 +4,8 @@
 // Each workgroup (1024 threads, two per CU) keeps a private copy of the
 // histogram in LDS (float64 sums via ds_add_f64, uint32 counts via
 // ds_add_u32) together with the bin edges, walks a grid-stride range of rows
-// eight at a time per thread (loads of the eight rows in flight together),
+// eight at a time per thread (loads of the eight rows in flight together,
+// then their eight bins found together),
 // and merges its non-empty slots into HBM with global atomics at the end
 // (few workgroups: few atomics on each slot).  Histograms too large for LDS
 // go straight to global atomics with the edges read from HBM.  Sums of float64 weights are exact in
@@ -18,6 +19,31 @@ namespace hepk {
 constexpr int HB = 1024;
 constexpr int HR = 8;  // rows per thread in flight
 constexpr int kMaxLdsSlots = 3000;  // 36 KiB of histogram + 12 KiB of edges
+
+// hist_slot_lohi for N values at once: every guess first, then every edge
+// pair read (all reads in flight together), then the checks, with a binary
+// search only where a guess was off.  NaN x gets slot 0 (callers skip it).
+template <int N>
+__device__ __forceinline__ void hist_slots_lohi(const float (&x)[N], const float *E, int nbins, float lo, float hi,
+                                                float inv_w, int (&s)[N]) {
+    int k[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const float g = (x[n] - lo) * inv_w;
+        const int gi = (g >= 0.0f) ? ((g < static_cast<float>(nbins)) ? static_cast<int>(g) + 1 : nbins) : 1;
+        s[n] = !(x[n] >= lo) ? 0 : (x[n] >= hi ? nbins + 1 : gi);
+        k[n] = (s[n] >= 1 && s[n] <= nbins) ? s[n] : 1;
+    }
+    float a[N], b[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        a[n] = E[k[n] - 1];
+        b[n] = E[k[n]];
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+        if (s[n] >= 1 && s[n] <= nbins && (x[n] < a[n] || x[n] >= b[n])) s[n] = bin_search(E, nbins, x[n]);
+}
 
 template <typename X, bool LDS>
 __global__ __launch_bounds__(HB) void hist_kernel(const X *__restrict__ x, const float *__restrict__ w,
@@ -42,39 +68,40 @@ __global__ __launch_bounds__(HB) void hist_kernel(const X *__restrict__ x, const
         for (int i = threadIdx.x; i <= nbins; i += HB) e_s[i] = edges[i];
         __syncthreads();
     }
-    auto one = [&](float v, double wt) {
-        if (v != v) return;
+    auto add = [&](int s, double wt) {
         if (LDS) {
-            const int s = hist_slot_lohi(v, e_s, nbins, lo, hi, inv_w);
             atomic_add_f64(&sw_s[s], wt);
             atomicAdd(&c_s[s], 1u);
         } else {
-            const int s = hist_slot_lohi(v, edges, nbins, lo, hi, inv_w);
             atomic_add_f64(&sumw[s], wt);
             atomic_add_u64(&counts[s], 1u);
         }
     };
     const int64_t stride = static_cast<int64_t>(gridDim.x) * HB;
     int64_t i = static_cast<int64_t>(blockIdx.x) * HB + threadIdx.x;
-    // HR rows per step, loads first
-    for (; i + (HR - 1) * stride < n; i += HR * stride) {
+    // HR rows per step (the last step predicated), loads first
+    for (; i < n; i += HR * stride) {
         float v[HR];
         float wt[HR];
         bool keep[HR];
 #pragma unroll
         for (int u = 0; u < HR; ++u) {
             const int64_t r = i + u * stride;
-            keep[u] = !m || m[r] != 0;
-            v[u] = static_cast<float>(x[r]);
-            wt[u] = w ? w[r] : 1.0f;
+            keep[u] = false;
+            v[u] = 0.0f;
+            wt[u] = 1.0f;
+            if (r < n) {
+                keep[u] = !m || m[r] != 0;
+                v[u] = static_cast<float>(x[r]);
+                if (w) wt[u] = w[r];
+            }
         }
+        // all HR bins found together (one round of edge reads)
+        int sl[HR];
+        hist_slots_lohi<HR>(v, LDS ? e_s : edges, nbins, lo, hi, inv_w, sl);
 #pragma unroll
         for (int u = 0; u < HR; ++u)
-            if (keep[u]) one(v[u], static_cast<double>(wt[u]));
-    }
-    for (; i < n; i += stride) {
-        if (m && !m[i]) continue;
-        one(static_cast<float>(x[i]), w ? static_cast<double>(w[i]) : 1.0);
+            if (keep[u] && v[u] == v[u]) add(sl[u], static_cast<double>(wt[u]));
     }
     if (LDS) {
         __syncthreads();
