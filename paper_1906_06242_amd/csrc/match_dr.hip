@@ -35,7 +35,7 @@ __global__ __launch_bounds__(64 * MW) void match_dr_kernel(
     const uint8_t *__restrict__ mask_a, const int64_t *__restrict__ off_b, const T *__restrict__ eta_b,
     const T *__restrict__ phi_b, const uint8_t *__restrict__ mask_b, int64_t n_events, float thr2,
     float *__restrict__ min_dr2, int32_t *__restrict__ idx_b, uint8_t *__restrict__ clean) {
-    __shared__ float beta_s[MW][64 * MKB], bphi_s[MW][64 * MKB];
+    __shared__ float beta_s[MW][64 * MKB + 2], bphi_s[MW][64 * MKB + 2];  // +2: reads past a range's end
     __shared__ uint32_t arng_s[MW][64 * MKA];  // per a object: its event's b range (first | count << 16)
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -136,26 +136,61 @@ __global__ __launch_bounds__(64 * MW) void match_dr_kernel(
             if (k < ae) ar[k] = pk;
         }
         wave_fence_dr();
-        // ---- one lane per a object
+        // ---- one lane per a object, slots in pairs: the pair's b ranges,
+        // then the first two b objects of each range, each set of LDS reads
+        // in flight together; only longer ranges loop over the rest.  A slot
+        // past the tile's a objects reads a stale word (its range is not
+        // used); reads past a range's end land in the next event's b objects
+        // or the two padding entries and are not used either.
 #pragma unroll
-        for (int k = 0; k < MKA; ++k) {
-            const int i = lane + 64 * k;
-            if (i < na) {
-                const uint32_t pk = ar[i];
-                const int b0 = static_cast<int>(pk & 0xffffu), b1 = b0 + static_cast<int>(pk >> 16);
-                float best = INFINITY;
-                int32_t bi = -1;
-                for (int b = b0; b < b1; ++b) {
-                    const float d2 = delta_r2(vea[k], vpa[k], be[b], bp[b]);
-                    if (d2 < best) {
-                        best = d2;
-                        bi = b - b0;
+        for (int k0 = 0; k0 < MKA; k0 += 2) {
+            uint32_t pk[2];
+            float e0[2], p0[2], e1[2], p1[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) pk[u] = ar[lane + 64 * (k0 + u)];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int f = lane + 64 * (k0 + u) < na ? static_cast<int>(pk[u] & 0xffffu) : 0;
+                e0[u] = be[f];
+                p0[u] = bp[f];
+                e1[u] = be[f + 1];
+                p1[u] = bp[f + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int k = k0 + u;
+                const int i = lane + 64 * k;
+                if (i < na) {
+                    const int b0 = static_cast<int>(pk[u] & 0xffffu), nbk = static_cast<int>(pk[u] >> 16);
+                    float best = INFINITY;
+                    int32_t bi = -1;
+                    // ascending order with a strict '<': the lowest index wins ties
+                    if (nbk >= 1) {
+                        const float d2 = delta_r2(vea[k], vpa[k], e0[u], p0[u]);
+                        if (d2 < best) {
+                            best = d2;
+                            bi = 0;
+                        }
                     }
+                    if (nbk >= 2) {
+                        const float d2 = delta_r2(vea[k], vpa[k], e1[u], p1[u]);
+                        if (d2 < best) {
+                            best = d2;
+                            bi = 1;
+                        }
+                    }
+                    for (int b = b0 + 2; b < b0 + nbk; ++b) {
+                        const float d2 = delta_r2(vea[k], vpa[k], be[b], bp[b]);
+                        if (d2 < best) {
+                            best = d2;
+                            bi = b - b0;
+                        }
+                    }
+                    const int64_t a = A0 + i;
+                    if (min_dr2) min_dr2[a] = best;
+                    if (idx_b) idx_b[a] = bi;
+                    if (clean) clean[a] = (oka[k] && !(best <= thr2)) ? 1 : 0;
                 }
-                const int64_t a = A0 + i;
-                if (min_dr2) min_dr2[a] = best;
-                if (idx_b) idx_b[a] = bi;
-                if (clean) clean[a] = (oka[k] && !(best <= thr2)) ? 1 : 0;
             }
         }
         wave_fence_dr();  // the next tile overwrites the staging
