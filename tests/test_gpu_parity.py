@@ -172,9 +172,35 @@ def test_match_dr_golden():
     assert np.array_equal(bits(host(md)), bits(wmd)) and np.array_equal(host(ix), wix)
 
 
-@pytest.mark.parametrize("case", ["config0", "f16", "large_events"])
+def _tied_b(rng, n):
+    """b objects in repeated pairs, (p0 p0 p1 p1 ...) or shifted by one
+    (p0 p1 p1 p2 p2 ...), so equal dR^2 fall on positions 0/1, 1/2, 2/3, ...
+    of an event's range: the first of the tied objects must win."""
+    ca = np.minimum(rng.poisson(5, n), 20)
+    cb = rng.integers(0, 8, n)
+    offa = np.concatenate([[0], np.cumsum(ca)]).astype(np.int64)
+    offb = np.concatenate([[0], np.cumsum(cb)]).astype(np.int64)
+    eb = np.empty(offb[-1], np.float32)
+    pb = np.empty(offb[-1], np.float32)
+    for e in range(n):
+        k = int(cb[e])
+        src = (np.arange(k) + (e & 1)) // 2
+        pts_e = rng.normal(0, 1.5, k).astype(np.float32)
+        pts_p = rng.uniform(-np.pi, np.pi, k).astype(np.float32)
+        eb[offb[e]:offb[e + 1]] = pts_e[src]
+        pb[offb[e]:offb[e + 1]] = pts_p[src]
+    ea = rng.normal(0, 1.5, offa[-1]).astype(np.float32)
+    pa = rng.uniform(-np.pi, np.pi, offa[-1]).astype(np.float32)
+    mb = (rng.uniform(size=offb[-1]) < 0.8).astype(np.uint8)
+    return offa, ea, pa, offb, eb, pb, mb
+
+
+@pytest.mark.parametrize("case", ["config0", "f16", "large_events", "ties"])
 def test_match_dr_matches_oracle(case):
-    if case == "large_events":
+    if case == "ties":
+        offa, ea, pa, offb, eb, pb, mb = _tied_b(np.random.default_rng(8), 3000)
+        ma = None
+    elif case == "large_events":
         n = 2000
         rng = np.random.default_rng(5)
         ca = np.minimum(rng.poisson(5, n), 20)
