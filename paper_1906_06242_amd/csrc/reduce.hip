@@ -75,11 +75,14 @@ __global__ __launch_bounds__(RB) void reduce_kernel(const int64_t *__restrict__ 
                                                     const uint8_t *__restrict__ evt_mask, void *out,
                                                     int32_t *out_arg, int index_only) {
     __shared__ float val_s[RW][(OP == R_COUNT) ? 1 : 64 * RK];
-    __shared__ uint8_t msk_s[RW][64 * RK];
+    // the tile's mask bytes as the 4-byte words that hold them (the first
+    // byte of the range at byte s of the first word)
+    constexpr int RMW = (64 * RK + 3 + 255) / 256;  // words per lane
+    __shared__ uint32_t msk_s[RW][64 * RMW];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float *vs = val_s[wave];
-    uint8_t *ms = msk_s[wave];
+    uint32_t *msw = msk_s[wave];
     const int64_t n_tiles = ceil_div(n_events, 64);
     const bool walk_objects = !(OP == R_COUNT && !obj_mask);
     const int64_t step = static_cast<int64_t>(gridDim.x) * RW;
@@ -114,25 +117,42 @@ __global__ __launch_bounds__(RB) void reduce_kernel(const int64_t *__restrict__ 
         } else if (tot <= 64 * RK) {
             const int n = static_cast<int>(tot);
             float v[RK];
-            uint8_t mk[RK];
 #pragma unroll
             for (int k = 0; k < RK; ++k) {
                 const int i = lane + 64 * k;
                 v[k] = 0.0f;
-                mk[k] = 1;
-                if (i < n) {
-                    if (OP != R_COUNT) v[k] = ldf(content, A + i);
-                    if (obj_mask) mk[k] = obj_mask[A + i];
+                if (OP != R_COUNT && i < n) v[k] = ldf(content, A + i);
+            }
+            // mask bytes in 4-byte loads: the aligned words that hold bytes
+            // [A, A + n) (each holds one of them, so it lies in the buffer's
+            // pages)
+            int s = 0, nw = 0;
+            uint32_t mw[RMW];
+            if (obj_mask) {
+                const uint8_t *p = obj_mask + A;
+                s = static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3u);
+                const uint32_t *pw = reinterpret_cast<const uint32_t *>(p - s);
+                nw = n > 0 ? (n + s + 3) >> 2 : 0;  // every word holds a byte of the range
+#pragma unroll
+                for (int k = 0; k < RMW; ++k) {
+                    const int w = lane + 64 * k;
+                    mw[k] = w < nw ? pw[w] : 0u;
                 }
             }
 #pragma unroll
             for (int k = 0; k < RK; ++k) {
                 const int i = lane + 64 * k;
-                if (i < n) {
-                    if (OP != R_COUNT) vs[i] = v[k];
-                    ms[i] = mk[k];
+                if (OP != R_COUNT && i < n) vs[i] = v[k];
+            }
+            if (obj_mask) {
+#pragma unroll
+                for (int k = 0; k < RMW; ++k) {
+                    const int w = lane + 64 * k;
+                    if (w < nw) msw[w] = mw[k];
                 }
             }
+            const uint8_t *ms = reinterpret_cast<const uint8_t *>(msw) + s;
+            const bool all = obj_mask == nullptr;
             wave_fence();
             const int b0 = static_cast<int>(a0), b1 = static_cast<int>(a1);  // within the tile's 512
             if (take) {
@@ -140,11 +160,11 @@ __global__ __launch_bounds__(RB) void reduce_kernel(const int64_t *__restrict__ 
                 int k = b0;
                 for (; k + 2 <= b1; k += 2) {
                     const float v0 = OP != R_COUNT ? vs[k] : 0.0f, v1 = OP != R_COUNT ? vs[k + 1] : 0.0f;
-                    const bool m0 = ms[k] != 0, m1 = ms[k + 1] != 0;
+                    const bool m0 = all || ms[k] != 0, m1 = all || ms[k + 1] != 0;
                     r.add(v0, m0, k - b0);
                     r.add(v1, m1, k + 1 - b0);
                 }
-                if (k < b1) r.add(OP != R_COUNT ? vs[k] : 0.0f, ms[k] != 0, k - b0);
+                if (k < b1) r.add(OP != R_COUNT ? vs[k] : 0.0f, all || ms[k] != 0, k - b0);
             }
             wave_fence();  // the next tile overwrites the staging
         } else if (take) {

@@ -147,6 +147,15 @@ def test_reduce_matches_oracle(case):
                 for op in (ref.ARGMAX, ref.ARGMIN):
                     assert np.array_equal(host(H.reduce(op, doff, dx, obj_mask=dom, evt_mask=dem)),
                                           ref.reduce(op, off, xv, obj_mask=omask, evt_mask=emask))
+    # an object mask whose first byte is not 4-byte aligned (a view into a
+    # larger buffer): the kernel reads the mask as aligned 4-byte words
+    for k in (1, 2, 3):
+        say(f"reduce {case} mask offset {k}")
+        dom = dev(np.concatenate([np.full(k, 9, np.uint8), om]))[k:]
+        cw = ref.reduce(ref.COUNT, off, obj_mask=om)
+        assert np.array_equal(host(H.reduce(H.COUNT, doff, obj_mask=dom)), cw)
+        sw = ref.reduce(ref.SUM, off, x, obj_mask=om)
+        assert np.array_equal(bits(host(H.reduce(H.SUM, doff, dev(x), obj_mask=dom))), bits(sw))
 
 
 def test_reduce_sum_order_case():
