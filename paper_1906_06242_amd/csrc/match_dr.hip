@@ -29,6 +29,40 @@ __device__ __forceinline__ void wave_fence_dr() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Mask bytes of a tile are read as the aligned 4-byte words that hold them
+// (one load moves four masks; every word holds a byte of the range, so it
+// lies in the buffer's pages): mask_words issues the loads, mask_stage puts
+// them into the wavefront's LDS and returns where byte 0 of the range is.
+constexpr int MBW = (64 * MKB + 3 + 255) / 256;  // mask words per lane, b objects
+constexpr int MAW = (64 * MKA + 3 + 255) / 256;  // and a objects
+template <int W>
+struct MaskWords {
+    uint32_t v[W];
+    int s, nw;
+};
+template <int W>
+__device__ __forceinline__ MaskWords<W> mask_words(const uint8_t *p, int n, int lane) {
+    MaskWords<W> m;
+    m.s = static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3u);
+    m.nw = n > 0 ? (n + m.s + 3) >> 2 : 0;
+    const uint32_t *pw = reinterpret_cast<const uint32_t *>(p - m.s);
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const int w = lane + 64 * k;
+        m.v[k] = w < m.nw ? pw[w] : 0u;
+    }
+    return m;
+}
+template <int W>
+__device__ __forceinline__ const uint8_t *mask_stage(const MaskWords<W> &m, uint32_t *lds, int lane) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const int w = lane + 64 * k;
+        if (w < m.nw) lds[w] = m.v[k];
+    }
+    return reinterpret_cast<const uint8_t *>(lds) + m.s;
+}
+
 template <typename T>
 __global__ __launch_bounds__(64 * MW) void match_dr_kernel(
     const int64_t *__restrict__ off_a, const T *__restrict__ eta_a, const T *__restrict__ phi_a,
@@ -37,6 +71,7 @@ __global__ __launch_bounds__(64 * MW) void match_dr_kernel(
     float *__restrict__ min_dr2, int32_t *__restrict__ idx_b, uint8_t *__restrict__ clean) {
     __shared__ float beta_s[MW][64 * MKB + 2], bphi_s[MW][64 * MKB + 2];  // +2: reads past a range's end
     __shared__ uint32_t arng_s[MW][64 * MKA];  // per a object: its event's b range (first | count << 16)
+    __shared__ uint32_t mskb_s[MW][64 * MBW], mska_s[MW][64 * MAW];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float *be = beta_s[wave], *bp = bphi_s[wave];
@@ -101,7 +136,6 @@ __global__ __launch_bounds__(64 * MW) void match_dr_kernel(
             if (i < nb) {
                 veb[k] = ldf(eta_b, B0 + i);
                 vpb[k] = ldf(phi_b, B0 + i);
-                if (mask_b && !mask_b[B0 + i]) veb[k] = __builtin_nanf("");
             }
         }
         float vea[MKA], vpa[MKA];
@@ -114,8 +148,23 @@ __global__ __launch_bounds__(64 * MW) void match_dr_kernel(
             if (i < na) {
                 vea[k] = ldf(eta_a, A0 + i);
                 vpa[k] = ldf(phi_a, A0 + i);
-                if (mask_a) oka[k] = mask_a[A0 + i] != 0;
             }
+        }
+        MaskWords<MBW> mwb{};
+        MaskWords<MAW> mwa{};
+        if (mask_b) mwb = mask_words<MBW>(mask_b + B0, nb, lane);
+        if (mask_a) mwa = mask_words<MAW>(mask_a + A0, na, lane);
+        if (mask_b || mask_a) {
+            const uint8_t *mbs = mask_b ? mask_stage<MBW>(mwb, mskb_s[wave], lane) : nullptr;
+            const uint8_t *mas = mask_a ? mask_stage<MAW>(mwa, mska_s[wave], lane) : nullptr;
+            wave_fence_dr();
+            // a masked-out b gets eta = NaN: its dR^2 is NaN and never the minimum
+#pragma unroll
+            for (int k = 0; k < MKB; ++k)
+                if (mask_b && lane + 64 * k < nb && !mbs[lane + 64 * k]) veb[k] = __builtin_nanf("");
+#pragma unroll
+            for (int k = 0; k < MKA; ++k)
+                if (mask_a && lane + 64 * k < na) oka[k] = mas[lane + 64 * k] != 0;
         }
         // ---- b objects and the per-a b ranges into LDS
 #pragma unroll

@@ -241,6 +241,16 @@ def test_match_dr_matches_oracle(case):
         assert np.array_equal(bits(host(md)), bits(wmd))
         assert np.array_equal(host(ix), wix)
         assert np.array_equal(host(cl), wcl)
+    # masks whose first byte is not 4-byte aligned (views into larger
+    # buffers): the kernel reads masks as aligned 4-byte words
+    wmd, wix, wcl = ref.match_dr(offa, ea, pa, offb, eb, pb, 0.4, mask_a=ma, mask_b=mb)
+    for k in (1, 2, 3):
+        say(f"match_dr {case} mask offset {k}")
+        vb = dev(np.concatenate([np.ones(k, np.uint8), mb]))[k:]
+        va = dev(np.concatenate([np.ones(k, np.uint8), ma]))[k:] if ma is not None else None
+        md, ix, cl = H.match_dr(dev(offa), dev(ea), dev(pa), dev(offb), dev(eb), dev(pb), 0.4, mask_a=va, mask_b=vb)
+        assert np.array_equal(bits(host(md)), bits(wmd)) and np.array_equal(host(ix), wix)
+        assert np.array_equal(host(cl), wcl)
     # no mask on b, only the clean output requested
     _, _, wcl = ref.match_dr(offa, ea, pa, offb, eb, pb, 0.4)
     _, _, cl = H.match_dr(dev(offa), dev(ea), dev(pa), dev(offb), dev(eb), dev(pb), 0.4, want=("clean",))
