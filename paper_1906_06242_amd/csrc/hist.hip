@@ -115,6 +115,103 @@ __global__ __launch_bounds__(HB) void hist_kernel(const X *__restrict__ x, const
     }
 }
 
+// Four consecutive values of x as float (one 16- or 8-byte load).
+__device__ __forceinline__ void load4(const float *p, float (&o)[4]) {
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    o[0] = v.x, o[1] = v.y, o[2] = v.z, o[3] = v.w;
+}
+__device__ __forceinline__ void load4(const int32_t *p, float (&o)[4]) {
+    const int4 v = *reinterpret_cast<const int4 *>(p);
+    o[0] = static_cast<float>(v.x), o[1] = static_cast<float>(v.y);
+    o[2] = static_cast<float>(v.z), o[3] = static_cast<float>(v.w);
+}
+__device__ __forceinline__ void load4(const _Float16 *p, float (&o)[4]) {
+    const uint2 v = *reinterpret_cast<const uint2 *>(p);
+    const uint32_t u[2] = {v.x, v.y};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        o[j] = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(u[j >> 1] >> (16 * (j & 1)))));
+}
+
+// The same fill with rows taken four at a time (rows 4q..4q+3 of quad q):
+// x, w and the mask read with one 16-, 16- and 4-byte load per quad, two
+// quads per thread per step.  Needs x, w aligned to their 4-row size and the
+// mask to 4 bytes.  The last quad may run past n: its loads stay inside the
+// aligned 4-row block that holds row 4q (so inside the buffer's pages), and
+// rows >= n are not filled.
+template <typename X, bool LDS>
+__global__ __launch_bounds__(HB) void hist_vec_kernel(const X *__restrict__ x, const float *__restrict__ w,
+                                                      const uint8_t *__restrict__ m, int64_t n,
+                                                      const float *__restrict__ edges, int nbins,
+                                                      double *__restrict__ sumw, uint64_t *__restrict__ counts) {
+    extern __shared__ double hist_lds[];
+    const int nslots = nbins + 2;
+    double *sw_s = hist_lds;
+    uint32_t *c_s = reinterpret_cast<uint32_t *>(hist_lds + (LDS ? nslots : 0));
+    float *e_s = reinterpret_cast<float *>(c_s + (LDS ? nslots : 0));
+    const float lo = as_const(edges)[0];
+    const float hi = as_const(edges)[nbins];
+    const float span = hi - lo;
+    const float inv_w = (span > 0.0f && span < INFINITY) ? static_cast<float>(nbins) / span : 0.0f;
+    if (LDS) {
+        for (int i = threadIdx.x; i < nslots; i += HB) {
+            sw_s[i] = 0.0;
+            c_s[i] = 0u;
+        }
+        for (int i = threadIdx.x; i <= nbins; i += HB) e_s[i] = edges[i];
+        __syncthreads();
+    }
+    auto add = [&](int s, double wt) {
+        if (LDS) {
+            atomic_add_f64(&sw_s[s], wt);
+            atomicAdd(&c_s[s], 1u);
+        } else {
+            atomic_add_f64(&sumw[s], wt);
+            atomic_add_u64(&counts[s], 1u);
+        }
+    };
+    constexpr int HQ = HR / 4;  // quads per thread per step
+    const int64_t nq = (n + 3) >> 2;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * HB;
+    for (int64_t q = static_cast<int64_t>(blockIdx.x) * HB + threadIdx.x; q < nq; q += HQ * stride) {
+        float v[HR], wt[HR];
+        bool keep[HR];
+#pragma unroll
+        for (int h = 0; h < HQ; ++h) {
+            const int64_t qq = q + h * stride;
+            float xv[4] = {0.0f, 0.0f, 0.0f, 0.0f}, wv[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+            uint32_t mv = 0xffffffffu;
+            const bool in = qq < nq;
+            if (in) {
+                load4(x + 4 * qq, xv);
+                if (w) load4(w + 4 * qq, wv);
+                if (m) mv = *reinterpret_cast<const uint32_t *>(m + 4 * qq);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                v[4 * h + j] = xv[j];
+                wt[4 * h + j] = wv[j];
+                keep[4 * h + j] = in && 4 * qq + j < n && ((mv >> (8 * j)) & 0xffu) != 0;
+            }
+        }
+        int sl[HR];
+        hist_slots_lohi<HR>(v, LDS ? e_s : edges, nbins, lo, hi, inv_w, sl);
+#pragma unroll
+        for (int u = 0; u < HR; ++u)
+            if (keep[u] && v[u] == v[u]) add(sl[u], static_cast<double>(wt[u]));
+    }
+    if (LDS) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < nslots; k += HB) {
+            const uint32_t c = c_s[k];
+            if (c) {
+                atomic_add_u64(&counts[k], c);
+                atomic_add_f64(&sumw[k], sw_s[k]);
+            }
+        }
+    }
+}
+
 template <typename X>
 static int launch_hist(const void *x, const float *w, const uint8_t *m, int64_t n, const hepk_hist *h,
                        hipStream_t stream) {
@@ -123,6 +220,16 @@ static int launch_hist(const void *x, const float *w, const uint8_t *m, int64_t 
     const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n, HB * HR), 2 * device_cus()));
     const size_t lds_bytes = static_cast<size_t>(nslots) * (sizeof(double) + sizeof(uint32_t)) +
                              static_cast<size_t>(h->nbins + 1) * sizeof(float);
+    auto aligned = [](const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; };
+    if (aligned(x, 4 * sizeof(X)) && (!w || aligned(w, 16)) && (!m || aligned(m, 4))) {
+        if (lds)
+            hist_vec_kernel<X, true><<<grid, HB, lds_bytes, stream>>>(static_cast<const X *>(x), w, m, n, h->edges,
+                                                                      h->nbins, h->sumw, h->counts);
+        else
+            hist_vec_kernel<X, false><<<grid, HB, 0, stream>>>(static_cast<const X *>(x), w, m, n, h->edges,
+                                                               h->nbins, h->sumw, h->counts);
+        return check_launch("hepk_hist_fill");
+    }
     if (lds)
         hist_kernel<X, true><<<grid, HB, lds_bytes, stream>>>(static_cast<const X *>(x), w, m, n, h->edges,
                                                               h->nbins, h->sumw, h->counts);

@@ -290,6 +290,17 @@ def test_hist_fill_matches_oracle(edges_kind):
         H.hist_fill(dev(x), de, s, c, w=dev(wt) if wt is not None else None,
                     evt_mask=dev(mk) if mk is not None else None)
         assert_hist((host(s), host(c)), (2 * ws, 2 * wc), edges_kind + " twice")
+    # views at an offset: k = 4 keeps every input aligned (four-row loads),
+    # k = 1 and 3 do not (one row per load)
+    ws, wc = ref.hist_fill(x, edges, w, m)
+    for k in (1, 3, 4):
+        s = torch.zeros(len(edges) + 1, dtype=torch.float64, device="cuda")
+        c = torch.zeros(len(edges) + 1, dtype=torch.int64, device="cuda")
+        xv = dev(np.concatenate([np.zeros(k, np.float32), x]))[k:]
+        wv = dev(np.concatenate([np.zeros(k, np.float32), w]))[k:]
+        mv = dev(np.concatenate([np.zeros(k, np.uint8), m]))[k:]
+        H.hist_fill(xv, de, s, c, w=wv, evt_mask=mv)
+        assert_hist((host(s), host(c)), (ws, wc), f"{edges_kind} views at {k}")
 
 
 def test_hist_fill_int_and_half_inputs():
