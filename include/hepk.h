@@ -26,8 +26,7 @@
  * before the call returns.  Per-object and per-event outputs are overwritten
  * for every row; histograms accumulate into the caller's contents.  The only
  * allocations the library makes are inside a hepk_plan (released by
- * hepk_plan_destroy) and stream-ordered temporaries of hepk_reduce's prefix
- * offsets, freed on the same stream.
+ * hepk_plan_destroy).
  *
  * Execution.  Every call enqueues its kernels on `stream` (NULL: the null
  * stream of the current device) and returns without synchronising.
@@ -46,7 +45,7 @@
 extern "C" {
 #endif
 
-#define HEPK_ABI_VERSION 2
+#define HEPK_ABI_VERSION 3
 #define HEPK_MAX_CUTS 8
 
 typedef enum hepk_status {
@@ -93,7 +92,9 @@ typedef enum hepk_reduce_op {
  * gets the empty result.
  *   COUNT  out int32[N]: number of counted objects; offsets_out (nullable,
  *          int64[N+1]): 0 followed by the running sum of out (the offsets of
- *          the selected sub-collection).  content may be NULL.
+ *          the selected sub-collection; the scan stages its partial sums in
+ *          offsets_out itself, so no temporary is allocated).  content may
+ *          be NULL.
  *   SUM    out float32[N]: left-to-right float32 sum from 0.0f, in object
  *          order -- the order of Listing 1's inner loop, kept exactly.
  *   MAX/MIN out float32[N]: extremum (-inf/+inf when empty); out_arg
@@ -273,6 +274,39 @@ int hepk_plan_get_tune(hepk_plan p, hepk_tune *tune /* host */);
 /* Runs the fused pass, accumulating into sumw/counts (hepk_plan_hist_slots
  * entries each). */
 int hepk_pipeline(hepk_plan p, double *sumw, uint64_t *counts, hipStream_t stream);
+
+/* Per-event record of the fused pass for one (event, query, scale): the
+ * intermediate values of Sec. IV's selection -- the number of selected muons,
+ * of selected and of b-tagged jets, H_T (Listing 1's left-to-right float32
+ * sum of the selected jets' scaled pt) and the leading selected jet's scaled
+ * pt (-inf when none), as the chain of primitives would compute them.
+ *   state 3: the event passes (it was filled into the histograms);
+ *   state 2: its jets were walked and it fails;
+ *   state 1: it was shown unable to pass before the walk (fewer selected
+ *            muons than min_mu, fewer jets before any cut than min_jet, or --
+ *            several scales and jet_pt >= 0 -- fewer selected or b-tagged jets
+ *            at the largest scale than required); only n_mu is meaningful,
+ *            the other fields hold 0, 0, 0.0f and -inf. */
+typedef struct hepk_event_record {
+    int32_t n_mu, n_jet, n_b, state;
+    float ht, lead;
+} hepk_event_record;
+
+/* Where the records of hepk_pipeline_debug go: the record of event e of
+ * dataset d for scale v of query slot q is rec[base + v * stride + e]
+ * (stride = total events of the plan's datasets); *n_records (host) is the
+ * length rec must have.  Any output pointer may be NULL. */
+int hepk_plan_debug_layout(hepk_plan p, int32_t d, int32_t q, int64_t *base /* host */,
+                           int64_t *stride /* host */, int64_t *n_records /* host */);
+
+/* hepk_pipeline that also writes every event's record for every active query
+ * and scale into rec (device, hepk_plan_debug_layout's n_records entries;
+ * records of idle slots are left as they are).  Same kernels as
+ * hepk_pipeline, instantiated with the record stores; the histograms it adds
+ * are the same.  For checking the pass event by event; not for production
+ * passes. */
+int hepk_pipeline_debug(hepk_plan p, double *sumw, uint64_t *counts, hepk_event_record *rec /* device */,
+                        hipStream_t stream);
 
 /* Same, over datasets [d0, d0 + nd) only. */
 int hepk_pipeline_range(hepk_plan p, int32_t d0, int32_t nd, double *sumw, uint64_t *counts,

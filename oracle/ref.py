@@ -220,3 +220,50 @@ def pipeline(ds, queries) -> List[List[tuple]]:
                                   C.cast(ps, C.c_void_p), C.cast(pc, C.c_void_p)))
     del keep
     return out
+
+
+def pipeline_events(ds, q) -> List[dict]:
+    """Per-event values of the analysis pass for one query, composed from the
+    primitives above as Sec. III's steering code would chain them (object
+    selection -> Delta-R cleaning -> per-event reductions -> event selection;
+    Listing 1 defines the H_T sum).  Independent of hepkref_pipeline, which
+    composes the same primitives in C.
+
+    Returns, per jet-energy scale v of the query, a dict of numpy arrays over
+    the events: n_mu, n_jet, n_b (int32), ht, lead (float32; lead = -inf when
+    no jet is selected) and passed (uint8).
+    """
+    j, m, el = ds.jets, ds.muons, ds.electrons
+    n = ds.n_events
+    mcuts = [(m.cols["pt"], GT, q.mu_pt), (m.cols["eta"], ABS_LT, q.mu_abseta)]
+    if "iso" in m.cols:
+        mcuts.append((m.cols["iso"], LT, q.mu_iso))
+    msel = select(mcuts, m.n_objects)
+    n_mu = reduce(COUNT, m.offsets, obj_mask=msel)
+    _, _, clean = match_dr(j.offsets, j.cols["eta"], j.cols["phi"], m.offsets, m.cols["eta"],
+                           m.cols["phi"], q.dr, mask_b=msel)
+    if el is not None:
+        esel = select([(el.cols["pt"], GT, q.el_pt), (el.cols["eta"], ABS_LT, q.el_abseta)], el.n_objects)
+        _, _, clean = match_dr(j.offsets, j.cols["eta"], j.cols["phi"], el.offsets, el.cols["eta"],
+                               el.cols["phi"], q.dr, mask_a=clean, mask_b=esel)
+    # float16 content widens exactly; the scaled pt is one float32 product
+    pt = np.ascontiguousarray(j.cols["pt"]).astype(np.float32)
+    has_bt = "btag" in j.cols
+    out = []
+    for s in np.asarray(q.scales, np.float32):
+        ptv = pt * np.float32(s)
+        jsel = select([(ptv, GT, q.jet_pt), (j.cols["eta"], ABS_LT, q.jet_abseta)], j.n_objects,
+                      mask_in=clean)
+        n_jet = reduce(COUNT, j.offsets, obj_mask=jsel)
+        ht = reduce(SUM, j.offsets, ptv, obj_mask=jsel)
+        lead = reduce(MAX, j.offsets, ptv, obj_mask=jsel)
+        evc = [(n_mu, GE, q.min_mu), (n_jet, GE, q.min_jet)]
+        if has_bt:
+            bsel = select([(j.cols["btag"], GT, q.btag)], j.n_objects, mask_in=jsel)
+            n_b = reduce(COUNT, j.offsets, obj_mask=bsel)
+            evc.append((n_b, GE, q.min_b))
+        else:
+            n_b = np.zeros(n, np.int32)
+        out.append({"n_mu": n_mu, "n_jet": n_jet, "n_b": n_b, "ht": ht, "lead": lead,
+                    "passed": select(evc, n)})
+    return out

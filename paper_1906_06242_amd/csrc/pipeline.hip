@@ -6,54 +6,16 @@
 #include <cstring>
 #include <vector>
 
-#include "pipeline_kernel.hpp"
+#include "plan.hpp"
 
 namespace hepk {
-// the multi-scale kernels are instantiated in pipeline_ms.hip
-extern template KernelFn pick_kernel<true>(int, bool, int, int, bool);
-template KernelFn pick_kernel<false>(int, bool, int, int, bool);
+// the multi-scale kernels are instantiated in pipeline_ms.hip, the kernels
+// that write per-event records in pipeline_dbg.hip and pipeline_ms_dbg.hip
+extern template KernelFn pick_kernel<true, false>(int, bool, int, int, bool);
+extern template KernelFn pick_kernel<false, true>(int, bool, int, int, bool);
+extern template KernelFn pick_kernel<true, true>(int, bool, int, int, bool);
+template KernelFn pick_kernel<false, false>(int, bool, int, int, bool);
 }  // namespace hepk
-
-struct hepk_plan_s {
-    int device = 0;
-    int32_t n_ds = 0, n_q = 0;
-    int dtype = HEPK_F32;
-    bool ext = false;
-    bool shared = false;
-    bool ms = false;  // some query slot holds several jet-energy scales
-    hepk_tune tune{};
-    int grid = 0;
-    hepk::KernelFn fn_lds = nullptr, fn_glob = nullptr;
-    size_t lds_static_lds = 0, lds_static_glob = 0;  // static LDS of the two kernels
-    size_t lds_max = 0;                              // the device's LDS per workgroup
-    hepk::PipeArgs args{};             // table pointers; chunk range and histograms set per launch
-    std::vector<int64_t> tile_pre;     // n_ds + 1: tiles of the datasets before each (chunk d = dataset d)
-    int64_t ds_block = 0;              // histogram slots per dataset block
-    int64_t n_slots = 0;
-    std::vector<hepk::QDev> qd;        // host copy of the query table
-    std::vector<int32_t> cap_bins;     // (slot, h): reserved bins
-    std::vector<int32_t> cap_scales;   // slot: reserved scales
-    int32_t lds_slots = 0;             // LDS histogram slots of the active queries
-    int32_t n_edges = 0, n_scales = 0;
-    bool edges_lds = false, scales_lds = false;
-    void *dev_mem = nullptr;
-    hepk::QDev *d_q = nullptr;
-    float *d_scales = nullptr, *d_edges = nullptr;
-    // pinned staging ring for hepk_plan_set_query
-    char *pinned = nullptr;
-    size_t stage_bytes = 0;
-    int ring_pos = 0;
-    std::vector<hipEvent_t> ring_ev;
-    std::vector<bool> ring_used;
-    // graph launch
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    hipGraphNode_t gnode = nullptr;
-    hepk::KernelFn gfn = nullptr;
-    hepk::PipeArgs gargs{};
-    size_t glds = 0;
-    int ggrid = 0;
-};
 
 namespace hepk {
 
@@ -137,19 +99,10 @@ static int check_query(const hepk_query &Q, int i) {
 
 static int64_t hist_base(hepk_plan p, int d) { return p->shared ? 0 : d * p->ds_block; }
 
-struct Launch {
-    KernelFn fn;
-    int grid, block;
-    size_t lds;         // dynamic LDS
-    size_t lds_static;  // the kernel's static LDS
-    size_t lds_max;
-    PipeArgs a;
-};
-
-static Launch make_launch(hepk_plan p, int32_t c0, int32_t c1, double *sumw, uint64_t *counts) {
+Launch make_launch(hepk_plan p, int32_t c0, int32_t c1, double *sumw, uint64_t *counts, hepk_event_record *rec) {
     Launch L{};
     const bool ldsh = use_lds_hist(p);
-    L.fn = ldsh ? p->fn_lds : p->fn_glob;
+    L.fn = rec ? (ldsh ? p->fn_lds_dbg : p->fn_glob_dbg) : (ldsh ? p->fn_lds : p->fn_glob);
     L.block = p->tune.block;
     // workgroups: as many as fit, but at least one tile per wavefront each
     const int64_t n_tiles = p->tile_pre[c1] - p->tile_pre[c0];
@@ -163,6 +116,8 @@ static Launch make_launch(hepk_plan p, int32_t c0, int32_t c1, double *sumw, uin
     L.a.ds_slots = ldsh ? p->lds_slots : 0;
     L.a.sumw = sumw;
     L.a.counts = counts;
+    L.a.rec = rec;
+    L.a.rec_events = p->ev_pre.back();
     return L;
 }
 
@@ -174,7 +129,7 @@ static int check_lds(const Launch &L) {
     return HEPK_OK;
 }
 
-static int run_launch(const Launch &L, hipStream_t stream) {
+int run_launch(const Launch &L, hipStream_t stream) {
     if (int rc = check_lds(L)) return rc;
     void *kargs[] = {const_cast<PipeArgs *>(&L.a)};
     HEPK_HIP(hipLaunchKernel(reinterpret_cast<const void *>(L.fn), dim3(L.grid), dim3(L.block), kargs, L.lds,
@@ -188,7 +143,11 @@ static bool any_active(hepk_plan p) {
     return false;
 }
 
-static void free_plan(hepk_plan p) {
+bool has_work(hepk_plan p, int32_t c0, int32_t c1) {
+    return c1 > c0 && p->tile_pre[c1] != p->tile_pre[c0] && any_active(p);
+}
+
+void free_plan(hepk_plan p) {
     if (!p) return;
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -205,10 +164,10 @@ static int plan_fail(hepk_plan p, int rc) {
     return rc;
 }
 
-extern "C" int hepk_plan_create_ex(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_t n_query,
-                                   const hepk_plan_opts *opts, hepk_plan *out) {
-    using namespace hepk;
-    clear_error();
+namespace hepk {
+
+int plan_build(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_t n_query,
+                      const hepk_plan_opts *opts, hepk_plan *out, std::vector<char> &img, TableLayout &lay) {
     HEPK_REQUIRE(out, "hepk_plan_create: out is NULL");
     *out = nullptr;
     HEPK_REQUIRE(n_ds >= 1 && ds, "hepk_plan_create: need at least one dataset");
@@ -310,11 +269,10 @@ extern "C" int hepk_plan_create_ex(const hepk_dataset *ds, int32_t n_ds, const h
     p->tune = t;
     relayout(p);
 
-    const int waves = t.block / 64;
     const int tw = 64 * t.ev_per_thread;
     std::vector<DsDev> dd(n_ds);
     std::vector<int64_t> tiles(n_ds);
-    int64_t total_tiles = 0;
+    p->ev_pre.assign(n_ds + 1, 0);
     for (int d = 0; d < n_ds; ++d) {
         const hepk_dataset &D = ds[d];
         DsDev &e = dd[d];
@@ -335,25 +293,33 @@ extern "C" int hepk_plan_create_ex(const hepk_dataset *ds, int32_t n_ds, const h
         e.ephi = D.electrons.phi;
         e.w = D.weights;
         e.hist0 = hist_base(p, d);
+        e.ev0 = p->ev_pre[d];
+        p->ev_pre[d + 1] = p->ev_pre[d] + D.n_events;
         tiles[d] = ceil_div(D.n_events, tw);
-        total_tiles += tiles[d];
     }
 
     p->ms = max_sc > 1;
-    auto pick = p->ms ? pick_kernel<true> : pick_kernel<false>;
+    auto pick = p->ms ? pick_kernel<true, false> : pick_kernel<false, false>;
+    auto pick_dbg = p->ms ? pick_kernel<true, true> : pick_kernel<false, true>;
     p->fn_lds = pick(dtype, ext, t.block, t.ev_per_thread, true);
     p->fn_glob = pick(dtype, ext, t.block, t.ev_per_thread, false);
+    p->fn_lds_dbg = pick_dbg(dtype, ext, t.block, t.ev_per_thread, true);
+    p->fn_glob_dbg = pick_dbg(dtype, ext, t.block, t.ev_per_thread, false);
     {
-        hipFuncAttributes fa{}, fg{};
+        hipFuncAttributes fa{}, fg{}, fad{}, fgd{};
         int mx = 0;
         if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(p->fn_lds)) != hipSuccess ||
             hipFuncGetAttributes(&fg, reinterpret_cast<const void *>(p->fn_glob)) != hipSuccess ||
+            hipFuncGetAttributes(&fad, reinterpret_cast<const void *>(p->fn_lds_dbg)) != hipSuccess ||
+            hipFuncGetAttributes(&fgd, reinterpret_cast<const void *>(p->fn_glob_dbg)) != hipSuccess ||
             hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) != hipSuccess) {
             set_error("hepk_plan_create: kernel or device attribute query failed");
             return plan_fail(p, HEPK_EHIP);
         }
         p->lds_static_lds = fa.sharedSizeBytes;
         p->lds_static_glob = fg.sharedSizeBytes;
+        // the record kernels take the same launch only with the same LDS
+        p->dbg_ok = fad.sharedSizeBytes == fa.sharedSizeBytes && fgd.sharedSizeBytes == fg.sharedSizeBytes;
         p->lds_max = static_cast<size_t>(mx);
         // the tables go to LDS only if they fit beside the kernel's own LDS
         if (p->lds_static_glob + table_lds_bytes(p) > p->lds_max) p->edges_lds = p->scales_lds = false;
@@ -385,34 +351,70 @@ extern "C" int hepk_plan_create_ex(const hepk_dataset *ds, int32_t n_ds, const h
     p->grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(grid, 1 << 20)));
     p->tune.grid = p->grid;
 
-    // one device allocation for the tables
+    // the table image: one block for all tables
     const size_t sz_ds = sizeof(DsDev) * n_ds, sz_ch = sizeof(Chunk) * std::max<size_t>(1, chunks.size());
     const size_t sz_q = sizeof(QDev) * n_query, sz_sc = sizeof(float) * scales.size();
     const size_t sz_e = sizeof(float) * edge_table.size();
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    const size_t o_ds = 0, o_ch = al(sz_ds), o_q = o_ch + al(sz_ch), o_sc = o_q + al(sz_q), o_e = o_sc + al(sz_sc);
-    const size_t total = o_e + al(sz_e);
-    if (hipMalloc(&p->dev_mem, total) != hipSuccess) {
-        set_error("hepk_plan_create: hipMalloc of %zu bytes failed", total);
+    lay.o_ds = 0;
+    lay.o_ch = al(sz_ds);
+    lay.o_q = lay.o_ch + al(sz_ch);
+    lay.o_sc = lay.o_q + al(sz_q);
+    lay.o_e = lay.o_sc + al(sz_sc);
+    lay.total = lay.o_e + al(sz_e);
+    lay.max_cap = max_cap;
+    lay.max_sc = max_sc;
+    img.assign(lay.total, 0);
+    std::memcpy(img.data() + lay.o_ds, dd.data(), sz_ds);
+    if (!chunks.empty()) std::memcpy(img.data() + lay.o_ch, chunks.data(), sizeof(Chunk) * chunks.size());
+    std::memcpy(img.data() + lay.o_q, p->qd.data(), sz_q);
+    if (sz_sc) std::memcpy(img.data() + lay.o_sc, scales.data(), sz_sc);
+    if (sz_e) std::memcpy(img.data() + lay.o_e, edge_table.data(), sz_e);
+    *out = p;
+    return HEPK_OK;
+}
+
+void plan_bind(hepk_plan p, char *base, const TableLayout &lay) {
+    p->d_q = reinterpret_cast<QDev *>(base + lay.o_q);
+    p->d_scales = reinterpret_cast<float *>(base + lay.o_sc);
+    p->d_edges = reinterpret_cast<float *>(base + lay.o_e);
+    PipeArgs &A = p->args;
+    A.ds = reinterpret_cast<const DsDev *>(base + lay.o_ds);
+    A.qs = p->d_q;
+    A.scales = p->d_scales;
+    A.chunks = reinterpret_cast<const Chunk *>(base + lay.o_ch);
+    A.edges = p->d_edges;
+    A.n_q = p->n_q;
+    A.n_edges = p->n_edges;
+    A.edges_in_lds = p->edges_lds ? 1 : 0;
+    A.n_scales = p->n_scales;
+    A.scales_in_lds = p->scales_lds ? 1 : 0;
+}
+
+}  // namespace hepk
+
+extern "C" int hepk_plan_create_ex(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_t n_query,
+                                   const hepk_plan_opts *opts, hepk_plan *out) {
+    using namespace hepk;
+    clear_error();
+    std::vector<char> img;
+    TableLayout lay{};
+    hepk_plan p = nullptr;
+    if (int rc = plan_build(ds, n_ds, q, n_query, opts, &p, img, lay)) return rc;
+    if (hipMalloc(&p->dev_mem, lay.total) != hipSuccess) {
+        set_error("hepk_plan_create: hipMalloc of %zu bytes failed", lay.total);
         return plan_fail(p, HEPK_ENOMEM);
     }
-    char *base = static_cast<char *>(p->dev_mem);
-    std::vector<char> host(total, 0);
-    std::memcpy(host.data() + o_ds, dd.data(), sz_ds);
-    if (!chunks.empty()) std::memcpy(host.data() + o_ch, chunks.data(), sizeof(Chunk) * chunks.size());
-    std::memcpy(host.data() + o_q, p->qd.data(), sz_q);
-    if (sz_sc) std::memcpy(host.data() + o_sc, scales.data(), sz_sc);
-    if (sz_e) std::memcpy(host.data() + o_e, edge_table.data(), sz_e);
-    if (hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(p->dev_mem, img.data(), lay.total, hipMemcpyHostToDevice) != hipSuccess) {
         set_error("hepk_plan_create: table upload failed");
         return plan_fail(p, HEPK_EHIP);
     }
-    p->d_q = reinterpret_cast<QDev *>(base + o_q);
-    p->d_scales = reinterpret_cast<float *>(base + o_sc);
-    p->d_edges = reinterpret_cast<float *>(base + o_e);
+    plan_bind(p, static_cast<char *>(p->dev_mem), lay);
 
     // staging ring: a full query table plus one slot's edges and scales per entry
-    p->stage_bytes = al(sz_q) + al(sizeof(float) * 3 * (max_cap + 1)) + al(sizeof(float) * max_sc);
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    p->stage_bytes = al(sizeof(QDev) * n_query) + al(sizeof(float) * 3 * (lay.max_cap + 1)) +
+                     al(sizeof(float) * lay.max_sc);
     if (hipHostMalloc(reinterpret_cast<void **>(&p->pinned), p->stage_bytes * kStageRing, hipHostMallocDefault) !=
         hipSuccess) {
         set_error("hepk_plan_create: pinned staging allocation failed");
@@ -425,18 +427,6 @@ extern "C" int hepk_plan_create_ex(const hepk_dataset *ds, int32_t n_ds, const h
             set_error("hepk_plan_create: event creation failed");
             return plan_fail(p, HEPK_EHIP);
         }
-
-    PipeArgs &A = p->args;
-    A.ds = reinterpret_cast<const DsDev *>(base + o_ds);
-    A.qs = p->d_q;
-    A.scales = p->d_scales;
-    A.chunks = reinterpret_cast<const Chunk *>(base + o_ch);
-    A.edges = p->d_edges;
-    A.n_q = n_query;
-    A.n_edges = p->n_edges;
-    A.edges_in_lds = p->edges_lds ? 1 : 0;
-    A.n_scales = p->n_scales;
-    A.scales_in_lds = p->scales_lds ? 1 : 0;
     *out = p;
     return HEPK_OK;
 }
@@ -528,7 +518,7 @@ extern "C" int hepk_plan_get_tune(hepk_plan p, hepk_tune *tune) {
 
 static int pipeline_chunks(hepk_plan p, int32_t c0, int32_t c1, double *sumw, uint64_t *counts, hipStream_t stream) {
     using namespace hepk;
-    if (c1 <= c0 || p->tile_pre[c1] == p->tile_pre[c0] || !any_active(p)) return HEPK_OK;
+    if (!has_work(p, c0, c1)) return HEPK_OK;
     int dev = 0;
     HEPK_HIP(hipGetDevice(&dev));
     HEPK_REQUIRE(dev == p->device, "hepk_pipeline: plan made on device %d, current device %d", p->device, dev);
@@ -540,6 +530,35 @@ extern "C" int hepk_pipeline(hepk_plan p, double *sumw, uint64_t *counts, hipStr
     HEPK_REQUIRE(p, "hepk_pipeline: plan is NULL");
     HEPK_REQUIRE(sumw && counts, "hepk_pipeline: histogram buffers are NULL");
     return pipeline_chunks(p, 0, p->n_ds, sumw, counts, stream);
+}
+
+extern "C" int hepk_plan_debug_layout(hepk_plan p, int32_t d, int32_t q, int64_t *base, int64_t *stride,
+                                      int64_t *n_records) {
+    hepk::clear_error();
+    HEPK_REQUIRE(p, "hepk_plan_debug_layout: plan is NULL");
+    HEPK_REQUIRE(d >= 0 && d < p->n_ds && q >= 0 && q < p->n_q, "hepk_plan_debug_layout: index out of range");
+    const int64_t ne = p->ev_pre.back();
+    if (base) *base = static_cast<int64_t>(p->qd[q].scale0) * ne + p->ev_pre[d];
+    if (stride) *stride = ne;
+    if (n_records) *n_records = static_cast<int64_t>(p->n_scales) * ne;
+    return HEPK_OK;
+}
+
+extern "C" int hepk_pipeline_debug(hepk_plan p, double *sumw, uint64_t *counts, hepk_event_record *rec,
+                                   hipStream_t stream) {
+    using namespace hepk;
+    clear_error();
+    HEPK_REQUIRE(p, "hepk_pipeline_debug: plan is NULL");
+    HEPK_REQUIRE(sumw && counts && rec, "hepk_pipeline_debug: NULL buffer");
+    if (!p->dbg_ok) {
+        set_error("hepk_pipeline_debug: record kernels differ in LDS from the product kernels");
+        return HEPK_EUNSUPPORTED;
+    }
+    if (p->tile_pre[p->n_ds] == 0 || !any_active(p)) return HEPK_OK;
+    int dev = 0;
+    HEPK_HIP(hipGetDevice(&dev));
+    HEPK_REQUIRE(dev == p->device, "hepk_pipeline_debug: plan made on device %d, current device %d", p->device, dev);
+    return run_launch(make_launch(p, 0, p->n_ds, sumw, counts, rec), stream);
 }
 
 extern "C" int hepk_pipeline_range(hepk_plan p, int32_t d0, int32_t nd, double *sumw, uint64_t *counts,

@@ -67,6 +67,7 @@ struct DsDev {
     const void *ept, *eeta, *ephi;
     const float *w;
     int64_t hist0;  // first slot of this dataset's block of histograms
+    int64_t ev0;    // events of the datasets before this one (per-event records)
 };
 
 struct QDev {
@@ -103,7 +104,17 @@ struct PipeArgs {
     int32_t n_scales, scales_in_lds;               // the scale table, copied to LDS when small
     double *sumw;
     uint64_t *counts;
+    // per-event records (kernels instantiated with DBG only): the record of
+    // event e of dataset d for scale v of query q is
+    // rec[(q.scale0 + v) * rec_events + d.ev0 + e]
+    hepk_event_record *rec;
+    int64_t rec_events;
 };
+
+// Writes the record of one event and scale (DBG kernels only).
+__device__ __forceinline__ hepk_event_record *rec_at(const PipeArgs &P, int row, int64_t ev) {
+    return P.rec + static_cast<int64_t>(row) * P.rec_events + ev;
+}
 
 template <bool LDSH>
 struct HistSink {
@@ -217,7 +228,7 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // One event, one lane, columns read straight from HBM.
-template <typename T, bool EXT, bool LDSH>
+template <typename T, bool EXT, bool LDSH, bool DBG>
 __device__ void event_direct(const PipeArgs &P, const DsDev &D, int64_t e, const float *edges,
                              const HistSink<LDSH> &sink) {
     const bool has_iso = D.miso != nullptr;
@@ -264,6 +275,7 @@ __device__ void event_direct(const PipeArgs &P, const DsDev &D, int64_t e, const
                 if (has_bt && ldf(jbt, j) > Q.btag) ++nb;
             }
             const bool pass = nmu >= Q.min_mu && nj >= Q.min_jet && (!has_bt || nb >= Q.min_b);
+            if (DBG) *rec_at(P, Q.scale0 + v, D.ev0 + e) = hepk_event_record{nmu, nj, nb, pass ? 3 : 2, ht, lead};
             if (pass) fill3(sink, Q, edges, v, ht, lead, nj, w);
         }
     }
@@ -449,7 +461,11 @@ __device__ __forceinline__ void compact(const bool (&sel)[K], const float (&eta)
 // wavefronts need twice the LDS); several scales: two, which is what LDS
 // allows next to the histograms of 20 scales, so the walk and the fills
 // may use the registers for instruction-level parallelism instead.
-template <typename T, bool EXT, int WAVES, int EVPL, bool LDSH, bool MS>
+// DBG: also write every event's per-scale record (counts, H_T, leading pt,
+// whether the event was walked and whether it passed) to P.rec -- the
+// intermediate values of the pass, for checking them one by one.  Product
+// launches use DBG = false; the arithmetic is the same in both.
+template <typename T, bool EXT, int WAVES, int EVPL, bool LDSH, bool MS, bool DBG>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(MS ? 2 : (EXT ? 4 : 6)))) void
 pipeline_kernel(PipeArgs P) {
     using C = Caps<EVPL, EXT>;
@@ -836,6 +852,9 @@ pipeline_kernel(PipeArgs P) {
                         else
                             walk_jets<1, EXT>(L, jb[r], elig ? je[r] : jb[r], sc, jet_pt, ht, lead, njs, nbt);
                         const bool pass[1] = {elig && njs[0] >= min_jet && nbt[0] >= min_b};
+                        if (DBG && lane + 64 * r < ne)
+                            *rec_at(P, Q.scale0, D.ev0 + e0 + lane + 64 * r) = hepk_event_record{
+                                nmu[r], njs[0], nbt[0], elig ? (pass[0] ? 3 : 2) : 1, ht[0], lead[0]};
                         if (pass[0]) {
                             const float xs[3] = {ht[0], lead[0], static_cast<float>(njs[0])};
                             fill(xs, pass, 0, static_cast<double>(wv[r]));
@@ -867,12 +886,34 @@ pipeline_kernel(PipeArgs P) {
                             walk_jets<1, EXT>(L, jb[r], je[r], smaxa, jet_pt, ht1, lead1, nj1, nb1);
                             elig = nj1[0] >= min_jet && nb1[0] >= min_b;
                         }
+                        if (DBG && lane + 64 * r < ne) {
+                            // the muon count of every event; the rest only of
+                            // events that are not walked (the walk writes the
+                            // other fields of walked events' records)
+                            const int64_t ge = D.ev0 + e0 + lane + 64 * r;
+                            for (int v = 0; v < Q.n_scale; ++v) {
+                                hepk_event_record *o = rec_at(P, Q.scale0 + v, ge);
+                                o->n_mu = nmu[r];
+                                if (!elig) {
+                                    o->n_jet = 0;
+                                    o->n_b = 0;
+                                    o->state = 1;
+                                    o->ht = 0.0f;
+                                    o->lead = -INFINITY;
+                                }
+                            }
+                        }
                         const uint64_t bal = __ballot(elig);
                         const int at = nel + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
                                                  static_cast<uint32_t>(bal >> 32),
                                                  __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bal), 0u)));
                         if (elig) {
-                            L.u.w.evjr[at] = static_cast<uint32_t>(jb[r]) | (static_cast<uint32_t>(je[r]) << 16);
+                            // jet range: first in bits 0-9, end in bits 16-25
+                            // (both below 64 * JK <= 832); DBG kernels keep the
+                            // event's place in the tile in the bits between
+                            const uint32_t ev = static_cast<uint32_t>(lane + 64 * r);
+                            L.u.w.evjr[at] = static_cast<uint32_t>(jb[r]) | (static_cast<uint32_t>(je[r]) << 16) |
+                                             (DBG ? (((ev & 63u) << 10) | ((ev >> 6) << 26)) : 0u);
                             L.u.w.evw[at] = wv[r];
                         }
                         nel += __popcll(bal);
@@ -892,13 +933,26 @@ pipeline_kernel(PipeArgs P) {
                         for (int u = 0; u < kG; ++u) sc[u] = scl[min(g * kG + u, V - 1)];
                         float ht[kG], lead[kG];
                         int njs[kG], nbt[kG];
-                        walk_jets<kG, EXT>(L, static_cast<int>(jr & 0xffffu), static_cast<int>(jr >> 16), sc, jet_pt,
-                                           ht, lead, njs, nbt);
+                        walk_jets<kG, EXT>(L, static_cast<int>(jr & 0x3ffu), static_cast<int>((jr >> 16) & 0x3ffu), sc,
+                                           jet_pt, ht, lead, njs, nbt);
                         bool pass[kG], any = false;
 #pragma unroll
                         for (int u = 0; u < kG; ++u) {
                             pass[u] = g * kG + u < V && njs[u] >= min_jet && nbt[u] >= min_b;
                             any |= pass[u];
+                        }
+                        if (DBG) {
+                            const int64_t ge = D.ev0 + e0 + (((jr >> 10) & 63u) | ((jr >> 26) << 6));
+#pragma unroll
+                            for (int u = 0; u < kG; ++u) {
+                                if (g * kG + u >= V) continue;
+                                hepk_event_record *o = rec_at(P, scale0 + g * kG + u, ge);
+                                o->n_jet = njs[u];
+                                o->n_b = nbt[u];
+                                o->state = pass[u] ? 3 : 2;
+                                o->ht = ht[u];
+                                o->lead = lead[u];
+                            }
                         }
                         if (any) {
                             // two scales' bins per search: the batch that fits the
@@ -949,7 +1003,7 @@ pipeline_kernel(PipeArgs P) {
             }
             if (oversize(B)) {
                 const DsDev Dc = D;
-                if (lane == 0) event_direct<T, EXT, LDSH>(P, Dc, e, edges, sink);
+                if (lane == 0) event_direct<T, EXT, LDSH, DBG>(P, Dc, e, edges, sink);
             } else {
                 Raw R;
                 issue(e, n, B, R);
@@ -992,30 +1046,32 @@ pipeline_kernel(PipeArgs P) {
 
 using KernelFn = void (*)(PipeArgs);
 
-template <typename T, bool EXT, int WAVES, int EVPL, bool LDSH, bool MS>
+template <typename T, bool EXT, int WAVES, int EVPL, bool LDSH, bool MS, bool DBG>
 static KernelFn kfn() {
-    return reinterpret_cast<KernelFn>(&pipeline_kernel<T, EXT, WAVES, EVPL, LDSH, MS>);
+    return reinterpret_cast<KernelFn>(&pipeline_kernel<T, EXT, WAVES, EVPL, LDSH, MS, DBG>);
 }
 
-template <typename T, bool EXT, int WAVES, int EVPL, bool MS>
+template <typename T, bool EXT, int WAVES, int EVPL, bool MS, bool DBG>
 static KernelFn pick_h(bool ldsh) {
-    return ldsh ? kfn<T, EXT, WAVES, EVPL, true, MS>() : kfn<T, EXT, WAVES, EVPL, false, MS>();
+    return ldsh ? kfn<T, EXT, WAVES, EVPL, true, MS, DBG>() : kfn<T, EXT, WAVES, EVPL, false, MS, DBG>();
 }
 
-template <typename T, bool EXT, bool MS>
+template <typename T, bool EXT, bool MS, bool DBG>
 static KernelFn pick_shape(int block, int evpt, bool ldsh) {
-    if (block == 1024) return pick_h<T, EXT, 16, 1, MS>(ldsh);  // one event per thread only
-    if (block == 512) return evpt == 2 ? pick_h<T, EXT, 8, 2, MS>(ldsh) : pick_h<T, EXT, 8, 1, MS>(ldsh);
-    return evpt == 2 ? pick_h<T, EXT, 4, 2, MS>(ldsh) : pick_h<T, EXT, 4, 1, MS>(ldsh);
+    if (block == 1024) return pick_h<T, EXT, 16, 1, MS, DBG>(ldsh);  // one event per thread only
+    if (block == 512)
+        return evpt == 2 ? pick_h<T, EXT, 8, 2, MS, DBG>(ldsh) : pick_h<T, EXT, 8, 1, MS, DBG>(ldsh);
+    return evpt == 2 ? pick_h<T, EXT, 4, 2, MS, DBG>(ldsh) : pick_h<T, EXT, 4, 1, MS, DBG>(ldsh);
 }
 
-// The kernel for a launch shape; each value of MS is instantiated in its own
-// translation unit (they compile in parallel).
-template <bool MS>
+// The kernel for a launch shape; each (MS, DBG) pair is instantiated in its
+// own translation unit (they compile in parallel).
+template <bool MS, bool DBG>
 KernelFn pick_kernel(int dtype, bool ext, int block, int evpt, bool ldsh) {
-    if (dtype == HEPK_F16) return ext ? pick_shape<_Float16, true, MS>(block, evpt, ldsh)
-                                      : pick_shape<_Float16, false, MS>(block, evpt, ldsh);
-    return ext ? pick_shape<float, true, MS>(block, evpt, ldsh) : pick_shape<float, false, MS>(block, evpt, ldsh);
+    if (dtype == HEPK_F16) return ext ? pick_shape<_Float16, true, MS, DBG>(block, evpt, ldsh)
+                                      : pick_shape<_Float16, false, MS, DBG>(block, evpt, ldsh);
+    return ext ? pick_shape<float, true, MS, DBG>(block, evpt, ldsh)
+               : pick_shape<float, false, MS, DBG>(block, evpt, ldsh);
 }
 
 // LDS for the workgroup's private histograms: up to 64 KiB (60 histograms of

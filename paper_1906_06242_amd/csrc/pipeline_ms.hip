@@ -1,8 +1,8 @@
 // Instantiates the fused analysis kernel for plans whose queries have
-// several jet-energy scales (compiled apart from pipeline.hip so the two
-// sets of kernels build in parallel).
+// several jet-energy scales (compiled apart from pipeline.hip so the sets of
+// kernels build in parallel).
 #include "pipeline_kernel.hpp"
 
 namespace hepk {
-template KernelFn pick_kernel<true>(int, bool, int, int, bool);
+template KernelFn pick_kernel<true, false>(int, bool, int, int, bool);
 }  // namespace hepk

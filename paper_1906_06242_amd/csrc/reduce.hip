@@ -187,27 +187,39 @@ __global__ __launch_bounds__(RB) void reduce_kernel(const int64_t *__restrict__ 
     }
 }
 
-// tile_tot[tile] = sum of the counts of events [tile * RB, tile * RB + RB).
-__global__ __launch_bounds__(RB) void tile_sums_kernel(const int32_t *counts, int64_t n_events, int64_t *tile_tot) {
+// Prefix offsets of the selected sub-collection without a temporary: the
+// total of tile t (events [t * RB, t * RB + RB)) is staged in offsets_out at
+// tile_slot(t) = min((t + 1) * RB, N), the entry whose final value is the sum
+// of the counts of tiles 0..t.  An in-place inclusive scan over those entries
+// makes them final; each tile then reads its exclusive prefix from the entry
+// before its first event (that of tile t - 1) and writes its other entries.
+__host__ __device__ inline int64_t tile_slot(int64_t t, int64_t n_events) {
+    return (t + 1) * RB < n_events ? (t + 1) * RB : n_events;
+}
+
+// offsets_out[tile_slot(t)] = sum of the counts of tile t.
+__global__ __launch_bounds__(RB) void tile_sums_kernel(const int32_t *counts, int64_t n_events, int64_t *offsets_out) {
     __shared__ int64_t scan_s[RB];
     const int64_t n_tiles = ceil_div(n_events, RB);
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t e = tile * RB + threadIdx.x;
         const int64_t incl = block_inclusive_scan(e < n_events ? counts[e] : 0, scan_s);
-        if (threadIdx.x == RB - 1) tile_tot[tile] = incl;
+        if (threadIdx.x == RB - 1) offsets_out[tile_slot(tile, n_events)] = incl;
         __syncthreads();
     }
 }
 
-// Exclusive scan, in place, of n int64 values by one workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void scan_tiles_kernel(int64_t *v, int64_t n) {
+// Inclusive scan, in place, of the staged tile totals by one workgroup of
+// 1024 threads (each thread a contiguous run of tiles).
+__global__ __launch_bounds__(1024) void scan_tiles_kernel(int64_t *offsets_out, int64_t n_events) {
     __shared__ int64_t buf[1024];
     const int tid = threadIdx.x;
+    const int64_t n = ceil_div(n_events, RB);
     const int64_t per = ceil_div(n, 1024);
     const int64_t b = tid * per;
     const int64_t e = (b + per < n) ? b + per : n;
     int64_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += v[i];
+    for (int64_t i = b; i < e; ++i) s += offsets_out[tile_slot(i, n_events)];
     buf[tid] = s;
     __syncthreads();
     for (int d = 1; d < 1024; d <<= 1) {
@@ -216,45 +228,55 @@ __global__ __launch_bounds__(1024) void scan_tiles_kernel(int64_t *v, int64_t n)
         buf[tid] += add;
         __syncthreads();
     }
-    int64_t run = buf[tid] - s;  // exclusive prefix of this thread's chunk
+    int64_t run = buf[tid] - s;  // exclusive prefix of this thread's run
     for (int64_t i = b; i < e; ++i) {
-        int64_t x = v[i];
-        v[i] = run;
-        run += x;
+        int64_t &v = offsets_out[tile_slot(i, n_events)];
+        run += v;
+        v = run;
     }
 }
 
-// offsets_out[0] = 0, offsets_out[e+1] = sum of counts[0..e].
+// offsets_out[0] = 0, offsets_out[e+1] = sum of counts[0..e]: the entries
+// not staged (each tile's staged entry is final already and is the base the
+// next tile reads, so it is not written again).
 __global__ __launch_bounds__(RB) void offsets_from_counts_kernel(const int32_t *counts, int64_t n_events,
-                                                                 const int64_t *tile_pre, int64_t *offsets_out) {
+                                                                 int64_t *offsets_out) {
     __shared__ int64_t scan_s[RB];
     const int tid = threadIdx.x;
     const int64_t n_tiles = ceil_div(n_events, RB);
     if (blockIdx.x == 0 && tid == 0) offsets_out[0] = 0;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t base = tile > 0 ? offsets_out[tile * RB] : 0;
         const int64_t e = tile * RB + tid;
         const int64_t c = (e < n_events) ? counts[e] : 0;
         const int64_t incl = block_inclusive_scan(c, scan_s);
-        if (e < n_events) offsets_out[e + 1] = tile_pre[tile] + incl;
+        if (e < n_events && e + 1 != tile_slot(tile, n_events)) offsets_out[e + 1] = base + incl;
         __syncthreads();
     }
 }
 
 template <typename T, int OP>
 static int launch_reduce(const int64_t *off, int64_t n, const void *content, const uint8_t *om,
-                         const uint8_t *em, void *out, int32_t *out_arg, int index_only, int64_t *tile_tot,
-                         hipStream_t stream) {
+                         const uint8_t *em, void *out, int32_t *out_arg, int index_only, hipStream_t stream) {
     const int64_t n_wave_tiles = ceil_div(n, 64);
     const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n_wave_tiles, RW), 16 * device_cus()));
     reduce_kernel<T, OP><<<grid, RB, 0, stream>>>(off, n, static_cast<const T *>(content), om, em, out,
                                                   out_arg, index_only);
-    int rc = check_launch("hepk_reduce");
-    if (rc == HEPK_OK && tile_tot) {
-        const int g = static_cast<int>(std::min<int64_t>(ceil_div(n, RB), 8 * device_cus()));
-        tile_sums_kernel<<<g, RB, 0, stream>>>(static_cast<const int32_t *>(out), n, tile_tot);
-        rc = check_launch("hepk_reduce tile sums");
+    return check_launch("hepk_reduce");
+}
+
+// offsets_out from the counts just written (three launches, no temporary).
+static int launch_offsets(const int32_t *counts, int64_t n, int64_t *offsets_out, hipStream_t stream) {
+    const int64_t n_tiles = ceil_div(n, RB);
+    const int g = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_tiles, 8 * device_cus())));
+    if (n > 0) {
+        tile_sums_kernel<<<g, RB, 0, stream>>>(counts, n, offsets_out);
+        if (int rc = check_launch("hepk_reduce tile sums")) return rc;
+        scan_tiles_kernel<<<1, 1024, 0, stream>>>(offsets_out, n);
+        if (int rc = check_launch("hepk_reduce scan")) return rc;
     }
-    return rc;
+    offsets_from_counts_kernel<<<g, RB, 0, stream>>>(counts, n, offsets_out);
+    return check_launch("hepk_reduce offsets");
 }
 
 }  // namespace hepk
@@ -277,65 +299,35 @@ extern "C" int hepk_reduce(int32_t op, const int64_t *offsets, int64_t n_events,
         }
         HEPK_REQUIRE(content || n_events == 0, "hepk_reduce: content is NULL");
     }
-    if (n_events == 0) {
-        if (offsets_out) {  // writes offsets_out[0] = 0 only
-            offsets_from_counts_kernel<<<1, RB, 0, stream>>>(nullptr, 0, nullptr, offsets_out);
-            return check_launch("hepk_reduce offsets");
-        }
-        return HEPK_OK;
-    }
-    int64_t *tile_tot = nullptr;
-    const int64_t n_tiles = ceil_div(n_events, RB);
-    if (offsets_out) {
-        hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&tile_tot), n_tiles * sizeof(int64_t), stream);
-        if (e != hipSuccess) {
-            set_error("hepk_reduce: temporary of %lld bytes: %s", (long long)(n_tiles * 8), hipGetErrorString(e));
-            return HEPK_ENOMEM;
-        }
-    }
+    if (n_events == 0) return offsets_out ? launch_offsets(nullptr, 0, offsets_out, stream) : HEPK_OK;
     int rc;
     const bool h = dtype == HEPK_F16;
     switch (op) {
     case HEPK_COUNT:
         rc = launch_reduce<float, R_COUNT>(offsets, n_events, nullptr, obj_mask, evt_mask, out, nullptr, 0,
-                                           tile_tot, stream);
+                                           stream);
         break;
     case HEPK_SUM:
         rc = h ? launch_reduce<_Float16, R_SUM>(offsets, n_events, content, obj_mask, evt_mask, out, nullptr, 0,
-                                                nullptr, stream)
+                                                stream)
                : launch_reduce<float, R_SUM>(offsets, n_events, content, obj_mask, evt_mask, out, nullptr, 0,
-                                             nullptr, stream);
+                                             stream);
         break;
     case HEPK_MAX:
     case HEPK_ARGMAX:
         rc = h ? launch_reduce<_Float16, R_MAX>(offsets, n_events, content, obj_mask, evt_mask, out, out_arg,
-                                                op == HEPK_ARGMAX, nullptr, stream)
+                                                op == HEPK_ARGMAX, stream)
                : launch_reduce<float, R_MAX>(offsets, n_events, content, obj_mask, evt_mask, out, out_arg,
-                                             op == HEPK_ARGMAX, nullptr, stream);
+                                             op == HEPK_ARGMAX, stream);
         break;
     default:
         rc = h ? launch_reduce<_Float16, R_MIN>(offsets, n_events, content, obj_mask, evt_mask, out, out_arg,
-                                                op == HEPK_ARGMIN, nullptr, stream)
+                                                op == HEPK_ARGMIN, stream)
                : launch_reduce<float, R_MIN>(offsets, n_events, content, obj_mask, evt_mask, out, out_arg,
-                                             op == HEPK_ARGMIN, nullptr, stream);
+                                             op == HEPK_ARGMIN, stream);
         break;
     }
-    if (rc == HEPK_OK && offsets_out) {
-        scan_tiles_kernel<<<1, 1024, 0, stream>>>(tile_tot, n_tiles);
-        rc = check_launch("hepk_reduce scan");
-        if (rc == HEPK_OK) {
-            const int grid = static_cast<int>(std::min<int64_t>(n_tiles, 8 * device_cus()));
-            offsets_from_counts_kernel<<<grid, RB, 0, stream>>>(static_cast<const int32_t *>(out), n_events,
-                                                                tile_tot, offsets_out);
-            rc = check_launch("hepk_reduce offsets");
-        }
-    }
-    if (tile_tot) {
-        hipError_t e = hipFreeAsync(tile_tot, stream);
-        if (rc == HEPK_OK && e != hipSuccess) {
-            set_error("hepk_reduce: hipFreeAsync: %s", hipGetErrorString(e));
-            rc = HEPK_EHIP;
-        }
-    }
+    if (rc == HEPK_OK && offsets_out)
+        rc = launch_offsets(static_cast<const int32_t *>(out), n_events, offsets_out, stream);
     return rc;
 }

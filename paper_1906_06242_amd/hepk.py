@@ -25,7 +25,13 @@ EXPORTS = (
     "hepk_plan_create", "hepk_plan_create_ex", "hepk_plan_set_query", "hepk_plan_hist_slots",
     "hepk_plan_hist_offset", "hepk_plan_get_tune", "hepk_pipeline", "hepk_pipeline_range",
     "hepk_pipeline_graph", "hepk_autotune", "hepk_plan_destroy", "hepk_last_error", "hepk_abi_version",
+    "hepk_plan_debug_layout", "hepk_pipeline_debug",
 )
+
+# hepk_event_record, as a numpy structured dtype (24 bytes)
+EVENT_RECORD = [("n_mu", "<i4"), ("n_jet", "<i4"), ("n_b", "<i4"), ("state", "<i4"),
+                ("ht", "<f4"), ("lead", "<f4")]
+REC_SKIPPED, REC_FAILS, REC_PASSES = 1, 2, 3
 
 
 class HepkError(RuntimeError):
@@ -115,6 +121,8 @@ def load(path: str = LIB_PATH):
     lib.hepk_plan_hist_offset.argtypes = [vp, i32, i32, i32, i32, C.POINTER(i64), C.POINTER(i32)]
     lib.hepk_plan_get_tune.argtypes = [vp, C.POINTER(Tune)]
     lib.hepk_pipeline.argtypes = [vp, vp, vp, vp]
+    lib.hepk_plan_debug_layout.argtypes = [vp, i32, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    lib.hepk_pipeline_debug.argtypes = [vp, vp, vp, vp, vp]
     lib.hepk_plan_destroy.argtypes = [vp]
     lib.hepk_last_error.restype = C.c_char_p
     lib.hepk_last_error.argtypes = []
@@ -362,6 +370,31 @@ class Plan:
 
     def run_range(self, d0: int, nd: int, sumw, counts, stream=None):
         _call("hepk_pipeline_range", self.handle, d0, nd, _ptr(sumw), _ptr(counts), _stream(stream))
+
+    def run_debug(self, sumw, counts, stream=None):
+        """hepk_pipeline_debug: the pass plus every event's record; returns
+        rec[d][q][v] = numpy structured array (EVENT_RECORD) of the dataset's
+        events (None for idle slots).  Records never written keep state -1."""
+        import numpy as np
+        import torch
+        n = C.c_int64()
+        _call("hepk_plan_debug_layout", self.handle, 0, 0, None, None, C.byref(n))
+        raw = torch.full((max(1, n.value) * 6,), -1, dtype=torch.int32, device="cuda")
+        _call("hepk_pipeline_debug", self.handle, _ptr(sumw), _ptr(counts), _ptr(raw), _stream(stream))
+        host_rec = raw.cpu().numpy().view(np.dtype(EVENT_RECORD))
+        out = []
+        for d, ds in enumerate(self.datasets):
+            per_d = []
+            for qi, q in enumerate(self.queries):
+                if q is None:
+                    per_d.append(None)
+                    continue
+                base, stride = C.c_int64(), C.c_int64()
+                _call("hepk_plan_debug_layout", self.handle, d, qi, C.byref(base), C.byref(stride), None)
+                per_d.append([host_rec[base.value + v * stride.value:base.value + v * stride.value + ds.n_events]
+                              for v in range(q.n_scale)])
+            out.append(per_d)
+        return out
 
     def run_graph(self, sumw, counts, stream=None):
         _call("hepk_pipeline_graph", self.handle, _ptr(sumw), _ptr(counts), _stream(stream))

@@ -158,6 +158,23 @@ def test_reduce_matches_oracle(case):
         assert np.array_equal(bits(host(H.reduce(H.SUM, doff, dev(x), obj_mask=dom))), bits(sw))
 
 
+@pytest.mark.parametrize("n", [1, 255, 256, 257, 512, 769, 100000])
+def test_reduce_offsets_tile_edges(n):
+    """COUNT with offsets_out at event counts around the 256-event tiles of
+    the scan (the tile totals are staged inside offsets_out itself): every
+    entry written, equal to the oracle's exclusive scan."""
+    import torch
+    say(f"reduce offsets n={n}")
+    off, x, rng = _jagged(20 + n, n)
+    om = (rng.uniform(size=len(x)) < 0.6).astype(np.uint8)
+    cw, ow = ref.reduce(ref.COUNT, off, obj_mask=om, want_offsets=True)
+    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+    offo = torch.full((n + 1,), -7, dtype=torch.int64, device="cuda")
+    H._call("hepk_reduce", H.COUNT, H._ptr(dev(off)), n, None, H.F32, H._ptr(dev(om)), None, H._ptr(cnt), None,
+            H._ptr(offo), H._stream())
+    assert np.array_equal(host(cnt), cw) and np.array_equal(host(offo), ow)
+
+
 def test_reduce_sum_order_case():
     say("reduce sum order")
     off = np.array([0, 3, 6, 6], np.int64)
@@ -204,7 +221,15 @@ def _tied_b(rng, n):
     return offa, ea, pa, offb, eb, pb, mb
 
 
-@pytest.mark.parametrize("case", ["config0", "f16", "large_events", "ties"])
+def _nonfinite(rng, *cols):
+    """NaN and +-inf written into about 1% of each column's entries."""
+    bad = np.array([np.nan, np.inf, -np.inf], np.float32)
+    for c in cols:
+        idx = rng.integers(0, c.size, max(1, c.size // 100))
+        c[idx] = bad[rng.integers(0, 3, idx.size)].astype(c.dtype)
+
+
+@pytest.mark.parametrize("case", ["config0", "f16", "large_events", "ties", "nonfinite", "nonfinite_f16"])
 def test_match_dr_matches_oracle(case):
     if case == "ties":
         offa, ea, pa, offb, eb, pb, mb = _tied_b(np.random.default_rng(8), 3000)
@@ -226,13 +251,20 @@ def test_match_dr_matches_oracle(case):
         ma = (rng.uniform(size=offa[-1]) < 0.9).astype(np.uint8)
     else:
         ds = datagen.make_dataset(0, 100000 if case == "config0" else 30000,
-                                  content_dtype="f16" if case == "f16" else "f32")
+                                  content_dtype="f16" if case.endswith("f16") else "f32")
         j, m = ds.jets, ds.muons
         offa, ea, pa = j.offsets, j.cols["eta"], j.cols["phi"]
         offb, eb, pb = m.offsets, m.cols["eta"], m.cols["phi"]
         mb = ((m.cols["pt"] > 20) & (np.abs(m.cols["eta"].astype(np.float32)) < np.float32(2.4))
               & (m.cols["iso"] < np.float32(0.15))).astype(np.uint8)
         ma = None
+        if case.startswith("nonfinite"):
+            # reading c9: a NaN dR^2 never becomes the minimum, an infinite
+            # one never beats the empty +inf (index stays -1), both clean
+            rng = np.random.default_rng(11)
+            _nonfinite(rng, ea, pa, eb, pb)
+            mb[rng.integers(0, mb.size, mb.size // 4)] = 1  # some non-finite b are selected
+            ma = (rng.uniform(size=ea.size) < 0.9).astype(np.uint8)
     say(f"match_dr {case} n={len(offa) - 1}")
     for dr in (0.4, 0.0, 1.2):
         wmd, wix, wcl = ref.match_dr(offa, ea, pa, offb, eb, pb, dr, mask_a=ma, mask_b=mb)
@@ -716,7 +748,8 @@ def test_autotune_picks_a_valid_configuration():
     q = datagen.Query()
     dds = [H.DeviceDataset(d) for d in dss]
     best, ms = H.autotune(dds, [q], reps=3)
-    assert best["block"] in (256, 512) and best["ev_per_thread"] in (1, 2) and best["hist_mode"] in (0, 1)
+    assert best["block"] in (256, 512, 1024) and best["ev_per_thread"] in (1, 2) and best["hist_mode"] in (0, 1)
+    assert best["block"] < 1024 or best["ev_per_thread"] == 1
     assert ms > 0
     plan = H.Plan(dds, [q], best)
     s, c = plan.new_hists()
