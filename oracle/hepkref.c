@@ -127,7 +127,7 @@ int hepkref_reduce(int32_t op, const int64_t *offsets, int64_t n_events,
                    void *out, int32_t *out_arg, int64_t *offsets_out)
 {
     if (n_events < 0 || !offsets || (n_events > 0 && !out)) return HEPKREF_EINVAL;
-    if (op < HEPKREF_COUNT || op > HEPKREF_ARGMIN) return HEPKREF_EINVAL;
+    if (op < HEPKREF_COUNT || op > HEPKREF_PROD) return HEPKREF_EINVAL;
     if (op != HEPKREF_COUNT) {
         if (!valid_float_dtype(dtype)) return HEPKREF_EUNSUPPORTED;
         if (!content && n_events > 0 && offsets[n_events] > 0) return HEPKREF_EINVAL;
@@ -151,6 +151,14 @@ int hepkref_reduce(int32_t op, const int64_t *offsets, int64_t n_events,
                 for (int64_t i = i0; i < i1; i++)
                     if (!obj_mask || obj_mask[i]) acc = acc + load_f(content, dtype, i);
             ((float *)out)[e] = acc;
+        } else if (op == HEPKREF_PROD) {
+            /* the pairwise operator of the generic reduction taken as the
+             * float32 product, left to right from 1 */
+            float prod = 1.0f;
+            if (take_event)
+                for (int64_t i = i0; i < i1; i++)
+                    if (!obj_mask || obj_mask[i]) prod = prod * load_f(content, dtype, i);
+            ((float *)out)[e] = prod;
         } else {
             int want_max = (op == HEPKREF_MAX || op == HEPKREF_ARGMAX);
             float best = want_max ? -INFINITY : INFINITY;
@@ -228,6 +236,14 @@ int hepkref_hist_fill(const void *x, int32_t dtype, const float *w,
                       const float *edges, int32_t nbins,
                       double *sumw, uint64_t *counts)
 {
+    return hepkref_hist_fill_w2(x, dtype, w, evt_mask, n, edges, nbins, sumw, NULL, counts);
+}
+
+int hepkref_hist_fill_w2(const void *x, int32_t dtype, const float *w,
+                         const uint8_t *evt_mask, int64_t n,
+                         const float *edges, int32_t nbins,
+                         double *sumw, double *sumw2, uint64_t *counts)
+{
     if (n < 0 || nbins < 1 || !edges || !sumw || !counts || (n > 0 && !x))
         return HEPKREF_EINVAL;
     if (dtype != HEPKREF_F32 && dtype != HEPKREF_F16 && dtype != HEPKREF_I32)
@@ -250,6 +266,93 @@ int hepkref_hist_fill(const void *x, int32_t dtype, const float *w,
         }
         counts[b] += 1u;
         sumw[b] += (double)(w ? w[i] : 1.0f);
+        if (sumw2) {
+            double wi = (double)(w ? w[i] : 1.0f);
+            sumw2[b] += wi * wi;
+        }
+    }
+    return HEPKREF_OK;
+}
+
+/* ---- lookup histograms (Sec. III: the kernel that returns, for each element
+ * of a data array, the content of the lookup-histogram bin holding it, used
+ * for histogram-based reweighting; Sec. IV: event weights and jet energy
+ * corrections from histogram lookups, systematic corrections by linear
+ * interpolation) ---- */
+
+static float load_any(const void *x, int32_t dtype, int64_t i)
+{
+    if (dtype == HEPKREF_I32) return (float)((const int32_t *)x)[i];
+    return load_f(x, dtype, i);
+}
+
+/* The slot of v (not NaN) in edges[0..nbins]: the number of edges at or below v
+ * (0 below the first edge, nbins+1 at or above the last). */
+static int32_t edges_at_or_below(float v, const float *edges, int32_t nbins)
+{
+    int32_t s = 0;
+    for (int32_t k = 0; k <= nbins; k++)
+        if (edges[k] <= v) s++;
+    return s;
+}
+
+int hepkref_get_bin_contents(const void *x, int32_t dtype, int64_t n,
+                             const float *edges, int32_t nbins, const float *contents,
+                             float *out)
+{
+    if (n < 0 || nbins < 1 || !edges || !contents || (n > 0 && (!x || !out))) return HEPKREF_EINVAL;
+    if (dtype != HEPKREF_F32 && dtype != HEPKREF_F16 && dtype != HEPKREF_I32) return HEPKREF_EINVAL;
+    for (int64_t i = 0; i < n; i++) {
+        float v = load_any(x, dtype, i);
+        out[i] = (v != v) ? NAN : contents[edges_at_or_below(v, edges, nbins)];
+    }
+    return HEPKREF_OK;
+}
+
+/* centre of bin i (1..nbins), float32 */
+static float bin_centre(const float *edges, int32_t i)
+{
+    return (edges[i - 1] + edges[i]) * 0.5f;
+}
+
+/* interpolation of one value in bins 1..nbins of c (c[i] is bin i's value) */
+static float interp_one(float v, const float *edges, int32_t nbins, const float *c)
+{
+    if (v != v) return NAN;
+    if (v <= bin_centre(edges, 1)) return c[1];
+    if (v >= bin_centre(edges, nbins)) return c[nbins];
+    int32_t i = 1;
+    while (!(v < bin_centre(edges, i + 1))) i++;
+    float m_i = bin_centre(edges, i);
+    float slope = (c[i + 1] - c[i]) / (bin_centre(edges, i + 1) - m_i);
+    return c[i] + (v - m_i) * slope;
+}
+
+int hepkref_interp(const void *x, int32_t dtype, int64_t n,
+                   const float *edges, int32_t nbins, const float *contents, float *out)
+{
+    if (n < 0 || nbins < 1 || !edges || !contents || (n > 0 && (!x || !out))) return HEPKREF_EINVAL;
+    if (dtype != HEPKREF_F32 && dtype != HEPKREF_F16 && dtype != HEPKREF_I32) return HEPKREF_EINVAL;
+    for (int64_t i = 0; i < n; i++) out[i] = interp_one(load_any(x, dtype, i), edges, nbins, contents);
+    return HEPKREF_OK;
+}
+
+int hepkref_jes_delta(const void *pt, const void *eta, int32_t dtype, int64_t n,
+                      const float *eta_edges, int32_t n_eta,
+                      const float *pt_edges, int32_t n_pt, const float *delta, float *out)
+{
+    if (n < 0 || n_eta < 1 || n_pt < 1 || !eta_edges || !pt_edges || !delta ||
+        (n > 0 && (!pt || !eta || !out)))
+        return HEPKREF_EINVAL;
+    if (!valid_float_dtype(dtype)) return HEPKREF_EINVAL;
+    for (int64_t i = 0; i < n; i++) {
+        float ae = fabsf(load_f(eta, dtype, i));
+        int32_t row = (ae != ae) ? 1 : edges_at_or_below(ae, eta_edges, n_eta);
+        if (row < 1) row = 1;
+        if (row > n_eta) row = n_eta;
+        /* the row's values as bins 1..n_pt of interp_one */
+        const float *c = delta + (int64_t)(row - 1) * n_pt - 1;
+        out[i] = interp_one(load_f(pt, dtype, i), pt_edges, n_pt, c);
     }
     return HEPKREF_OK;
 }
@@ -286,7 +389,7 @@ static hepkref_cut mkicut(const void *col, int32_t op, int32_t ithr)
 }
 
 int hepkref_pipeline(const hepkref_dataset *ds, const hepkref_query *qs, int32_t n_query,
-                     double *const *sumw, uint64_t *const *counts)
+                     double *const *sumw, double *const *sumw2, uint64_t *const *counts)
 {
     if (!ds || !qs || n_query < 0 || !sumw || !counts) return HEPKREF_EINVAL;
     if (!valid_float_dtype(ds->dtype) || ds->n_events < 0) return HEPKREF_EINVAL;
@@ -301,6 +404,9 @@ int hepkref_pipeline(const hepkref_dataset *ds, const hepkref_query *qs, int32_t
     uint8_t *clean = xmalloc((size_t)Mj), *clean_e = xmalloc((size_t)Mj);
     uint8_t *jsel = xmalloc((size_t)Mj), *bsel = xmalloc((size_t)Mj);
     float *ptv = xmalloc(sizeof(float) * (size_t)Mj);
+    float *delta = xmalloc(sizeof(float) * (size_t)Mj);
+    float *mu_sf = xmalloc(sizeof(float) * (size_t)Mm);
+    float *wev = xmalloc(sizeof(float) * (size_t)N), *evf = xmalloc(sizeof(float) * (size_t)N);
     int32_t *n_mu = xmalloc(sizeof(int32_t) * (size_t)N);
     int32_t *n_jet = xmalloc(sizeof(int32_t) * (size_t)N);
     int32_t *n_b = xmalloc(sizeof(int32_t) * (size_t)N);
@@ -335,10 +441,32 @@ int hepkref_pipeline(const hepkref_dataset *ds, const hepkref_query *qs, int32_t
             memcpy(clean, clean_e, (size_t)Mj);
         }
 
+        /* event weights: w, times the pileup lookup, times the product of
+         * the selected muons' scale factors (Sec. IV: event weights from
+         * histogram lookups), each product rounded to float32 */
+        for (int64_t e = 0; e < N; e++) wev[e] = ds->weights[e];
+        if (q->pu_edges && ds->npu) {
+            hepkref_get_bin_contents(ds->npu, HEPKREF_F32, N, q->pu_edges, q->pu_nbins, q->pu_contents, evf);
+            for (int64_t e = 0; e < N; e++) wev[e] = wev[e] * evf[e];
+        }
+        if (q->sf_edges) {
+            hepkref_get_bin_contents(ds->muons.pt, dt, Mm, q->sf_edges, q->sf_nbins, q->sf_contents, mu_sf);
+            hepkref_reduce(HEPKREF_PROD, ds->muons.off, N, mu_sf, HEPKREF_F32, msel, NULL, evf, NULL, NULL);
+            for (int64_t e = 0; e < N; e++) wev[e] = wev[e] * evf[e];
+        }
+        /* jet energy scale from a lookup: the shift per jet, once per query */
+        if (q->jes_mode == 1)
+            hepkref_jes_delta(ds->jets.pt, ds->jets.eta, dt, Mj, q->jes_eta_edges, q->jes_n_eta,
+                              q->jes_pt_edges, q->jes_n_pt, q->jes_delta, delta);
+
         for (int32_t v = 0; v < q->n_scale; v++) {
-            /* jet energy scale applied to pt (one float32 product) */
+            /* jet energy scale applied to pt (one float32 product; with a
+             * lookup, the factor 1 + s * delta rounded first) */
             const float s = q->scales[v];
-            for (int64_t j = 0; j < Mj; j++) ptv[j] = load_f(ds->jets.pt, dt, j) * s;
+            if (q->jes_mode == 1)
+                for (int64_t j = 0; j < Mj; j++) ptv[j] = load_f(ds->jets.pt, dt, j) * (1.0f + s * delta[j]);
+            else
+                for (int64_t j = 0; j < Mj; j++) ptv[j] = load_f(ds->jets.pt, dt, j) * s;
             hepkref_cut jc[2];
             jc[0] = mkcut(ptv, HEPKREF_F32, HEPKREF_GT, q->jet_pt);
             jc[1] = mkcut(ds->jets.eta, dt, HEPKREF_ABS_LT, q->jet_abseta);
@@ -360,18 +488,19 @@ int hepkref_pipeline(const hepkref_dataset *ds, const hepkref_query *qs, int32_t
             }
             hepkref_select(ev, nev, N, NULL, pass);
 
-            hepkref_hist_fill(ht, HEPKREF_F32, ds->weights, pass, N, q->edges[0], q->nbins[0],
-                              sumw[k], counts[k]);
+            hepkref_hist_fill_w2(ht, HEPKREF_F32, wev, pass, N, q->edges[0], q->nbins[0],
+                                 sumw[k], sumw2 ? sumw2[k] : NULL, counts[k]);
             k++;
-            hepkref_hist_fill(lead, HEPKREF_F32, ds->weights, pass, N, q->edges[1], q->nbins[1],
-                              sumw[k], counts[k]);
+            hepkref_hist_fill_w2(lead, HEPKREF_F32, wev, pass, N, q->edges[1], q->nbins[1],
+                                 sumw[k], sumw2 ? sumw2[k] : NULL, counts[k]);
             k++;
-            hepkref_hist_fill(n_jet, HEPKREF_I32, ds->weights, pass, N, q->edges[2], q->nbins[2],
-                              sumw[k], counts[k]);
+            hepkref_hist_fill_w2(n_jet, HEPKREF_I32, wev, pass, N, q->edges[2], q->nbins[2],
+                                 sumw[k], sumw2 ? sumw2[k] : NULL, counts[k]);
             k++;
         }
     }
     free(msel); free(esel); free(clean); free(clean_e); free(jsel); free(bsel); free(ptv);
+    free(delta); free(mu_sf); free(wev); free(evf);
     free(n_mu); free(n_jet); free(n_b); free(ht); free(lead); free(pass);
     return HEPKREF_OK;
 }

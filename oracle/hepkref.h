@@ -49,7 +49,8 @@ typedef struct {
 } hepkref_cut;
 
 /* per-event reductions over the objects of each event (Sec. III) */
-enum { HEPKREF_COUNT = 0, HEPKREF_SUM, HEPKREF_MAX, HEPKREF_MIN, HEPKREF_ARGMAX, HEPKREF_ARGMIN };
+enum { HEPKREF_COUNT = 0, HEPKREF_SUM, HEPKREF_MAX, HEPKREF_MIN, HEPKREF_ARGMAX, HEPKREF_ARGMIN,
+       HEPKREF_PROD };
 
 /* exact float16 -> float32 widening (IEEE 754 binary16) */
 float hepkref_half_to_float(uint16_t h);
@@ -60,7 +61,8 @@ int hepkref_select(const hepkref_cut *cuts, int32_t n_cuts, int64_t n,
 
 /* Per-event reduction.  COUNT -> int32 out (number of masked-in objects) and
  * optional offsets_out (int64, N+1, exclusive prefix sum of the counts);
- * SUM -> float32 left-to-right sum starting at 0; MAX/MIN -> float32 value
+ * SUM -> float32 left-to-right sum starting at 0; PROD -> float32
+ * left-to-right product starting at 1; MAX/MIN -> float32 value
  * (-inf/+inf when empty) and optional int32 out_arg (local index of the first
  * extremum, -1 when empty); ARGMAX/ARGMIN -> int32 local index into out.
  * Events with evt_mask == 0 get the empty result. */
@@ -89,6 +91,42 @@ int hepkref_hist_fill(const void *x, int32_t dtype, const float *w,
                       const float *edges, int32_t nbins,
                       double *sumw, uint64_t *counts);
 
+/* The same fill that also accumulates the sum of squared weights,
+ * sumw2[b] += (double)w * (double)w (sumw2 may be NULL). */
+int hepkref_hist_fill_w2(const void *x, int32_t dtype, const float *w,
+                         const uint8_t *evt_mask, int64_t n,
+                         const float *edges, int32_t nbins,
+                         double *sumw, double *sumw2, uint64_t *counts);
+
+/* ---- lookup histograms ----------------------------------------------------
+ * A lookup histogram is bin edges e_0 < ... < e_nbins plus a float32 content
+ * per slot, laid out like a filled histogram: contents[0] for x < e_0,
+ * contents[i] for e_{i-1} <= x < e_i, contents[nbins+1] for x >= e_nbins. */
+
+/* out[i] = the content of the slot holding x[i] (NaN x -> NaN). */
+int hepkref_get_bin_contents(const void *x, int32_t dtype, int64_t n,
+                             const float *edges, int32_t nbins, const float *contents,
+                             float *out);
+
+/* Linear interpolation between bin centres: with m_i = (e_{i-1} + e_i) * 0.5
+ * (float32) the centre of bin i and c_i = contents[i] (i = 1..nbins):
+ * out = c_1 for x <= m_1, c_nbins for x >= m_nbins, else for
+ * m_i <= x < m_{i+1}: c_i + (x - m_i) * s_i with the slope
+ * s_i = (c_{i+1} - c_i) / (m_{i+1} - m_i), every operation rounded to
+ * float32.  NaN x -> NaN. */
+int hepkref_interp(const void *x, int32_t dtype, int64_t n,
+                   const float *edges, int32_t nbins, const float *contents, float *out);
+
+/* Jet-energy-scale shift from a two-dimensional table: the row of |eta|
+ * among n_eta bins (eta_edges, n_eta+1 entries; |eta| below the first edge,
+ * beyond the last or NaN take the nearest row: first for NaN), then the
+ * linear interpolation of hepkref_interp in pt over that row's n_pt values
+ * (pt_edges, n_pt+1 entries).  delta is n_eta * n_pt float32, row-major (bin
+ * values only, no under/overflow entries). */
+int hepkref_jes_delta(const void *pt, const void *eta, int32_t dtype, int64_t n,
+                      const float *eta_edges, int32_t n_eta,
+                      const float *pt_edges, int32_t n_pt, const float *delta, float *out);
+
 /* ---- the end-to-end analysis pass --------------------------------------- */
 
 typedef struct {
@@ -102,6 +140,7 @@ typedef struct {
     int32_t dtype;           /* content dtype, F32 or F16 */
     hepkref_coll jets, muons, electrons;  /* electrons.off == NULL: absent */
     const float *weights;    /* float32[N] */
+    const float *npu;        /* float32[N] pileup per event; NULL: absent */
 } hepkref_dataset;
 
 typedef struct {
@@ -114,14 +153,26 @@ typedef struct {
     const float *scales;     /* n_scale jet-energy-scale factors */
     const float *edges[3];   /* HT, leading-jet pt, jet multiplicity */
     int32_t nbins[3];
+    /* event weight from lookups (NULL edges: that factor is absent):
+     * w * pileup(npu) * product over selected muons of sf(muon pt) */
+    const float *pu_edges, *pu_contents;
+    int32_t pu_nbins;
+    const float *sf_edges, *sf_contents;
+    int32_t sf_nbins;
+    /* jet energy scale: jes_mode 0: ptv = pt * s_v (scales are factors);
+     * 1: ptv = pt * (1 + s_v * delta(pt, |eta|)) (scales are shifts; delta
+     * from hepkref_jes_delta's table) */
+    int32_t jes_mode;
+    const float *jes_eta_edges, *jes_pt_edges, *jes_delta;
+    int32_t jes_n_eta, jes_n_pt;
 } hepkref_query;
 
 /* For each query q and scale v, fills histograms (HT, leading pt, nJet) of the
- * events passing the selection.  sumw[k], counts[k] point at the k-th
- * histogram (nbins+2 slots), k running over q, then v, then the three
- * observables.  Accumulates. */
+ * events passing the selection.  sumw[k], counts[k] (and sumw2[k] when
+ * sumw2 is not NULL) point at the k-th histogram (nbins+2 slots), k running
+ * over q, then v, then the three observables.  Accumulates. */
 int hepkref_pipeline(const hepkref_dataset *ds, const hepkref_query *q, int32_t n_query,
-                     double *const *sumw, uint64_t *const *counts);
+                     double *const *sumw, double *const *sumw2, uint64_t *const *counts);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,7 @@ CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
 
 F32, F16, I32 = 0, 1, 2
 GT, GE, LT, LE, ABS_LT, ABS_LE = range(6)
-COUNT, SUM, MAX, MIN, ARGMAX, ARGMIN = range(6)
+COUNT, SUM, MAX, MIN, ARGMAX, ARGMIN, PROD = range(7)
 
 
 def build(force: bool = False, extra_flags: Sequence[str] = ()) -> str:
@@ -51,7 +51,7 @@ class Coll(C.Structure):
 class DatasetS(C.Structure):
     _fields_ = [("n_events", C.c_int64), ("dtype", C.c_int32),
                 ("jets", Coll), ("muons", Coll), ("electrons", Coll),
-                ("weights", C.c_void_p)]
+                ("weights", C.c_void_p), ("npu", C.c_void_p)]
 
 
 class QueryS(C.Structure):
@@ -61,7 +61,11 @@ class QueryS(C.Structure):
                 ("dr", C.c_float), ("btag", C.c_float),
                 ("min_mu", C.c_int32), ("min_jet", C.c_int32), ("min_b", C.c_int32),
                 ("n_scale", C.c_int32), ("scales", C.c_void_p),
-                ("edges", C.c_void_p * 3), ("nbins", C.c_int32 * 3)]
+                ("edges", C.c_void_p * 3), ("nbins", C.c_int32 * 3),
+                ("pu_edges", C.c_void_p), ("pu_contents", C.c_void_p), ("pu_nbins", C.c_int32),
+                ("sf_edges", C.c_void_p), ("sf_contents", C.c_void_p), ("sf_nbins", C.c_int32),
+                ("jes_mode", C.c_int32), ("jes_eta_edges", C.c_void_p), ("jes_pt_edges", C.c_void_p),
+                ("jes_delta", C.c_void_p), ("jes_n_eta", C.c_int32), ("jes_n_pt", C.c_int32)]
 
 
 _lib = None
@@ -80,8 +84,16 @@ def lib():
             C.c_int32, C.c_int64, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p]
         _lib.hepkref_hist_fill.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
                                            C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+        _lib.hepkref_hist_fill_w2.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
+                                              C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib.hepkref_get_bin_contents.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int32,
+                                                  C.c_void_p, C.c_void_p]
+        _lib.hepkref_interp.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int32,
+                                        C.c_void_p, C.c_void_p]
+        _lib.hepkref_jes_delta.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int32,
+                                           C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
         _lib.hepkref_pipeline.argtypes = [C.POINTER(DatasetS), C.POINTER(QueryS), C.c_int32,
-                                          C.c_void_p, C.c_void_p]
+                                          C.c_void_p, C.c_void_p, C.c_void_p]
     return _lib
 
 
@@ -122,6 +134,8 @@ def select(cuts, n: int, mask_in=None) -> np.ndarray:
 def reduce(op: int, offsets: np.ndarray, content=None, obj_mask=None, evt_mask=None,
            want_arg: bool = False, want_offsets: bool = False):
     n = len(offsets) - 1
+    if content is not None:
+        content = np.ascontiguousarray(content)
     if op in (COUNT, ARGMAX, ARGMIN):
         out = np.empty(n, np.int32)
     else:
@@ -166,6 +180,51 @@ def hist_fill(x, edges, w=None, evt_mask=None, sumw=None, counts=None):
     return sumw, counts
 
 
+def hist_fill_w2(x, edges, w=None, evt_mask=None):
+    """(sumw, sumw2, counts) of a fresh histogram."""
+    nb = len(edges) - 1
+    sumw, sumw2 = np.zeros(nb + 2, np.float64), np.zeros(nb + 2, np.float64)
+    counts = np.zeros(nb + 2, np.uint64)
+    edges = np.ascontiguousarray(edges, np.float32)
+    _check(lib().hepkref_hist_fill_w2(x.ctypes.data, _dt(x), _p(w), _p(evt_mask), len(x), edges.ctypes.data,
+                                      nb, sumw.ctypes.data, sumw2.ctypes.data, counts.ctypes.data))
+    return sumw, sumw2, counts
+
+
+def get_bin_contents(x, edges, contents) -> np.ndarray:
+    """Lookup-histogram content of each element (contents: nbins+2 slots)."""
+    x = np.ascontiguousarray(x)
+    edges = np.ascontiguousarray(edges, np.float32)
+    contents = np.ascontiguousarray(contents, np.float32)
+    out = np.empty(len(x), np.float32)
+    _check(lib().hepkref_get_bin_contents(x.ctypes.data, _dt(x), len(x), edges.ctypes.data, len(edges) - 1,
+                                          contents.ctypes.data, out.ctypes.data))
+    return out
+
+
+def interp(x, edges, contents) -> np.ndarray:
+    """Linear interpolation between bin centres (contents: nbins+2 slots)."""
+    x = np.ascontiguousarray(x)
+    edges = np.ascontiguousarray(edges, np.float32)
+    contents = np.ascontiguousarray(contents, np.float32)
+    out = np.empty(len(x), np.float32)
+    _check(lib().hepkref_interp(x.ctypes.data, _dt(x), len(x), edges.ctypes.data, len(edges) - 1,
+                                contents.ctypes.data, out.ctypes.data))
+    return out
+
+
+def jes_delta(pt, eta, eta_edges, pt_edges, delta) -> np.ndarray:
+    """Per-object shift from a (|eta| row, interpolated pt) table."""
+    pt, eta = np.ascontiguousarray(pt), np.ascontiguousarray(eta)
+    ee = np.ascontiguousarray(eta_edges, np.float32)
+    pe = np.ascontiguousarray(pt_edges, np.float32)
+    d = np.ascontiguousarray(delta, np.float32)
+    out = np.empty(len(pt), np.float32)
+    _check(lib().hepkref_jes_delta(pt.ctypes.data, eta.ctypes.data, _dt(pt), len(pt), ee.ctypes.data,
+                                   len(ee) - 1, pe.ctypes.data, len(pe) - 1, d.ctypes.data, out.ctypes.data))
+    return out
+
+
 def _coll(c, names):
     if c is None:
         return Coll(None, None, None, None, None), []
@@ -178,46 +237,72 @@ def _coll(c, names):
                 c.cols["phi"].ctypes.data, extra), keep
 
 
-def pipeline(ds, queries) -> List[List[tuple]]:
+def query_struct(q, keep: list) -> QueryS:
+    """A datagen.Query as the oracle's struct; arrays it points to go into keep."""
+    def arr(a):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, np.float32)
+        keep.append(a)
+        return a.ctypes.data
+    sc = np.ascontiguousarray(q.scales, np.float32)
+    eds = [np.ascontiguousarray(e, np.float32) for e in q.edges()]
+    keep += [sc] + eds
+    qs = QueryS(q.mu_pt, q.mu_abseta, q.mu_iso, q.el_pt, q.el_abseta, q.jet_pt,
+                q.jet_abseta, q.dr, q.btag, q.min_mu, q.min_jet, q.min_b,
+                len(sc), sc.ctypes.data)
+    for h in range(3):
+        qs.edges[h] = eds[h].ctypes.data
+        qs.nbins[h] = len(eds[h]) - 1
+    if q.pu is not None:
+        qs.pu_edges, qs.pu_contents, qs.pu_nbins = arr(q.pu[0]), arr(q.pu[1]), len(q.pu[0]) - 1
+    if q.sf is not None:
+        qs.sf_edges, qs.sf_contents, qs.sf_nbins = arr(q.sf[0]), arr(q.sf[1]), len(q.sf[0]) - 1
+    if q.jes is not None:
+        ee, pe, d = q.jes
+        qs.jes_mode = 1
+        qs.jes_eta_edges, qs.jes_pt_edges, qs.jes_delta = arr(ee), arr(pe), arr(d)
+        qs.jes_n_eta, qs.jes_n_pt = len(ee) - 1, len(pe) - 1
+    return qs
+
+
+def pipeline(ds, queries, want_sumw2: bool = False) -> List[List[tuple]]:
     """Run the analysis pass on a datagen.Dataset for a list of datagen.Query.
 
-    Returns hists[q][v] = [(sumw, counts)] * 3 for (HT, leading pt, nJet).
+    Returns hists[q][v] = [(sumw, counts)] * 3 for (HT, leading pt, nJet),
+    or [(sumw, counts, sumw2)] * 3 with want_sumw2.
     """
     keep = []
     jets, k1 = _coll(ds.jets, ("pt", "eta", "phi", "btag"))
     mus, k2 = _coll(ds.muons, ("pt", "eta", "phi", "iso"))
     els, k3 = _coll(ds.electrons, ("pt", "eta", "phi"))
     keep += k1 + k2 + k3
+    npu = getattr(ds, "npu", None)
     dss = DatasetS(ds.n_events, F16 if ds.content_dtype == "f16" else F32,
-                   jets, mus, els, ds.weight.ctypes.data)
+                   jets, mus, els, ds.weight.ctypes.data, _p(npu))
     qarr = (QueryS * max(1, len(queries)))()
-    out, ptr_s, ptr_c = [], [], []
+    out, ptr_s, ptr_c, ptr_w2 = [], [], [], []
     for i, q in enumerate(queries):
-        sc = np.ascontiguousarray(q.scales, np.float32)
-        eds = [np.ascontiguousarray(e, np.float32) for e in q.edges()]
-        keep += [sc] + eds
-        qs = QueryS(q.mu_pt, q.mu_abseta, q.mu_iso, q.el_pt, q.el_abseta, q.jet_pt,
-                    q.jet_abseta, q.dr, q.btag, q.min_mu, q.min_jet, q.min_b,
-                    len(sc), sc.ctypes.data)
-        for h in range(3):
-            qs.edges[h] = eds[h].ctypes.data
-            qs.nbins[h] = len(eds[h]) - 1
-        qarr[i] = qs
+        qarr[i] = query_struct(q, keep)
         per_q = []
-        for v in range(len(sc)):
+        for v in range(q.n_scale):
             per_v = []
             for h in range(3):
-                s = np.zeros(len(eds[h]) + 1, np.float64)
-                c = np.zeros(len(eds[h]) + 1, np.uint64)
+                nb = len(q.edges()[h]) - 1
+                s = np.zeros(nb + 2, np.float64)
+                c = np.zeros(nb + 2, np.uint64)
+                w2 = np.zeros(nb + 2, np.float64)
                 ptr_s.append(s.ctypes.data)
                 ptr_c.append(c.ctypes.data)
-                per_v.append((s, c))
+                ptr_w2.append(w2.ctypes.data)
+                per_v.append((s, c, w2) if want_sumw2 else (s, c))
             per_q.append(per_v)
         out.append(per_q)
     ps = (C.c_void_p * max(1, len(ptr_s)))(*ptr_s)
     pc = (C.c_void_p * max(1, len(ptr_c)))(*ptr_c)
-    _check(lib().hepkref_pipeline(C.byref(dss), qarr, len(queries),
-                                  C.cast(ps, C.c_void_p), C.cast(pc, C.c_void_p)))
+    pw = (C.c_void_p * max(1, len(ptr_w2)))(*ptr_w2)
+    _check(lib().hepkref_pipeline(C.byref(dss), qarr, len(queries), C.cast(ps, C.c_void_p),
+                                  C.cast(pw, C.c_void_p) if want_sumw2 else None, C.cast(pc, C.c_void_p)))
     del keep
     return out
 
@@ -231,7 +316,7 @@ def pipeline_events(ds, q) -> List[dict]:
 
     Returns, per jet-energy scale v of the query, a dict of numpy arrays over
     the events: n_mu, n_jet, n_b (int32), ht, lead (float32; lead = -inf when
-    no jet is selected) and passed (uint8).
+    no jet is selected), passed (uint8) and the event weight (float32).
     """
     j, m, el = ds.jets, ds.muons, ds.electrons
     n = ds.n_events
@@ -249,9 +334,18 @@ def pipeline_events(ds, q) -> List[dict]:
     # float16 content widens exactly; the scaled pt is one float32 product
     pt = np.ascontiguousarray(j.cols["pt"]).astype(np.float32)
     has_bt = "btag" in j.cols
+    # event weight: w, times the pileup lookup, times the product of the
+    # selected muons' scale factors (each product rounded to float32)
+    wev = np.ascontiguousarray(ds.weight, np.float32).copy()
+    if q.pu is not None and getattr(ds, "npu", None) is not None:
+        wev = wev * get_bin_contents(ds.npu, *q.pu)
+    if q.sf is not None:
+        sf = get_bin_contents(m.cols["pt"], *q.sf)
+        wev = wev * reduce(PROD, m.offsets, sf, obj_mask=msel)
+    delta = jes_delta(j.cols["pt"], j.cols["eta"], *q.jes) if q.jes is not None else None
     out = []
     for s in np.asarray(q.scales, np.float32):
-        ptv = pt * np.float32(s)
+        ptv = pt * (np.float32(1.0) + s * delta) if delta is not None else pt * np.float32(s)
         jsel = select([(ptv, GT, q.jet_pt), (j.cols["eta"], ABS_LT, q.jet_abseta)], j.n_objects,
                       mask_in=clean)
         n_jet = reduce(COUNT, j.offsets, obj_mask=jsel)
@@ -265,5 +359,5 @@ def pipeline_events(ds, q) -> List[dict]:
         else:
             n_b = np.zeros(n, np.int32)
         out.append({"n_mu": n_mu, "n_jet": n_jet, "n_b": n_b, "ht": ht, "lead": lead,
-                    "passed": select(evc, n)})
+                    "passed": select(evc, n), "weight": wev})
     return out

@@ -55,6 +55,7 @@ class Dataset:
     electrons: Optional[Collection] = None
     content_dtype: str = "f32"             # "f32" or "f16"
     seed: int = 0
+    npu: Optional[np.ndarray] = None       # float32[N] pileup per event (with_pileup)
 
     def collections(self):
         out = [("jets", self.jets), ("muons", self.muons)]
@@ -71,6 +72,10 @@ class Dataset:
         if self.electrons is not None:
             b += 8 * (self.n_events + 1) + esz * self.electrons.n_objects * 3
         return b
+
+    def nbytes_read_lookup(self) -> int:
+        """Bytes read by a pass that also takes the pileup column."""
+        return self.nbytes_read() + (4 * self.n_events if self.npu is not None else 0)
 
     def nbytes_stored(self) -> int:
         b = self.weight.nbytes
@@ -221,6 +226,57 @@ def jes_scales(n_steps: int = 10, step: float = 0.01) -> np.ndarray:
     return np.array(up + dn, dtype=np.float64).astype(np.float32)
 
 
+def with_pileup(ds: Dataset, seed: int, mean: float = 20.0) -> Dataset:
+    """A copy of ds with a pileup column: the number of simultaneous
+    interactions per event, Poisson(mean), stored as float32 (drawn from its
+    own stream, default_rng([seed, 0x50550])) -- the per-event variable of
+    pileup reweighting."""
+    rng = np.random.default_rng([seed, 0x50550])
+    npu = rng.poisson(mean, ds.n_events).astype(np.float32)
+    return Dataset(ds.n_events, ds.jets, ds.muons, ds.weight, ds.electrons, ds.content_dtype, ds.seed, npu)
+
+
+def pileup_table(data_mean: float = 22.0, sim_mean: float = 20.0, nbins: int = 80):
+    """Synthetic pileup-reweighting table (edges, contents): in unit bins of
+    the pileup count 0..nbins, the ratio of Poisson(data_mean) to
+    Poisson(sim_mean) probabilities; 1 in the under- and overflow slots."""
+    k = np.arange(nbins, dtype=np.float64)
+    lg = np.array([math.lgamma(x + 1.0) for x in k])
+    ratio = np.exp(k * math.log(data_mean) - data_mean - lg - (k * math.log(sim_mean) - sim_mean - lg))
+    contents = np.concatenate([[1.0], ratio, [1.0]]).astype(np.float32)
+    return uniform_edges(nbins, 0.0, float(nbins)), contents
+
+
+def muon_sf_table():
+    """Synthetic muon efficiency scale factors (edges, contents) in muon pt:
+    rising from 0.95 towards 0.99; under/overflow take the nearest bin's
+    value."""
+    edges = np.array([20, 25, 30, 40, 50, 60, 80, 120, 200, 500], np.float64)
+    centres = 0.5 * (edges[:-1] + edges[1:])
+    sf = 0.95 + 0.04 * (1.0 - np.exp(-(centres - 20.0) / 30.0))
+    contents = np.concatenate([[sf[0]], sf, [sf[-1]]]).astype(np.float32)
+    return edges.astype(np.float32), contents
+
+
+def jes_table():
+    """Synthetic in-situ jet-energy-scale uncertainty (eta_edges, pt_edges,
+    delta[n_eta, n_pt]): rows of |eta| bins, values at log-spaced pt bin
+    centres, larger at low pt and forward |eta|."""
+    eta_edges = np.array([0.0, 0.5, 1.0, 1.5, 2.0, 2.5, 3.0, 4.7], np.float64)
+    pt_edges = np.geomspace(20.0, 1000.0, 25)
+    cpt = np.sqrt(pt_edges[:-1] * pt_edges[1:])
+    rows = np.arange(len(eta_edges) - 1, dtype=np.float64)[:, None]
+    delta = 0.015 + 0.06 * np.exp(-cpt[None, :] / 60.0) + 0.004 * rows
+    return eta_edges.astype(np.float32), pt_edges.astype(np.float32), delta.astype(np.float32)
+
+
+def jes_lookup_shifts(n_steps: int = 10, step: float = 0.5) -> np.ndarray:
+    """Shifts k of the lookup jet-energy scale pt * (1 + k * delta): +k*step
+    then -k*step for k = 1..n_steps, float32."""
+    up = [k * step for k in range(1, n_steps + 1)]
+    return np.array(up + [-x for x in up], dtype=np.float64).astype(np.float32)
+
+
 @dataclass
 class Query:
     """Cuts, event requirements and binnings of one analysis pass.
@@ -248,6 +304,12 @@ class Query:
     edges_lead: np.ndarray = field(default_factory=lambda: uniform_edges(100, 0.0, 1000.0))
     edges_njet: np.ndarray = field(default_factory=lambda: uniform_edges(21, 0.0, 21.0))
     arrival: float = 0.0                   # seconds (serving stream only)
+    # lookup corrections (None: absent): event weight w * pu(npu) * product of
+    # sf(pt) over selected muons; jet energy scale pt * (1 + s * delta(pt, |eta|))
+    # with the scales read as shifts s (jes = (eta_edges, pt_edges, delta))
+    pu: Optional[tuple] = None             # (edges, contents[nbins+2])
+    sf: Optional[tuple] = None             # (edges, contents[nbins+2])
+    jes: Optional[tuple] = None
 
     def edges(self):
         return (self.edges_ht, self.edges_lead, self.edges_njet)
@@ -260,6 +322,13 @@ class Query:
 def extended_query() -> Query:
     """Extended schema: b-tag requirement and 20 jet-energy-scale variations."""
     return Query(min_b=1, scales=jes_scales())
+
+
+def lookup_query(min_b: int = 1) -> Query:
+    """Lookup corrections: pileup and muon scale-factor event weights and 20
+    jet-energy-scale variations from the interpolated uncertainty table."""
+    return Query(min_b=min_b, scales=jes_lookup_shifts(), pu=pileup_table(), sf=muon_sf_table(),
+                 jes=jes_table())
 
 
 def batch_sizes(seed: int = 0, n: int = 64, lo: float = 1e4, hi: float = 5e6) -> np.ndarray:

@@ -45,6 +45,18 @@ MUTANTS = [
     ("b-jet requirement ignored", "ev[nev++] = mkicut(n_b, HEPKREF_GE, q->min_b);", "(void)0;"),
     ("H_T over unselected jets", "hepkref_reduce(HEPKREF_SUM, ds->jets.off, N, ptv, HEPKREF_F32, jsel",
      "hepkref_reduce(HEPKREF_SUM, ds->jets.off, N, ptv, HEPKREF_F32, NULL"),
+    ("interpolation slope inverted", "/ (bin_centre(edges, i + 1) - m_i);", "/ (m_i - bin_centre(edges, i + 1));"),
+    ("interpolation clamps to the underflow slot", "if (v <= bin_centre(edges, 1)) return c[1];",
+     "if (v <= bin_centre(edges, 1)) return c[0];"),
+    ("lookup slot excludes its lower edge", "if (edges[k] <= v) s++;", "if (edges[k] < v) s++;"),
+    ("JES row from signed eta", "float ae = fabsf(load_f(eta, dtype, i));", "float ae = load_f(eta, dtype, i);"),
+    ("product starts at zero", "float prod = 1.0f;", "float prod = 0.0f;"),
+    ("sumw2 adds the weight", "sumw2[b] += wi * wi;", "sumw2[b] += wi;"),
+    ("pileup weight ignored", "for (int64_t e = 0; e < N; e++) wev[e] = wev[e] * evf[e];", "(void)0;"),
+    ("scale factors of unselected muons",
+     "hepkref_reduce(HEPKREF_PROD, ds->muons.off, N, mu_sf, HEPKREF_F32, msel,",
+     "hepkref_reduce(HEPKREF_PROD, ds->muons.off, N, mu_sf, HEPKREF_F32, NULL,"),
+    ("lookup JES shift dropped", "(1.0f + s * delta[j])", "(1.0f + delta[j])"),
     ("event mask ignored by count",
      "if (take_event)\n                for (int64_t i = i0; i < i1; i++)\n                    if (!obj_mask",
      "if (1)\n                for (int64_t i = i0; i < i1; i++)\n                    if (!obj_mask"),

@@ -450,3 +450,184 @@ def test_pipeline_extended_counts_match_numpy():
         want = np.bincount(nj[passed].astype(np.int64), minlength=21)[:21]
         assert np.array_equal(h[v][2][1][1:22], want.astype(np.uint64))
         assert h[v][0][0].sum() == ds.weight[passed].astype(np.float64).sum()
+
+
+# ---------------------------------------------------------------- lookups
+
+F32 = np.float32
+
+
+def test_get_bin_contents_matches_searchsorted():
+    rng = np.random.default_rng(21)
+    edges = np.sort(rng.uniform(-5, 5, 12)).astype(F32)
+    contents = rng.normal(1, 0.2, 13).astype(F32)
+    x = rng.uniform(-7, 7, 5000).astype(F32)
+    x[:12] = edges                              # exact edges: x == e_k is in slot k + 1
+    x[12:15] = [np.nan, np.inf, -np.inf]
+    got = ref.get_bin_contents(x, edges, contents)
+    assert np.array_equal(got[:12], contents[1:13])
+    assert np.isnan(got[12]) and got[13] == contents[-1] and got[14] == contents[0]
+    slot = np.searchsorted(edges, x[15:], side="right")
+    assert np.array_equal(got[15:], contents[slot])
+    xi = rng.integers(-8, 8, 200).astype(np.int32)
+    assert np.array_equal(ref.get_bin_contents(xi, edges, contents),
+                          contents[np.searchsorted(edges, xi.astype(F32), side="right")])
+    xh = x[15:].astype(np.float16)
+    assert np.array_equal(ref.get_bin_contents(xh, edges, contents),
+                          contents[np.searchsorted(edges, xh.astype(F32), side="right")])
+
+
+def test_interp_hand_values():
+    edges = np.array([0, 2, 4, 8], F32)                 # bin centres 1, 3, 6
+    contents = np.array([-9, 10, 20, 50, 99], F32)      # under- and overflow never used
+    x = np.array([-1, 1, 2, 3, 4.5, 6, 7, np.nan, 5.999], F32)
+    got = ref.interp(x, edges, contents)
+    assert got[:7].tolist() == [10, 10, 15, 20, 35, 50, 50]
+    assert np.isnan(got[7])
+    assert got[8] == F32(20) + (F32(5.999) - F32(3)) * F32(10)
+    # a linear table is reproduced exactly where every step is exact
+    e = np.arange(0, 10, 2).astype(F32)                 # centres 1, 3, 5, 7
+    c = np.array([0, 5, 9, 13, 17, 0], F32)             # c = 2 m + 3
+    xs = np.arange(1, 7, 0.25).astype(F32)
+    assert np.array_equal(ref.interp(xs, e, c), 2 * xs + 3)
+    # one bin: a constant
+    assert ref.interp(np.array([-5, 0.5, 9], F32), np.array([0, 1], F32), np.array([0, 7, 0], F32)).tolist() == [7, 7, 7]
+
+
+def test_interp_matches_numpy_interp():
+    rng = np.random.default_rng(22)
+    edges = np.sort(rng.uniform(0, 100, 31)).astype(F32)
+    contents = rng.normal(0, 3, 32).astype(F32)
+    m = ((edges[:-1] + edges[1:]) * F32(0.5)).astype(F32)
+    x = rng.uniform(-10, 110, 20000).astype(F32)
+    x[:30] = m
+    got = ref.interp(x, edges, contents)
+    assert np.array_equal(got[:30], contents[1:31])      # exactly the bin value at a centre
+    want = np.interp(x.astype(np.float64), m.astype(np.float64), contents[1:-1].astype(np.float64))
+    assert np.all(np.abs(got - want) <= 1e-5 * np.max(np.abs(contents)))
+
+
+def test_jes_delta_rows_and_interpolation():
+    rng = np.random.default_rng(23)
+    eta_edges = np.array([0.0, 0.5, 1.5, 2.5, 4.7], F32)
+    pt_edges = np.array([20, 40, 80, 160, 400], F32)
+    n = 3000
+    pt = (20 + rng.exponential(60, n)).astype(F32)
+    eta = rng.normal(0, 2.5, n).astype(F32)
+    eta[:4] = [np.nan, 4.7, -4.7, 9.0]
+    # constant rows: delta is the row number, which pins the |eta| row choice
+    rows = np.repeat(np.arange(1, 5, dtype=F32)[:, None], 4, axis=1)
+    got = ref.jes_delta(pt, eta, eta_edges, pt_edges, rows)
+    ae = np.abs(eta[4:])
+    want_row = np.clip(np.searchsorted(eta_edges, ae, side="right"), 1, 4)
+    assert np.array_equal(got[4:], want_row.astype(F32))
+    assert got[:4].tolist() == [1, 4, 4, 4]              # NaN -> first row; beyond the last edge -> last
+    # per-row tables against numpy.interp in pt
+    table = rng.uniform(0.01, 0.1, (4, 4)).astype(F32)
+    got = ref.jes_delta(pt, eta, eta_edges, pt_edges, table)
+    m = ((pt_edges[:-1] + pt_edges[1:]) * F32(0.5)).astype(np.float64)
+    for r in range(4):
+        sel = np.flatnonzero(want_row == r + 1) + 4
+        want = np.interp(pt[sel].astype(np.float64), m, table[r].astype(np.float64))
+        assert np.all(np.abs(got[sel] - want) <= 1e-6)
+
+
+def test_prod_left_to_right():
+    off = np.array([0, 3, 6, 6, 8], np.int64)
+    x = np.array([2, 3, 0.5, 1e30, 1e30, 1e-30, 4, 0.25], F32)
+    p = ref.reduce(ref.PROD, off, x)
+    # (1e30 * 1e30) overflows to inf before * 1e-30; a right-to-left order gives 1e30
+    assert p[0] == F32(3) and np.isposinf(p[1]) and p[2] == F32(1) and p[3] == F32(1)
+    m = np.array([1, 0, 1, 1, 1, 1, 1, 1], np.uint8)
+    em = np.array([1, 1, 1, 0], np.uint8)
+    assert ref.reduce(ref.PROD, off, x, obj_mask=m, evt_mask=em).tolist()[::3] == [1.0, 1.0]
+    assert ref.reduce(ref.PROD, off, x, obj_mask=m)[0] == F32(1)
+
+
+def test_hist_fill_sumw2():
+    rng = np.random.default_rng(24)
+    edges = datagen.uniform_edges(20, 0.0, 100.0)
+    x = rng.uniform(-10, 110, 30000).astype(F32)
+    w = rng.normal(1, 0.3, 30000).astype(F32)
+    mk = (rng.uniform(size=30000) < 0.7).astype(np.uint8)
+    s, s2, c = ref.hist_fill_w2(x, edges, w, mk)
+    sl = np.searchsorted(edges, x, side="right")
+    keep = mk == 1
+    want2 = np.bincount(sl[keep], weights=w[keep].astype(np.float64) ** 2, minlength=22)
+    assert np.allclose(s2, want2, rtol=1e-12, atol=0)
+    assert np.array_equal(s, ref.hist_fill(x, edges, w, mk)[0])
+    _, s2u, cu = ref.hist_fill_w2(x, edges)
+    assert np.array_equal(s2u, cu.astype(np.float64))
+
+
+def _hists(ds, q, **kw):
+    return ref.pipeline(ds, [q], **kw)[0]
+
+
+def test_pipeline_unit_lookups_change_nothing():
+    ds = datagen.with_pileup(datagen.make_dataset(25, 6000, extended=True), 25)
+    e = datagen.uniform_edges(10, 0.0, 100.0)
+    ones = np.ones(12, F32)
+    base = datagen.Query(min_b=1, scales=datagen.jes_scales()[:3])
+    looked = datagen.Query(min_b=1, scales=datagen.jes_scales()[:3], pu=(e, ones), sf=(e, ones))
+    a, b = _hists(ds, base), _hists(ds, looked)
+    for v in range(3):
+        for h in range(3):
+            assert np.array_equal(a[v][h][1], b[v][h][1])
+            assert np.array_equal(a[v][h][0].view(np.uint64), b[v][h][0].view(np.uint64))
+
+
+def test_pipeline_constant_lookups_scale_weights():
+    ds = datagen.with_pileup(datagen.make_dataset(26, 6000), 26)
+    e = datagen.uniform_edges(10, 0.0, 100.0)
+    a = _hists(ds, datagen.Query())
+    two = _hists(ds, datagen.Query(pu=(e, np.full(12, 2.0, F32))))
+    for h in range(3):
+        assert np.array_equal(a[0][h][1], two[0][h][1])
+        assert np.array_equal(2.0 * a[0][h][0], two[0][h][0])
+    # a scale factor of 0.5 per selected muon: weight w * 0.5^nMu
+    half = _hists(ds, datagen.Query(sf=(e, np.full(12, 0.5, F32))))
+    ev = ref.pipeline_events(ds, datagen.Query())[0]
+    w = ds.weight * (F32(0.5) ** ev["n_mu"]).astype(F32)
+    want = ref.hist_fill(ev["ht"], datagen.Query().edges_ht, w, ev["passed"])
+    assert np.array_equal(half[0][0][1], want[1]) and np.array_equal(half[0][0][0], want[0])
+
+
+def test_pipeline_lookup_jes_reduces_to_factors():
+    ds = datagen.make_dataset(27, 6000, extended=True)
+    ee, pe, d = datagen.jes_table()
+    shifts = datagen.jes_lookup_shifts()[:6]
+    # delta = 0: every shift is the nominal pass
+    zero = _hists(ds, datagen.Query(min_b=1, scales=shifts, jes=(ee, pe, np.zeros_like(d))))
+    nom = _hists(ds, datagen.Query(min_b=1))
+    for v in range(6):
+        for h in range(3):
+            assert np.array_equal(zero[v][h][1], nom[0][h][1])
+    # a constant delta: the shift s is the factor 1 + s * delta, rounded the same way
+    dc = F32(0.03)
+    const = _hists(ds, datagen.Query(min_b=1, scales=shifts, jes=(ee, pe, np.full_like(d, dc))))
+    fac = (F32(1) + shifts * dc).astype(F32)
+    byf = _hists(ds, datagen.Query(min_b=1, scales=fac))
+    for v in range(6):
+        for h in range(3):
+            assert np.array_equal(const[v][h][1], byf[v][h][1])
+            assert np.array_equal(const[v][h][0], byf[v][h][0])
+
+
+def test_pipeline_lookups_compose_from_primitives():
+    """The C pass with every lookup equals the same chain composed from the
+    primitives in Python (weights, H_T, passes), and its sumw2 is the sum of
+    the squared weights of the passing events."""
+    ds = datagen.with_pileup(datagen.make_dataset(28, 8000, extended=True), 28)
+    q = datagen.lookup_query()
+    got = _hists(ds, q, want_sumw2=True)
+    ev = ref.pipeline_events(ds, q)
+    for v in (0, 7, 13, 19):
+        e = ev[v]
+        for h, x in enumerate((e["ht"], e["lead"], e["n_jet"])):
+            s, s2, c = ref.hist_fill_w2(x, q.edges()[h], e["weight"], e["passed"])
+            gs, gc, gs2 = got[v][h]
+            assert np.array_equal(gc, c) and np.array_equal(gs, s)
+            assert np.allclose(gs2, s2, rtol=1e-12, atol=0)
+        p = e["passed"] == 1
+        assert np.isclose(got[v][0][2].sum(), np.sum(e["weight"][p].astype(np.float64) ** 2), rtol=1e-12)
