@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define HEPK_ABI_VERSION 3
+#define HEPK_ABI_VERSION 4
 #define HEPK_MAX_CUTS 8
 
 typedef enum hepk_status {
@@ -83,7 +83,8 @@ int hepk_select(const hepk_cut *cuts /* host, n_cuts */, int32_t n_cuts, int64_t
                 hipStream_t stream);
 
 typedef enum hepk_reduce_op {
-    HEPK_COUNT = 0, HEPK_SUM = 1, HEPK_MAX = 2, HEPK_MIN = 3, HEPK_ARGMAX = 4, HEPK_ARGMIN = 5
+    HEPK_COUNT = 0, HEPK_SUM = 1, HEPK_MAX = 2, HEPK_MIN = 3, HEPK_ARGMAX = 4, HEPK_ARGMIN = 5,
+    HEPK_PROD = 6
 } hepk_reduce_op;
 
 /* Per-event reduction over the objects of each event (Sec. III: the H_T kernel
@@ -100,7 +101,10 @@ typedef enum hepk_reduce_op {
  *   MAX/MIN out float32[N]: extremum (-inf/+inf when empty); out_arg
  *          (nullable, int32[N]): local index of the first extremum, -1 if empty.
  *   ARGMAX/ARGMIN out int32[N]: that local index only.
- * content dtype F32 or F16 for SUM/MAX/MIN/ARG*.  Reduced content must be
+ *   PROD   out float32[N]: left-to-right float32 product from 1.0f (the
+ *          generic pairwise operator of Sec. III taken as the product; e.g. the
+ *          product of per-lepton scale factors that weights an event, Sec. IV).
+ * content dtype F32 or F16 for SUM/PROD/MAX/MIN/ARG*.  Reduced content must be
  * NaN-free for MAX/MIN results to be meaningful. */
 int hepk_reduce(int32_t op, const int64_t *offsets /* N+1 */, int64_t n_events,
                 const void *content /* M, nullable for COUNT */, int32_t dtype,
@@ -144,6 +148,50 @@ typedef struct hepk_hist {
 int hepk_hist_fill(const void *x, int32_t dtype, const float *w /* nullable, n */,
                    const uint8_t *evt_mask /* nullable, n */, int64_t n,
                    const hepk_hist *h /* host */, hipStream_t stream);
+
+/* The same fill that also accumulates the sum of squared weights,
+ * sumw2[slot] += (double)w[i] * (double)w[i] (sumw2: device, nbins+2 float64,
+ * required), the per-bin variance estimate of a weighted histogram. */
+int hepk_hist_fill_w2(const void *x, int32_t dtype, const float *w /* nullable, n */,
+                      const uint8_t *evt_mask /* nullable, n */, int64_t n,
+                      const hepk_hist *h /* host */, double *sumw2 /* nbins+2 */, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Lookup histograms (Sec. III get_bin_contents: histogram-based reweighting;
+ * Sec. IV: event weights and jet energy corrections from histogram lookups,
+ * systematic corrections by linear interpolation).
+ *
+ * A lookup histogram has the slot layout of a filled one: strictly increasing
+ * float32 edges E[0..nbins] and nbins+2 float32 contents, contents[0] for
+ * x < E[0], contents[s] for E[s-1] <= x < E[s], contents[nbins+1] for
+ * x >= E[nbins].  Neighbouring edges must have a finite float32 sum.
+ * ------------------------------------------------------------------------- */
+
+/* out[i] = the content of the slot holding x[i]; NaN x gives the quiet NaN
+ * 0x7fc00000.  x dtype F32, F16 or I32 (converted to float32). */
+int hepk_get_bin_contents(const void *x, int32_t dtype, int64_t n, const float *edges /* nbins+1 */,
+                          int32_t nbins, const float *contents /* nbins+2 */, float *out /* n */,
+                          hipStream_t stream);
+
+/* Linear interpolation between bin centres.  With m_s = (E[s-1] + E[s]) * 0.5
+ * the centre of bin s and c_s = contents[s] (s = 1..nbins; the under- and
+ * overflow contents are not used): out = c_1 for x <= m_1, c_nbins for
+ * x >= m_nbins, else, for m_i <= x < m_{i+1},
+ * c_i + (x - m_i) * ((c_{i+1} - c_i) / (m_{i+1} - m_i)), each operation one
+ * float32 rounding.  NaN x gives 0x7fc00000.  x dtype F32, F16 or I32. */
+int hepk_interp(const void *x, int32_t dtype, int64_t n, const float *edges /* nbins+1 */, int32_t nbins,
+                const float *contents /* nbins+2 */, float *out /* n */, hipStream_t stream);
+
+/* Jet-energy-scale shift from a two-dimensional table (Sec. IV: jet energy
+ * corrections from histogram lookups): the row of |eta[i]| among n_eta bins
+ * (eta_edges; |eta| below the first edge or NaN takes the first row, at or
+ * beyond the last edge the last row), then hepk_interp in pt[i] over that
+ * row's n_pt values (pt_edges).  delta: n_eta * n_pt float32, row-major, bin
+ * values only.  pt/eta dtype F32 or F16. */
+int hepk_jes_delta(const void *pt, const void *eta, int32_t dtype, int64_t n,
+                   const float *eta_edges /* n_eta+1 */, int32_t n_eta,
+                   const float *pt_edges /* n_pt+1 */, int32_t n_pt, const float *delta /* n_eta*n_pt */,
+                   float *out /* n */, hipStream_t stream);
 
 /* Checks offsets[0] == 0, offsets non-decreasing and offsets[n_events] ==
  * n_objects; writes the number of violations to *bad (device int64). */
@@ -192,6 +240,9 @@ typedef struct hepk_dataset {
     int32_t dtype;                   /* content dtype: HEPK_F32 or HEPK_F16 */
     hepk_collection jets, muons, electrons;
     const float *weights;            /* float32[n_events]; NULL: weight 1 */
+    const float *npu;                /* float32[n_events] pileup (number of simultaneous
+                                        interactions) per event; NULL: absent, then a
+                                        query's pileup weight factor is not applied */
 } hepk_dataset;
 
 typedef struct hepk_query {
@@ -206,6 +257,24 @@ typedef struct hepk_query {
     const float *edges[3];           /* (host) H_T, lead, nJet bin edges, nbins+1 each,
                                         strictly increasing; copied into the plan */
     int32_t nbins[3];
+    /* Lookup corrections (Sec. IV: event weights and jet energy corrections
+     * from histogram lookups), all (host) tables copied into the plan;
+     * NULL edges: that correction is absent.  Lookup histograms have the
+     * layout of hepk_get_bin_contents (contents nbins+2).
+     *   event weight = (w * pu(npu)) * (product, left to right from 1, of
+     *   sf(pt) over the event's selected muons), each product one float32
+     *   rounding; pu applies only to datasets with an npu column.
+     *   jes_mode 0: the scales are factors, ptv = pt * s (positive, finite);
+     *   jes_mode 1: the scales are shifts s (finite, any sign) and
+     *   ptv = pt * (1 + s * delta), delta = hepk_jes_delta(pt, eta) of the
+     *   table (jes_eta_edges, jes_pt_edges, jes_delta). */
+    const float *pu_edges, *pu_contents;   /* pu_nbins+1, pu_nbins+2 */
+    int32_t pu_nbins;
+    const float *sf_edges, *sf_contents;   /* sf_nbins+1, sf_nbins+2 */
+    int32_t sf_nbins;
+    int32_t jes_mode;
+    const float *jes_eta_edges, *jes_pt_edges, *jes_delta;  /* n_eta+1, n_pt+1, n_eta*n_pt */
+    int32_t jes_n_eta, jes_n_pt;
 } hepk_query;
 
 /* Launch configuration of the fused kernel.  block: threads per workgroup
@@ -244,6 +313,8 @@ typedef struct hepk_plan_opts {
     int32_t reserve_bins;    /* > 0: every query slot reserves reserve_bins bins per
                                 histogram so hepk_plan_set_query can later install any query
                                 with nbins <= reserve_bins (and n_scale <= the slot's) */
+    int32_t sumw2;           /* 1: the plan can also keep sums of squared weights
+                                (hepk_pipeline_w2); implied by lookup corrections */
 } hepk_plan_opts;
 
 int hepk_plan_create_ex(const hepk_dataset *ds /* host, n_ds */, int32_t n_ds,
@@ -257,7 +328,9 @@ int hepk_plan_create_ex(const hepk_dataset *ds /* host, n_ds */, int32_t n_ds,
  * that stream afterwards see the new query and earlier ones the old.  The
  * slot's histogram blocks stay where they are; with reserve_bins > 0 the
  * blocks have reserve_bins + 2 slots of which the first nbins + 2 are used.
- * Updates and launches of one plan must go to one stream. */
+ * Updates and launches of one plan must go to one stream.  A query with
+ * lookup corrections is installed only by plan creation (HEPK_EUNSUPPORTED
+ * here). */
 int hepk_plan_set_query(hepk_plan p, int32_t slot, const hepk_query *q /* host, nullable */,
                         hipStream_t stream);
 
@@ -290,6 +363,8 @@ int hepk_pipeline(hepk_plan p, double *sumw, uint64_t *counts, hipStream_t strea
 typedef struct hepk_event_record {
     int32_t n_mu, n_jet, n_b, state;
     float ht, lead;
+    float w;            /* the event's weight for this query (with lookup factors) */
+    int32_t reserved;   /* 0 */
 } hepk_event_record;
 
 /* Where the records of hepk_pipeline_debug go: the record of event e of
@@ -308,7 +383,13 @@ int hepk_plan_debug_layout(hepk_plan p, int32_t d, int32_t q, int64_t *base /* h
 int hepk_pipeline_debug(hepk_plan p, double *sumw, uint64_t *counts, hepk_event_record *rec /* device */,
                         hipStream_t stream);
 
-/* Same, over datasets [d0, d0 + nd) only. */
+/* hepk_pipeline that also accumulates the sums of squared weights,
+ * sumw2[slot] += (double)w * (double)w per fill (hepk_plan_hist_slots
+ * float64 entries), the per-bin variance of weighted histograms.  The plan
+ * must have lookup corrections or opts.sumw2 (else HEPK_EINVAL). */
+int hepk_pipeline_w2(hepk_plan p, double *sumw, double *sumw2, uint64_t *counts, hipStream_t stream);
+
+/* Same as hepk_pipeline, over datasets [d0, d0 + nd) only. */
 int hepk_pipeline_range(hepk_plan p, int32_t d0, int32_t nd, double *sumw, uint64_t *counts,
                         hipStream_t stream);
 

@@ -7,7 +7,8 @@
 // eight at a time per thread (loads of the eight rows in flight together,
 // then their eight bins found together),
 // and merges its non-empty slots into HBM with global atomics at the end
-// (few workgroups: few atomics on each slot).  Histograms too large for LDS
+// (few workgroups: few atomics on each slot); with hepk_hist_fill_w2 also the
+// float64 sums of squared weights.  Histograms too large for LDS
 // go straight to global atomics with the edges read from HBM.  Sums of float64 weights are exact in
 // any order while every partial sum is a multiple of the smallest weight's ulp
 // below 2^53 of it, which holds for the float32 weights of this analysis;
@@ -18,7 +19,8 @@ namespace hepk {
 
 constexpr int HB = 1024;
 constexpr int HR = 8;  // rows per thread in flight
-constexpr int kMaxLdsSlots = 3000;  // 36 KiB of histogram + 12 KiB of edges
+constexpr int kMaxLdsSlots = 3000;    // 36 KiB of histogram + 12 KiB of edges
+constexpr int kMaxLdsSlotsW2 = 2400;  // with the squared weights: 48 KiB + 9.6 KiB
 
 // hist_slot_lohi for N values at once: every guess first, then every edge
 // pair read (all reads in flight together), then the checks, with a binary
@@ -45,15 +47,17 @@ __device__ __forceinline__ void hist_slots_lohi(const float (&x)[N], const float
         if (s[n] >= 1 && s[n] <= nbins && (x[n] < a[n] || x[n] >= b[n])) s[n] = bin_search(E, nbins, x[n]);
 }
 
-template <typename X, bool LDS>
+template <typename X, bool LDS, bool W2>
 __global__ __launch_bounds__(HB) void hist_kernel(const X *__restrict__ x, const float *__restrict__ w,
                                                   const uint8_t *__restrict__ m, int64_t n,
                                                   const float *__restrict__ edges, int nbins,
-                                                  double *__restrict__ sumw, uint64_t *__restrict__ counts) {
+                                                  double *__restrict__ sumw, double *__restrict__ sumw2,
+                                                  uint64_t *__restrict__ counts) {
     extern __shared__ double hist_lds[];
     const int nslots = nbins + 2;
     double *sw_s = hist_lds;
-    uint32_t *c_s = reinterpret_cast<uint32_t *>(hist_lds + (LDS ? nslots : 0));
+    double *sw2_s = hist_lds + (LDS ? nslots : 0);
+    uint32_t *c_s = reinterpret_cast<uint32_t *>(sw2_s + ((LDS && W2) ? nslots : 0));
     float *e_s = reinterpret_cast<float *>(c_s + (LDS ? nslots : 0));
     // end edges and the bin-guess start values (the guess is verified against the edges)
     const float lo = as_const(edges)[0];
@@ -63,6 +67,7 @@ __global__ __launch_bounds__(HB) void hist_kernel(const X *__restrict__ x, const
     if (LDS) {
         for (int i = threadIdx.x; i < nslots; i += HB) {
             sw_s[i] = 0.0;
+            if (W2) sw2_s[i] = 0.0;
             c_s[i] = 0u;
         }
         for (int i = threadIdx.x; i <= nbins; i += HB) e_s[i] = edges[i];
@@ -71,9 +76,11 @@ __global__ __launch_bounds__(HB) void hist_kernel(const X *__restrict__ x, const
     auto add = [&](int s, double wt) {
         if (LDS) {
             atomic_add_f64(&sw_s[s], wt);
+            if (W2) atomic_add_f64(&sw2_s[s], wt * wt);
             atomicAdd(&c_s[s], 1u);
         } else {
             atomic_add_f64(&sumw[s], wt);
+            if (W2) atomic_add_f64(&sumw2[s], wt * wt);
             atomic_add_u64(&counts[s], 1u);
         }
     };
@@ -110,6 +117,7 @@ __global__ __launch_bounds__(HB) void hist_kernel(const X *__restrict__ x, const
             if (c) {
                 atomic_add_u64(&counts[k], c);
                 atomic_add_f64(&sumw[k], sw_s[k]);
+                if (W2) atomic_add_f64(&sumw2[k], sw2_s[k]);
             }
         }
     }
@@ -139,15 +147,17 @@ __device__ __forceinline__ void load4(const _Float16 *p, float (&o)[4]) {
 // mask to 4 bytes.  The last quad may run past n: its loads stay inside the
 // aligned 4-row block that holds row 4q (so inside the buffer's pages), and
 // rows >= n are not filled.
-template <typename X, bool LDS>
+template <typename X, bool LDS, bool W2>
 __global__ __launch_bounds__(HB) void hist_vec_kernel(const X *__restrict__ x, const float *__restrict__ w,
                                                       const uint8_t *__restrict__ m, int64_t n,
                                                       const float *__restrict__ edges, int nbins,
-                                                      double *__restrict__ sumw, uint64_t *__restrict__ counts) {
+                                                      double *__restrict__ sumw, double *__restrict__ sumw2,
+                                                      uint64_t *__restrict__ counts) {
     extern __shared__ double hist_lds[];
     const int nslots = nbins + 2;
     double *sw_s = hist_lds;
-    uint32_t *c_s = reinterpret_cast<uint32_t *>(hist_lds + (LDS ? nslots : 0));
+    double *sw2_s = hist_lds + (LDS ? nslots : 0);
+    uint32_t *c_s = reinterpret_cast<uint32_t *>(sw2_s + ((LDS && W2) ? nslots : 0));
     float *e_s = reinterpret_cast<float *>(c_s + (LDS ? nslots : 0));
     const float lo = as_const(edges)[0];
     const float hi = as_const(edges)[nbins];
@@ -156,6 +166,7 @@ __global__ __launch_bounds__(HB) void hist_vec_kernel(const X *__restrict__ x, c
     if (LDS) {
         for (int i = threadIdx.x; i < nslots; i += HB) {
             sw_s[i] = 0.0;
+            if (W2) sw2_s[i] = 0.0;
             c_s[i] = 0u;
         }
         for (int i = threadIdx.x; i <= nbins; i += HB) e_s[i] = edges[i];
@@ -164,9 +175,11 @@ __global__ __launch_bounds__(HB) void hist_vec_kernel(const X *__restrict__ x, c
     auto add = [&](int s, double wt) {
         if (LDS) {
             atomic_add_f64(&sw_s[s], wt);
+            if (W2) atomic_add_f64(&sw2_s[s], wt * wt);
             atomicAdd(&c_s[s], 1u);
         } else {
             atomic_add_f64(&sumw[s], wt);
+            if (W2) atomic_add_f64(&sumw2[s], wt * wt);
             atomic_add_u64(&counts[s], 1u);
         }
     };
@@ -207,44 +220,42 @@ __global__ __launch_bounds__(HB) void hist_vec_kernel(const X *__restrict__ x, c
             if (c) {
                 atomic_add_u64(&counts[k], c);
                 atomic_add_f64(&sumw[k], sw_s[k]);
+                if (W2) atomic_add_f64(&sumw2[k], sw2_s[k]);
             }
         }
     }
 }
 
-template <typename X>
+template <typename X, bool W2>
 static int launch_hist(const void *x, const float *w, const uint8_t *m, int64_t n, const hepk_hist *h,
-                       hipStream_t stream) {
+                       double *sumw2, hipStream_t stream) {
     const int nslots = h->nbins + 2;
-    const bool lds = nslots <= kMaxLdsSlots;
+    const bool lds = nslots <= (W2 ? kMaxLdsSlotsW2 : kMaxLdsSlots);
     const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n, HB * HR), 2 * device_cus()));
-    const size_t lds_bytes = static_cast<size_t>(nslots) * (sizeof(double) + sizeof(uint32_t)) +
+    const size_t lds_bytes = static_cast<size_t>(nslots) * ((W2 ? 2 : 1) * sizeof(double) + sizeof(uint32_t)) +
                              static_cast<size_t>(h->nbins + 1) * sizeof(float);
     auto aligned = [](const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; };
+    const X *xp = static_cast<const X *>(x);
     if (aligned(x, 4 * sizeof(X)) && (!w || aligned(w, 16)) && (!m || aligned(m, 4))) {
         if (lds)
-            hist_vec_kernel<X, true><<<grid, HB, lds_bytes, stream>>>(static_cast<const X *>(x), w, m, n, h->edges,
-                                                                      h->nbins, h->sumw, h->counts);
+            hist_vec_kernel<X, true, W2><<<grid, HB, lds_bytes, stream>>>(xp, w, m, n, h->edges, h->nbins, h->sumw,
+                                                                          sumw2, h->counts);
         else
-            hist_vec_kernel<X, false><<<grid, HB, 0, stream>>>(static_cast<const X *>(x), w, m, n, h->edges,
-                                                               h->nbins, h->sumw, h->counts);
+            hist_vec_kernel<X, false, W2><<<grid, HB, 0, stream>>>(xp, w, m, n, h->edges, h->nbins, h->sumw, sumw2,
+                                                                   h->counts);
         return check_launch("hepk_hist_fill");
     }
     if (lds)
-        hist_kernel<X, true><<<grid, HB, lds_bytes, stream>>>(static_cast<const X *>(x), w, m, n, h->edges,
-                                                              h->nbins, h->sumw, h->counts);
+        hist_kernel<X, true, W2><<<grid, HB, lds_bytes, stream>>>(xp, w, m, n, h->edges, h->nbins, h->sumw, sumw2,
+                                                                  h->counts);
     else
-        hist_kernel<X, false><<<grid, HB, 0, stream>>>(static_cast<const X *>(x), w, m, n, h->edges, h->nbins,
-                                                       h->sumw, h->counts);
+        hist_kernel<X, false, W2><<<grid, HB, 0, stream>>>(xp, w, m, n, h->edges, h->nbins, h->sumw, sumw2,
+                                                           h->counts);
     return check_launch("hepk_hist_fill");
 }
 
-}  // namespace hepk
-
-extern "C" int hepk_hist_fill(const void *x, int32_t dtype, const float *w, const uint8_t *evt_mask, int64_t n,
-                              const hepk_hist *h, hipStream_t stream) {
-    using namespace hepk;
-    clear_error();
+static int hist_fill(const void *x, int32_t dtype, const float *w, const uint8_t *evt_mask, int64_t n,
+                     const hepk_hist *h, double *sumw2, hipStream_t stream) {
     HEPK_REQUIRE(h, "hepk_hist_fill: hist is NULL");
     HEPK_REQUIRE(n >= 0, "hepk_hist_fill: n < 0");
     HEPK_REQUIRE(h->nbins >= 1, "hepk_hist_fill: nbins %d < 1", h->nbins);
@@ -253,7 +264,27 @@ extern "C" int hepk_hist_fill(const void *x, int32_t dtype, const float *w, cons
     HEPK_REQUIRE(dtype == HEPK_F32 || dtype == HEPK_F16 || dtype == HEPK_I32, "hepk_hist_fill: bad dtype %d",
                  dtype);
     if (n == 0) return HEPK_OK;
-    if (dtype == HEPK_F16) return launch_hist<_Float16>(x, w, evt_mask, n, h, stream);
-    if (dtype == HEPK_I32) return launch_hist<int32_t>(x, w, evt_mask, n, h, stream);
-    return launch_hist<float>(x, w, evt_mask, n, h, stream);
+    if (sumw2) {
+        if (dtype == HEPK_F16) return launch_hist<_Float16, true>(x, w, evt_mask, n, h, sumw2, stream);
+        if (dtype == HEPK_I32) return launch_hist<int32_t, true>(x, w, evt_mask, n, h, sumw2, stream);
+        return launch_hist<float, true>(x, w, evt_mask, n, h, sumw2, stream);
+    }
+    if (dtype == HEPK_F16) return launch_hist<_Float16, false>(x, w, evt_mask, n, h, nullptr, stream);
+    if (dtype == HEPK_I32) return launch_hist<int32_t, false>(x, w, evt_mask, n, h, nullptr, stream);
+    return launch_hist<float, false>(x, w, evt_mask, n, h, nullptr, stream);
+}
+
+}  // namespace hepk
+
+extern "C" int hepk_hist_fill(const void *x, int32_t dtype, const float *w, const uint8_t *evt_mask, int64_t n,
+                              const hepk_hist *h, hipStream_t stream) {
+    hepk::clear_error();
+    return hepk::hist_fill(x, dtype, w, evt_mask, n, h, nullptr, stream);
+}
+
+extern "C" int hepk_hist_fill_w2(const void *x, int32_t dtype, const float *w, const uint8_t *evt_mask, int64_t n,
+                                 const hepk_hist *h, double *sumw2, hipStream_t stream) {
+    hepk::clear_error();
+    HEPK_REQUIRE(sumw2, "hepk_hist_fill_w2: sumw2 is NULL");
+    return hepk::hist_fill(x, dtype, w, evt_mask, n, h, sumw2, stream);
 }

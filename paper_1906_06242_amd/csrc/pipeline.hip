@@ -10,11 +10,16 @@
 
 namespace hepk {
 // the multi-scale kernels are instantiated in pipeline_ms.hip, the kernels
-// that write per-event records in pipeline_dbg.hip and pipeline_ms_dbg.hip
-extern template KernelFn pick_kernel<true, false>(int, bool, int, int, bool);
-extern template KernelFn pick_kernel<false, true>(int, bool, int, int, bool);
-extern template KernelFn pick_kernel<true, true>(int, bool, int, int, bool);
-template KernelFn pick_kernel<false, false>(int, bool, int, int, bool);
+// that write per-event records in pipeline_dbg.hip and pipeline_ms_dbg.hip,
+// the kernels with lookup corrections in pipeline_lk*.hip
+extern template KernelFn pick_kernel<true, false, false>(int, bool, int, int, bool);
+extern template KernelFn pick_kernel<false, true, false>(int, bool, int, int, bool);
+extern template KernelFn pick_kernel<true, true, false>(int, bool, int, int, bool);
+extern template KernelFn pick_kernel<false, false, true>(int, bool, int, int, bool);
+extern template KernelFn pick_kernel<true, false, true>(int, bool, int, int, bool);
+extern template KernelFn pick_kernel<false, true, true>(int, bool, int, int, bool);
+extern template KernelFn pick_kernel<true, true, true>(int, bool, int, int, bool);
+template KernelFn pick_kernel<false, false, false>(int, bool, int, int, bool);
 }  // namespace hepk
 
 namespace hepk {
@@ -43,8 +48,10 @@ static size_t table_lds_bytes(hepk_plan p) {
            (p->scales_lds ? static_cast<size_t>(p->n_scales) * sizeof(float) : 0);
 }
 
+// LDS histograms: float64 sums (and, in lookup plans, float64 sums of squared
+// weights) and uint32 counts per slot.
 static size_t hist_lds_bytes(hepk_plan p) {
-    return static_cast<size_t>(p->lds_slots) * (sizeof(double) + sizeof(uint32_t));
+    return static_cast<size_t>(p->lds_slots) * ((p->lk ? 2 : 1) * sizeof(double) + sizeof(uint32_t));
 }
 
 // LDS histograms when asked for, within their budget, and when the kernel's
@@ -70,8 +77,15 @@ static void set_qdev(QDev &o, const hepk_query &Q, const float *const edges[3]) 
     o.min_b = Q.min_b;
     o.n_scale = Q.n_scale;
     o.smax = Q.scales[0];
-    for (int v = 1; v < Q.n_scale; ++v) o.smax = std::max(o.smax, Q.scales[v]);
+    o.smin = Q.scales[0];
+    for (int v = 1; v < Q.n_scale; ++v) {
+        o.smax = std::max(o.smax, Q.scales[v]);
+        o.smin = std::min(o.smin, Q.scales[v]);
+    }
     o.active = 1;
+    // lookup tables: placed by the plan (lk_place); absent until then
+    o.pu_nb = o.sf_nb = o.jr_nb = o.jc_nb = 0;
+    o.jes_mode = Q.jes_mode;
     for (int h = 0; h < 3; ++h) {
         const int nb = Q.nbins[h];
         const float *e = edges[h];
@@ -83,11 +97,39 @@ static void set_qdev(QDev &o, const hepk_query &Q, const float *const edges[3]) 
     }
 }
 
+// A lookup table's edges (nb + 1, strictly increasing, neighbour sums finite).
+static int check_table(const float *e, int32_t nb, const void *c, int i, const char *what) {
+    HEPK_REQUIRE(e && c && nb >= 1 && nb <= (1 << 16), "query %d %s table invalid", i, what);
+    for (int k = 0; k <= nb; ++k) HEPK_REQUIRE(std::isfinite(e[k]), "query %d %s edge %d not finite", i, what, k);
+    for (int k = 0; k < nb; ++k) {
+        HEPK_REQUIRE(e[k] < e[k + 1], "query %d %s edges not strictly increasing at %d", i, what, k);
+        HEPK_REQUIRE(std::isfinite(e[k] + e[k + 1]), "query %d %s edges %d, %d: sum not finite", i, what, k, k + 1);
+    }
+    return HEPK_OK;
+}
+
+static bool has_lookups(const hepk_query &Q) { return Q.pu_edges || Q.sf_edges || Q.jes_mode != 0; }
+
 static int check_query(const hepk_query &Q, int i) {
     HEPK_REQUIRE(Q.n_scale >= 1 && Q.scales, "query %d needs >= 1 scale", i);
-    for (int v = 0; v < Q.n_scale; ++v)
-        HEPK_REQUIRE(Q.scales[v] > 0.0f && std::isfinite(Q.scales[v]), "query %d scale %d is not positive and finite",
-                     i, v);
+    HEPK_REQUIRE(Q.jes_mode == 0 || Q.jes_mode == 1, "query %d jes_mode %d not 0 or 1", i, Q.jes_mode);
+    for (int v = 0; v < Q.n_scale; ++v) {
+        if (Q.jes_mode == 1)
+            HEPK_REQUIRE(std::isfinite(Q.scales[v]), "query %d shift %d is not finite", i, v);
+        else
+            HEPK_REQUIRE(Q.scales[v] > 0.0f && std::isfinite(Q.scales[v]),
+                         "query %d scale %d is not positive and finite", i, v);
+    }
+    if (Q.pu_edges)
+        if (int rc = check_table(Q.pu_edges, Q.pu_nbins, Q.pu_contents, i, "pileup")) return rc;
+    if (Q.sf_edges)
+        if (int rc = check_table(Q.sf_edges, Q.sf_nbins, Q.sf_contents, i, "muon scale-factor")) return rc;
+    if (Q.jes_mode == 1) {
+        if (int rc = check_table(Q.jes_eta_edges, Q.jes_n_eta, Q.jes_delta, i, "jet-energy-scale |eta|")) return rc;
+        if (int rc = check_table(Q.jes_pt_edges, Q.jes_n_pt, Q.jes_delta, i, "jet-energy-scale pt")) return rc;
+        HEPK_REQUIRE(static_cast<int64_t>(Q.jes_n_eta) * Q.jes_n_pt <= (1 << 16),
+                     "query %d jet-energy-scale table has more than 65536 values", i);
+    }
     for (int h = 0; h < 3; ++h) {
         HEPK_REQUIRE(Q.nbins[h] >= 1 && Q.edges[h], "query %d histogram %d invalid", i, h);
         for (int k = 0; k < Q.nbins[h]; ++k)
@@ -99,7 +141,44 @@ static int check_query(const hepk_query &Q, int i) {
 
 static int64_t hist_base(hepk_plan p, int d) { return p->shared ? 0 : d * p->ds_block; }
 
-Launch make_launch(hepk_plan p, int32_t c0, int32_t c1, double *sumw, uint64_t *counts, hepk_event_record *rec) {
+// Appends the query's lookup tables to the plan's edge table and points the
+// table entry at them.
+static void lk_place(QDev &o, const hepk_query &Q, std::vector<float> &tab) {
+    auto put = [&](const float *a, size_t n) {
+        const int32_t at = static_cast<int32_t>(tab.size());
+        tab.insert(tab.end(), a, a + n);
+        return at;
+    };
+    auto axis = [](const float *e, int nb, float &lo, float &hi, float &iw) {
+        lo = e[0];
+        hi = e[nb];
+        iw = bin_inv_width(lo, hi, nb);
+    };
+    if (Q.pu_edges) {
+        o.pu_nb = Q.pu_nbins;
+        o.pu_e = put(Q.pu_edges, Q.pu_nbins + 1);
+        o.pu_c = put(Q.pu_contents, Q.pu_nbins + 2);
+        axis(Q.pu_edges, Q.pu_nbins, o.pu_lo, o.pu_hi, o.pu_iw);
+    }
+    if (Q.sf_edges) {
+        o.sf_nb = Q.sf_nbins;
+        o.sf_e = put(Q.sf_edges, Q.sf_nbins + 1);
+        o.sf_c = put(Q.sf_contents, Q.sf_nbins + 2);
+        axis(Q.sf_edges, Q.sf_nbins, o.sf_lo, o.sf_hi, o.sf_iw);
+    }
+    if (Q.jes_mode == 1) {
+        o.jr_nb = Q.jes_n_eta;
+        o.jr_e = put(Q.jes_eta_edges, Q.jes_n_eta + 1);
+        o.jc_nb = Q.jes_n_pt;
+        o.jc_e = put(Q.jes_pt_edges, Q.jes_n_pt + 1);
+        o.jd = put(Q.jes_delta, static_cast<size_t>(Q.jes_n_eta) * Q.jes_n_pt);
+        axis(Q.jes_eta_edges, Q.jes_n_eta, o.jr_lo, o.jr_hi, o.jr_iw);
+        axis(Q.jes_pt_edges, Q.jes_n_pt, o.jc_lo, o.jc_hi, o.jc_iw);
+    }
+}
+
+Launch make_launch(hepk_plan p, int32_t c0, int32_t c1, double *sumw, uint64_t *counts, hepk_event_record *rec,
+                   double *sumw2) {
     Launch L{};
     const bool ldsh = use_lds_hist(p);
     L.fn = rec ? (ldsh ? p->fn_lds_dbg : p->fn_glob_dbg) : (ldsh ? p->fn_lds : p->fn_glob);
@@ -116,6 +195,7 @@ Launch make_launch(hepk_plan p, int32_t c0, int32_t c1, double *sumw, uint64_t *
     L.a.ds_slots = ldsh ? p->lds_slots : 0;
     L.a.sumw = sumw;
     L.a.counts = counts;
+    L.a.sumw2 = sumw2;
     L.a.rec = rec;
     L.a.rec_events = p->ev_pre.back();
     return L;
@@ -200,6 +280,9 @@ int plan_build(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_
     }
     hepk_plan_opts o{};
     if (opts) o = *opts;
+    HEPK_REQUIRE(o.sumw2 == 0 || o.sumw2 == 1, "hepk_plan_create: sumw2 %d not 0 or 1", o.sumw2);
+    bool lk = o.sumw2 != 0;
+    for (int i = 0; i < n_query; ++i) lk |= has_lookups(q[i]);
     // default launch shape: 512 threads; 1024 when a query has several
     // jet-energy scales (one LDS copy of their many histograms shared by 16
     // wavefronts instead of 8)
@@ -212,6 +295,7 @@ int plan_build(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_
     HEPK_REQUIRE(t.ev_per_thread == 1 || t.ev_per_thread == 2, "hepk_plan_create: ev_per_thread %d not 1 or 2",
                  t.ev_per_thread);
     HEPK_REQUIRE(t.block < 1024 || t.ev_per_thread == 1, "hepk_plan_create: block 1024 takes ev_per_thread 1");
+    if (lk) t.ev_per_thread = 1;  // the lookup kernels take one event per thread
     HEPK_REQUIRE(t.hist_mode == 0 || t.hist_mode == 1, "hepk_plan_create: hist_mode %d not 0 or 1", t.hist_mode);
     HEPK_REQUIRE(t.grid >= 0, "hepk_plan_create: grid < 0");
     HEPK_REQUIRE(o.reserve_bins >= 0 && o.reserve_bins < (1 << 20), "hepk_plan_create: reserve_bins out of range");
@@ -226,6 +310,7 @@ int plan_build(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_
     p->dtype = dtype;
     p->ext = ext;
     p->shared = o.shared_hist != 0;
+    p->lk = lk;
 
     // query slots: reserved bins/scales, global histogram blocks, edge and scale regions
     p->qd.assign(n_query, QDev{});
@@ -252,6 +337,7 @@ int plan_build(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_
             edge_table.insert(edge_table.end(), q[i].edges[h], q[i].edges[h] + q[i].nbins[h] + 1);
             edge_table.resize(e.ebase[h] + cap + 1, 0.0f);
         }
+        lk_place(e, q[i], edge_table);
         e.gper_scale = per;
         e.gslot0 = static_cast<int32_t>(gacc);
         gacc += static_cast<int64_t>(per) * q[i].n_scale;
@@ -292,6 +378,7 @@ int plan_build(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_
         e.eeta = D.electrons.eta;
         e.ephi = D.electrons.phi;
         e.w = D.weights;
+        e.npu = D.npu;
         e.hist0 = hist_base(p, d);
         e.ev0 = p->ev_pre[d];
         p->ev_pre[d + 1] = p->ev_pre[d] + D.n_events;
@@ -299,8 +386,10 @@ int plan_build(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_
     }
 
     p->ms = max_sc > 1;
-    auto pick = p->ms ? pick_kernel<true, false> : pick_kernel<false, false>;
-    auto pick_dbg = p->ms ? pick_kernel<true, true> : pick_kernel<false, true>;
+    auto pick = p->lk ? (p->ms ? pick_kernel<true, false, true> : pick_kernel<false, false, true>)
+                      : (p->ms ? pick_kernel<true, false, false> : pick_kernel<false, false, false>);
+    auto pick_dbg = p->lk ? (p->ms ? pick_kernel<true, true, true> : pick_kernel<false, true, true>)
+                          : (p->ms ? pick_kernel<true, true, false> : pick_kernel<false, true, false>);
     p->fn_lds = pick(dtype, ext, t.block, t.ev_per_thread, true);
     p->fn_glob = pick(dtype, ext, t.block, t.ev_per_thread, false);
     p->fn_lds_dbg = pick_dbg(dtype, ext, t.block, t.ev_per_thread, true);
@@ -450,6 +539,10 @@ extern "C" int hepk_plan_set_query(hepk_plan p, int32_t slot, const hepk_query *
     if (q) {
         int rc = check_query(*q, slot);
         if (rc) return rc;
+        if (has_lookups(*q)) {
+            set_error("hepk_plan_set_query: lookup corrections are installed by plan creation only");
+            return HEPK_EUNSUPPORTED;
+        }
         HEPK_REQUIRE(q->n_scale <= p->cap_scales[slot], "hepk_plan_set_query: %d scales, slot holds %d", q->n_scale,
                      p->cap_scales[slot]);
         for (int h = 0; h < 3; ++h)
@@ -530,6 +623,19 @@ extern "C" int hepk_pipeline(hepk_plan p, double *sumw, uint64_t *counts, hipStr
     HEPK_REQUIRE(p, "hepk_pipeline: plan is NULL");
     HEPK_REQUIRE(sumw && counts, "hepk_pipeline: histogram buffers are NULL");
     return pipeline_chunks(p, 0, p->n_ds, sumw, counts, stream);
+}
+
+extern "C" int hepk_pipeline_w2(hepk_plan p, double *sumw, double *sumw2, uint64_t *counts, hipStream_t stream) {
+    using namespace hepk;
+    clear_error();
+    HEPK_REQUIRE(p, "hepk_pipeline_w2: plan is NULL");
+    HEPK_REQUIRE(sumw && sumw2 && counts, "hepk_pipeline_w2: histogram buffers are NULL");
+    HEPK_REQUIRE(p->lk, "hepk_pipeline_w2: plan made without lookup corrections or opts.sumw2");
+    if (!has_work(p, 0, p->n_ds)) return HEPK_OK;
+    int dev = 0;
+    HEPK_HIP(hipGetDevice(&dev));
+    HEPK_REQUIRE(dev == p->device, "hepk_pipeline_w2: plan made on device %d, current device %d", p->device, dev);
+    return run_launch(make_launch(p, 0, p->n_ds, sumw, counts, nullptr, sumw2), stream);
 }
 
 extern "C" int hepk_plan_debug_layout(hepk_plan p, int32_t d, int32_t q, int64_t *base, int64_t *stride,

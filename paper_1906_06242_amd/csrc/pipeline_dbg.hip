@@ -3,5 +3,5 @@
 #include "pipeline_kernel.hpp"
 
 namespace hepk {
-template KernelFn pick_kernel<false, true>(int, bool, int, int, bool);
+template KernelFn pick_kernel<false, true, false>(int, bool, int, int, bool);
 }  // namespace hepk

@@ -56,6 +56,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "lookup.hpp"
 
 namespace hepk {
 
@@ -66,6 +67,7 @@ struct DsDev {
     const void *mpt, *meta, *mphi, *miso;
     const void *ept, *eeta, *ephi;
     const float *w;
+    const float *npu;  // pileup per event (lookup weights); NULL: absent
     int64_t hist0;  // first slot of this dataset's block of histograms
     int64_t ev0;    // events of the datasets before this one (per-event records)
 };
@@ -85,6 +87,17 @@ struct QDev {
     // and in the dataset's block in HBM (fixed per query slot).
     int32_t lslot0, lper_scale, lhoff[3];
     int32_t gslot0, gper_scale, ghoff[3];
+    // Lookup corrections (read by the LK kernels only).  Tables live in the
+    // plan's edge table: pileup and muon scale-factor histograms (bins, first
+    // edge, first slot content; pu_nb / sf_nb 0: that weight factor is
+    // absent) and, with jes_mode 1, the jet-energy-scale shift table (rows of
+    // |eta| bins, columns of pt bins, values row-major from jd); scales are
+    // then shifts s with ptv = pt * (1 + s * delta).  smin: smallest scale.
+    int32_t pu_nb, pu_e, pu_c, sf_nb, sf_e, sf_c;
+    int32_t jes_mode, jr_nb, jr_e, jc_nb, jc_e, jd;
+    float pu_lo, pu_hi, pu_iw, sf_lo, sf_hi, sf_iw;
+    float jr_lo, jr_hi, jr_iw, jc_lo, jc_hi, jc_iw;
+    float smin;
 };
 
 struct Chunk {
@@ -104,6 +117,7 @@ struct PipeArgs {
     int32_t n_scales, scales_in_lds;               // the scale table, copied to LDS when small
     double *sumw;
     uint64_t *counts;
+    double *sumw2;  // LK kernels: sums of squared weights (NULL: not kept)
     // per-event records (kernels instantiated with DBG only): the record of
     // event e of dataset d for scale v of query q is
     // rec[(q.scale0 + v) * rec_events + d.ev0 + e]
@@ -116,22 +130,52 @@ __device__ __forceinline__ hepk_event_record *rec_at(const PipeArgs &P, int row,
     return P.rec + static_cast<int64_t>(row) * P.rec_events + ev;
 }
 
-template <bool LDSH>
+template <bool LDSH, bool W2 = false>
 struct HistSink {
     double *sw;        // LDS (LDSH) or the dataset's block in HBM
     uint32_t *c32;     // LDS (LDSH)
     uint64_t *c64;     // HBM (!LDSH)
+    double *sw2;       // W2: squared weights (LDS or HBM like sw; NULL: not kept)
 
     __device__ __forceinline__ void add(int slot, double w) const {
-        if (LDSH) {
-            atomic_add_f64(&sw[slot], w);
+        atomic_add_f64(&sw[slot], w);
+        if (W2 && sw2) atomic_add_f64(&sw2[slot], w * w);
+        if (LDSH)
             atomicAdd(&c32[slot], 1u);
-        } else {
-            atomic_add_f64(&sw[slot], w);
+        else
             atomic_add_u64(&c64[slot], 1u);
-        }
     }
 };
+
+// The lookup tables of one query as axes over the edge table E.
+struct LkAxes {
+    Axis pu, sf, jr, jc;
+};
+
+template <typename QT>
+__device__ __forceinline__ LkAxes lk_axes(const QT &Q, const float *E) {
+    LkAxes a;
+    a.pu = Axis{E + Q.pu_e, Q.pu_nb, Q.pu_lo, Q.pu_hi, Q.pu_iw};
+    a.sf = Axis{E + Q.sf_e, Q.sf_nb, Q.sf_lo, Q.sf_hi, Q.sf_iw};
+    a.jr = Axis{E + Q.jr_e, Q.jr_nb, Q.jr_lo, Q.jr_hi, Q.jr_iw};
+    a.jc = Axis{E + Q.jc_e, Q.jc_nb, Q.jc_lo, Q.jc_hi, Q.jc_iw};
+    return a;
+}
+
+// The jet-energy-scale shift of a jet (pt, eta) from the query's table.
+__device__ __forceinline__ float jes_shift(const LkAxes &a, const float *E, int jd, float pt, float eta) {
+    const int row = lookup_row(a.jr, fabsf(eta));
+    return lookup_interp(a.jc, E + jd + (row - 1) * a.jc.nb, pt);
+}
+
+// Largest pt * (1 + s * d) over the scales in [smin, smax]: the factor is
+// monotone in s (its rounding is monotone) and the product monotone in the
+// factor, so the extremes are at smin or smax.  NaN when pt or d is NaN.
+__device__ __forceinline__ float shifted_pt_bound(float pt, float d, float smin, float smax) {
+    const float f_hi = 1.0f + smax * d, f_lo = 1.0f + smin * d;
+    const float a = pt * f_hi, b = pt * f_lo;
+    return (a != a) ? b : (b != b ? a : fmaxf(a, b));
+}
 
 // Histogram constants of one query, read once per query and held in
 // registers: they are uniform, and without the pin the compiler reloads each
@@ -204,8 +248,8 @@ __device__ __forceinline__ void find_bins(const FillC &F, const float *edges, co
 
 // Fills H_T, lead and nJet of one passing event for scale v of query Q (a
 // table entry read in place, so its fields are fetched where they are used).
-template <bool LDSH, typename QT>
-__device__ __forceinline__ void fill3(const HistSink<LDSH> &sink, const QT &Q, const float *edges, int v,
+template <bool LDSH, bool W2, typename QT>
+__device__ __forceinline__ void fill3(const HistSink<LDSH, W2> &sink, const QT &Q, const float *edges, int v,
                                       float ht, float lead, int nj, double w) {
     const int base = LDSH ? Q.lslot0 + v * Q.lper_scale : Q.gslot0 + v * Q.gper_scale;
     const float xs[3] = {ht, lead, static_cast<float>(nj)};
@@ -227,14 +271,15 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One event, one lane, columns read straight from HBM.
-template <typename T, bool EXT, bool LDSH, bool DBG>
+// One event, one lane, columns read straight from HBM.  LK: lookup event
+// weights and, with jes_mode 1, shifted jet energies.
+template <typename T, bool EXT, bool LDSH, bool DBG, bool LK>
 __device__ void event_direct(const PipeArgs &P, const DsDev &D, int64_t e, const float *edges,
-                             const HistSink<LDSH> &sink) {
+                             const HistSink<LDSH, LK> &sink) {
     const bool has_iso = D.miso != nullptr;
     const bool has_el = EXT && D.eoff != nullptr;
     const bool has_bt = EXT && D.jbt != nullptr;
-    const double w = D.w ? static_cast<double>(D.w[e]) : 1.0;
+    const float w0 = D.w ? D.w[e] : 1.0f;
     const int64_t j0 = D.joff[e], j1 = D.joff[e + 1];
     const int64_t m0 = D.moff[e], m1 = D.moff[e + 1];
     const int64_t l0 = has_el ? D.eoff[e] : 0, l1 = has_el ? D.eoff[e + 1] : 0;
@@ -254,13 +299,29 @@ __device__ void event_direct(const PipeArgs &P, const DsDev &D, int64_t e, const
         auto el_sel = [&](int64_t m) { return ldf(ept, m) > Q.el_pt && fabsf(ldf(eeta, m)) < Q.el_abseta; };
         int nmu = 0;
         for (int64_t m = m0; m < m1; ++m) nmu += mu_sel(m) ? 1 : 0;
+        // event weight: w, times the pileup lookup, times the product (left
+        // to right from 1) of the selected muons' scale factors
+        float wq = w0;
+        LkAxes ax{};
+        if (LK) {
+            ax = lk_axes(Q, edges);
+            if (Q.pu_nb > 0 && D.npu) wq = wq * lookup_bin(ax.pu, edges + Q.pu_c, D.npu[e]);
+            if (Q.sf_nb > 0) {
+                float prod = 1.0f;
+                for (int64_t m = m0; m < m1; ++m)
+                    if (mu_sel(m)) prod = prod * lookup_bin(ax.sf, edges + Q.sf_c, ldf(mpt, m));
+                wq = wq * prod;
+            }
+        }
+        const bool shift = LK && Q.jes_mode == 1;
         for (int v = 0; v < Q.n_scale; ++v) {
             const float s = as_const(P.scales)[Q.scale0 + v];
             int nj = 0, nb = 0;
             float ht = 0.0f, lead = -INFINITY;
             for (int64_t j = j0; j < j1; ++j) {
-                const float x = ldf(jpt, j) * s;
+                const float pt = ldf(jpt, j);
                 const float eta = ldf(jeta, j);
+                const float x = shift ? pt * (1.0f + s * jes_shift(ax, edges, Q.jd, pt, eta)) : pt * s;
                 if (!(x > Q.jet_pt && fabsf(eta) < Q.jet_abseta)) continue;
                 const float phi = ldf(jphi, j);
                 bool hit = false;
@@ -275,8 +336,9 @@ __device__ void event_direct(const PipeArgs &P, const DsDev &D, int64_t e, const
                 if (has_bt && ldf(jbt, j) > Q.btag) ++nb;
             }
             const bool pass = nmu >= Q.min_mu && nj >= Q.min_jet && (!has_bt || nb >= Q.min_b);
-            if (DBG) *rec_at(P, Q.scale0 + v, D.ev0 + e) = hepk_event_record{nmu, nj, nb, pass ? 3 : 2, ht, lead};
-            if (pass) fill3(sink, Q, edges, v, ht, lead, nj, w);
+            if (DBG)
+                *rec_at(P, Q.scale0 + v, D.ev0 + e) = hepk_event_record{nmu, nj, nb, pass ? 3 : 2, ht, lead, wq, 0};
+            if (pass) fill3(sink, Q, edges, v, ht, lead, nj, static_cast<double>(wq));
         }
     }
 }
@@ -298,7 +360,7 @@ struct Caps {
 // the high 16 bits, first | count << 8 each) until the cone test reads it;
 // the same word then holds the jet's pt (or NaN) for the per-event walk
 // (with one scale and jet_pt >= 0: pt * s of a selected jet, else +0).
-template <int EVPL, bool EXT>
+template <int EVPL, bool EXT, bool LK>
 struct WaveLds {
     using C = Caps<EVPL, EXT>;
     union {
@@ -308,6 +370,8 @@ struct WaveLds {
     uint32_t jre[(EXT && !C::PACK) ? C::JC : 1];  // electron ranges when not packed
     float seta[C::MC + 2], sphi[C::MC + 2];        // selected muons, compacted in tile order (+2 padding)
     float sea[EXT ? C::EC : 1], sep[EXT ? C::EC : 1];
+    float ssf[LK ? C::MC + 2 : 1];  // LK: selected muons' scale factors, compacted like seta
+    float jd[LK ? C::JC : 1];       // LK: each jet's energy-scale shift (jes_mode 1)
     uint8_t bt[EXT ? C::JC : 1];
     union {
         struct {  // steps 2-3: selected leptons before lepton m
@@ -324,8 +388,8 @@ struct WaveLds {
 
 // Adds weight w to the histograms of scales v0 + n / 3 (observable n % 3)
 // of the lanes whose pass[n / 3] is set; NaN values are not filled.
-template <int N, bool LDSH>
-__device__ __forceinline__ void fill_bins(const HistSink<LDSH> &sink, const FillC &F, const float *edges,
+template <int N, bool LDSH, bool W2>
+__device__ __forceinline__ void fill_bins(const HistSink<LDSH, W2> &sink, const FillC &F, const float *edges,
                                           const float (&xs)[N], const bool (&pass)[N / 3], int v0, double w) {
     int sl[N];
     find_bins<N>(F, edges, xs, sl);
@@ -340,14 +404,17 @@ constexpr int kG = 4;
 
 // Walks the jets [j0, j1) of one event in order (pt of each in LDS, NaN when
 // removed by the cone or |eta| cut) for G scales at once: per scale the
-// left-to-right float32 H_T of the selected jets (pt * s > jet_pt), their
+// left-to-right float32 H_T of the selected jets (ptv > jet_pt), their
 // count, b-tag count and maximum.  Adding only selected values keeps the sum
-// order of the definition.  The maximum needs no per-scale work: for s > 0,
-// rounding pt * s is monotone in pt, so the selected jets are those above a
-// pt bound and the largest selected pt * s is the largest cleaned pt times s
-// (rounded once), whenever any jet is selected.  Branch-free, two jets per
-// step (both LDS reads in flight).
-template <int G, bool EXT, typename WL>
+// order of the definition.  ptv = pt * s, or with JM (shifted energies)
+// pt * (1 + s * d) with the jet's shift d from LDS.  For ptv = pt * s the
+// maximum needs no per-scale work: for s > 0, rounding pt * s is monotone
+// in pt, so the selected jets are those above a pt bound and the largest
+// selected pt * s is the largest cleaned pt times s (rounded once), whenever
+// any jet is selected; with JM the factor differs per jet and the maximum is
+// taken per scale.  Branch-free, two jets per step (both LDS reads in
+// flight).
+template <int G, bool EXT, bool JM, typename WL>
 __device__ __forceinline__ void walk_jets(const WL &L, int j0, int j1, const float (&sc)[G], float jet_pt,
                                           float (&ht)[G], float (&lead)[G], int (&nj)[G], int (&nb)[G]) {
     float pmax = -INFINITY;
@@ -356,29 +423,50 @@ __device__ __forceinline__ void walk_jets(const WL &L, int j0, int j1, const flo
         ht[g] = 0.0f;
         nj[g] = 0;
         nb[g] = 0;
+        lead[g] = -INFINITY;
     }
-    auto step = [&](float p, int bt) {
+    auto step = [&](float p, float d, int bt) {
         pmax = fmaxf(pmax, p);  // NaN (removed jet) leaves it unchanged
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            const float x = p * sc[g];
+            const float f = JM ? 1.0f + sc[g] * d : sc[g];
+            const float x = p * f;
             const bool sel = x > jet_pt;
             const float hs = ht[g] + x;
             ht[g] = sel ? hs : ht[g];
             nj[g] += sel ? 1 : 0;
+            if (JM) lead[g] = sel ? fmaxf(lead[g], x) : lead[g];
             if (EXT) nb[g] += sel ? bt : 0;
         }
     };
     int k = j0;
     for (; k + 2 <= j1; k += 2) {
         const float p0 = L.jr[k].pt, p1 = L.jr[k + 1].pt;
+        const float d0 = JM ? L.jd[k] : 0.0f, d1 = JM ? L.jd[k + 1] : 0.0f;
         const int b0 = EXT ? L.bt[k] : 0, b1 = EXT ? L.bt[k + 1] : 0;
-        step(p0, b0);
-        step(p1, b1);
+        step(p0, d0, b0);
+        step(p1, d1, b1);
     }
-    if (k < j1) step(L.jr[k].pt, EXT ? static_cast<int>(L.bt[k]) : 0);
+    if (k < j1) step(L.jr[k].pt, JM ? L.jd[k] : 0.0f, EXT ? static_cast<int>(L.bt[k]) : 0);
+    if (!JM) {
 #pragma unroll
-    for (int g = 0; g < G; ++g) lead[g] = nj[g] > 0 ? pmax * sc[g] : -INFINITY;
+        for (int g = 0; g < G; ++g) lead[g] = nj[g] > 0 ? pmax * sc[g] : -INFINITY;
+    }
+}
+
+// Upper bounds, valid at every scale in [smin, smax] of a query with shifted
+// energies, of an event's selected and b-tagged jet counts: jets whose
+// largest pt * (1 + s * d) over that range exceeds jet_pt.
+template <bool EXT, typename WL>
+__device__ __forceinline__ void walk_shift_bound(const WL &L, int j0, int j1, float smin, float smax, float jet_pt,
+                                                 int &nj, int &nb) {
+    nj = 0;
+    nb = 0;
+    for (int k = j0; k < j1; ++k) {
+        const bool sel = shifted_pt_bound(L.jr[k].pt, L.jd[k], smin, smax) > jet_pt;
+        nj += sel ? 1 : 0;
+        if (EXT) nb += sel ? static_cast<int>(L.bt[k]) : 0;
+    }
 }
 
 // The same reductions for one scale s when the cone test already stored
@@ -430,11 +518,12 @@ __device__ __forceinline__ TileBounds tile_bounds(const DT &D, bool has_el, int6
 }
 
 // Compacts the selected objects of a tile (sel per slot k of this lane) into
-// (eta, phi) arrays in tile order; pre[m] = number of selected objects before
-// object m, pre[n] = total.
-template <int K>
+// (eta, phi) arrays in tile order (and, with V3, a third value into o3);
+// pre[m] = number of selected objects before object m, pre[n] = total.
+template <int K, bool V3 = false>
 __device__ __forceinline__ void compact(const bool (&sel)[K], const float (&eta)[K], const float (&phi)[K], int n,
-                                        int lane, float *oeta, float *ophi, uint16_t *pre) {
+                                        int lane, float *oeta, float *ophi, uint16_t *pre,
+                                        const float *v3 = nullptr, float *o3 = nullptr) {
     int run = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -447,6 +536,7 @@ __device__ __forceinline__ void compact(const bool (&sel)[K], const float (&eta)
         if (sel[k]) {
             oeta[before] = eta[k];
             ophi[before] = phi[k];
+            if (V3) o3[before] = v3[k];
         }
         run += __popcll(bal);
     }
@@ -465,13 +555,18 @@ __device__ __forceinline__ void compact(const bool (&sel)[K], const float (&eta)
 // whether the event was walked and whether it passed) to P.rec -- the
 // intermediate values of the pass, for checking them one by one.  Product
 // launches use DBG = false; the arithmetic is the same in both.
-template <typename T, bool EXT, int WAVES, int EVPL, bool LDSH, bool MS, bool DBG>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(MS ? 2 : (EXT ? 4 : 6)))) void
+// LK: the lookup corrections of Sec. IV -- event weights from the pileup and
+// muon scale-factor lookup histograms, jet energies shifted by an
+// interpolated table (jes_mode 1) -- and the sums of squared weights; a
+// query without lookups runs exactly as in the kernels without LK.
+template <typename T, bool EXT, int WAVES, int EVPL, bool LDSH, bool MS, bool DBG, bool LK>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(MS ? 2 : (EXT || LK ? 4 : 6)))) void
 pipeline_kernel(PipeArgs P) {
     using C = Caps<EVPL, EXT>;
     constexpr int TW = C::TW, JK = C::JK, MK = C::MK, EK = C::EK;
-    __shared__ WaveLds<EVPL, EXT> wl[WAVES];
-    extern __shared__ double dyn[];  // [sumw | counts (u32) | edges | scales] per workgroup
+    __shared__ WaveLds<EVPL, EXT, LK> wl[WAVES];
+    // per workgroup: [sumw | sumw2 (LK) | counts (u32) | edges | scales]
+    extern __shared__ double dyn[];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -479,11 +574,13 @@ pipeline_kernel(PipeArgs P) {
     auto &L = wl[wave];
 
     double *sw_s = dyn;
-    uint32_t *c_s = reinterpret_cast<uint32_t *>(dyn + (LDSH ? P.ds_slots : 0));
+    double *sw2_s = dyn + (LDSH ? P.ds_slots : 0);
+    uint32_t *c_s = reinterpret_cast<uint32_t *>(sw2_s + ((LDSH && LK) ? P.ds_slots : 0));
     float *e_s = reinterpret_cast<float *>(c_s + (LDSH ? P.ds_slots : 0));
     if (LDSH) {
         for (int i = tid; i < P.ds_slots; i += 64 * WAVES) {
             sw_s[i] = 0.0;
+            if (LK) sw2_s[i] = 0.0;
             c_s[i] = 0u;
         }
     }
@@ -521,13 +618,15 @@ pipeline_kernel(PipeArgs P) {
         const int64_t c_t1 = CH.t0 + min<int64_t>(my1 - CH.pre, CH.t1 - CH.t0);
         if (c_t1 <= c_t0) continue;
         const auto &D = as_const(P.ds)[CH.d];  // read in place, like the query table
-        HistSink<LDSH> sink;
+        HistSink<LDSH, LK> sink;
         if (LDSH) {
             sink.sw = sw_s;
             sink.c32 = c_s;
+            sink.sw2 = (LK && P.sumw2) ? sw2_s : nullptr;
         } else {
             sink.sw = P.sumw + D.hist0;
             sink.c64 = P.counts + D.hist0;
+            sink.sw2 = (LK && P.sumw2) ? P.sumw2 + D.hist0 : nullptr;
         }
         const bool has_iso = D.miso != nullptr;
         const bool has_el = EXT && D.eoff != nullptr;
@@ -538,6 +637,7 @@ pipeline_kernel(PipeArgs P) {
         struct Raw {
             uint32_t j0[EVPL], j1[EVPL], m0[EVPL], m1[EVPL], l0[EVPL], l1[EVPL];
             float w[EVPL];
+            float npu[LK ? EVPL : 1];
             float jpt[JK], jeta[JK], jphi[JK], jbt[EXT ? JK : 1];
             float mpt[MK], meta[MK], mphi[MK], miso[MK];
             float lpt[EK], leta[EK], lphi[EK];
@@ -557,12 +657,15 @@ pipeline_kernel(PipeArgs P) {
             const int nj = static_cast<int>(b.J1 - b.J0), nm = static_cast<int>(b.M1 - b.M0);
             const int nl = static_cast<int>(b.L1 - b.L0);
             const float *wp = D.w ? D.w + e0 : nullptr;
+            const float *pp = LK && D.npu ? D.npu + e0 : nullptr;
 #pragma unroll
             for (int r = 0; r < EVPL; ++r) {
                 const int ev = lane + 64 * r;
                 R.j0[r] = R.j1[r] = R.m0[r] = R.m1[r] = R.l0[r] = R.l1[r] = 0;
                 R.w[r] = 1.0f;
+                if (LK) R.npu[LK ? r : 0] = 0.0f;
                 if (ev < ne) {
+                    if (LK && pp) R.npu[LK ? r : 0] = pp[ev];
                     R.j0[r] = lo32(D.joff + e0 + ev);
                     R.j1[r] = lo32(D.joff + e0 + ev + 1);
                     R.m0[r] = lo32(D.moff + e0 + ev);
@@ -625,6 +728,10 @@ pipeline_kernel(PipeArgs P) {
 #pragma unroll
             for (int r = 0; r < EVPL; ++r)
                 asm volatile("" ::"v"(R.j0[r]), "v"(R.j1[r]), "v"(R.m0[r]), "v"(R.m1[r]), "v"(R.w[r]));
+            if (LK) {
+#pragma unroll
+                for (int r = 0; r < EVPL; ++r) asm volatile("" ::"v"(R.npu[LK ? r : 0]));
+            }
 #pragma unroll
             for (int k = 0; k < JK; ++k) asm volatile("" ::"v"(R.jpt[k]), "v"(R.jeta[k]), "v"(R.jphi[k]));
 #pragma unroll
@@ -687,6 +794,14 @@ pipeline_kernel(PipeArgs P) {
                              : "+s"(mu_pt), "+s"(mu_abseta), "+s"(mu_iso), "+s"(el_pt), "+s"(el_abseta),
                                "+s"(jet_pt), "+s"(thr2), "+s"(jet_abseta), "+s"(smax), "+s"(btag), "+s"(min_mu),
                                "+s"(min_jet), "+s"(min_b));
+                // lookup corrections of this query (LK kernels): which are on,
+                // the tables as axes over the edge table
+                const bool use_pu = LK && Q.pu_nb > 0 && D.npu != nullptr;
+                const bool use_sf = LK && Q.sf_nb > 0;
+                const bool shift = LK && Q.jes_mode == 1;
+                const float smin = LK ? Q.smin : 0.0f;
+                LkAxes ax{};
+                if (LK) ax = lk_axes(Q, edges);
                 // ---- 2. lepton selection; selected leptons compacted into LDS
                 // (all compares evaluated: no branches per slot)
                 {
@@ -695,7 +810,16 @@ pipeline_kernel(PipeArgs P) {
                     for (int k = 0; k < MK; ++k)
                         sel[k] = (lane + 64 * k < nm) & (mpt[k] > mu_pt) & (fabsf(meta[k]) < mu_abseta) &
                                  (!has_iso | (miso[k] < mu_iso));
-                    compact<MK>(sel, meta, mphi, nm, lane, L.seta, L.sphi, L.u.p.mpre);
+                    if (use_sf) {
+                        // each selected muon's scale factor, compacted beside it
+                        float sfv[MK];
+#pragma unroll
+                        for (int k = 0; k < MK; ++k)
+                            sfv[k] = sel[k] ? lookup_bin(ax.sf, edges + Q.sf_c, mpt[k]) : 1.0f;
+                        compact<MK, true>(sel, meta, mphi, nm, lane, L.seta, L.sphi, L.u.p.mpre, sfv, L.ssf);
+                    } else {
+                        compact<MK>(sel, meta, mphi, nm, lane, L.seta, L.sphi, L.u.p.mpre);
+                    }
                 }
                 if (EXT) {
                     bool sel[EK];
@@ -710,13 +834,22 @@ pipeline_kernel(PipeArgs P) {
                 // few jets before any cut) gets empty ranges: its jets' cone
                 // test is not needed
                 int nmu[EVPL];
+                float wq[EVPL];  // the event weight of this query
 #pragma unroll
                 for (int r = 0; r < EVPL; ++r) {
                     nmu[r] = 0;
+                    wq[r] = wv[r];
                     const int ev = lane + 64 * r;
                     if (ev < ne) {
                         const int s0 = L.u.p.mpre[mb[r]];
                         nmu[r] = L.u.p.mpre[me[r]] - s0;
+                        if (use_pu) wq[r] = wq[r] * lookup_bin(ax.pu, edges + Q.pu_c, R.npu[LK ? r : 0]);
+                        if (use_sf) {
+                            // product of the selected muons' scale factors, in order from 1
+                            float prod = 1.0f;
+                            for (int i = s0; i < s0 + nmu[r]; ++i) prod = prod * L.ssf[i];
+                            wq[r] = wq[r] * prod;
+                        }
                         const bool elig = nmu[r] >= min_mu && je[r] - jb[r] >= min_jet;
                         constexpr int CS = C::PACK ? 8 : 16;  // count shift
                         uint32_t pk = static_cast<uint32_t>(s0) | (static_cast<uint32_t>(elig ? nmu[r] : 0) << CS);
@@ -787,8 +920,11 @@ pipeline_kernel(PipeArgs P) {
                         const int k = k0 + b;
                         const int j = lane + 64 * k;
                         if (k >= JK || j >= nj) continue;
-                        const bool need =
-                            fabsf(jeta[k]) < jet_abseta && (jet_pt < 0.0f || jpt[k] * smax > jet_pt);
+                        // with shifted energies, the jet's shift and the largest
+                        // energy it takes over the query's scales
+                        const float dsh = shift ? jes_shift(ax, edges, Q.jd, jpt[k], jeta[k]) : 0.0f;
+                        const float ub = shift ? shifted_pt_bound(jpt[k], dsh, smin, smax) : jpt[k] * smax;
+                        const bool need = fabsf(jeta[k]) < jet_abseta && (jet_pt < 0.0f || ub > jet_pt);
                         const int c0 = static_cast<int>(C::PACK ? (pk[b] & 0xffu) : (pk[b] & 0xffffu));
                         const int cn = need ? static_cast<int>(C::PACK ? ((pk[b] >> 8) & 0xffu) : (pk[b] >> 16)) : 0;
                         bool hit = (cn >= 1 & delta_r2(jeta[k], jphi[k], e0[b], p0[b]) <= thr2) |
@@ -818,10 +954,14 @@ pipeline_kernel(PipeArgs P) {
                         const bool ok = need && !hit;
                         const bool tag = has_bt && jbt[EXT ? k : 0] > btag;
                         if (zsel) {
-                            L.jr[j].pt = ok ? jpt[k] * smax : 0.0f;
+                            // one scale s (= smax): the jet's energy pt * s, or
+                            // pt * (1 + s * d) when shifted
+                            const float f = shift ? 1.0f + smax * dsh : smax;
+                            L.jr[j].pt = ok ? jpt[k] * f : 0.0f;
                             if (EXT) L.bt[j] = (ok && tag) ? 1 : 0;
                         } else {
                             L.jr[j].pt = ok ? jpt[k] : __builtin_nanf("");
+                            if (LK) L.jd[LK ? j : 0] = dsh;
                             if (EXT) L.bt[j] = tag ? 1 : 0;
                         }
                     }
@@ -847,17 +987,20 @@ pipeline_kernel(PipeArgs P) {
                         const bool elig = lane + 64 * r < ne && nmu[r] >= min_mu && je[r] - jb[r] >= min_jet;
                         float ht[1], lead[1];
                         int njs[1], nbt[1];
+                        const int jend = elig ? je[r] : jb[r];
                         if (zsel)
-                            walk_selected<EXT>(L, jb[r], elig ? je[r] : jb[r], ht[0], lead[0], njs[0], nbt[0]);
+                            walk_selected<EXT>(L, jb[r], jend, ht[0], lead[0], njs[0], nbt[0]);
+                        else if (shift)
+                            walk_jets<1, EXT, true>(L, jb[r], jend, sc, jet_pt, ht, lead, njs, nbt);
                         else
-                            walk_jets<1, EXT>(L, jb[r], elig ? je[r] : jb[r], sc, jet_pt, ht, lead, njs, nbt);
+                            walk_jets<1, EXT, false>(L, jb[r], jend, sc, jet_pt, ht, lead, njs, nbt);
                         const bool pass[1] = {elig && njs[0] >= min_jet && nbt[0] >= min_b};
                         if (DBG && lane + 64 * r < ne)
                             *rec_at(P, Q.scale0, D.ev0 + e0 + lane + 64 * r) = hepk_event_record{
-                                nmu[r], njs[0], nbt[0], elig ? (pass[0] ? 3 : 2) : 1, ht[0], lead[0]};
+                                nmu[r], njs[0], nbt[0], elig ? (pass[0] ? 3 : 2) : 1, ht[0], lead[0], wq[r], 0};
                         if (pass[0]) {
                             const float xs[3] = {ht[0], lead[0], static_cast<float>(njs[0])};
-                            fill(xs, pass, 0, static_cast<double>(wv[r]));
+                            fill(xs, pass, 0, static_cast<double>(wq[r]));
                         }
                     }
                 } else {
@@ -883,7 +1026,10 @@ pipeline_kernel(PipeArgs P) {
                         if (prefilter && elig) {
                             float ht1[1], lead1[1];
                             int nj1[1], nb1[1];
-                            walk_jets<1, EXT>(L, jb[r], je[r], smaxa, jet_pt, ht1, lead1, nj1, nb1);
+                            if (shift)
+                                walk_shift_bound<EXT>(L, jb[r], je[r], smin, smax, jet_pt, nj1[0], nb1[0]);
+                            else
+                                walk_jets<1, EXT, false>(L, jb[r], je[r], smaxa, jet_pt, ht1, lead1, nj1, nb1);
                             elig = nj1[0] >= min_jet && nb1[0] >= min_b;
                         }
                         if (DBG && lane + 64 * r < ne) {
@@ -894,6 +1040,8 @@ pipeline_kernel(PipeArgs P) {
                             for (int v = 0; v < Q.n_scale; ++v) {
                                 hepk_event_record *o = rec_at(P, Q.scale0 + v, ge);
                                 o->n_mu = nmu[r];
+                                o->w = wq[r];
+                                o->reserved = 0;
                                 if (!elig) {
                                     o->n_jet = 0;
                                     o->n_b = 0;
@@ -914,7 +1062,7 @@ pipeline_kernel(PipeArgs P) {
                             const uint32_t ev = static_cast<uint32_t>(lane + 64 * r);
                             L.u.w.evjr[at] = static_cast<uint32_t>(jb[r]) | (static_cast<uint32_t>(je[r]) << 16) |
                                              (DBG ? (((ev & 63u) << 10) | ((ev >> 6) << 26)) : 0u);
-                            L.u.w.evw[at] = wv[r];
+                            L.u.w.evw[at] = wq[r];
                         }
                         nel += __popcll(bal);
                     }
@@ -933,8 +1081,11 @@ pipeline_kernel(PipeArgs P) {
                         for (int u = 0; u < kG; ++u) sc[u] = scl[min(g * kG + u, V - 1)];
                         float ht[kG], lead[kG];
                         int njs[kG], nbt[kG];
-                        walk_jets<kG, EXT>(L, static_cast<int>(jr & 0x3ffu), static_cast<int>((jr >> 16) & 0x3ffu), sc,
-                                           jet_pt, ht, lead, njs, nbt);
+                        const int wj0 = static_cast<int>(jr & 0x3ffu), wj1 = static_cast<int>((jr >> 16) & 0x3ffu);
+                        if (shift)
+                            walk_jets<kG, EXT, true>(L, wj0, wj1, sc, jet_pt, ht, lead, njs, nbt);
+                        else
+                            walk_jets<kG, EXT, false>(L, wj0, wj1, sc, jet_pt, ht, lead, njs, nbt);
                         bool pass[kG], any = false;
 #pragma unroll
                         for (int u = 0; u < kG; ++u) {
@@ -1003,7 +1154,7 @@ pipeline_kernel(PipeArgs P) {
             }
             if (oversize(B)) {
                 const DsDev Dc = D;
-                if (lane == 0) event_direct<T, EXT, LDSH, DBG>(P, Dc, e, edges, sink);
+                if (lane == 0) event_direct<T, EXT, LDSH, DBG, LK>(P, Dc, e, edges, sink);
             } else {
                 Raw R;
                 issue(e, n, B, R);
@@ -1033,8 +1184,10 @@ pipeline_kernel(PipeArgs P) {
                             if (c) {
                                 atomic_add_u64(&P.counts[gs + i], c);
                                 atomic_add_f64(&P.sumw[gs + i], sw_s[ls + i]);
+                                if (LK && P.sumw2) atomic_add_f64(&P.sumw2[gs + i], sw2_s[ls + i]);
                                 c_s[ls + i] = 0u;
                                 sw_s[ls + i] = 0.0;
+                                if (LK) sw2_s[ls + i] = 0.0;
                             }
                         }
                     }
@@ -1046,32 +1199,35 @@ pipeline_kernel(PipeArgs P) {
 
 using KernelFn = void (*)(PipeArgs);
 
-template <typename T, bool EXT, int WAVES, int EVPL, bool LDSH, bool MS, bool DBG>
+template <typename T, bool EXT, int WAVES, int EVPL, bool LDSH, bool MS, bool DBG, bool LK>
 static KernelFn kfn() {
-    return reinterpret_cast<KernelFn>(&pipeline_kernel<T, EXT, WAVES, EVPL, LDSH, MS, DBG>);
+    return reinterpret_cast<KernelFn>(&pipeline_kernel<T, EXT, WAVES, EVPL, LDSH, MS, DBG, LK>);
 }
 
-template <typename T, bool EXT, int WAVES, int EVPL, bool MS, bool DBG>
+template <typename T, bool EXT, int WAVES, int EVPL, bool MS, bool DBG, bool LK>
 static KernelFn pick_h(bool ldsh) {
-    return ldsh ? kfn<T, EXT, WAVES, EVPL, true, MS, DBG>() : kfn<T, EXT, WAVES, EVPL, false, MS, DBG>();
+    return ldsh ? kfn<T, EXT, WAVES, EVPL, true, MS, DBG, LK>() : kfn<T, EXT, WAVES, EVPL, false, MS, DBG, LK>();
 }
 
-template <typename T, bool EXT, bool MS, bool DBG>
+// LK kernels exist for one event per thread only (the plan takes that shape
+// for queries with lookups).
+template <typename T, bool EXT, bool MS, bool DBG, bool LK>
 static KernelFn pick_shape(int block, int evpt, bool ldsh) {
-    if (block == 1024) return pick_h<T, EXT, 16, 1, MS, DBG>(ldsh);  // one event per thread only
+    if (block == 1024) return pick_h<T, EXT, 16, 1, MS, DBG, LK>(ldsh);  // one event per thread only
+    if (LK) return block == 512 ? pick_h<T, EXT, 8, 1, MS, DBG, LK>(ldsh) : pick_h<T, EXT, 4, 1, MS, DBG, LK>(ldsh);
     if (block == 512)
-        return evpt == 2 ? pick_h<T, EXT, 8, 2, MS, DBG>(ldsh) : pick_h<T, EXT, 8, 1, MS, DBG>(ldsh);
-    return evpt == 2 ? pick_h<T, EXT, 4, 2, MS, DBG>(ldsh) : pick_h<T, EXT, 4, 1, MS, DBG>(ldsh);
+        return evpt == 2 ? pick_h<T, EXT, 8, 2, MS, DBG, LK>(ldsh) : pick_h<T, EXT, 8, 1, MS, DBG, LK>(ldsh);
+    return evpt == 2 ? pick_h<T, EXT, 4, 2, MS, DBG, LK>(ldsh) : pick_h<T, EXT, 4, 1, MS, DBG, LK>(ldsh);
 }
 
-// The kernel for a launch shape; each (MS, DBG) pair is instantiated in its
-// own translation unit (they compile in parallel).
-template <bool MS, bool DBG>
+// The kernel for a launch shape; each (MS, DBG, LK) triple is instantiated
+// in its own translation unit (they compile in parallel).
+template <bool MS, bool DBG, bool LK>
 KernelFn pick_kernel(int dtype, bool ext, int block, int evpt, bool ldsh) {
-    if (dtype == HEPK_F16) return ext ? pick_shape<_Float16, true, MS, DBG>(block, evpt, ldsh)
-                                      : pick_shape<_Float16, false, MS, DBG>(block, evpt, ldsh);
-    return ext ? pick_shape<float, true, MS, DBG>(block, evpt, ldsh)
-               : pick_shape<float, false, MS, DBG>(block, evpt, ldsh);
+    if (dtype == HEPK_F16) return ext ? pick_shape<_Float16, true, MS, DBG, LK>(block, evpt, ldsh)
+                                      : pick_shape<_Float16, false, MS, DBG, LK>(block, evpt, ldsh);
+    return ext ? pick_shape<float, true, MS, DBG, LK>(block, evpt, ldsh)
+               : pick_shape<float, false, MS, DBG, LK>(block, evpt, ldsh);
 }
 
 // LDS for the workgroup's private histograms: up to 64 KiB (60 histograms of

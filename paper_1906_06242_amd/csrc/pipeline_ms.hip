@@ -4,5 +4,5 @@
 #include "pipeline_kernel.hpp"
 
 namespace hepk {
-template KernelFn pick_kernel<true, false>(int, bool, int, int, bool);
+template KernelFn pick_kernel<true, false, false>(int, bool, int, int, bool);
 }  // namespace hepk

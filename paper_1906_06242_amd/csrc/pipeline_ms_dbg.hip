@@ -4,5 +4,5 @@
 #include "pipeline_kernel.hpp"
 
 namespace hepk {
-template KernelFn pick_kernel<true, true>(int, bool, int, int, bool);
+template KernelFn pick_kernel<true, true, false>(int, bool, int, int, bool);
 }  // namespace hepk

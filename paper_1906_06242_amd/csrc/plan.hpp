@@ -13,6 +13,7 @@ struct hepk_plan_s {
     bool ext = false;
     bool shared = false;
     bool ms = false;  // some query slot holds several jet-energy scales
+    bool lk = false;  // lookup-correction kernels (queries with lookups, or sums of squared weights)
     hepk_tune tune{};
     int grid = 0;
     hepk::KernelFn fn_lds = nullptr, fn_glob = nullptr;
@@ -78,9 +79,10 @@ int plan_build(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_
 // at base (laid out as lay).
 void plan_bind(hepk_plan p, char *base, const TableLayout &lay);
 
-// The launch over chunks [c0, c1) (per-event records into rec when not NULL).
+// The launch over chunks [c0, c1) (per-event records into rec when not NULL,
+// squared weights into sumw2 when not NULL: lookup plans only).
 Launch make_launch(hepk_plan p, int32_t c0, int32_t c1, double *sumw, uint64_t *counts,
-                   hepk_event_record *rec = nullptr);
+                   hepk_event_record *rec = nullptr, double *sumw2 = nullptr);
 
 // Checks the launch's LDS against the device's and enqueues it.
 int run_launch(const Launch &L, hipStream_t stream);

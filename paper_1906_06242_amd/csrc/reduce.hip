@@ -1,6 +1,6 @@
 // hepk_reduce: per-event segmented reductions over jagged content
-// (Sec. III: the H_T kernel of Listing 1 and the count/sum/max/min-within-
-// offsets kernels).
+// (Sec. III: the H_T kernel of Listing 1, the count/sum/max/min-within-
+// offsets kernels, and the generic pairwise operator taken as the product).
 //
 // Each wavefront owns tiles of 64 consecutive events and works through them
 // without waiting for the rest of its workgroup.  For one tile it reads the
@@ -22,7 +22,7 @@ constexpr int RB = 256;  // threads per workgroup; events per tile of the offset
 constexpr int RW = RB / 64;
 constexpr int RK = 8;    // objects per lane staged for one tile (512 per tile)
 
-enum { R_COUNT = 0, R_SUM = 1, R_MAX = 2, R_MIN = 3 };
+enum { R_COUNT = 0, R_SUM = 1, R_MAX = 2, R_MIN = 3, R_PROD = 4 };
 
 // Inclusive scan of one int64 per thread over a workgroup of RB threads.
 __device__ int64_t block_inclusive_scan(int64_t v, int64_t *buf) {
@@ -50,6 +50,7 @@ template <int OP>
 struct Acc {
     int32_t cnt = 0;
     float sum = 0.0f;
+    float prod = 1.0f;
     float best = (OP == R_MAX) ? -INFINITY : INFINITY;
     int32_t bi = -1;
     __device__ __forceinline__ void add(float v, bool keep, int32_t k) {
@@ -58,6 +59,8 @@ struct Acc {
             ++cnt;
         } else if (OP == R_SUM) {
             sum = sum + v;
+        } else if (OP == R_PROD) {
+            prod = prod * v;
         } else {
             const bool better = (OP == R_MAX) ? (v > best) : (v < best);
             if (bi < 0 || better) {
@@ -177,6 +180,8 @@ __global__ __launch_bounds__(RB) void reduce_kernel(const int64_t *__restrict__ 
                 static_cast<int32_t *>(out)[e] = r.cnt;
             } else if (OP == R_SUM) {
                 static_cast<float *>(out)[e] = r.sum;
+            } else if (OP == R_PROD) {
+                static_cast<float *>(out)[e] = r.prod;
             } else if (index_only) {
                 static_cast<int32_t *>(out)[e] = r.bi;
             } else {
@@ -286,7 +291,7 @@ extern "C" int hepk_reduce(int32_t op, const int64_t *offsets, int64_t n_events,
                            int32_t *out_arg, int64_t *offsets_out, hipStream_t stream) {
     using namespace hepk;
     clear_error();
-    HEPK_REQUIRE(op >= HEPK_COUNT && op <= HEPK_ARGMIN, "hepk_reduce: bad op %d", op);
+    HEPK_REQUIRE(op >= HEPK_COUNT && op <= HEPK_PROD, "hepk_reduce: bad op %d", op);
     HEPK_REQUIRE(n_events >= 0, "hepk_reduce: n_events < 0");
     HEPK_REQUIRE(offsets, "hepk_reduce: offsets is NULL");
     HEPK_REQUIRE(n_events == 0 || out, "hepk_reduce: out is NULL");
@@ -312,6 +317,12 @@ extern "C" int hepk_reduce(int32_t op, const int64_t *offsets, int64_t n_events,
                                                 stream)
                : launch_reduce<float, R_SUM>(offsets, n_events, content, obj_mask, evt_mask, out, nullptr, 0,
                                              stream);
+        break;
+    case HEPK_PROD:
+        rc = h ? launch_reduce<_Float16, R_PROD>(offsets, n_events, content, obj_mask, evt_mask, out, nullptr, 0,
+                                                 stream)
+               : launch_reduce<float, R_PROD>(offsets, n_events, content, obj_mask, evt_mask, out, nullptr, 0,
+                                              stream);
         break;
     case HEPK_MAX:
     case HEPK_ARGMAX:

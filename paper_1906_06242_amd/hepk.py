@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(PKG, "libhepk.so")
 OK, EINVAL, EHIP, EUNSUPPORTED, ENOMEM = 0, -1, -2, -3, -4
 F32, F16, I32 = 0, 1, 2
 GT, GE, LT, LE, ABS_LT, ABS_LE = range(6)
-COUNT, SUM, MAX, MIN, ARGMAX, ARGMIN = range(6)
+COUNT, SUM, MAX, MIN, ARGMAX, ARGMIN, PROD = range(7)
 MAX_CUTS = 8
 
 EXPORTS = (
@@ -26,11 +26,13 @@ EXPORTS = (
     "hepk_plan_hist_offset", "hepk_plan_get_tune", "hepk_pipeline", "hepk_pipeline_range",
     "hepk_pipeline_graph", "hepk_autotune", "hepk_plan_destroy", "hepk_last_error", "hepk_abi_version",
     "hepk_plan_debug_layout", "hepk_pipeline_debug",
+    "hepk_hist_fill_w2", "hepk_get_bin_contents", "hepk_interp", "hepk_jes_delta",
+    "hepk_pipeline_w2",
 )
 
-# hepk_event_record, as a numpy structured dtype (24 bytes)
+# hepk_event_record, as a numpy structured dtype (32 bytes)
 EVENT_RECORD = [("n_mu", "<i4"), ("n_jet", "<i4"), ("n_b", "<i4"), ("state", "<i4"),
-                ("ht", "<f4"), ("lead", "<f4")]
+                ("ht", "<f4"), ("lead", "<f4"), ("w", "<f4"), ("reserved", "<i4")]
 REC_SKIPPED, REC_FAILS, REC_PASSES = 1, 2, 3
 
 
@@ -58,7 +60,7 @@ class Collection(C.Structure):
 class DatasetS(C.Structure):
     _fields_ = [("n_events", C.c_int64), ("dtype", C.c_int32),
                 ("jets", Collection), ("muons", Collection), ("electrons", Collection),
-                ("weights", C.c_void_p)]
+                ("weights", C.c_void_p), ("npu", C.c_void_p)]
 
 
 class QueryS(C.Structure):
@@ -68,7 +70,11 @@ class QueryS(C.Structure):
                 ("dr", C.c_float), ("btag", C.c_float),
                 ("min_mu", C.c_int32), ("min_jet", C.c_int32), ("min_b", C.c_int32),
                 ("n_scale", C.c_int32), ("scales", C.c_void_p),
-                ("edges", C.c_void_p * 3), ("nbins", C.c_int32 * 3)]
+                ("edges", C.c_void_p * 3), ("nbins", C.c_int32 * 3),
+                ("pu_edges", C.c_void_p), ("pu_contents", C.c_void_p), ("pu_nbins", C.c_int32),
+                ("sf_edges", C.c_void_p), ("sf_contents", C.c_void_p), ("sf_nbins", C.c_int32),
+                ("jes_mode", C.c_int32), ("jes_eta_edges", C.c_void_p), ("jes_pt_edges", C.c_void_p),
+                ("jes_delta", C.c_void_p), ("jes_n_eta", C.c_int32), ("jes_n_pt", C.c_int32)]
 
 
 class Tune(C.Structure):
@@ -86,7 +92,7 @@ class Tune(C.Structure):
 
 
 class PlanOpts(C.Structure):
-    _fields_ = [("tune", Tune), ("shared_hist", C.c_int32), ("reserve_bins", C.c_int32)]
+    _fields_ = [("tune", Tune), ("shared_hist", C.c_int32), ("reserve_bins", C.c_int32), ("sumw2", C.c_int32)]
 
 
 _lib = None
@@ -106,6 +112,10 @@ def load(path: str = LIB_PATH):
     lib.hepk_reduce.argtypes = [i32, vp, i64, vp, i32, vp, vp, vp, vp, vp, vp]
     lib.hepk_match_dr.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i32, i64, C.c_float, vp, vp, vp, vp]
     lib.hepk_hist_fill.argtypes = [vp, i32, vp, vp, i64, C.POINTER(Hist), vp]
+    lib.hepk_hist_fill_w2.argtypes = [vp, i32, vp, vp, i64, C.POINTER(Hist), vp, vp]
+    lib.hepk_get_bin_contents.argtypes = [vp, i32, i64, vp, i32, vp, vp, vp]
+    lib.hepk_interp.argtypes = [vp, i32, i64, vp, i32, vp, vp, vp]
+    lib.hepk_jes_delta.argtypes = [vp, vp, i32, i64, vp, i32, vp, i32, vp, vp, vp]
     lib.hepk_validate_offsets.argtypes = [vp, i64, i64, vp, vp]
     lib.hepk_stream_read.argtypes = [vp, i64, vp, vp]
     lib.hepk_plan_create.argtypes = [C.POINTER(DatasetS), i32, C.POINTER(QueryS), i32,
@@ -121,6 +131,7 @@ def load(path: str = LIB_PATH):
     lib.hepk_plan_hist_offset.argtypes = [vp, i32, i32, i32, i32, C.POINTER(i64), C.POINTER(i32)]
     lib.hepk_plan_get_tune.argtypes = [vp, C.POINTER(Tune)]
     lib.hepk_pipeline.argtypes = [vp, vp, vp, vp]
+    lib.hepk_pipeline_w2.argtypes = [vp, vp, vp, vp, vp]
     lib.hepk_plan_debug_layout.argtypes = [vp, i32, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     lib.hepk_pipeline_debug.argtypes = [vp, vp, vp, vp, vp]
     lib.hepk_plan_destroy.argtypes = [vp]
@@ -212,11 +223,46 @@ def match_dr(off_a, eta_a, phi_a, off_b, eta_b, phi_b, dr: float, mask_a=None, m
     return md, ix, cl
 
 
-def hist_fill(x, edges, sumw, counts, w=None, evt_mask=None, stream=None):
+def hist_fill(x, edges, sumw, counts, w=None, evt_mask=None, sumw2=None, stream=None):
+    """Accumulating weighted fill; with sumw2 also the squared weights (hepk_hist_fill_w2)."""
     h = Hist(_ptr(edges), edges.numel() - 1, _ptr(sumw), _ptr(counts))
-    _call("hepk_hist_fill", _ptr(x), dtype_code(x), _ptr(w), _ptr(evt_mask), x.numel(),
-          C.byref(h), _stream(stream))
+    if sumw2 is None:
+        _call("hepk_hist_fill", _ptr(x), dtype_code(x), _ptr(w), _ptr(evt_mask), x.numel(),
+              C.byref(h), _stream(stream))
+    else:
+        _call("hepk_hist_fill_w2", _ptr(x), dtype_code(x), _ptr(w), _ptr(evt_mask), x.numel(),
+              C.byref(h), _ptr(sumw2), _stream(stream))
     return sumw, counts
+
+
+def _f32_out(n: int, out):
+    import torch
+    return torch.empty(n, dtype=torch.float32, device="cuda") if out is None else out
+
+
+def get_bin_contents(x, edges, contents, out=None, stream=None):
+    """Content of the lookup-histogram slot holding each element (contents: nbins+2)."""
+    out = _f32_out(x.numel(), out)
+    _call("hepk_get_bin_contents", _ptr(x), dtype_code(x), x.numel(), _ptr(edges), edges.numel() - 1,
+          _ptr(contents), _ptr(out), _stream(stream))
+    return out
+
+
+def interp(x, edges, contents, out=None, stream=None):
+    """Linear interpolation between the lookup histogram's bin centres."""
+    out = _f32_out(x.numel(), out)
+    _call("hepk_interp", _ptr(x), dtype_code(x), x.numel(), _ptr(edges), edges.numel() - 1,
+          _ptr(contents), _ptr(out), _stream(stream))
+    return out
+
+
+def jes_delta(pt, eta, eta_edges, pt_edges, delta, out=None, stream=None):
+    """Jet-energy-scale shift per object from the (|eta| row, pt) table delta[n_eta, n_pt]."""
+    out = _f32_out(pt.numel(), out)
+    _call("hepk_jes_delta", _ptr(pt), _ptr(eta), dtype_code(pt), pt.numel(), _ptr(eta_edges),
+          eta_edges.numel() - 1, _ptr(pt_edges), pt_edges.numel() - 1, _ptr(delta), _ptr(out),
+          _stream(stream))
+    return out
 
 
 def validate_offsets(offsets, n_objects: int, stream=None) -> int:
@@ -262,6 +308,9 @@ class DeviceDataset:
                 self.tensors[f"{cname}.{k}"] = torch.from_numpy(v).to(device)
         w = ds.weight if ds.weight.size else np.ones(1, np.float32)
         self.tensors["weight"] = torch.from_numpy(w).to(device)
+        if getattr(ds, "npu", None) is not None:
+            npu = ds.npu if ds.npu.size else np.zeros(1, np.float32)
+            self.tensors["npu"] = torch.from_numpy(np.ascontiguousarray(npu, np.float32)).to(device)
 
     @classmethod
     def from_tensors(cls, t: dict) -> "DeviceDataset":
@@ -300,10 +349,12 @@ class DeviceDataset:
                               _ptr(self.t(f"{name}.eta")), _ptr(self.t(f"{name}.phi")),
                               _ptr(self.t(f"{name}.{extra}")) if extra else None)
         w = self.t("weight")
+        npu = self.t("npu")
         return DatasetS(self.n_events, F16 if self.content_dtype == "f16" else F32,
                         coll("jets", "btag" if self.t("jets.btag") is not None else None),
                         coll("muons", "iso"), coll("electrons", None),
-                        _ptr(w) + 4 * self.e0 if w is not None else None)
+                        _ptr(w) + 4 * self.e0 if w is not None else None,
+                        _ptr(npu) + 4 * self.e0 if npu is not None else None)
 
 
 def query_struct(q, keep: list) -> QueryS:
@@ -317,6 +368,20 @@ def query_struct(q, keep: list) -> QueryS:
     for h in range(3):
         qs.edges[h] = eds[h].ctypes.data
         qs.nbins[h] = len(eds[h]) - 1
+
+    def arr(a):
+        a = np.ascontiguousarray(a, np.float32)
+        keep.append(a)
+        return a.ctypes.data
+    if getattr(q, "pu", None) is not None:
+        qs.pu_edges, qs.pu_contents, qs.pu_nbins = arr(q.pu[0]), arr(q.pu[1]), len(q.pu[0]) - 1
+    if getattr(q, "sf", None) is not None:
+        qs.sf_edges, qs.sf_contents, qs.sf_nbins = arr(q.sf[0]), arr(q.sf[1]), len(q.sf[0]) - 1
+    if getattr(q, "jes", None) is not None:
+        ee, pe, d = q.jes
+        qs.jes_mode = 1
+        qs.jes_eta_edges, qs.jes_pt_edges, qs.jes_delta = arr(ee), arr(pe), arr(d)
+        qs.jes_n_eta, qs.jes_n_pt = len(ee) - 1, len(pe) - 1
     return qs
 
 
@@ -329,12 +394,12 @@ class Plan:
     """
 
     def __init__(self, datasets: List[DeviceDataset], queries, tune: Optional[dict] = None,
-                 shared_hist: bool = False, reserve_bins: int = 0):
+                 shared_hist: bool = False, reserve_bins: int = 0, sumw2: bool = False):
         keep = []
         dsa = (DatasetS * len(datasets))(*[d.struct() for d in datasets])
         qa = (QueryS * len(queries))(*[query_struct(q, keep) for q in queries])
         opts = PlanOpts(Tune.of(tune) if tune is not None else Tune(0, 0, 0, 0),
-                        1 if shared_hist else 0, reserve_bins)
+                        1 if shared_hist else 0, reserve_bins, 1 if sumw2 else 0)
         h = C.c_void_p()
         _call("hepk_plan_create_ex", dsa, len(datasets), qa, len(queries), C.byref(opts), C.byref(h))
         self.handle = h
@@ -368,6 +433,10 @@ class Plan:
     def run(self, sumw, counts, stream=None):
         _call("hepk_pipeline", self.handle, _ptr(sumw), _ptr(counts), _stream(stream))
 
+    def run_w2(self, sumw, sumw2, counts, stream=None):
+        """hepk_pipeline_w2: the pass that also sums squared weights."""
+        _call("hepk_pipeline_w2", self.handle, _ptr(sumw), _ptr(sumw2), _ptr(counts), _stream(stream))
+
     def run_range(self, d0: int, nd: int, sumw, counts, stream=None):
         _call("hepk_pipeline_range", self.handle, d0, nd, _ptr(sumw), _ptr(counts), _stream(stream))
 
@@ -379,7 +448,7 @@ class Plan:
         import torch
         n = C.c_int64()
         _call("hepk_plan_debug_layout", self.handle, 0, 0, None, None, C.byref(n))
-        raw = torch.full((max(1, n.value) * 6,), -1, dtype=torch.int32, device="cuda")
+        raw = torch.full((max(1, n.value) * 8,), -1, dtype=torch.int32, device="cuda")
         _call("hepk_pipeline_debug", self.handle, _ptr(sumw), _ptr(counts), _ptr(raw), _stream(stream))
         host_rec = raw.cpu().numpy().view(np.dtype(EVENT_RECORD))
         out = []

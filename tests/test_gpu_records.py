@@ -118,6 +118,7 @@ def check_records(ds, queries, tune=None, what=""):
             st = r["state"]
             assert np.all((st >= 1) & (st <= 3)), f"{tag}: {int(np.sum(st < 1))} records not written"
             assert np.array_equal(r["n_mu"], w["n_mu"]), f"{tag}: n_mu"
+            assert np.array_equal(u32(r["w"]), u32(w["weight"])), f"{tag}: event weight"
             walked = st >= 2
             n_walked += int(walked.sum())
             for f in ("n_jet", "n_b"):
