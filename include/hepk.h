@@ -399,6 +399,23 @@ int hepk_pipeline_range(hepk_plan p, int32_t d0, int32_t nd, double *sumw, uint6
  * graph launch each. */
 int hepk_pipeline_graph(hepk_plan p, double *sumw, uint64_t *counts, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the fused
+ * pass of hepk_plan_create + hepk_pipeline in one call that allocates
+ * nothing.  The tables a plan would upload (datasets, work chunks, queries,
+ * scales, bin edges) are copied, stream-ordered on `stream`, into a fixed
+ * device array of 1 MiB that the library holds per device until the process
+ * ends; tables larger than that are rejected with HEPK_EINVAL before anything
+ * is enqueued.  Same kernels, launch configuration (tune NULL: the default)
+ * and histogram layout as hepk_plan_create; accumulates into sumw/counts
+ * (hepk_plan_hist_slots entries of that plan).  Every call on a device
+ * shares its array: calls that overlap on one device (other streams or host
+ * threads) race; calls on one stream follow each other safely. */
+int hepk_pipeline_noalloc(const hepk_dataset *ds /* host, n_ds */, int32_t n_ds,
+                          const hepk_query *q /* host, n_query */, int32_t n_query,
+                          const hepk_tune *tune /* host, nullable */, double *sumw, uint64_t *counts,
+                          hipStream_t stream);
+
 /* Launch-configuration search (Sec. IV: kernel scheduling was the bottleneck
  * of the paper's GPU runs).  Times the fused pass over ds/q for every
  * candidate -- block 256/512 with 1 or 2 events per thread, block 1024 with

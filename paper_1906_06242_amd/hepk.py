@@ -27,7 +27,7 @@ EXPORTS = (
     "hepk_pipeline_graph", "hepk_autotune", "hepk_plan_destroy", "hepk_last_error", "hepk_abi_version",
     "hepk_plan_debug_layout", "hepk_pipeline_debug",
     "hepk_hist_fill_w2", "hepk_get_bin_contents", "hepk_interp", "hepk_jes_delta",
-    "hepk_pipeline_w2",
+    "hepk_pipeline_noalloc", "hepk_pipeline_w2",
 )
 
 # hepk_event_record, as a numpy structured dtype (32 bytes)
@@ -135,6 +135,8 @@ def load(path: str = LIB_PATH):
     lib.hepk_plan_debug_layout.argtypes = [vp, i32, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     lib.hepk_pipeline_debug.argtypes = [vp, vp, vp, vp, vp]
     lib.hepk_plan_destroy.argtypes = [vp]
+    lib.hepk_pipeline_noalloc.argtypes = [C.POINTER(DatasetS), i32, C.POINTER(QueryS), i32, C.POINTER(Tune),
+                                          vp, vp, vp]
     lib.hepk_last_error.restype = C.c_char_p
     lib.hepk_last_error.argtypes = []
     lib.hepk_abi_version.restype = C.c_int
@@ -500,6 +502,19 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def pipeline_noalloc(datasets: List[DeviceDataset], queries, sumw, counts, tune: Optional[dict] = None,
+                     stream=None):
+    """hepk_pipeline_noalloc: the fused pass without a plan (no device
+    allocation); histograms laid out as a Plan over the same datasets and
+    queries lays them out."""
+    keep = []
+    dsa = (DatasetS * len(datasets))(*[d.struct() for d in datasets])
+    qa = (QueryS * len(queries))(*[query_struct(q, keep) for q in queries])
+    t = C.byref(Tune.of(tune)) if tune is not None else None
+    _call("hepk_pipeline_noalloc", dsa, len(datasets), qa, len(queries), t, _ptr(sumw), _ptr(counts),
+          _stream(stream))
 
 
 def autotune(datasets: List[DeviceDataset], queries, reps: int = 5, stream=None):
