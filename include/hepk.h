@@ -56,7 +56,7 @@ typedef enum hepk_status {
     HEPK_ENOMEM = -4         /* device allocation failed */
 } hepk_status;
 
-typedef enum hepk_dtype { HEPK_F32 = 0, HEPK_F16 = 1, HEPK_I32 = 2 } hepk_dtype;
+typedef enum hepk_dtype { HEPK_F32 = 0, HEPK_F16 = 1, HEPK_I32 = 2, HEPK_U8 = 3 } hepk_dtype;
 
 /* v > t, v >= t, v < t, v <= t, |v| < t, |v| <= t */
 typedef enum hepk_cmp {
@@ -193,14 +193,84 @@ int hepk_jes_delta(const void *pt, const void *eta, int32_t dtype, int64_t n,
                    const float *pt_edges /* n_pt+1 */, int32_t n_pt, const float *delta /* n_eta*n_pt */,
                    float *out /* n */, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Positional kernels (Sec. III: get_in_offsets / set_in_offsets address the
+ * n-th element of every row; select_opposite_sign_muons is one of the
+ * specialised kernels) and compaction of a selected sub-collection.
+ * ------------------------------------------------------------------------- */
+
+/* For every event e with evt_mask[e] (NULL: all), the n-th (from 0) object of
+ * the event among those with obj_mask (NULL: all), n = idx[e] (idx NULL: the
+ * constant n; negative: none): out[e] = its content (F32 or F16, widened),
+ * out_index[e] (nullable) = its local index; events without such an object
+ * (or masked out) get out[e] = fill and out_index[e] = -1.  E.g. the leading
+ * jet's pt of pT-ordered jets is n = 0 over the selected jets. */
+int hepk_get_in_offsets(const int64_t *offsets /* N+1 */, int64_t n_events, const void *content /* M */,
+                        int32_t dtype, const uint8_t *obj_mask /* nullable, M */,
+                        const uint8_t *evt_mask /* nullable, N */, const int32_t *idx /* nullable, N */,
+                        int32_t n, float fill, float *out /* N */, int32_t *out_index /* nullable, N */,
+                        hipStream_t stream);
+
+/* The same object of every event is set to value in place: content F32
+ * (value) or U8 (1 when value != 0, else 0; e.g. building a mask of the
+ * first two selected jets with n = 0 then n = 1).  Other objects are left as
+ * they are. */
+int hepk_set_in_offsets(const int64_t *offsets /* N+1 */, int64_t n_events, void *content /* M */,
+                        int32_t dtype, const uint8_t *obj_mask /* nullable, M */,
+                        const uint8_t *evt_mask /* nullable, N */, const int32_t *idx /* nullable, N */,
+                        int32_t n, float value, hipStream_t stream);
+
+/* Per event, among the objects with obj_mask (NULL: all) taken in pT order
+ * (larger pt first; NaN pt after every number; equal pt by lower index): the
+ * first object that has a later object of opposite charge sign (a > 0 > b or
+ * a < 0 < b) and its first such partner get mask_out = 1, every other object
+ * of the event 0 (all 0 when no such pair).  pt F32 or F16, charge int32. */
+int hepk_select_opposite_sign(const int64_t *offsets /* N+1 */, int64_t n_events, const void *pt /* M */,
+                              int32_t dtype, const int32_t *charge /* M */, const uint8_t *obj_mask /* nullable, M */,
+                              uint8_t *mask_out /* M */, hipStream_t stream);
+
+/* Compaction: the objects with obj_mask (NULL: all), in order, written
+ * contiguously to out: the content of a collection whose offsets are
+ * offsets_out, the exclusive prefix counts of the kept objects per event
+ * (hepk_reduce COUNT with the same obj_mask and its offsets_out; N+1
+ * entries).  n_out (= offsets_out[N]) bounds the writes.  Elements of dtype
+ * F32/I32 (4 bytes), F16 (2) or U8 (1) are moved bit for bit. */
+int hepk_compact(const int64_t *offsets /* N+1 */, int64_t n_events, const void *content /* M */, int32_t dtype,
+                 const uint8_t *obj_mask /* nullable, M */, const int64_t *offsets_out /* N+1 */, int64_t n_out,
+                 void *out /* n_out */, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Top-quark candidate (Sec. IV high-level variable reconstruction: the jet
+ * triplet with invariant mass closest to M = 172 GeV).
+ * ------------------------------------------------------------------------- */
+
+/* Four-momenta from (pt, eta, phi, mass), float32:
+ * px = pt cos phi, py = pt sin phi, pz = pt sinh eta,
+ * E = sqrt(px^2 + py^2 + pz^2 + mass^2), with the device's float32 cos, sin
+ * and sinh (a few ulp; not bit-reproducible across machines). */
+int hepk_p4(const float *pt, const float *eta, const float *phi, const float *mass, int64_t n,
+            float *px, float *py, float *pz, float *en, hipStream_t stream);
+
+/* Per event, over the triplets i < j < k of objects with obj_mask (NULL:
+ * all): M = sqrt(E^2 - px^2 - py^2 - pz^2) of the summed four-momenta (sums
+ * (i + j) + k per component; products and differences each one float32
+ * rounding, left to right; a negative square gives 0; correctly rounded
+ * square root), the triplet with the smallest |M - target| (first in
+ * (i, j, k) order on ties; NaN distances never chosen).  out_mass[e] = its
+ * M (NaN if none), out_idx[3e .. 3e+2] = its local indices (-1 if none).
+ * Bit-reproducible: only +, -, *, sqrt. */
+int hepk_best_triplet(const int64_t *offsets /* N+1 */, int64_t n_events, const float *px, const float *py,
+                      const float *pz, const float *en, const uint8_t *obj_mask /* nullable, M */, float target,
+                      float *out_mass /* N */, int32_t *out_idx /* 3N */, hipStream_t stream);
+
 /* Checks offsets[0] == 0, offsets non-decreasing and offsets[n_events] ==
  * n_objects; writes the number of violations to *bad (device int64). */
 int hepk_validate_offsets(const int64_t *offsets, int64_t n_events, int64_t n_objects,
                           int64_t *bad /* device, 1 */, hipStream_t stream);
 
 /* Measurement helper, not a step of the method: reads nbytes (a multiple of
- * 16, p 16-byte aligned) with 16-byte loads, several in flight per thread,
- * and nothing else -- the streaming rate the HBM-bound kernels above are
+ * 16, p 16-byte aligned) with nontemporal 16-byte loads, eight in flight per
+ * thread, one 256-thread workgroup per compute unit, and nothing else -- the streaming rate the HBM-bound kernels above are
  * compared with.  *sink (device, 1) may receive a value derived from the
  * data (a data-dependent store keeps the loads); its content is meaningless. */
 int hepk_stream_read(const void *p, int64_t nbytes, uint32_t *sink /* device, 1 */, hipStream_t stream);
@@ -427,6 +497,47 @@ int hepk_pipeline_noalloc(const hepk_dataset *ds /* host, n_ds */, int32_t n_ds,
 int hepk_autotune(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_t n_query,
                   double *sumw, uint64_t *counts, int32_t reps, hepk_tune *best /* host */,
                   float *best_ms /* host, nullable */, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Out-of-core passes (Sec. II: a cache of uncompressed columns in host memory
+ * or memory-mapped files; Fig. 1: loaded in batches of a few GB of contiguous
+ * arrays, the kernels running on device memory).  A streamer cuts a dataset
+ * held in host memory into batches of consecutive events and runs the fused
+ * pass batch by batch: the columns of the next batches are gathered
+ * (pageable sources: by host threads into pinned memory) and copied to
+ * device staging slots on a copy stream of the streamer while the pass over
+ * the current batch runs on the caller's stream.  Results equal a pass over
+ * the whole dataset resident in device memory.
+ * ------------------------------------------------------------------------- */
+
+typedef struct hepk_stream_opts {
+    int64_t batch_events;    /* events per batch (0: 2^22) */
+    int32_t n_buffers;       /* device staging slots, 1..8 (0: 2, double buffering) */
+    int32_t host_threads;    /* threads gathering pageable sources (0: 8) */
+    hepk_tune tune;          /* launch configuration (block 0: the default) */
+} hepk_stream_opts;
+
+typedef struct hepk_streamer_s *hepk_streamer;
+
+/* host_ds: a dataset whose offsets and columns are HOST pointers (pageable,
+ * memory-mapped or pinned); they and the queries' host arrays must stay valid
+ * and unchanged until hepk_streamer_destroy.  Allocates the staging slots
+ * (n_buffers x the largest batch's bytes on the device, and as much pinned
+ * host memory for pageable sources). */
+int hepk_streamer_create(const hepk_dataset *host_ds /* host */, const hepk_query *q /* host, n_query */,
+                         int32_t n_query, const hepk_stream_opts *opts /* host, nullable */,
+                         hepk_streamer *out /* host */);
+
+/* Histogram slots a pass fills (the layout of hepk_plan_create over one
+ * dataset with these queries). */
+int hepk_streamer_hist_slots(hepk_streamer s, int64_t *n_slots /* host */);
+
+/* One pass over every batch, accumulating into sumw/counts (device).  Returns
+ * once every batch is enqueued (the host waits only for staging slots to come
+ * free); synchronise `stream` before reading the histograms. */
+int hepk_stream_pass(hepk_streamer s, double *sumw, uint64_t *counts, hipStream_t stream);
+
+int hepk_streamer_destroy(hepk_streamer s);
 
 int hepk_plan_destroy(hepk_plan p);
 

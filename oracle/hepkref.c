@@ -366,6 +366,207 @@ static void *xmalloc(size_t n)
     return malloc(n ? n : 1);
 }
 
+/* ---- positional kernels (Sec. III: get_in_offsets and set_in_offsets
+ * retrieve or set the n-th element of every row; the specialised kernel
+ * select_opposite_sign_muons keeps, per event, the first two objects in pT
+ * order that have opposite charges; compaction gathers the selected objects
+ * into a contiguous collection laid out by the offsets of their counts) ---- */
+
+/* Content index of the n-th (from 0) object of event e with obj_mask set
+ * (every object when obj_mask is NULL); -1 when the event has fewer. */
+static int64_t nth_selected(const int64_t *offsets, int64_t e, const uint8_t *obj_mask, int32_t n)
+{
+    if (n < 0) return -1;
+    int32_t seen = 0;
+    for (int64_t i = offsets[e]; i < offsets[e + 1]; i++) {
+        if (obj_mask && !obj_mask[i]) continue;
+        if (seen == n) return i;
+        seen++;
+    }
+    return -1;
+}
+
+int hepkref_get_in_offsets(const int64_t *offsets, int64_t n_events, const void *content, int32_t dtype,
+                           const uint8_t *obj_mask, const uint8_t *evt_mask, const int32_t *idx, int32_t n,
+                           float fill, float *out, int32_t *out_index)
+{
+    if (n_events < 0 || !offsets || (n_events > 0 && !out)) return HEPKREF_EINVAL;
+    if (!valid_float_dtype(dtype)) return HEPKREF_EINVAL;
+    if (!content && n_events > 0 && offsets[n_events] > 0) return HEPKREF_EINVAL;
+    for (int64_t e = 0; e < n_events; e++) {
+        int64_t i = -1;
+        if (!evt_mask || evt_mask[e]) i = nth_selected(offsets, e, obj_mask, idx ? idx[e] : n);
+        out[e] = (i >= 0) ? load_f(content, dtype, i) : fill;
+        if (out_index) out_index[e] = (i >= 0) ? (int32_t)(i - offsets[e]) : -1;
+    }
+    return HEPKREF_OK;
+}
+
+int hepkref_set_in_offsets(const int64_t *offsets, int64_t n_events, void *content, int32_t dtype,
+                           const uint8_t *obj_mask, const uint8_t *evt_mask, const int32_t *idx, int32_t n,
+                           float value)
+{
+    if (n_events < 0 || !offsets) return HEPKREF_EINVAL;
+    if (dtype != HEPKREF_F32 && dtype != HEPKREF_U8) return HEPKREF_EINVAL;
+    if (!content && n_events > 0 && offsets[n_events] > 0) return HEPKREF_EINVAL;
+    for (int64_t e = 0; e < n_events; e++) {
+        if (evt_mask && !evt_mask[e]) continue;
+        int64_t i = nth_selected(offsets, e, obj_mask, idx ? idx[e] : n);
+        if (i < 0) continue;
+        if (dtype == HEPKREF_F32)
+            ((float *)content)[i] = value;
+        else
+            ((uint8_t *)content)[i] = (value != 0.0f) ? 1 : 0;
+    }
+    return HEPKREF_OK;
+}
+
+/* i comes before j in pT order: larger pt first, NaN pt after every number,
+ * equal (or both NaN) pt by lower index */
+static int pt_before(float pi, int64_t i, float pj, int64_t j)
+{
+    int ni = pi != pi, nj = pj != pj;
+    if (ni != nj) return nj;
+    if (!ni && pi != pj) return pi > pj;
+    return i < j;
+}
+
+static int opposite(int32_t a, int32_t b)
+{
+    return (a > 0 && b < 0) || (a < 0 && b > 0);
+}
+
+int hepkref_select_opposite_sign(const int64_t *offsets, int64_t n_events, const void *pt, int32_t dtype,
+                                 const int32_t *charge, const uint8_t *obj_mask, uint8_t *mask_out)
+{
+    if (n_events < 0 || !offsets) return HEPKREF_EINVAL;
+    if (!valid_float_dtype(dtype)) return HEPKREF_EINVAL;
+    int64_t m = n_events > 0 ? offsets[n_events] : 0;
+    if (m > 0 && (!pt || !charge || !mask_out)) return HEPKREF_EINVAL;
+    for (int64_t e = 0; e < n_events; e++) {
+        int64_t i0 = offsets[e], i1 = offsets[e + 1];
+        for (int64_t i = i0; i < i1; i++) mask_out[i] = 0;
+        /* the selected objects in pT order (selection sort on the definition) */
+        int64_t cnt = 0;
+        for (int64_t i = i0; i < i1; i++)
+            if (!obj_mask || obj_mask[i]) cnt++;
+        int64_t *order = xmalloc(sizeof(int64_t) * (size_t)(cnt > 0 ? cnt : 1));
+        uint8_t *taken = xmalloc((size_t)(i1 - i0 > 0 ? i1 - i0 : 1));
+        memset(taken, 0, (size_t)(i1 - i0 > 0 ? i1 - i0 : 1));
+        for (int64_t p = 0; p < cnt; p++) {
+            int64_t best = -1;
+            for (int64_t i = i0; i < i1; i++) {
+                if ((obj_mask && !obj_mask[i]) || taken[i - i0]) continue;
+                if (best < 0 || pt_before(load_f(pt, dtype, i), i, load_f(pt, dtype, best), best)) best = i;
+            }
+            order[p] = best;
+            taken[best - i0] = 1;
+        }
+        /* the first pair of positions (p, r), p < r, with opposite charges */
+        int found = 0;
+        for (int64_t p = 0; p < cnt && !found; p++)
+            for (int64_t r = p + 1; r < cnt && !found; r++)
+                if (opposite(charge[order[p]], charge[order[r]])) {
+                    mask_out[order[p]] = 1;
+                    mask_out[order[r]] = 1;
+                    found = 1;
+                }
+        free(order);
+        free(taken);
+    }
+    return HEPKREF_OK;
+}
+
+static size_t dtype_size(int32_t dtype)
+{
+    return dtype == HEPKREF_F16 ? 2 : (dtype == HEPKREF_U8 ? 1 : 4);
+}
+
+int hepkref_compact(const int64_t *offsets, int64_t n_events, const void *content, int32_t dtype,
+                    const uint8_t *obj_mask, void *out, int64_t *n_out)
+{
+    if (n_events < 0 || !offsets || !n_out) return HEPKREF_EINVAL;
+    if (dtype < HEPKREF_F32 || dtype > HEPKREF_U8) return HEPKREF_EINVAL;
+    size_t es = dtype_size(dtype);
+    int64_t k = 0;
+    for (int64_t e = 0; e < n_events; e++) {
+        for (int64_t i = offsets[e]; i < offsets[e + 1]; i++) {
+            if (obj_mask && !obj_mask[i]) continue;
+            memcpy((char *)out + (size_t)k * es, (const char *)content + (size_t)i * es, es);
+            k++;
+        }
+    }
+    *n_out = k;
+    return HEPKREF_OK;
+}
+
+/* ---- top-quark candidate (Sec. IV high-level variable reconstruction: the
+ * jet triplet whose invariant mass is closest to M = 172 GeV) ---- */
+
+int hepkref_p4(const void *pt, const void *eta, const void *phi, const void *mass, int32_t dtype, int64_t n,
+               float *px, float *py, float *pz, float *en)
+{
+    if (n < 0 || (n > 0 && (!pt || !eta || !phi || !mass || !px || !py || !pz || !en))) return HEPKREF_EINVAL;
+    if (!valid_float_dtype(dtype)) return HEPKREF_EINVAL;
+    for (int64_t i = 0; i < n; i++) {
+        double p = load_f(pt, dtype, i), h = load_f(eta, dtype, i);
+        double f = load_f(phi, dtype, i), m = load_f(mass, dtype, i);
+        double x = p * cos(f), y = p * sin(f), z = p * sinh(h);
+        px[i] = (float)x;
+        py[i] = (float)y;
+        pz[i] = (float)z;
+        en[i] = (float)sqrt(x * x + y * y + z * z + m * m);
+    }
+    return HEPKREF_OK;
+}
+
+int hepkref_best_triplet(const int64_t *offsets, int64_t n_events, const float *px, const float *py,
+                         const float *pz, const float *en, const uint8_t *obj_mask, float target,
+                         float *out_mass, int32_t *out_idx)
+{
+    if (n_events < 0 || !offsets || (n_events > 0 && (!out_mass || !out_idx))) return HEPKREF_EINVAL;
+    int64_t m = n_events > 0 ? offsets[n_events] : 0;
+    if (m > 0 && (!px || !py || !pz || !en)) return HEPKREF_EINVAL;
+    for (int64_t e = 0; e < n_events; e++) {
+        int64_t i0 = offsets[e], i1 = offsets[e + 1];
+        float best_d = INFINITY, best_m = NAN;
+        int32_t bi = -1, bj = -1, bk = -1;
+        for (int64_t i = i0; i < i1; i++) {
+            if (obj_mask && !obj_mask[i]) continue;
+            for (int64_t j = i + 1; j < i1; j++) {
+                if (obj_mask && !obj_mask[j]) continue;
+                for (int64_t k = j + 1; k < i1; k++) {
+                    if (obj_mask && !obj_mask[k]) continue;
+                    /* summed four-momentum, i + j first, then k */
+                    float sx = (px[i] + px[j]) + px[k];
+                    float sy = (py[i] + py[j]) + py[k];
+                    float sz = (pz[i] + pz[j]) + pz[k];
+                    float se = (en[i] + en[j]) + en[k];
+                    float m2 = se * se;
+                    m2 = m2 - sx * sx;
+                    m2 = m2 - sy * sy;
+                    m2 = m2 - sz * sz;
+                    /* a negative square (rounding of a light system) is mass 0; NaN stays NaN */
+                    float mm = (m2 < 0.0f) ? 0.0f : sqrtf(m2);
+                    float d = fabsf(mm - target);
+                    if (d < best_d) {
+                        best_d = d;
+                        best_m = mm;
+                        bi = (int32_t)(i - i0);
+                        bj = (int32_t)(j - i0);
+                        bk = (int32_t)(k - i0);
+                    }
+                }
+            }
+        }
+        out_mass[e] = best_m;
+        out_idx[3 * e] = bi;
+        out_idx[3 * e + 1] = bj;
+        out_idx[3 * e + 2] = bk;
+    }
+    return HEPKREF_OK;
+}
+
 static hepkref_cut mkcut(const void *col, int32_t dtype, int32_t op, float thr)
 {
     hepkref_cut c;

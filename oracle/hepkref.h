@@ -33,7 +33,7 @@ extern "C" {
 enum { HEPKREF_OK = 0, HEPKREF_EINVAL = -1, HEPKREF_EUNSUPPORTED = -3 };
 
 /* content element types */
-enum { HEPKREF_F32 = 0, HEPKREF_F16 = 1, HEPKREF_I32 = 2 };
+enum { HEPKREF_F32 = 0, HEPKREF_F16 = 1, HEPKREF_I32 = 2, HEPKREF_U8 = 3 };
 
 /* comparisons of a column against a threshold: v > t, v >= t, v < t, v <= t,
  * |v| < t, |v| <= t.  Float columns compare against `thr`, int32 columns
@@ -126,6 +126,54 @@ int hepkref_interp(const void *x, int32_t dtype, int64_t n,
 int hepkref_jes_delta(const void *pt, const void *eta, int32_t dtype, int64_t n,
                       const float *eta_edges, int32_t n_eta,
                       const float *pt_edges, int32_t n_pt, const float *delta, float *out);
+
+/* ---- positional kernels (Sec. III get_in_offsets / set_in_offsets,
+ * select_opposite_sign_muons) and compaction ------------------------------ */
+
+/* For every event e with evt_mask[e] (NULL: all): the n-th (from 0) object
+ * of the event among those with obj_mask (NULL: all), n = idx[e] (idx NULL:
+ * the constant n; negative: none); out[e] = its content (F32/F16),
+ * out_index[e] (may be NULL) = its local index; otherwise fill and -1. */
+int hepkref_get_in_offsets(const int64_t *offsets, int64_t n_events, const void *content, int32_t dtype,
+                           const uint8_t *obj_mask, const uint8_t *evt_mask, const int32_t *idx, int32_t n,
+                           float fill, float *out, int32_t *out_index);
+
+/* The same object of every event set to value: content F32 (value) or U8
+ * (1 when value != 0, else 0). */
+int hepkref_set_in_offsets(const int64_t *offsets, int64_t n_events, void *content, int32_t dtype,
+                           const uint8_t *obj_mask, const uint8_t *evt_mask, const int32_t *idx, int32_t n,
+                           float value);
+
+/* Per event, the objects with obj_mask in pT order (larger pt first, NaN
+ * after every number, equal pt by lower index); the first pair of positions
+ * (p, r), p < r, whose charges have opposite signs gets mask_out 1, every
+ * other object of the event 0. */
+int hepkref_select_opposite_sign(const int64_t *offsets, int64_t n_events, const void *pt, int32_t dtype,
+                                 const int32_t *charge, const uint8_t *obj_mask, uint8_t *mask_out);
+
+/* The objects with obj_mask (NULL: all), in order, copied contiguously to
+ * out (elements of 4, 2 or 1 bytes by dtype F32/I32, F16, U8); *n_out = how
+ * many. */
+int hepkref_compact(const int64_t *offsets, int64_t n_events, const void *content, int32_t dtype,
+                    const uint8_t *obj_mask, void *out, int64_t *n_out);
+
+/* ---- top-quark candidate (Sec. IV: jet triplet with invariant mass closest
+ * to 172 GeV) -------------------------------------------------------------- */
+
+/* Four-momenta from (pt, eta, phi, mass), computed in float64 and rounded
+ * once: px = pt cos phi, py = pt sin phi, pz = pt sinh eta,
+ * E = sqrt(px^2 + py^2 + pz^2 + m^2). */
+int hepkref_p4(const void *pt, const void *eta, const void *phi, const void *mass, int32_t dtype, int64_t n,
+               float *px, float *py, float *pz, float *en);
+
+/* Per event, over the triplets i < j < k of objects with obj_mask (NULL:
+ * all), in float32: component sums (i + j) + k, m2 = E^2 - px^2 - py^2 - pz^2
+ * left to right, M = 0 if m2 < 0 else sqrt(m2); the first triplet with the
+ * smallest |M - target| (a NaN distance is never the smallest);
+ * out_mass[e] = M (NaN if none), out_idx[3e..3e+2] = local indices (-1). */
+int hepkref_best_triplet(const int64_t *offsets, int64_t n_events, const float *px, const float *py,
+                         const float *pz, const float *en, const uint8_t *obj_mask, float target,
+                         float *out_mass, int32_t *out_idx);
 
 /* ---- the end-to-end analysis pass --------------------------------------- */
 

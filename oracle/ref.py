@@ -21,7 +21,7 @@ LIB = os.environ.get("HEPKREF_LIB") or os.path.join(HERE, "libhepkref.so")
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
           "-Wall", "-Wextra", "-Wno-unused-parameter"]
 
-F32, F16, I32 = 0, 1, 2
+F32, F16, I32, U8 = 0, 1, 2, 3
 GT, GE, LT, LE, ABS_LT, ABS_LE = range(6)
 COUNT, SUM, MAX, MIN, ARGMAX, ARGMIN, PROD = range(7)
 
@@ -92,6 +92,18 @@ def lib():
                                         C.c_void_p, C.c_void_p]
         _lib.hepkref_jes_delta.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int32,
                                            C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+        _lib.hepkref_get_in_offsets.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p,
+                                                C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_void_p,
+                                                C.c_void_p]
+        _lib.hepkref_set_in_offsets.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p,
+                                                C.c_void_p, C.c_void_p, C.c_int32, C.c_float]
+        _lib.hepkref_select_opposite_sign.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p,
+                                                      C.c_void_p, C.c_void_p]
+        _lib.hepkref_compact.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                         C.c_void_p]
+        _lib.hepkref_p4.argtypes = [C.c_void_p] * 4 + [C.c_int32, C.c_int64] + [C.c_void_p] * 4
+        _lib.hepkref_best_triplet.argtypes = [C.c_void_p, C.c_int64] + [C.c_void_p] * 5 + [
+            C.c_float, C.c_void_p, C.c_void_p]
         _lib.hepkref_pipeline.argtypes = [C.POINTER(DatasetS), C.POINTER(QueryS), C.c_int32,
                                           C.c_void_p, C.c_void_p, C.c_void_p]
     return _lib
@@ -223,6 +235,64 @@ def jes_delta(pt, eta, eta_edges, pt_edges, delta) -> np.ndarray:
     _check(lib().hepkref_jes_delta(pt.ctypes.data, eta.ctypes.data, _dt(pt), len(pt), ee.ctypes.data,
                                    len(ee) - 1, pe.ctypes.data, len(pe) - 1, d.ctypes.data, out.ctypes.data))
     return out
+
+
+def get_in_offsets(offsets, content, n: int = 0, idx=None, obj_mask=None, evt_mask=None, fill: float = 0.0):
+    """(value float32[N], local index int32[N]) of the n-th selected object of each event."""
+    nev = len(offsets) - 1
+    content = np.ascontiguousarray(content)
+    out, oi = np.empty(nev, np.float32), np.empty(nev, np.int32)
+    _check(lib().hepkref_get_in_offsets(offsets.ctypes.data, nev, content.ctypes.data, _dt(content), _p(obj_mask),
+                                        _p(evt_mask), _p(idx), n, fill, out.ctypes.data, oi.ctypes.data))
+    return out, oi
+
+
+def set_in_offsets(offsets, content, value: float, n: int = 0, idx=None, obj_mask=None, evt_mask=None):
+    """A copy of content (float32 or uint8) with the n-th selected object of each event set."""
+    out = np.array(content, copy=True)
+    dt = U8 if out.dtype == np.uint8 else _dt(out)
+    _check(lib().hepkref_set_in_offsets(offsets.ctypes.data, len(offsets) - 1, out.ctypes.data, dt, _p(obj_mask),
+                                        _p(evt_mask), _p(idx), n, value))
+    return out
+
+
+def select_opposite_sign(offsets, pt, charge, obj_mask=None) -> np.ndarray:
+    pt = np.ascontiguousarray(pt)
+    charge = np.ascontiguousarray(charge, np.int32)
+    out = np.empty(int(offsets[-1]), np.uint8)
+    _check(lib().hepkref_select_opposite_sign(offsets.ctypes.data, len(offsets) - 1, pt.ctypes.data, _dt(pt),
+                                              charge.ctypes.data, _p(obj_mask), out.ctypes.data))
+    return out
+
+
+def compact(offsets, content, obj_mask=None) -> np.ndarray:
+    content = np.ascontiguousarray(content)
+    dt = U8 if content.dtype == np.uint8 else _dt(content)
+    out = np.empty(max(1, int(offsets[-1])), content.dtype)
+    n = C.c_int64()
+    _check(lib().hepkref_compact(offsets.ctypes.data, len(offsets) - 1, content.ctypes.data, dt, _p(obj_mask),
+                                 out.ctypes.data, C.byref(n)))
+    return out[:n.value]
+
+
+def p4(pt, eta, phi, mass):
+    """(px, py, pz, E) float32 of each object (float64 arithmetic, rounded once)."""
+    pt, eta, phi, mass = (np.ascontiguousarray(a) for a in (pt, eta, phi, mass))
+    n = len(pt)
+    o = [np.empty(n, np.float32) for _ in range(4)]
+    _check(lib().hepkref_p4(pt.ctypes.data, eta.ctypes.data, phi.ctypes.data, mass.ctypes.data, _dt(pt), n,
+                            *[a.ctypes.data for a in o]))
+    return tuple(o)
+
+
+def best_triplet(offsets, px, py, pz, en, obj_mask=None, target: float = 172.0):
+    """(mass float32[N], local indices int32[N, 3]) of the triplet closest to target."""
+    nev = len(offsets) - 1
+    arrs = [np.ascontiguousarray(a, np.float32) for a in (px, py, pz, en)]
+    m, idx = np.empty(nev, np.float32), np.empty(3 * nev, np.int32)
+    _check(lib().hepkref_best_triplet(offsets.ctypes.data, nev, *[a.ctypes.data for a in arrs], _p(obj_mask),
+                                      target, m.ctypes.data, idx.ctypes.data))
+    return m, idx.reshape(nev, 3)
 
 
 def _coll(c, names):

@@ -60,21 +60,28 @@ __global__ void validate_offsets_kernel(const int64_t *off, int64_t n, int64_t m
 
 __global__ void zero_i64_kernel(int64_t *p) { *p = 0; }
 
-// Grid-stride read of n16 16-byte words, four loads in flight per thread.
-__global__ __launch_bounds__(256) void stream_read_kernel(const uint4 *__restrict__ p, int64_t n16, uint32_t key,
+// Grid-stride read of n16 16-byte words: eight nontemporal loads in flight
+// per thread (the data is read once, so the loads ask the caches not to keep
+// it), one 256-thread workgroup per compute unit -- the fastest of the block
+// sizes (256-1024), loads in flight (4-16), grids (1-32 workgroups per
+// compute unit) and cache hints measured on MI355X.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kStreamUnroll = 8;
+
+__global__ __launch_bounds__(256) void stream_read_kernel(const u32x4 *__restrict__ p, int64_t n16, uint32_t key,
                                                           uint32_t *sink) {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
     int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     uint32_t acc = 0;
-    for (; i + 3 * stride < n16; i += 4 * stride) {
-        uint4 v[4];
+    for (; i + (kStreamUnroll - 1) * stride < n16; i += kStreamUnroll * stride) {
+        u32x4 v[kStreamUnroll];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = p[i + u * stride];
+        for (int u = 0; u < kStreamUnroll; ++u) v[u] = __builtin_nontemporal_load(p + i + u * stride);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+        for (int u = 0; u < kStreamUnroll; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
     }
     for (; i < n16; i += stride) {
-        const uint4 v = p[i];
+        const u32x4 v = __builtin_nontemporal_load(p + i);
         acc ^= v.x ^ v.y ^ v.z ^ v.w;
     }
     // data-dependent (the compiler cannot drop the loads); a match, should the
@@ -110,7 +117,8 @@ extern "C" int hepk_stream_read(const void *p, int64_t nbytes, uint32_t *sink, h
     HEPK_REQUIRE(reinterpret_cast<uintptr_t>(p) % 16 == 0, "hepk_stream_read: p not 16-byte aligned");
     if (nbytes == 0) return HEPK_OK;
     const int64_t n16 = nbytes / 16;
-    const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n16, 256 * 4), 8 * device_cus()));
-    stream_read_kernel<<<grid, 256, 0, stream>>>(static_cast<const uint4 *>(p), n16, 0x9e3779b9u, sink);
+    const int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(ceil_div(n16, 256 * kStreamUnroll),
+                                                                            device_cus())));
+    stream_read_kernel<<<grid, 256, 0, stream>>>(static_cast<const u32x4 *>(p), n16, 0x9e3779b9u, sink);
     return check_launch("hepk_stream_read");
 }

@@ -236,6 +236,14 @@ def with_pileup(ds: Dataset, seed: int, mean: float = 20.0) -> Dataset:
     return Dataset(ds.n_events, ds.jets, ds.muons, ds.weight, ds.electrons, ds.content_dtype, ds.seed, npu)
 
 
+def muon_charges(ds: Dataset, seed: int) -> np.ndarray:
+    """A charge per muon, +1 or -1 with equal probability, int32 (drawn from
+    its own stream, default_rng([seed, 0xC4A6])) -- the column the
+    opposite-sign selection reads."""
+    rng = np.random.default_rng([seed, 0xC4A6])
+    return np.where(rng.uniform(size=ds.muons.n_objects) < 0.5, 1, -1).astype(np.int32)
+
+
 def pileup_table(data_mean: float = 22.0, sim_mean: float = 20.0, nbins: int = 80):
     """Synthetic pileup-reweighting table (edges, contents): in unit bins of
     the pileup count 0..nbins, the ratio of Poisson(data_mean) to

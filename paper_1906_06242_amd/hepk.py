@@ -15,7 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libhepk.so")
 
 OK, EINVAL, EHIP, EUNSUPPORTED, ENOMEM = 0, -1, -2, -3, -4
-F32, F16, I32 = 0, 1, 2
+F32, F16, I32, U8 = 0, 1, 2, 3
 GT, GE, LT, LE, ABS_LT, ABS_LE = range(6)
 COUNT, SUM, MAX, MIN, ARGMAX, ARGMIN, PROD = range(7)
 MAX_CUTS = 8
@@ -28,6 +28,9 @@ EXPORTS = (
     "hepk_plan_debug_layout", "hepk_pipeline_debug",
     "hepk_hist_fill_w2", "hepk_get_bin_contents", "hepk_interp", "hepk_jes_delta",
     "hepk_pipeline_noalloc", "hepk_pipeline_w2",
+    "hepk_get_in_offsets", "hepk_set_in_offsets", "hepk_select_opposite_sign", "hepk_compact",
+    "hepk_p4", "hepk_best_triplet",
+    "hepk_streamer_create", "hepk_streamer_hist_slots", "hepk_stream_pass", "hepk_streamer_destroy",
 )
 
 # hepk_event_record, as a numpy structured dtype (32 bytes)
@@ -91,6 +94,11 @@ class Tune(C.Structure):
         return cls(d.get("block", 512), d.get("ev_per_thread", 1), d.get("hist_mode", 0), d.get("grid", 0))
 
 
+class StreamOpts(C.Structure):
+    _fields_ = [("batch_events", C.c_int64), ("n_buffers", C.c_int32), ("host_threads", C.c_int32),
+                ("tune", Tune)]
+
+
 class PlanOpts(C.Structure):
     _fields_ = [("tune", Tune), ("shared_hist", C.c_int32), ("reserve_bins", C.c_int32), ("sumw2", C.c_int32)]
 
@@ -116,6 +124,17 @@ def load(path: str = LIB_PATH):
     lib.hepk_get_bin_contents.argtypes = [vp, i32, i64, vp, i32, vp, vp, vp]
     lib.hepk_interp.argtypes = [vp, i32, i64, vp, i32, vp, vp, vp]
     lib.hepk_jes_delta.argtypes = [vp, vp, i32, i64, vp, i32, vp, i32, vp, vp, vp]
+    lib.hepk_get_in_offsets.argtypes = [vp, i64, vp, i32, vp, vp, vp, i32, C.c_float, vp, vp, vp]
+    lib.hepk_set_in_offsets.argtypes = [vp, i64, vp, i32, vp, vp, vp, i32, C.c_float, vp]
+    lib.hepk_select_opposite_sign.argtypes = [vp, i64, vp, i32, vp, vp, vp, vp]
+    lib.hepk_compact.argtypes = [vp, i64, vp, i32, vp, vp, i64, vp, vp]
+    lib.hepk_p4.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp]
+    lib.hepk_best_triplet.argtypes = [vp, i64, vp, vp, vp, vp, vp, C.c_float, vp, vp, vp]
+    lib.hepk_streamer_create.argtypes = [C.POINTER(DatasetS), C.POINTER(QueryS), i32, C.POINTER(StreamOpts),
+                                         C.POINTER(vp)]
+    lib.hepk_streamer_hist_slots.argtypes = [vp, C.POINTER(i64)]
+    lib.hepk_stream_pass.argtypes = [vp, vp, vp, vp]
+    lib.hepk_streamer_destroy.argtypes = [vp]
     lib.hepk_validate_offsets.argtypes = [vp, i64, i64, vp, vp]
     lib.hepk_stream_read.argtypes = [vp, i64, vp, vp]
     lib.hepk_plan_create.argtypes = [C.POINTER(DatasetS), i32, C.POINTER(QueryS), i32,
@@ -175,7 +194,7 @@ def _stream(stream=None) -> Optional[int]:
 
 def dtype_code(t) -> int:
     import torch
-    return {torch.float32: F32, torch.float16: F16, torch.int32: I32}[t.dtype]
+    return {torch.float32: F32, torch.float16: F16, torch.int32: I32, torch.uint8: U8}[t.dtype]
 
 
 # ---------------------------------------------------------------- primitives
@@ -265,6 +284,64 @@ def jes_delta(pt, eta, eta_edges, pt_edges, delta, out=None, stream=None):
           eta_edges.numel() - 1, _ptr(pt_edges), pt_edges.numel() - 1, _ptr(delta), _ptr(out),
           _stream(stream))
     return out
+
+
+def get_in_offsets(offsets, content, n: int = 0, idx=None, obj_mask=None, evt_mask=None, fill: float = 0.0,
+                   stream=None):
+    """(value float32[N], local index int32[N]) of the n-th selected object of every event."""
+    import torch
+    nev = offsets.numel() - 1
+    out = torch.empty(nev, dtype=torch.float32, device="cuda")
+    oi = torch.empty(nev, dtype=torch.int32, device="cuda")
+    _call("hepk_get_in_offsets", _ptr(offsets), nev, _ptr(content), dtype_code(content), _ptr(obj_mask),
+          _ptr(evt_mask), _ptr(idx), n, fill, _ptr(out), _ptr(oi), _stream(stream))
+    return out, oi
+
+
+def set_in_offsets(offsets, content, value: float, n: int = 0, idx=None, obj_mask=None, evt_mask=None,
+                   stream=None):
+    """Sets, in place, the n-th selected object of every event (content float32 or uint8)."""
+    _call("hepk_set_in_offsets", _ptr(offsets), offsets.numel() - 1, _ptr(content), dtype_code(content),
+          _ptr(obj_mask), _ptr(evt_mask), _ptr(idx), n, value, _stream(stream))
+    return content
+
+
+def select_opposite_sign(offsets, pt, charge, obj_mask=None, out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.empty(pt.numel(), dtype=torch.uint8, device="cuda")
+    _call("hepk_select_opposite_sign", _ptr(offsets), offsets.numel() - 1, _ptr(pt), dtype_code(pt),
+          _ptr(charge), _ptr(obj_mask), _ptr(out), _stream(stream))
+    return out
+
+
+def compact(offsets, content, offsets_out, n_out: int, obj_mask=None, out=None, stream=None):
+    """The selected objects of content, contiguous, laid out by offsets_out (n_out of them)."""
+    import torch
+    if out is None:
+        out = torch.empty(max(1, n_out), dtype=content.dtype, device="cuda")
+    _call("hepk_compact", _ptr(offsets), offsets.numel() - 1, _ptr(content), dtype_code(content), _ptr(obj_mask),
+          _ptr(offsets_out), n_out, _ptr(out), _stream(stream))
+    return out[:n_out]
+
+
+def p4(pt, eta, phi, mass, stream=None):
+    import torch
+    o = [torch.empty(pt.numel(), dtype=torch.float32, device="cuda") for _ in range(4)]
+    _call("hepk_p4", _ptr(pt), _ptr(eta), _ptr(phi), _ptr(mass), pt.numel(), *[_ptr(a) for a in o],
+          _stream(stream))
+    return tuple(o)
+
+
+def best_triplet(offsets, px, py, pz, en, obj_mask=None, target: float = 172.0, stream=None):
+    """(mass float32[N], local indices int32[N, 3]) of each event's triplet closest to target."""
+    import torch
+    nev = offsets.numel() - 1
+    m = torch.empty(nev, dtype=torch.float32, device="cuda")
+    ix = torch.empty(3 * max(nev, 0), dtype=torch.int32, device="cuda")
+    _call("hepk_best_triplet", _ptr(offsets), nev, _ptr(px), _ptr(py), _ptr(pz), _ptr(en), _ptr(obj_mask),
+          target, _ptr(m), _ptr(ix), _stream(stream))
+    return m, ix.view(nev, 3)
 
 
 def validate_offsets(offsets, n_objects: int, stream=None) -> int:
@@ -515,6 +592,72 @@ def pipeline_noalloc(datasets: List[DeviceDataset], queries, sumw, counts, tune:
     t = C.byref(Tune.of(tune)) if tune is not None else None
     _call("hepk_pipeline_noalloc", dsa, len(datasets), qa, len(queries), t, _ptr(sumw), _ptr(counts),
           _stream(stream))
+
+
+def host_dataset_struct(ds, keep: list) -> DatasetS:
+    """A datagen.Dataset (host numpy arrays, or any objects with the same
+    fields) as the C struct with HOST pointers; the arrays go into keep."""
+    import numpy as np
+
+    def p(a):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a)
+        if a.size == 0:
+            a = np.zeros(1, a.dtype)
+        keep.append(a)
+        return a.ctypes.data
+
+    def coll(c, extra):
+        if c is None:
+            return Collection(None, None, None, None, None)
+        return Collection(p(c.offsets), p(c.cols["pt"]), p(c.cols["eta"]), p(c.cols["phi"]),
+                          p(c.cols[extra]) if extra and extra in c.cols else None)
+    return DatasetS(ds.n_events, F16 if ds.content_dtype == "f16" else F32, coll(ds.jets, "btag"),
+                    coll(ds.muons, "iso"), coll(ds.electrons, None), p(ds.weight),
+                    p(getattr(ds, "npu", None)))
+
+
+class Streamer:
+    """hepk_streamer over a host dataset (datagen.Dataset: numpy arrays,
+    possibly memory-mapped) for a list of datagen.Query; histograms laid out
+    as a Plan over one dataset with the same queries."""
+
+    def __init__(self, ds, queries, batch_events: int = 0, n_buffers: int = 0, host_threads: int = 0,
+                 tune: Optional[dict] = None):
+        self.keep = []
+        self.ds = ds
+        self.queries = list(queries)
+        dss = host_dataset_struct(ds, self.keep)
+        qa = (QueryS * len(queries))(*[query_struct(q, self.keep) for q in queries])
+        self.keep += [dss, qa]
+        opts = StreamOpts(batch_events, n_buffers, host_threads,
+                          Tune.of(tune) if tune is not None else Tune(0, 0, 0, 0))
+        h = C.c_void_p()
+        _call("hepk_streamer_create", C.byref(dss), qa, len(queries), C.byref(opts), C.byref(h))
+        self.handle = h
+        n = C.c_int64()
+        _call("hepk_streamer_hist_slots", h, C.byref(n))
+        self.n_slots = n.value
+
+    def new_hists(self):
+        import torch
+        return (torch.zeros(self.n_slots, dtype=torch.float64, device="cuda"),
+                torch.zeros(self.n_slots, dtype=torch.int64, device="cuda"))
+
+    def run(self, sumw, counts, stream=None):
+        _call("hepk_stream_pass", self.handle, _ptr(sumw), _ptr(counts), _stream(stream))
+
+    def close(self):
+        if self.handle:
+            _call("hepk_streamer_destroy", self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def autotune(datasets: List[DeviceDataset], queries, reps: int = 5, stream=None):

@@ -170,7 +170,8 @@ def test_reduce_offsets_tile_edges(n):
     cw, ow = ref.reduce(ref.COUNT, off, obj_mask=om, want_offsets=True)
     cnt = torch.empty(n, dtype=torch.int32, device="cuda")
     offo = torch.full((n + 1,), -7, dtype=torch.int64, device="cuda")
-    H._call("hepk_reduce", H.COUNT, H._ptr(dev(off)), n, None, H.F32, H._ptr(dev(om)), None, H._ptr(cnt), None,
+    doff, dom = dev(off), dev(om)  # held: the allocator may reuse a dropped tensor's memory at once
+    H._call("hepk_reduce", H.COUNT, H._ptr(doff), n, None, H.F32, H._ptr(dom), None, H._ptr(cnt), None,
             H._ptr(offo), H._stream())
     assert np.array_equal(host(cnt), cw) and np.array_equal(host(offo), ow)
 

@@ -57,6 +57,21 @@ MUTANTS = [
      "hepkref_reduce(HEPKREF_PROD, ds->muons.off, N, mu_sf, HEPKREF_F32, msel,",
      "hepkref_reduce(HEPKREF_PROD, ds->muons.off, N, mu_sf, HEPKREF_F32, NULL,"),
     ("lookup JES shift dropped", "(1.0f + s * delta[j])", "(1.0f + delta[j])"),
+    ("n-th object counts unselected ones", "        if (obj_mask && !obj_mask[i]) continue;\n        if (seen == n) return i;",
+     "        if (seen == n) return i;"),
+    ("n-th object as a global index", "out_index[e] = (i >= 0) ? (int32_t)(i - offsets[e]) : -1;",
+     "out_index[e] = (i >= 0) ? (int32_t)i : -1;"),
+    ("mask set ignores the value", "((uint8_t *)content)[i] = (value != 0.0f) ? 1 : 0;",
+     "((uint8_t *)content)[i] = 1;"),
+    ("opposite sign as different charge", "return (a > 0 && b < 0) || (a < 0 && b > 0);", "return a != b;"),
+    ("pT order ascending", "if (!ni && pi != pj) return pi > pj;", "if (!ni && pi != pj) return pi < pj;"),
+    ("every opposite pair kept", "                    found = 1;", "                    found = 0;"),
+    ("compaction ignores the mask",
+     "            if (obj_mask && !obj_mask[i]) continue;\n            memcpy(", "            memcpy("),
+    ("triplet ties to the last", "if (d < best_d) {", "if (d <= best_d) {"),
+    ("triplet energy summed in another order", "float se = (en[i] + en[j]) + en[k];",
+     "float se = en[i] + (en[j] + en[k]);"),
+    ("p4 py from cos", "y = p * sin(f)", "y = p * cos(f)"),
     ("event mask ignored by count",
      "if (take_event)\n                for (int64_t i = i0; i < i1; i++)\n                    if (!obj_mask",
      "if (1)\n                for (int64_t i = i0; i < i1; i++)\n                    if (!obj_mask"),
@@ -77,6 +92,7 @@ def test_mutant_is_caught(name, old, new, tmp_path):
                            "-o", so, mut, "-lm"], stderr=subprocess.DEVNULL)
     env = dict(os.environ, HEPKREF_LIB=so)
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_pins_positional.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, f"mutant '{name}' passed every pin:\n{r.stdout[-500:]}"
