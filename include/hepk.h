@@ -385,6 +385,9 @@ typedef struct hepk_plan_opts {
                                 with nbins <= reserve_bins (and n_scale <= the slot's) */
     int32_t sumw2;           /* 1: the plan can also keep sums of squared weights
                                 (hepk_pipeline_w2); implied by lookup corrections */
+    int64_t hist_arena_slots;/* > 0: the histogram buffers have at least this many slots
+                                (hepk_plan_hist_slots), an arena in which
+                                hepk_plan_set_query_at places each query's histograms */
 } hepk_plan_opts;
 
 int hepk_plan_create_ex(const hepk_dataset *ds /* host, n_ds */, int32_t n_ds,
@@ -403,6 +406,17 @@ int hepk_plan_create_ex(const hepk_dataset *ds /* host, n_ds */, int32_t n_ds,
  * here). */
 int hepk_plan_set_query(hepk_plan p, int32_t slot, const hepk_query *q /* host, nullable */,
                         hipStream_t stream);
+
+/* hepk_plan_set_query that also places the slot's histograms: the query's
+ * blocks are laid out compactly (nbins+2 per observable, observables then
+ * scales) from slot hist_slot0 of the histogram buffers, which must hold
+ * them (HEPK_EINVAL otherwise).  The caller owns the placement, e.g. an
+ * allocator over an arena made with opts.hist_arena_slots, so histogram memory
+ * is what gates which queries a server can hold at once; queries with up to
+ * reserve_bins bins per histogram fit a slot's edge table.  Later
+ * hepk_plan_set_query calls on the slot keep this placement. */
+int hepk_plan_set_query_at(hepk_plan p, int32_t slot, const hepk_query *q /* host */, int64_t hist_slot0,
+                           hipStream_t stream);
 
 /* Total histogram slots of the plan (length of sumw and counts). */
 int hepk_plan_hist_slots(hepk_plan p, int64_t *n_slots /* host */);

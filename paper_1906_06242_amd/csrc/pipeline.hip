@@ -342,7 +342,12 @@ int plan_build(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_
         e.gslot0 = static_cast<int32_t>(gacc);
         gacc += static_cast<int64_t>(per) * q[i].n_scale;
     }
-    if (gacc >= (int64_t(1) << 30) || edge_table.size() >= (size_t(1) << 30)) {
+    if (o.hist_arena_slots < 0 || o.hist_arena_slots >= (int64_t(1) << 31)) {
+        set_error("hepk_plan_create: hist_arena_slots %lld out of [0, 2^31)", (long long)o.hist_arena_slots);
+        return plan_fail(p, HEPK_EINVAL);
+    }
+    gacc = std::max<int64_t>(gacc, o.hist_arena_slots);
+    if (gacc >= (int64_t(1) << 31) || edge_table.size() >= (size_t(1) << 30)) {
         set_error("hepk_plan_create: %lld histogram slots per dataset is too many", (long long)gacc);
         return plan_fail(p, HEPK_EINVAL);
     }
@@ -531,9 +536,10 @@ extern "C" int hepk_plan_create(const hepk_dataset *ds, int32_t n_ds, const hepk
     return hepk_plan_create_ex(ds, n_ds, q, n_query, &o, out);
 }
 
-extern "C" int hepk_plan_set_query(hepk_plan p, int32_t slot, const hepk_query *q, hipStream_t stream) {
+// Installs q (NULL: idle) in a slot; at >= 0 also places the slot's
+// histograms at that slot of the histogram buffers, laid out compactly.
+static int set_query(hepk_plan p, int32_t slot, const hepk_query *q, int64_t at, hipStream_t stream) {
     using namespace hepk;
-    clear_error();
     HEPK_REQUIRE(p, "hepk_plan_set_query: plan is NULL");
     HEPK_REQUIRE(slot >= 0 && slot < p->n_q, "hepk_plan_set_query: slot %d out of [0, %d)", slot, p->n_q);
     if (q) {
@@ -559,8 +565,25 @@ extern "C" int hepk_plan_set_query(hepk_plan p, int32_t slot, const hepk_query *
     const int max_cap = *std::max_element(p->cap_bins.begin(), p->cap_bins.end());
     float *st_e = reinterpret_cast<float *>(st + al(sz_q));
     float *st_s = reinterpret_cast<float *>(st + al(sz_q) + al(sizeof(float) * 3 * (max_cap + 1)));
+    if (q && at >= 0) {
+        // the compact layout of this query from `at`, inside the buffers
+        int32_t per = 0;
+        for (int h = 0; h < 3; ++h) per += q->nbins[h] + 2;
+        const int64_t need = static_cast<int64_t>(per) * q->n_scale;
+        HEPK_REQUIRE(at + need <= p->ds_block, "hepk_plan_set_query_at: slots [%lld, %lld) beyond the %lld of the plan",
+                     (long long)at, (long long)(at + need), (long long)p->ds_block);
+    }
     if (q) {
         set_qdev(e, *q, q->edges);
+        if (at >= 0) {
+            int32_t per = 0;
+            for (int h = 0; h < 3; ++h) {
+                e.ghoff[h] = per;
+                per += q->nbins[h] + 2;
+            }
+            e.gper_scale = per;
+            e.gslot0 = static_cast<int32_t>(at);
+        }
         for (int h = 0; h < 3; ++h) std::memcpy(st_e + h * (max_cap + 1), q->edges[h], sizeof(float) * (q->nbins[h] + 1));
         std::memcpy(st_s, q->scales, sizeof(float) * q->n_scale);
     } else {
@@ -579,6 +602,19 @@ extern "C" int hepk_plan_set_query(hepk_plan p, int32_t slot, const hepk_query *
     HEPK_HIP(hipEventRecord(p->ring_ev[r], stream));
     p->ring_used[r] = true;
     return HEPK_OK;
+}
+
+extern "C" int hepk_plan_set_query(hepk_plan p, int32_t slot, const hepk_query *q, hipStream_t stream) {
+    hepk::clear_error();
+    return set_query(p, slot, q, -1, stream);
+}
+
+extern "C" int hepk_plan_set_query_at(hepk_plan p, int32_t slot, const hepk_query *q, int64_t hist_slot0,
+                                      hipStream_t stream) {
+    hepk::clear_error();
+    HEPK_REQUIRE(q, "hepk_plan_set_query_at: query is NULL (use hepk_plan_set_query to idle a slot)");
+    HEPK_REQUIRE(hist_slot0 >= 0, "hepk_plan_set_query_at: hist_slot0 < 0");
+    return set_query(p, slot, q, hist_slot0, stream);
 }
 
 extern "C" int hepk_plan_hist_slots(hepk_plan p, int64_t *n_slots) {

@@ -447,5 +447,20 @@ def host_slice(dev_ds: dict, e0: int, e1: int) -> Dataset:
                 cols[key.split(".", 1)[1]] = t[a:b].cpu().numpy()
         built[name] = Collection(off - a, cols)
     w = dev_ds["weight"][e0:e1].cpu().numpy()
+    npu = dev_ds["npu"][e0:e1].cpu().numpy() if "npu" in dev_ds else None
     return Dataset(e1 - e0, built["jets"], built["muons"], w, built.get("electrons"),
-                   dev_ds.get("content_dtype", "f32"))
+                   dev_ds.get("content_dtype", "f32"), npu=npu)
+
+
+def with_pileup_device(dev_ds: dict, seed: int, mean: float = 20.0) -> dict:
+    """The on-device dataset with a pileup column, Poisson(mean) as float32,
+    drawn on the GPU (generator seed seed * 1_000_003 + 0x50550)."""
+    import torch
+    n = int(dev_ds["n_events"])
+    dev = dev_ds["weight"].device
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed * 1_000_003 + 0x50550)
+    lam = torch.full((max(n, 1),), mean, dtype=torch.float64, device=dev)
+    out = dict(dev_ds)
+    out["npu"] = torch.poisson(lam, generator=g).to(torch.float32)[:max(n, 1)]
+    return out

@@ -31,6 +31,7 @@ EXPORTS = (
     "hepk_get_in_offsets", "hepk_set_in_offsets", "hepk_select_opposite_sign", "hepk_compact",
     "hepk_p4", "hepk_best_triplet",
     "hepk_streamer_create", "hepk_streamer_hist_slots", "hepk_stream_pass", "hepk_streamer_destroy",
+    "hepk_plan_set_query_at",
 )
 
 # hepk_event_record, as a numpy structured dtype (32 bytes)
@@ -100,7 +101,8 @@ class StreamOpts(C.Structure):
 
 
 class PlanOpts(C.Structure):
-    _fields_ = [("tune", Tune), ("shared_hist", C.c_int32), ("reserve_bins", C.c_int32), ("sumw2", C.c_int32)]
+    _fields_ = [("tune", Tune), ("shared_hist", C.c_int32), ("reserve_bins", C.c_int32), ("sumw2", C.c_int32),
+                ("hist_arena_slots", C.c_int64)]
 
 
 _lib = None
@@ -142,6 +144,7 @@ def load(path: str = LIB_PATH):
     lib.hepk_plan_create_ex.argtypes = [C.POINTER(DatasetS), i32, C.POINTER(QueryS), i32,
                                         C.POINTER(PlanOpts), C.POINTER(vp)]
     lib.hepk_plan_set_query.argtypes = [vp, i32, C.POINTER(QueryS), vp]
+    lib.hepk_plan_set_query_at.argtypes = [vp, i32, C.POINTER(QueryS), i64, vp]
     lib.hepk_pipeline_range.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.hepk_pipeline_graph.argtypes = [vp, vp, vp, vp]
     lib.hepk_autotune.argtypes = [C.POINTER(DatasetS), i32, C.POINTER(QueryS), i32, vp, vp, i32,
@@ -473,12 +476,12 @@ class Plan:
     """
 
     def __init__(self, datasets: List[DeviceDataset], queries, tune: Optional[dict] = None,
-                 shared_hist: bool = False, reserve_bins: int = 0, sumw2: bool = False):
+                 shared_hist: bool = False, reserve_bins: int = 0, sumw2: bool = False, hist_arena_slots: int = 0):
         keep = []
         dsa = (DatasetS * len(datasets))(*[d.struct() for d in datasets])
         qa = (QueryS * len(queries))(*[query_struct(q, keep) for q in queries])
         opts = PlanOpts(Tune.of(tune) if tune is not None else Tune(0, 0, 0, 0),
-                        1 if shared_hist else 0, reserve_bins, 1 if sumw2 else 0)
+                        1 if shared_hist else 0, reserve_bins, 1 if sumw2 else 0, hist_arena_slots)
         h = C.c_void_p()
         _call("hepk_plan_create_ex", dsa, len(datasets), qa, len(queries), C.byref(opts), C.byref(h))
         self.handle = h
@@ -492,11 +495,15 @@ class Plan:
         _call("hepk_plan_get_tune", h, C.byref(t))
         self.tune = t.as_dict()
 
-    def set_query(self, slot: int, q, stream=None):
-        """Install query q (None: idle) in a slot, ordered on the stream."""
+    def set_query(self, slot: int, q, stream=None, at: Optional[int] = None):
+        """Install query q (None: idle) in a slot, ordered on the stream; with
+        `at`, its histograms are placed from that slot of the buffers."""
         keep = []
         qs = C.byref(query_struct(q, keep)) if q is not None else None
-        _call("hepk_plan_set_query", self.handle, slot, qs, _stream(stream))
+        if at is None:
+            _call("hepk_plan_set_query", self.handle, slot, qs, _stream(stream))
+        else:
+            _call("hepk_plan_set_query_at", self.handle, slot, qs, at, _stream(stream))
         self.queries[slot] = q
 
     def hist_offset(self, d: int, q: int, v: int, h: int):
@@ -660,9 +667,53 @@ class Streamer:
             pass
 
 
-def autotune(datasets: List[DeviceDataset], queries, reps: int = 5, stream=None):
-    """Fastest launch configuration for these datasets and queries (hepk_autotune)."""
+def autotune_cache_path() -> str:
+    """Where launch-configuration search results are kept (HEPK_AUTOTUNE_CACHE,
+    else ~/.cache/hepk/autotune.json)."""
+    return os.environ.get("HEPK_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "hepk", "autotune.json"))
+
+
+def workload_key(datasets, queries, device: Optional[str] = None) -> str:
+    """Cache key of a launch-configuration search: the device (name,
+    architecture, compute units) and the workload (events per dataset, content
+    dtype, collections present, and per query its scales, binnings and
+    lookups)."""
+    import hashlib
+    import json
+    if device is None:
+        import torch
+        p = torch.cuda.get_device_properties(torch.cuda.current_device())
+        device = f"{p.name}|{getattr(p, 'gcnArchName', '')}|{p.multi_processor_count}"
+    sig = {"events": [int(d.n_events) for d in datasets],
+           "dtype": [d.content_dtype for d in datasets],
+           "collections": [sorted(k for k in d.tensors if k.endswith(".offsets") or k.endswith(".btag"))
+                           for d in datasets],
+           "queries": [[int(q.n_scale), [len(e) - 1 for e in q.edges()], q.pu is not None, q.sf is not None,
+                        q.jes is not None] for q in queries]}
+    return device + "|" + hashlib.sha256(json.dumps(sig, sort_keys=True).encode()).hexdigest()[:24]
+
+
+def autotune(datasets: List[DeviceDataset], queries, reps: int = 5, stream=None, cache=None,
+             device: Optional[str] = None):
+    """Fastest launch configuration for these datasets and queries
+    (hepk_autotune), and its median time in ms.  cache: a JSON file path (None:
+    autotune_cache_path(); False: no cache) holding earlier results keyed by
+    workload_key; a hit returns the stored result without searching."""
+    import json
     import torch
+    path = autotune_cache_path() if cache is None else cache
+    key = workload_key(datasets, queries, device) if path else None
+    table = {}
+    if path and os.path.exists(path):
+        try:
+            with open(path) as f:
+                table = json.load(f)
+        except (OSError, ValueError):
+            table = {}
+        if key in table:
+            hit = table[key]
+            return dict(hit["tune"]), float(hit["ms"])
     keep = []
     dsa = (DatasetS * len(datasets))(*[d.struct() for d in datasets])
     qa = (QueryS * len(queries))(*[query_struct(q, keep) for q in queries])
@@ -674,4 +725,12 @@ def autotune(datasets: List[DeviceDataset], queries, reps: int = 5, stream=None)
     ms = C.c_float()
     _call("hepk_autotune", dsa, len(datasets), qa, len(queries), _ptr(s), _ptr(c), reps,
           C.byref(best), C.byref(ms), _stream(stream))
-    return best.as_dict(), ms.value
+    res = best.as_dict(), ms.value
+    if path:
+        table[key] = {"tune": res[0], "ms": res[1]}
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    return res

@@ -9,9 +9,16 @@ launches when a query slot and histogram memory are free, joins the scan at
 the current chunk, and completes after C launches (every chunk seen once);
 its histograms are then copied to the host and its slot is cleared and freed.
 Queries arriving while others run therefore overlap on the device instead of
-waiting in a queue.  Results do not depend on the chunk a query starts at:
-counts are exact in any order, and float64 sums of float32 weights are exact
-in any order while partial sums stay below 2^53 of the smallest weight's ulp.
+waiting in a queue.  Histogram memory is an arena of the device budget: each
+admitted query's histograms are placed in a free range of it (first fit), so
+the budget, not a fixed per-slot reservation, decides how many queries and
+how many bins fit at once; a query larger than the whole arena is rejected.
+A query can be cancelled, or given a deadline after which it is dropped
+(waiting or running); its slot and arena range are then freed.
+
+Results do not depend on the chunk a query starts at: counts are exact in any
+order, and float64 sums of float32 weights are exact in any order while
+partial sums stay below 2^53 of the smallest weight's ulp.
 
 Scheduler and device are separated by a small backend interface
 (GpuBackend here), so the scheduling logic can be exercised without a GPU.
@@ -27,13 +34,21 @@ from typing import Callable, Deque, Dict, List, Optional
 
 @dataclass
 class Ticket:
-    """One submitted query and what happened to it."""
+    """One submitted query and what happened to it.
+
+    status: pending, active, finishing, done, cancelled, timeout, rejected.
+    Times: arrival, admitted (a slot and an arena range given), retired (its
+    last chunk pass enqueued), done (histograms on the host, or dropped)."""
     qid: int
     query: object
     arrival: float
+    deadline: float = math.inf
+    status: str = "pending"
     admitted: float = math.nan
+    retired: float = math.nan
     done: float = math.nan
     slot: int = -1
+    at: int = -1                       # first histogram slot in the arena
     start_chunk: int = -1
     chunks_seen: int = 0
     hist_bytes: int = 0
@@ -44,16 +59,69 @@ class Ticket:
     def latency(self) -> float:
         return self.done - self.arrival
 
+    @property
+    def queue_wait(self) -> float:
+        return self.admitted - self.arrival
+
+    @property
+    def scan(self) -> float:
+        return self.retired - self.admitted
+
+    @property
+    def copy_out(self) -> float:
+        return self.done - self.retired
+
+
+def query_slots(q) -> int:
+    """Histogram slots of one query: nbins + 2 per observable and scale."""
+    return q.n_scale * sum(len(e) + 1 for e in q.edges())
+
 
 def query_hist_bytes(q) -> int:
     """Device histogram memory of one query: float64 + uint64 per slot."""
-    return 16 * q.n_scale * sum(len(e) + 1 for e in q.edges())
+    return 16 * query_slots(q)
+
+
+class Arena:
+    """First-fit allocator of histogram slots [0, size) with coalescing."""
+
+    def __init__(self, size: int):
+        self.size = size
+        self.free = [(0, size)] if size > 0 else []   # sorted (start, length)
+
+    def alloc(self, n: int) -> int:
+        for i, (a, m) in enumerate(self.free):
+            if m >= n:
+                if m == n:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (a + n, m - n)
+                return a
+        return -1
+
+    def release(self, a: int, n: int) -> None:
+        self.free.append((a, n))
+        self.free.sort()
+        merged = []
+        for s, m in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == s:
+                merged[-1] = (merged[-1][0], merged[-1][1] + m)
+            else:
+                merged.append((s, m))
+        self.free = merged
+
+    def used(self) -> int:
+        return self.size - sum(m for _, m in self.free)
 
 
 class GpuBackend:
-    """Device side of the server: one plan, shared histograms, query slots."""
+    """Device side of the server: one plan over the chunks, query slots, and
+    one histogram arena of hist_budget bytes shared by the admitted queries
+    (each placed by the scheduler); queries may have up to max_bins bins per
+    histogram."""
 
-    def __init__(self, dd, n_chunks: int, n_slots: int, max_bins: int = 200, tune=None, stream=None):
+    def __init__(self, dd, n_chunks: int, n_slots: int, hist_budget: int = 1 << 26, max_bins: int = 2000,
+                 tune=None, stream=None):
         import torch
         from . import datagen
         from . import hepk as H
@@ -64,25 +132,23 @@ class GpuBackend:
         self.chunks = [dd.view(bounds[c], bounds[c + 1]) for c in range(n_chunks)]
         self.n_chunks = n_chunks
         self.n_slots = n_slots
+        self.arena_slots = hist_budget // 16
         self.stream = stream or torch.cuda.current_stream()
         placeholder = datagen.Query()
         self.plan = H.Plan(self.chunks, [placeholder] * n_slots, tune, shared_hist=True,
-                           reserve_bins=max_bins)
+                           reserve_bins=max_bins, hist_arena_slots=self.arena_slots)
         self.sumw, self.counts = self.plan.new_hists()
         self.max_bins = max_bins
         for s in range(n_slots):
             self.plan.set_query(s, None, self.stream)
-        self.blocks = []      # per slot: [(offset, nbins_capacity)] * 3
-        for s in range(n_slots):
-            self.blocks.append([self.plan.hist_offset(0, s, 0, h)[0] for h in range(3)])
         # pinned host staging for results, one per slot
         width = max_bins + 2
         self.pin_s = torch.zeros((n_slots, 3, width), dtype=torch.float64).pin_memory()
         self.pin_c = torch.zeros((n_slots, 3, width), dtype=torch.int64).pin_memory()
         self.launch_events: Deque = collections.deque()
 
-    def set_query(self, slot: int, q) -> None:
-        self.plan.set_query(slot, q, self.stream)
+    def set_query(self, slot: int, q, at: int = -1) -> None:
+        self.plan.set_query(slot, q, self.stream, at=None if q is None or at < 0 else at)
 
     def launch(self, chunk: int) -> None:
         torch = self.torch
@@ -101,19 +167,32 @@ class GpuBackend:
         if self.launch_events:
             self.launch_events.popleft().synchronize()
 
-    def snapshot_and_clear(self, slot: int, q):
-        """Enqueue: copy the slot's histograms to pinned host memory, then zero them."""
+    def _blocks(self, q, at: int):
+        off = at
+        for e in q.edges():
+            nb = len(e) + 1
+            yield off, nb
+            off += nb
+
+    def snapshot_and_clear(self, slot: int, q, at: int):
+        """Enqueue: copy the query's histograms to the slot's pinned host
+        memory, then zero its arena range."""
         torch = self.torch
         with torch.cuda.stream(self.stream):
-            for h, e in enumerate(q.edges()):
-                off, nb = self.blocks[slot][h], len(e) + 1
+            for h, (off, nb) in enumerate(self._blocks(q, at)):
                 self.pin_s[slot, h, :nb].copy_(self.sumw[off:off + nb], non_blocking=True)
                 self.pin_c[slot, h, :nb].copy_(self.counts[off:off + nb], non_blocking=True)
-                self.sumw[off:off + nb].zero_()
-                self.counts[off:off + nb].zero_()
+            self.sumw[at:at + query_slots(q)].zero_()
+            self.counts[at:at + query_slots(q)].zero_()
             ev = torch.cuda.Event()
             ev.record(self.stream)
         return ev
+
+    def clear(self, slot: int, q, at: int) -> None:
+        """Enqueue: zero a dropped query's arena range (after its passes)."""
+        with self.torch.cuda.stream(self.stream):
+            self.sumw[at:at + query_slots(q)].zero_()
+            self.counts[at:at + query_slots(q)].zero_()
 
     def ready(self, snap) -> bool:
         return snap.query()
@@ -133,20 +212,27 @@ class GpuBackend:
 
 
 class Server:
-    """Continuous-batching scheduler over a backend with C chunks and S slots.
+    """Continuous-batching scheduler over a backend with C chunks, S slots and
+    a histogram arena of backend.arena_slots slots.
 
     hist_budget: device bytes of histograms that admitted queries may hold
-    (admission stops when the next query would exceed it).
-    max_ahead: launches allowed in flight before the host waits.
+    (at most the arena; admission stops when the next query's range does not
+    fit).  timeout: seconds after arrival after which a query that has not
+    finished is dropped (None: never).  max_ahead: launches allowed in flight
+    before the host waits.
     """
 
-    def __init__(self, backend, hist_budget: int = 1 << 30, max_ahead: int = 2,
+    def __init__(self, backend, hist_budget: Optional[int] = None, max_ahead: int = 2,
+                 timeout: Optional[float] = None,
                  clock: Callable[[], float] = time.perf_counter,
                  sleep: Callable[[float], None] = time.sleep):
         self.b = backend
         self.C = backend.n_chunks
-        self.hist_budget = hist_budget
+        arena = backend.arena_slots if hist_budget is None else min(backend.arena_slots, hist_budget // 16)
+        self.arena = Arena(arena)
+        self.hist_budget = 16 * arena
         self.max_ahead = max_ahead
+        self.timeout = timeout
         self.clock = clock
         self.sleep = sleep
         self.pending: Deque[Ticket] = collections.deque()
@@ -154,25 +240,48 @@ class Server:
         self.active: Dict[int, Ticket] = {}
         self.finishing: List[Ticket] = []
         self.done: List[Ticket] = []
+        self.dropped: List[Ticket] = []
         self.chunk = 0
-        self.hist_used = 0
         self.launches = 0
         self._qid = 0
 
+    @property
+    def hist_used(self) -> int:
+        return 16 * self.arena.used()
+
     # -------------------------------------------------------------- interface
-    def submit(self, q, arrival: Optional[float] = None) -> Ticket:
+    def submit(self, q, arrival: Optional[float] = None, timeout: Optional[float] = None) -> Ticket:
         t = Ticket(self._qid, q, self.clock() if arrival is None else arrival)
         t.hist_bytes = query_hist_bytes(q)
+        limit = self.timeout if timeout is None else timeout
+        if limit is not None:
+            t.deadline = t.arrival + limit
         self._qid += 1
-        self.pending.append(t)
+        if query_slots(q) > self.arena.size:
+            self._drop(t, "rejected")
+        else:
+            self.pending.append(t)
         return t
+
+    def cancel(self, t: Ticket) -> bool:
+        """Drops a waiting or running query (False if it already finished)."""
+        if t.status == "pending":
+            self.pending.remove(t)
+            self._drop(t, "cancelled")
+            return True
+        if t.status == "active":
+            self._stop(t, "cancelled")
+            return True
+        return False
 
     def busy(self) -> bool:
         return bool(self.pending or self.active or self.finishing)
 
     def step(self) -> None:
-        """Retire finished queries, admit waiting ones, launch one chunk pass."""
+        """Retire finished queries, drop expired ones, admit waiting ones,
+        launch one chunk pass."""
         self._collect()
+        self._expire()
         self._admit()
         if self.active:
             while self.b.in_flight() >= self.max_ahead:
@@ -217,39 +326,68 @@ class Server:
     def _admit(self) -> None:
         while self.pending and self.free:
             t = self.pending[0]
-            if self.active and self.hist_used + t.hist_bytes > self.hist_budget:
-                break
+            at = self.arena.alloc(query_slots(t.query))
+            if at < 0:
+                break  # its histograms do not fit until running queries finish
             self.pending.popleft()
             t.slot = self.free.pop()
+            t.at = at
+            t.status = "active"
             t.admitted = self.clock()
             t.start_chunk = self.chunk
-            self.hist_used += t.hist_bytes
-            self.b.set_query(t.slot, t.query)
+            self.b.set_query(t.slot, t.query, at)
             self.active[t.slot] = t
+
+    def _expire(self) -> None:
+        now = self.clock()
+        for t in [t for t in self.pending if t.deadline <= now]:
+            self.pending.remove(t)
+            self._drop(t, "timeout")
+        for t in [t for t in self.active.values() if t.deadline <= now]:
+            self._stop(t, "timeout")
+
+    def _drop(self, t: Ticket, why: str) -> None:
+        t.status = why
+        t.done = self.clock()
+        self.dropped.append(t)
+
+    def _stop(self, t: Ticket, why: str) -> None:
+        # stream order: the passes already enqueued, then the slot goes idle
+        # and the range is zeroed, then it may be given to another query
+        self.b.set_query(t.slot, None)
+        self.b.clear(t.slot, t.query, t.at)
+        del self.active[t.slot]
+        self.free.append(t.slot)
+        self.arena.release(t.at, query_slots(t.query))
+        self._drop(t, why)
 
     def _retire(self, t: Ticket) -> None:
         # a slot's host staging holds one result: collect an earlier one first
         for u in [u for u in self.finishing if u.slot == t.slot]:
-            u.result = self.b.result(u.slot, u.query, u._snap)
-            u.done = self.clock()
-            self.done.append(u)
+            self._finish(u, self.b.result(u.slot, u.query, u._snap))
             self.finishing.remove(u)
         # stream order: this query's last pass, then the copy-out and clearing,
         # then the slot's next query
-        t._snap = self.b.snapshot_and_clear(t.slot, t.query)
+        t.retired = self.clock()
+        t._snap = self.b.snapshot_and_clear(t.slot, t.query, t.at)
         self.b.set_query(t.slot, None)
         del self.active[t.slot]
+        t.status = "finishing"
         self.finishing.append(t)
         self.free.append(t.slot)
-        self.hist_used -= t.hist_bytes
+        self.arena.release(t.at, query_slots(t.query))
+
+    def _finish(self, t: Ticket, result) -> None:
+        t.result = result
+        t.done = self.clock()
+        t.status = "done"
+        self.done.append(t)
 
     def _collect(self) -> None:
         keep = []
         for t in self.finishing:
             if self.b.ready(t._snap):
-                t.result = self.b.result(t.slot, t.query, t._snap)
-                t.done = self.clock()
-                self.done.append(t)
+                self._finish(t, self.b.result(t.slot, t.query, t._snap))
             else:
                 keep.append(t)
         self.finishing = keep
@@ -257,9 +395,7 @@ class Server:
     def _drain(self) -> None:
         while self.finishing:
             t = self.finishing.pop(0)
-            t.result = self.b.result(t.slot, t.query, t._snap)
-            t.done = self.clock()
-            self.done.append(t)
+            self._finish(t, self.b.result(t.slot, t.query, t._snap))
 
 
 def percentile(xs, p: float) -> float:

@@ -189,3 +189,25 @@ def test_slot_range_graph_autotune_reject_bad_arguments(lib):
     opts = H.PlanOpts(H.Tune(0, 0, 0, 0), 0, 0)
     assert _rc("hepk_plan_create_ex", ds, 1, q, 1, C.byref(opts), C.byref(out)) == H.EINVAL
     assert "increasing" in H.last_error()
+
+
+def test_autotune_cache_hit_needs_no_device(tmp_path):
+    """A stored launch-configuration search result is returned for the same
+    device and workload without searching (no device call on this path)."""
+    import json
+    from paper_1906_06242_amd import datagen
+
+    class Fake:  # the fields workload_key reads of a resident dataset
+        def __init__(self, n):
+            self.n_events, self.content_dtype = n, "f32"
+            self.tensors = {"jets.offsets": None, "muons.offsets": None}
+    dds, qs = [Fake(1000), Fake(20)], [datagen.Query()]
+    key = H.workload_key(dds, qs, device="dev0")
+    assert key != H.workload_key([Fake(1001), Fake(20)], qs, device="dev0")
+    assert key != H.workload_key(dds, qs, device="dev1")
+    assert key != H.workload_key(dds, [datagen.Query(scales=datagen.jes_scales())], device="dev0")
+    path = tmp_path / "autotune.json"
+    path.write_text(json.dumps({key: {"tune": {"block": 256, "ev_per_thread": 2, "hist_mode": 0, "grid": 0},
+                                      "ms": 1.5}}))
+    best, ms = H.autotune(dds, qs, cache=str(path), device="dev0")
+    assert best["block"] == 256 and best["ev_per_thread"] == 2 and ms == 1.5

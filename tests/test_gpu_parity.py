@@ -743,12 +743,19 @@ def test_graph_replays_match_eager():
     plan.close()
 
 
-def test_autotune_picks_a_valid_configuration():
+def test_autotune_picks_a_valid_configuration(tmp_path, monkeypatch):
     say("autotune")
     dss = [datagen.make_dataset(4000 + i, n) for i, n in enumerate([30000, 5000, 60000])]
     q = datagen.Query()
     dds = [H.DeviceDataset(d) for d in dss]
-    best, ms = H.autotune(dds, [q], reps=3)
+    cache = str(tmp_path / "autotune.json")
+    best, ms = H.autotune(dds, [q], reps=3, cache=cache)
+    # the second search of the same workload on this device is the stored result
+    calls = []
+    real = H._call
+    monkeypatch.setattr(H, "_call", lambda name, *a: (calls.append(name), real(name, *a))[1])
+    assert H.autotune(dds, [q], reps=3, cache=cache) == (best, ms) and "hepk_autotune" not in calls
+    monkeypatch.undo()
     assert best["block"] in (256, 512, 1024) and best["ev_per_thread"] in (1, 2) and best["hist_mode"] in (0, 1)
     assert best["block"] < 1024 or best["ev_per_thread"] == 1
     assert ms > 0
