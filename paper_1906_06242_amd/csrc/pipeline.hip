@@ -395,11 +395,16 @@ int plan_build(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_
                       : (p->ms ? pick_kernel<true, false, false> : pick_kernel<false, false, false>);
     auto pick_dbg = p->lk ? (p->ms ? pick_kernel<true, true, true> : pick_kernel<false, true, true>)
                           : (p->ms ? pick_kernel<true, true, false> : pick_kernel<false, true, false>);
-    p->fn_lds = pick(dtype, ext, t.block, t.ev_per_thread, true);
-    p->fn_glob = pick(dtype, ext, t.block, t.ev_per_thread, false);
-    p->fn_lds_dbg = pick_dbg(dtype, ext, t.block, t.ev_per_thread, true);
-    p->fn_glob_dbg = pick_dbg(dtype, ext, t.block, t.ev_per_thread, false);
-    {
+    // With the default launch shape, a smaller workgroup is taken when the
+    // histograms do not fit in LDS beside a larger one's per-wavefront
+    // staging (many histograms with squared weights): LDS histograms at lower
+    // occupancy beat global atomics on a few hot bins by far.
+    const bool default_block = o.tune.block == 0;
+    for (;;) {
+        p->fn_lds = pick(dtype, ext, t.block, t.ev_per_thread, true);
+        p->fn_glob = pick(dtype, ext, t.block, t.ev_per_thread, false);
+        p->fn_lds_dbg = pick_dbg(dtype, ext, t.block, t.ev_per_thread, true);
+        p->fn_glob_dbg = pick_dbg(dtype, ext, t.block, t.ev_per_thread, false);
         hipFuncAttributes fa{}, fg{}, fad{}, fgd{};
         int mx = 0;
         if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(p->fn_lds)) != hipSuccess ||
@@ -416,12 +421,17 @@ int plan_build(const hepk_dataset *ds, int32_t n_ds, const hepk_query *q, int32_
         p->dbg_ok = fad.sharedSizeBytes == fa.sharedSizeBytes && fgd.sharedSizeBytes == fg.sharedSizeBytes;
         p->lds_max = static_cast<size_t>(mx);
         // the tables go to LDS only if they fit beside the kernel's own LDS
+        p->edges_lds = static_cast<size_t>(p->n_edges) * sizeof(float) <= static_cast<size_t>(kMaxLdsEdgeBytes);
+        p->scales_lds = static_cast<size_t>(p->n_scales) * sizeof(float) <= static_cast<size_t>(kMaxLdsScaleBytes);
         if (p->lds_static_glob + table_lds_bytes(p) > p->lds_max) p->edges_lds = p->scales_lds = false;
         if (p->lds_static_glob + table_lds_bytes(p) > p->lds_max) {
             set_error("hepk_plan_create: kernel needs %zu bytes of LDS, device has %zu", p->lds_static_glob,
                       p->lds_max);
             return plan_fail(p, HEPK_EUNSUPPORTED);
         }
+        if (!default_block || t.hist_mode != 0 || use_lds_hist(p) || t.block == 256) break;
+        t.block = t.block == 1024 ? 512 : 256;
+        p->tune = t;
     }
     const size_t lds_hist = use_lds_hist(p) ? hist_lds_bytes(p) : 0;
     const size_t lds_bytes = lds_hist + table_lds_bytes(p);

@@ -1230,10 +1230,11 @@ KernelFn pick_kernel(int dtype, bool ext, int block, int evpt, bool ldsh) {
                : pick_shape<float, false, MS, DBG, LK>(block, evpt, ldsh);
 }
 
-// LDS for the workgroup's private histograms: up to 64 KiB (60 histograms of
-// 100 bins fit); larger sets go to global atomics.  More LDS lowers occupancy,
+// LDS for the workgroup's private histograms: up to 144 KiB (60 histograms of
+// 100 bins with squared weights fit), as long as the workgroup's total fits
+// the device; larger sets go to global atomics.  More LDS lowers occupancy,
 // which the launch-configuration search weighs against atomic contention.
-constexpr int kMaxLdsHistBytes = 64 * 1024;
+constexpr int kMaxLdsHistBytes = 144 * 1024;
 constexpr int kMaxLdsEdgeBytes = 4 * 1024;
 constexpr int kMaxLdsScaleBytes = 1024;
 

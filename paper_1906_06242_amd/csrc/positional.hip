@@ -77,6 +77,10 @@ __device__ __forceinline__ bool opposite_sign(int32_t a, int32_t b) { return (a 
 // charges whose (rank, rank) is smallest in lexicographic order -- the first
 // object in pT order that has an opposite-charge partner after it, and its
 // first such partner.  Both get mask 1, every other object of the event 0.
+// Events of up to kOsRegs objects are held in registers (one read of each
+// column per object); larger ones are ranked straight from memory.
+constexpr int kOsRegs = 8;
+
 template <typename T>
 __global__ __launch_bounds__(PB) void opposite_sign_kernel(const int64_t *__restrict__ off, int64_t n_events,
                                                            const T *__restrict__ pt, const int32_t *__restrict__ q,
@@ -85,6 +89,48 @@ __global__ __launch_bounds__(PB) void opposite_sign_kernel(const int64_t *__rest
     const int64_t stride = static_cast<int64_t>(gridDim.x) * PB;
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * PB + threadIdx.x; e < n_events; e += stride) {
         const int64_t i0 = off[e], i1 = off[e + 1];
+        const int64_t n = i1 - i0;
+        if (n <= kOsRegs) {
+            float p[kOsRegs];
+            int32_t c[kOsRegs];
+            bool s[kOsRegs];
+#pragma unroll
+            for (int k = 0; k < kOsRegs; ++k) {
+                p[k] = 0.0f;
+                c[k] = 0;
+                s[k] = false;
+                if (k < n) {
+                    p[k] = ldf(pt, i0 + k);
+                    c[k] = q[i0 + k];
+                    s[k] = !om || om[i0 + k] != 0;
+                }
+            }
+            int rank[kOsRegs];
+#pragma unroll
+            for (int a = 0; a < kOsRegs; ++a) {
+                rank[a] = 0;
+#pragma unroll
+                for (int b = 0; b < kOsRegs; ++b)
+                    rank[a] += (b != a && s[b] && pt_before(p[b], b, p[a], a)) ? 1 : 0;
+            }
+            int ba = -1, bb = -1, ra = kOsRegs, rb = kOsRegs;
+#pragma unroll
+            for (int a = 0; a < kOsRegs; ++a)
+#pragma unroll
+                for (int b = 0; b < kOsRegs; ++b) {
+                    const bool ok = s[a] && s[b] && rank[a] < rank[b] && opposite_sign(c[a], c[b]);
+                    if (ok && (rank[a] < ra || (rank[a] == ra && rank[b] < rb))) {
+                        ra = rank[a];
+                        rb = rank[b];
+                        ba = a;
+                        bb = b;
+                    }
+                }
+#pragma unroll
+            for (int k = 0; k < kOsRegs; ++k)
+                if (k < n) out[i0 + k] = (k == ba || k == bb) ? 1 : 0;
+            continue;
+        }
         int64_t ba = -1, bb = -1, ra = INT64_MAX, rb = INT64_MAX;
         for (int64_t a = i0; a < i1; ++a) {
             out[a] = 0;

@@ -4,16 +4,30 @@
 //
 // hepk_p4 turns (pt, eta, phi, mass) into Cartesian four-momenta
 // (elementwise).  hepk_best_triplet searches, per event, every triplet of
-// selected objects: each wavefront owns tiles of 64 consecutive events,
-// stages the tile's four-momenta and mask in its LDS with all loads in
-// flight, and one lane per event runs over its triplets (i < j < k) in
-// order, the pair sum i + j held while k runs.  Per triplet: three float32
-// sums per component, the mass square E^2 - px^2 - py^2 - pz^2 (each product
-// and difference rounded on its own), a correctly rounded square root and
-// the distance to the target; a strict '<' keeps the first triplet on ties.
-// The search is the first part of the analysis whose work grows faster than
-// its input (C(n, 3) triplets for n jets).  Tiles with more objects than the
-// LDS staging holds walk their events straight from HBM.
+// selected objects.  The work per event grows as C(n, 3), so one lane per
+// event would leave most lanes of a wavefront idle behind its densest event;
+// instead each wavefront owns tiles of 64 consecutive events and spreads the
+// tile's triplets evenly over its 64 lanes:
+//   1. the tile's objects are loaded with all loads in flight, and the
+//      selected ones compacted by wavefront ballot into LDS (four-momenta and
+//      local index), so each event's selected objects are contiguous;
+//   2. the events' triplet counts C(n_e, 3) are prefix-summed across the
+//      wavefront;
+//   3. lane l takes the l-th 1/64 of the tile's triplets in lexicographic
+//      order (i < j < k within an event, events in order), finds its first
+//      triplet by a search over the prefix sums and the combinatorial number
+//      system, and walks on from there;
+//   4. per triplet: three float32 sums per component, the mass square
+//      E^2 - px^2 - py^2 - pz^2 (each product and difference rounded on its
+//      own), a correctly rounded square root and the distance d to the
+//      target; a lane keeps the smallest (d, rank in the event) and merges it
+//      with an LDS 64-bit atomic minimum when it leaves an event, which keeps
+//      the first triplet in order on ties (a NaN or infinite d is never
+//      taken);
+//   5. each event lane turns its minimum back into (i, j, k) and recomputes
+//      the mass with the same operations.
+// Tiles with more objects than the LDS staging holds search their events one
+// lane per event straight from HBM.
 #include "common.hpp"
 
 namespace hepk {
@@ -89,15 +103,57 @@ __device__ __forceinline__ Best search(const P &X, const P &Y, const P &Z, const
     return b;
 }
 
+// Triplets with first index i among n objects: C(n - i - 1, 2).
+__device__ __forceinline__ int64_t c2(int64_t m) { return m * (m - 1) / 2; }
+__device__ __forceinline__ int64_t c3(int64_t m) { return m * (m - 1) * (m - 2) / 6; }
+
+// Mass of a triplet and its distance to the target (the arithmetic of the
+// search; NaN stays NaN).
+__device__ __forceinline__ void triplet_mass(const float *X, const float *Y, const float *Z, const float *E, int i, int j,
+                                             int k, float target, float &mm, float &d) {
+    const float sx = (X[i] + X[j]) + X[k], sy = (Y[i] + Y[j]) + Y[k];
+    const float sz = (Z[i] + Z[j]) + Z[k], se = (E[i] + E[j]) + E[k];
+    float m2 = se * se;
+    m2 = m2 - sx * sx;
+    m2 = m2 - sy * sy;
+    m2 = m2 - sz * sz;
+    mm = (m2 < 0.0f) ? 0.0f : sqrtf(m2);
+    d = fabsf(mm - target);
+}
+
+// (i, j, k) of the triplet of lexicographic rank r among n objects.
+__device__ __forceinline__ void unrank(int64_t r, int n, int &i, int &j, int &k) {
+    i = 0;
+    while (r >= c2(n - i - 1)) {
+        r -= c2(n - i - 1);
+        ++i;
+    }
+    j = i + 1;
+    while (r >= n - j - 1) {
+        r -= n - j - 1;
+        ++j;
+    }
+    k = j + 1 + static_cast<int>(r);
+}
+
+struct TripletLds {
+    float x[64 * TK], y[64 * TK], z[64 * TK], e[64 * TK];  // selected objects, compacted
+    uint16_t li[64 * TK];                                  // their local index in the event
+    uint16_t pre[64 * TK + 1];                             // selected objects before each object
+    int64_t tp[65];                                        // triplets of the events before each
+    uint64_t key[64];                                      // per event: min (d bits << 32 | rank)
+    int32_t s0[64], n[64];                                 // per event: first selected, count
+};
+
 __global__ __launch_bounds__(TB) void best_triplet_kernel(const int64_t *__restrict__ off, int64_t n_events,
                                                           const float *__restrict__ px, const float *__restrict__ py,
                                                           const float *__restrict__ pz, const float *__restrict__ en,
                                                           const uint8_t *__restrict__ om, float target,
                                                           float *__restrict__ out_mass, int32_t *__restrict__ out_idx) {
-    __shared__ float sx[TWV][64 * TK], sy[TWV][64 * TK], sz[TWV][64 * TK], se[TWV][64 * TK];
-    __shared__ uint8_t sm[TWV][64 * TK];
+    __shared__ TripletLds lds[TWV];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    TripletLds &L = lds[wave];
     const int64_t n_tiles = ceil_div(n_events, 64);
     const int64_t step = static_cast<int64_t>(gridDim.x) * TWV;
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * TWV + wave; t < n_tiles; t += step) {
@@ -112,53 +168,150 @@ __global__ __launch_bounds__(TB) void best_triplet_kernel(const int64_t *__restr
             a0 = off[e] - A;
             a1 = off[e + 1] - A;
         }
-        Best b;
-        if (tot <= 64 * TK) {
-            const int n = static_cast<int>(tot);
-            float vx[TK], vy[TK], vz[TK], ve[TK];
-            uint8_t vm[TK];
-#pragma unroll
-            for (int k = 0; k < TK; ++k) {
-                const int i = lane + 64 * k;
-                vx[k] = vy[k] = vz[k] = ve[k] = 0.0f;
-                vm[k] = 0;
-                if (i < n) {
-                    vx[k] = px[A + i];
-                    vy[k] = py[A + i];
-                    vz[k] = pz[A + i];
-                    ve[k] = en[A + i];
-                    vm[k] = om ? om[A + i] : 1;
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < TK; ++k) {
-                const int i = lane + 64 * k;
-                if (i < n) {
-                    sx[wave][i] = vx[k];
-                    sy[wave][i] = vy[k];
-                    sz[wave][i] = vz[k];
-                    se[wave][i] = ve[k];
-                    sm[wave][i] = vm[k];
-                }
-            }
-            wave_fence_t();
+        if (tot > 64 * TK) {
+            // dense tile: one lane per event from HBM
+            Best b;
             if (act) {
-                const uint8_t *msk = sm[wave];
-                auto sel = [&](int64_t i) { return msk[i] != 0; };
-                b = search(sx[wave], sy[wave], sz[wave], se[wave], sel, a0, a1 - a0, target);
+                auto sel = [&](int64_t i) { return !om || om[A + i] != 0; };
+                b = search(px + A, py + A, pz + A, en + A, sel, a0, a1 - a0, target);
+                out_mass[e] = b.m;
+                out_idx[3 * e] = b.i;
+                out_idx[3 * e + 1] = b.j;
+                out_idx[3 * e + 2] = b.k;
             }
-            wave_fence_t();  // the next tile overwrites the staging
-        } else if (act) {
-            auto sel = [&](int64_t i) { return !om || om[A + i] != 0; };
-            const float *X = px + A, *Y = py + A, *Z = pz + A, *E = en + A;
-            b = search(X, Y, Z, E, sel, a0, a1 - a0, target);
+            continue;
         }
+        // 1. loads, then the selected objects compacted in tile order
+        const int nobj = static_cast<int>(tot);
+        float vx[TK], vy[TK], vz[TK], ve[TK];
+        bool sel[TK];
+#pragma unroll
+        for (int k = 0; k < TK; ++k) {
+            const int i = lane + 64 * k;
+            vx[k] = vy[k] = vz[k] = ve[k] = 0.0f;
+            sel[k] = false;
+            if (i < nobj) {
+                vx[k] = px[A + i];
+                vy[k] = py[A + i];
+                vz[k] = pz[A + i];
+                ve[k] = en[A + i];
+                sel[k] = !om || om[A + i] != 0;
+            }
+        }
+        int run = 0;
+#pragma unroll
+        for (int k = 0; k < TK; ++k) {
+            const int i = lane + 64 * k;
+            const uint64_t bal = __ballot(sel[k]);
+            const int before = run + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+                                         static_cast<uint32_t>(bal >> 32),
+                                         __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bal), 0u)));
+            if (i < nobj) L.pre[i] = static_cast<uint16_t>(before);
+            if (sel[k]) {
+                L.x[before] = vx[k];
+                L.y[before] = vy[k];
+                L.z[before] = vz[k];
+                L.e[before] = ve[k];
+            }
+            run += __popcll(bal);
+        }
+        if (lane == 0) L.pre[nobj] = static_cast<uint16_t>(run);
+        wave_fence_t();
+        // 2. per event: first selected object, count, triplets; the local
+        // index of each selected object; prefix sums over the tile
+        int s0 = 0, nn = 0;
         if (act) {
-            out_mass[e] = b.m;
-            out_idx[3 * e] = b.i;
-            out_idx[3 * e + 1] = b.j;
-            out_idx[3 * e + 2] = b.k;
+            s0 = L.pre[a0];
+            nn = L.pre[a1] - s0;
+            for (int64_t i = a0; i < a1; ++i)
+                if (L.pre[i + 1] != L.pre[i]) L.li[L.pre[i]] = static_cast<uint16_t>(i - a0);
         }
+        const int64_t tcount = act ? c3(nn) : 0;
+        int64_t incl = tcount;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t up = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += up;
+        }
+        L.tp[lane + 1] = incl;
+        if (lane == 0) L.tp[0] = 0;
+        L.s0[lane] = s0;
+        L.n[lane] = nn;
+        L.key[lane] = ~0ull;
+        wave_fence_t();
+        // 3-4. this lane's share of the tile's triplets
+        const int64_t T = L.tp[64];
+        const int64_t t0 = T * lane / 64, t1 = T * (lane + 1) / 64;
+        if (t0 < t1) {
+            int ev = 0;  // the last event with tp[ev] <= t0
+            for (int lo = 0, hi = 63; lo <= hi;) {
+                const int mid = (lo + hi) >> 1;
+                if (L.tp[mid] <= t0) {
+                    ev = mid;
+                    lo = mid + 1;
+                } else {
+                    hi = mid - 1;
+                }
+            }
+            while (L.tp[ev + 1] <= t0) ++ev;  // skip events without triplets
+            int n = L.n[ev], base = L.s0[ev];
+            int64_t rank = t0 - L.tp[ev];
+            int i, j, k;
+            unrank(rank, n, i, j, k);
+            uint64_t best = ~0ull;
+            for (int64_t tt = t0; tt < t1; ++tt) {
+                float mm, d;
+                triplet_mass(L.x + base, L.y + base, L.z + base, L.e + base, i, j, k, target, mm, d);
+                if (d < INFINITY) {  // NaN and infinite distances are never taken
+                    const uint64_t key = (static_cast<uint64_t>(__float_as_uint(d)) << 32) | static_cast<uint64_t>(rank);
+                    best = key < best ? key : best;
+                }
+                // next triplet in order
+                ++rank;
+                if (++k == n) {
+                    if (++j == n - 1) {
+                        if (++i == n - 2) {
+                            // the event is done: merge and move to the next with triplets
+                            if (best != ~0ull) atomicMin(reinterpret_cast<unsigned long long *>(&L.key[ev]), best);
+                            best = ~0ull;
+                            if (tt + 1 < t1) {
+                                do {
+                                    ++ev;
+                                } while (L.tp[ev + 1] == L.tp[ev]);
+                                n = L.n[ev];
+                                base = L.s0[ev];
+                            }
+                            i = 0;
+                            rank = 0;
+                        }
+                        j = i + 1;
+                    }
+                    k = j + 1;
+                }
+            }
+            if (best != ~0ull) atomicMin(reinterpret_cast<unsigned long long *>(&L.key[ev]), best);
+        }
+        wave_fence_t();
+        // 5. each event's minimum back to its triplet and mass
+        if (act) {
+            const uint64_t key = L.key[lane];
+            float mm = __builtin_nanf("");
+            int32_t bi = -1, bj = -1, bk = -1;
+            if (key != ~0ull) {
+                int i, j, k;
+                unrank(static_cast<int64_t>(key & 0xffffffffu), nn, i, j, k);
+                float d;
+                triplet_mass(L.x + s0, L.y + s0, L.z + s0, L.e + s0, i, j, k, target, mm, d);
+                bi = L.li[s0 + i];
+                bj = L.li[s0 + j];
+                bk = L.li[s0 + k];
+            }
+            out_mass[e] = mm;
+            out_idx[3 * e] = bi;
+            out_idx[3 * e + 1] = bj;
+            out_idx[3 * e + 2] = bk;
+        }
+        wave_fence_t();  // the next tile overwrites the staging
     }
 }
 

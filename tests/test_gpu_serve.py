@@ -63,3 +63,34 @@ def test_queries_alone_equal_mix_equal_oracle():
         starts.add(t.start_chunk)
     assert len(starts) > 1
     assert max(t.latency for t in done) > 0
+
+
+def test_arena_placement_big_binnings_and_cancel():
+    """Queries placed in a small histogram arena (memory gates admission), one
+    with 1500-bin histograms, one cancelled while running: the others equal
+    the oracle, and a query reusing the cancelled one's range starts clean."""
+    import torch
+    H.load()
+    say("serve: arena")
+    ds = datagen.make_dataset(22, 60000)
+    dd = H.DeviceDataset(ds)
+    big = datagen.Query(edges_ht=datagen.uniform_edges(1500, 0.0, 3000.0), jet_pt=35.0)
+    qs = datagen.draw_queries(10, 4, qps=2000.0)
+    from paper_1906_06242_amd.serve import query_hist_bytes
+    budget = query_hist_bytes(big) + 2 * max(query_hist_bytes(q) for q in qs)
+    be = GpuBackend(dd, n_chunks=4, n_slots=6, hist_budget=budget, max_bins=1600)
+    srv = Server(be)
+    tickets = [srv.submit(q) for q in [qs[0], big, qs[1]]]
+    srv.step()
+    victim = tickets[0]
+    assert victim.status == "active" and srv.cancel(victim)
+    tickets += [srv.submit(q) for q in qs[2:]]
+    while srv.busy():
+        srv.step()
+    srv._drain()
+    be.close()
+    assert victim.status == "cancelled"
+    for t in tickets[1:]:
+        assert t.status == "done", t.status
+        same(t.result, ref.pipeline(ds, [t.query])[0][0], f"query {t.qid} vs oracle")
+    assert srv.arena.used() == 0
