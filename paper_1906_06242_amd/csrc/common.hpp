@@ -59,6 +59,31 @@ __device__ __forceinline__ float ldf(const T *p, I i) {
     return static_cast<float>(p[i]);  // _Float16 -> float is v_cvt_f32_f16: exact
 }
 
+// A raw buffer resource over the nbytes bytes at p (gfx9 format word: 32-bit
+// data, no swizzle, stride 0).  The hardware range check turns every load at
+// a byte offset at or beyond nbytes into 0, so a load of slot i of a tile
+// needs no per-lane bounds test and no zero default.
+using buf_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ buf_t buf_span(const void *p, uint32_t nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, static_cast<int>(nbytes), 0x00020000);
+}
+
+// Element i of a float32 or float16 buffer as float (0 beyond the range).
+template <typename T>
+__device__ __forceinline__ float buf_ldf(buf_t r, int i) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, 0));
+    } else {
+        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, i * 2, 0, 0);
+        return static_cast<float>(__builtin_bit_cast(_Float16, h));
+    }
+}
+
+// The 32-bit word at byte offset `byte` of a buffer (0 beyond the range).
+__device__ __forceinline__ uint32_t buf_u32(buf_t r, int byte) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, byte, 0, 0);
+}
+
 __device__ __forceinline__ float ld_any(const void *p, int32_t dtype, int64_t i) {
     if (dtype == HEPK_F16) return static_cast<float>(static_cast<const _Float16 *>(p)[i]);
     if (dtype == HEPK_I32) return static_cast<float>(static_cast<const int32_t *>(p)[i]);

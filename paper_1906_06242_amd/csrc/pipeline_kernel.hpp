@@ -501,19 +501,22 @@ __device__ __forceinline__ void walk_selected(const WL &L, int j0, int j1, float
     lead = n > 0 ? m : -INFINITY;
 }
 
+// A tile's first object of each collection and its object counts (32-bit:
+// the counts are what the kernel compares and indexes with).
 struct TileBounds {
-    int64_t J0, J1, M0, M1, L0, L1;
+    int64_t J0, M0, L0;
+    int32_t nj, nm, nl;
 };
 
 template <bool EXT, typename DT>
 __device__ __forceinline__ TileBounds tile_bounds(const DT &D, bool has_el, int64_t e0, int ne) {
     TileBounds b;
     b.J0 = as_const(D.joff)[e0];
-    b.J1 = as_const(D.joff)[e0 + ne];
+    b.nj = static_cast<int32_t>(as_const(D.joff)[e0 + ne] - b.J0);
     b.M0 = as_const(D.moff)[e0];
-    b.M1 = as_const(D.moff)[e0 + ne];
+    b.nm = static_cast<int32_t>(as_const(D.moff)[e0 + ne] - b.M0);
     b.L0 = (EXT && has_el) ? as_const(D.eoff)[e0] : 0;
-    b.L1 = (EXT && has_el) ? as_const(D.eoff)[e0 + ne] : 0;
+    b.nl = (EXT && has_el) ? static_cast<int32_t>(as_const(D.eoff)[e0 + ne] - b.L0) : 0;
     return b;
 }
 
@@ -569,7 +572,7 @@ pipeline_kernel(PipeArgs P) {
     extern __shared__ double dyn[];
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
+    int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     auto &L = wl[wave];
 
@@ -642,83 +645,98 @@ pipeline_kernel(PipeArgs P) {
             float mpt[MK], meta[MK], mphi[MK], miso[MK];
             float lpt[EK], leta[EK], lphi[EK];
         };
-        auto lo32 = [](const int64_t *p) { return *reinterpret_cast<const uint32_t *>(p); };
-        auto bounds_of = [&](int64_t tt) {
-            const int64_t e = tt * TW;
-            return tile_bounds<EXT>(D, has_el, e, static_cast<int>(min<int64_t>(TW, D.n_events - e)));
+        // The chunk's tiles are counted from c_t0 in 32 bits (a workgroup's
+        // share of one dataset has far fewer than 2^31 tiles); only the last
+        // one can hold fewer than TW events.
+        const int nt = static_cast<int>(c_t1 - c_t0);
+        const int64_t ebase = c_t0 * TW;
+        const int tn_last = static_cast<int>(min<int64_t>(TW, D.n_events - (c_t1 - 1) * TW));
+        auto tile_events = [&](int r) { return r == nt - 1 ? tn_last : TW; };
+        auto bounds_of = [&](int r) {
+            return tile_bounds<EXT>(D, has_el, ebase + static_cast<int64_t>(r) * TW, tile_events(r));
         };
+        // (compared unsigned: a count of 2^31 to 2^32 objects, which valid
+        // offsets of one tile never give, also goes the per-event way)
         auto oversize = [&](const TileBounds &b) {
-            return b.J1 - b.J0 > C::JC || b.M1 - b.M0 > C::MC || b.L1 - b.L0 > C::EC;
+            return static_cast<uint32_t>(b.nj) > static_cast<uint32_t>(C::JC) ||
+                   static_cast<uint32_t>(b.nm) > static_cast<uint32_t>(C::MC) ||
+                   static_cast<uint32_t>(b.nl) > static_cast<uint32_t>(C::EC);
         };
         // ---- 1. all of a tile's loads, without waiting: both offsets of each
-        // event lane's event, its weight, and up to JK jets, MK muons and EK
-        // electrons per lane (consecutive lanes, consecutive objects)
+        // event lane's event (their low 32-bit words), its weight, and up to
+        // JK jets, MK muons and EK electrons per lane (consecutive lanes,
+        // consecutive objects).  Buffer loads over exactly the tile's range
+        // of each column read 0 past its end, which is the value every
+        // unused slot must hold.
         auto issue = [&](int64_t e0, int ne, const TileBounds &b, Raw &R) {
-            const int nj = static_cast<int>(b.J1 - b.J0), nm = static_cast<int>(b.M1 - b.M0);
-            const int nl = static_cast<int>(b.L1 - b.L0);
-            const float *wp = D.w ? D.w + e0 : nullptr;
-            const float *pp = LK && D.npu ? D.npu + e0 : nullptr;
+            const int nj = b.nj, nm = b.nm, nl = b.nl;
+            // offsets: events e0 .. e0 + ne (both ends of each event)
+            const uint32_t ob = static_cast<uint32_t>(ne + 1) * 8u;
+            const buf_t bjo = buf_span(D.joff + e0, ob), bmo = buf_span(D.moff + e0, ob);
+            const buf_t beo = buf_span((EXT && has_el) ? D.eoff + e0 : D.joff + e0, ob);
+            const buf_t bw = buf_span(D.w ? static_cast<const void *>(D.w + e0) : D.joff, static_cast<uint32_t>(ne) * 4u);
+            const buf_t bpu =
+                buf_span(LK && D.npu ? static_cast<const void *>(D.npu + e0) : D.joff, static_cast<uint32_t>(ne) * 4u);
 #pragma unroll
             for (int r = 0; r < EVPL; ++r) {
                 const int ev = lane + 64 * r;
-                R.j0[r] = R.j1[r] = R.m0[r] = R.m1[r] = R.l0[r] = R.l1[r] = 0;
-                R.w[r] = 1.0f;
-                if (LK) R.npu[LK ? r : 0] = 0.0f;
-                if (ev < ne) {
-                    if (LK && pp) R.npu[LK ? r : 0] = pp[ev];
-                    R.j0[r] = lo32(D.joff + e0 + ev);
-                    R.j1[r] = lo32(D.joff + e0 + ev + 1);
-                    R.m0[r] = lo32(D.moff + e0 + ev);
-                    R.m1[r] = lo32(D.moff + e0 + ev + 1);
-                    if (EXT && has_el) {
-                        R.l0[r] = lo32(D.eoff + e0 + ev);
-                        R.l1[r] = lo32(D.eoff + e0 + ev + 1);
-                    }
-                    if (wp) R.w[r] = wp[ev];
+                R.j0[r] = buf_u32(bjo, ev * 8);
+                R.j1[r] = buf_u32(bjo, ev * 8 + 8);
+                R.m0[r] = buf_u32(bmo, ev * 8);
+                R.m1[r] = buf_u32(bmo, ev * 8 + 8);
+                R.l0[r] = R.l1[r] = 0;
+                if (EXT && has_el) {
+                    R.l0[r] = buf_u32(beo, ev * 8);
+                    R.l1[r] = buf_u32(beo, ev * 8 + 8);
                 }
+                R.w[r] = D.w ? __builtin_bit_cast(float, buf_u32(bw, ev * 4)) : 1.0f;
+                if (LK) R.npu[LK ? r : 0] = D.npu ? __builtin_bit_cast(float, buf_u32(bpu, ev * 4)) : 0.0f;
             }
-            const T *cjpt = static_cast<const T *>(D.jpt) + b.J0, *cjeta = static_cast<const T *>(D.jeta) + b.J0;
-            const T *cjphi = static_cast<const T *>(D.jphi) + b.J0;
-            const T *cjbt = has_bt ? static_cast<const T *>(D.jbt) + b.J0 : nullptr;
+            const uint32_t es = sizeof(T);
+            const buf_t bjpt = buf_span(static_cast<const T *>(D.jpt) + b.J0, nj * es);
+            const buf_t bjeta = buf_span(static_cast<const T *>(D.jeta) + b.J0, nj * es);
+            const buf_t bjphi = buf_span(static_cast<const T *>(D.jphi) + b.J0, nj * es);
 #pragma unroll
             for (int k = 0; k < JK; ++k) {
                 const int j = lane + 64 * k;
-                R.jpt[k] = R.jeta[k] = R.jphi[k] = 0.0f;
+                R.jpt[k] = buf_ldf<T>(bjpt, j);
+                R.jeta[k] = buf_ldf<T>(bjeta, j);
+                R.jphi[k] = buf_ldf<T>(bjphi, j);
                 if (EXT) R.jbt[EXT ? k : 0] = 0.0f;
-                if (j < nj) {
-                    R.jpt[k] = ldf(cjpt, j);
-                    R.jeta[k] = ldf(cjeta, j);
-                    R.jphi[k] = ldf(cjphi, j);
-                    if (EXT && has_bt) R.jbt[EXT ? k : 0] = ldf(cjbt, j);
-                }
             }
-            const T *cmpt = static_cast<const T *>(D.mpt) + b.M0, *cmeta = static_cast<const T *>(D.meta) + b.M0;
-            const T *cmphi = static_cast<const T *>(D.mphi) + b.M0;
-            const T *cmiso = has_iso ? static_cast<const T *>(D.miso) + b.M0 : nullptr;
+            if (EXT && has_bt) {
+                const buf_t bjbt = buf_span(static_cast<const T *>(D.jbt) + b.J0, nj * es);
+#pragma unroll
+                for (int k = 0; k < JK; ++k) R.jbt[EXT ? k : 0] = buf_ldf<T>(bjbt, lane + 64 * k);
+            }
+            const buf_t bmpt = buf_span(static_cast<const T *>(D.mpt) + b.M0, nm * es);
+            const buf_t bmeta = buf_span(static_cast<const T *>(D.meta) + b.M0, nm * es);
+            const buf_t bmphi = buf_span(static_cast<const T *>(D.mphi) + b.M0, nm * es);
 #pragma unroll
             for (int k = 0; k < MK; ++k) {
                 const int m = lane + 64 * k;
-                R.mpt[k] = R.meta[k] = R.mphi[k] = R.miso[k] = 0.0f;
-                if (m < nm) {
-                    R.mpt[k] = ldf(cmpt, m);
-                    R.meta[k] = ldf(cmeta, m);
-                    R.mphi[k] = ldf(cmphi, m);
-                    if (has_iso) R.miso[k] = ldf(cmiso, m);
-                }
+                R.mpt[k] = buf_ldf<T>(bmpt, m);
+                R.meta[k] = buf_ldf<T>(bmeta, m);
+                R.mphi[k] = buf_ldf<T>(bmphi, m);
+                R.miso[k] = 0.0f;
+            }
+            if (has_iso) {
+                const buf_t bmiso = buf_span(static_cast<const T *>(D.miso) + b.M0, nm * es);
+#pragma unroll
+                for (int k = 0; k < MK; ++k) R.miso[k] = buf_ldf<T>(bmiso, lane + 64 * k);
             }
 #pragma unroll
             for (int k = 0; k < EK; ++k) R.lpt[k] = R.leta[k] = R.lphi[k] = 0.0f;
             if (EXT && has_el) {
-                const T *cept = static_cast<const T *>(D.ept) + b.L0, *ceeta = static_cast<const T *>(D.eeta) + b.L0;
-                const T *cephi = static_cast<const T *>(D.ephi) + b.L0;
+                const buf_t bept = buf_span(static_cast<const T *>(D.ept) + b.L0, nl * es);
+                const buf_t beeta = buf_span(static_cast<const T *>(D.eeta) + b.L0, nl * es);
+                const buf_t bephi = buf_span(static_cast<const T *>(D.ephi) + b.L0, nl * es);
 #pragma unroll
                 for (int k = 0; k < EK; ++k) {
                     const int m = lane + 64 * k;
-                    if (m < nl) {
-                        R.lpt[k] = ldf(cept, m);
-                        R.leta[k] = ldf(ceeta, m);
-                        R.lphi[k] = ldf(cephi, m);
-                    }
+                    R.lpt[k] = buf_ldf<T>(bept, m);
+                    R.leta[k] = buf_ldf<T>(beeta, m);
+                    R.lphi[k] = buf_ldf<T>(bephi, m);
                 }
             }
         };
@@ -748,8 +766,7 @@ pipeline_kernel(PipeArgs P) {
         };
         // Steps 2-5 for every query on a settled tile.
         auto work = [&](int64_t e0, int ne, const TileBounds &B, Raw &R) {
-            const int nj = static_cast<int>(B.J1 - B.J0), nm = static_cast<int>(B.M1 - B.M0);
-            const int nl = static_cast<int>(B.L1 - B.L0);
+            const int nj = B.nj, nm = B.nm, nl = B.nl;
             int32_t jb[EVPL], je[EVPL], mb[EVPL], me[EVPL], lb[EVPL], le[EVPL];
             float wv[EVPL];
 #pragma unroll
@@ -1135,16 +1152,21 @@ pipeline_kernel(PipeArgs P) {
         // (a few scalar loads), that sub-tile runs like a tile, and the rest
         // of the tile follows.  Only a single event beyond the capacity goes
         // one lane, straight from HBM.
-        int64_t t = c_t0 + wave;
+        int r = wave;  // this wavefront's tile (relative to c_t0)
+        int eo = 0;    // events of tile r already run
         TileBounds nb{};
-        int64_t e = t * TW, eend = min<int64_t>(e + TW, D.n_events);  // events of tile t not yet run
-        if (t < c_t1) nb = bounds_of(t);
-        while (t < c_t1) {
-            int n = static_cast<int>(eend - e);
+        if (r < nt) nb = bounds_of(r);
+        while (r < nt) {
+            // the lane index is re-read here so that values derived from it
+            // are recomputed per tile instead of held (and spilled) across it
+            asm volatile("" : "+v"(lane));
+            const int tn = tile_events(r);
+            const int64_t e = ebase + static_cast<int64_t>(r) * TW + eo;
+            int n = tn - eo;
             TileBounds B;
-            if (e == t * TW) {
+            if (eo == 0) {
                 B = nb;
-                if (t + WAVES < c_t1) nb = bounds_of(t + WAVES);
+                if (r + WAVES < nt) nb = bounds_of(r + WAVES);
             } else {
                 B = tile_bounds<EXT>(D, has_el, e, n);
             }
@@ -1161,11 +1183,10 @@ pipeline_kernel(PipeArgs P) {
                 settle(R);
                 work(e, n, B, R);
             }
-            e += n;
-            if (e >= eend) {
-                t += WAVES;
-                e = t * TW;
-                eend = min<int64_t>(e + TW, D.n_events);
+            eo += n;
+            if (eo >= tn) {
+                r += WAVES;
+                eo = 0;
             }
         }
         // merge the LDS histograms into the dataset's block in HBM (the next
