@@ -794,6 +794,9 @@ pipeline_kernel(PipeArgs P) {
             (void)jbt;
             (void)lpt;
             for (int q = 0; q < P.n_q; ++q) {
+                // (values derived from the lane index are recomputed per
+                // query rather than held across the query loop)
+                asm volatile("" : "+v"(lane));
                 // the query's fields are read in place (scalar loads near their
                 // uses) rather than copied: a copy would hold ~45 SGPRs for the
                 // whole query and spill
