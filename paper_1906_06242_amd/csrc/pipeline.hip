@@ -61,6 +61,53 @@ static bool use_lds_hist(hepk_plan p) {
            p->lds_static_lds + hist_lds_bytes(p) + table_lds_bytes(p) <= p->lds_max;
 }
 
+// Where the kernels' bin guess can be wrong.  The guess for x is
+// floor(g(x)) + 1 with g(x) = (x - lo) * inv_w in float32 (each operation
+// rounded, as on the device), capped at nb; g is monotone in x.  For x in bin
+// i (E[i-1] <= x < E[i]), g(x) lies between A = g(E[i-1]) and B = g(the float
+// below E[i]), so the guess is too high only if B >= i, and then only where
+// f = frac(g) <= B - i, and too low only if A < i - 1, and then only where
+// f >= 1 - (i - 1 - A); the last bin is never too high (the cap).  Returned:
+// t with every such f satisfying |f - 0.5| >= t in the kernel's float32
+// (0.5 - f and f - 0.5 round monotonically in f); t > 0.5 flags none of them
+// and t <= 0 all.
+static float guess_bound(const float *e, int nb, float lo, float iw) {
+    auto g = [&](float x) {
+        const float d = x - lo;
+        const float r = d * iw;
+        return static_cast<double>(r);
+    };
+    double dhi = -1.0, dlo = 0.0;
+    bool finite = true;
+    for (int i = 1; i <= nb; ++i) {
+        const double a = g(e[i - 1]);
+        finite &= std::isfinite(a);
+        dlo = std::max(dlo, (i - 1) - a);
+        if (i < nb) {
+            const double b = g(std::nextafter(e[i], -INFINITY));
+            finite &= std::isfinite(b);
+            dhi = std::max(dhi, b - i);
+        }
+    }
+    if (!finite || dhi >= 0.5 || dlo >= 0.5) return -1.0f;
+    float t = 1.5f;  // neither side can be wrong
+    if (dhi >= 0.0) {
+        // too high possible for f <= dhi: flagged by 0.5 - f >= 0.5 - fh
+        // with fh = dhi rounded up to float32
+        float fh = static_cast<float>(dhi);
+        if (static_cast<double>(fh) < dhi) fh = std::nextafter(fh, INFINITY);
+        t = std::min(t, 0.5f - fh);
+    }
+    if (dlo > 0.0) {
+        // too low possible for f >= 1 - dlo: flagged by f - 0.5 >= fl - 0.5
+        // with fl = 1 - dlo rounded down to float32
+        float fl = static_cast<float>(1.0 - dlo);
+        if (static_cast<double>(fl) > 1.0 - dlo) fl = std::nextafter(fl, -INFINITY);
+        t = std::min(t, fl - 0.5f);
+    }
+    return t;
+}
+
 // Fills the query-dependent fields of a table entry; the caller has checked q.
 static void set_qdev(QDev &o, const hepk_query &Q, const float *const edges[3]) {
     o.mu_pt = Q.mu_pt;
@@ -94,6 +141,7 @@ static void set_qdev(QDev &o, const hepk_query &Q, const float *const edges[3]) 
         o.lo[h] = e[0];
         o.hi[h] = e[nb];
         o.inv_w[h] = (span > 0.0f && std::isfinite(span)) ? static_cast<float>(nb) / span : 0.0f;
+        o.chk[h] = guess_bound(e, nb, o.lo[h], o.inv_w[h]);
     }
 }
 

@@ -82,6 +82,11 @@ struct QDev {
     int32_t ebase[3];    // first edge of each observable in the plan's edge table
     float lo[3], hi[3];  // first and last edge of each observable
     float inv_w[3];      // nbins / (hi - lo): start value of the bin search
+    // The guess g = (x - lo) * inv_w (float32) can name a wrong bin only
+    // where its fraction f = g - floor(g) has |f - 0.5| >= chk (a bound the
+    // plan derives from the edges, guess_bounds); only such guesses are
+    // checked against the edges.
+    float chk[3];
     // Histogram of (scale v, observable h) starts at slot0 + v * per_scale +
     // hoff[h]: in the workgroup's LDS copy (compact over the active queries)
     // and in the dataset's block in HBM (fixed per query slot).
@@ -183,7 +188,7 @@ __device__ __forceinline__ float shifted_pt_bound(float pt, float d, float smin,
 struct FillC {
     int32_t base, per;       // first slot of scale 0, slots per scale (LDS or global layout)
     int32_t nb[3], eb[3], off[3];
-    float lo[3], hi[3], iw[3];
+    float lo[3], hi[3], iw[3], ck[3];
 };
 
 template <typename X>
@@ -193,8 +198,8 @@ __device__ __forceinline__ X pin(X x) {
 }
 
 // All fields are read first and pinned by one statement, so their loads are
-// issued together and waited for once.
-template <bool LDSH, typename QT>
+// issued together and waited for once (the guess bounds only with CERT).
+template <bool LDSH, bool CERT, typename QT>
 __device__ __forceinline__ FillC fill_consts(const QT &Q) {
     FillC F;
     F.base = LDSH ? Q.lslot0 : Q.gslot0;
@@ -207,42 +212,71 @@ __device__ __forceinline__ FillC fill_consts(const QT &Q) {
         F.lo[h] = Q.lo[h];
         F.hi[h] = Q.hi[h];
         F.iw[h] = Q.inv_w[h];
+        F.ck[h] = CERT ? Q.chk[h] : 0.0f;
     }
     asm volatile(""
                  : "+s"(F.base), "+s"(F.per), "+s"(F.nb[0]), "+s"(F.nb[1]), "+s"(F.nb[2]), "+s"(F.eb[0]),
                    "+s"(F.eb[1]), "+s"(F.eb[2]), "+s"(F.off[0]), "+s"(F.off[1]), "+s"(F.off[2]), "+s"(F.lo[0]),
                    "+s"(F.lo[1]), "+s"(F.lo[2]), "+s"(F.hi[0]), "+s"(F.hi[1]), "+s"(F.hi[2]), "+s"(F.iw[0]),
                    "+s"(F.iw[1]), "+s"(F.iw[2]));
+    if (CERT) asm volatile("" : "+s"(F.ck[0]), "+s"(F.ck[1]), "+s"(F.ck[2]));
     return F;
 }
 
 // Slots of N values, x[n] going to observable n % 3 (H_T, lead, nJet): the
-// same slot as hist_slot_lohi, computed for all N at once -- every guess,
-// then every edge pair read (one LDS round trip for all of them), then the
-// check, with a binary search only where the guess was off (rounding at an
-// edge, or non-uniform edges).
-template <int N>
+// same slot as hist_slot_lohi.  Without CERT every guess from the
+// uniform-bin formula is checked against its bin's edges (one LDS round trip
+// for all N values).  With CERT the guess is taken as exact unless its
+// fraction is within the plan's bound of 0 or 1 (chk), so only lanes with such
+// a guess read edges -- rarely any lane of a wavefront, so the round trip is
+// usually skipped; this pays where a lane fills many values (several scales).
+// Either way a binary search replaces a guess that was off.
+template <int N, bool CERT>
 __device__ __forceinline__ void find_bins(const FillC &F, const float *edges, const float (&x)[N], int (&s)[N]) {
-    int k[N];
+    if (!CERT) {
+        int k[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const int h = n % 3;
+            const float g = (x[n] - F.lo[h]) * F.iw[h];
+            const int gi = g >= 0.0f ? (g < static_cast<float>(F.nb[h]) ? static_cast<int>(g) + 1 : F.nb[h]) : 1;
+            s[n] = !(x[n] >= F.lo[h]) ? 0 : (x[n] >= F.hi[h] ? F.nb[h] + 1 : gi);
+            k[n] = F.eb[h] + ((s[n] >= 1 && s[n] <= F.nb[h]) ? s[n] : 1);
+        }
+        float a[N], b[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            a[n] = edges[k[n] - 1];
+            b[n] = edges[k[n]];
+        }
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const int h = n % 3;
+            if (s[n] >= 1 && s[n] <= F.nb[h] && (x[n] < a[n] || x[n] >= b[n]))
+                s[n] = bin_search(edges + F.eb[h], F.nb[h], x[n]);
+        }
+        return;
+    }
+    bool chk = false;  // some value of this lane needs the edges
 #pragma unroll
     for (int n = 0; n < N; ++n) {
         const int h = n % 3;
         const float g = (x[n] - F.lo[h]) * F.iw[h];
-        const int gi = g >= 0.0f ? (g < static_cast<float>(F.nb[h]) ? static_cast<int>(g) + 1 : F.nb[h]) : 1;
+        const bool in = g < static_cast<float>(F.nb[h]);
+        const int gi = g >= 0.0f ? (in ? static_cast<int>(g) + 1 : F.nb[h]) : 1;
         s[n] = !(x[n] >= F.lo[h]) ? 0 : (x[n] >= F.hi[h] ? F.nb[h] + 1 : gi);
-        k[n] = F.eb[h] + ((s[n] >= 1 && s[n] <= F.nb[h]) ? s[n] : 1);
+        const float f = g - static_cast<float>(gi - 1);
+        chk |= s[n] >= 1 && s[n] <= F.nb[h] && (!in || !(g >= 0.0f) || fabsf(f - 0.5f) >= F.ck[h]);
     }
-    float a[N], b[N];
+    if (chk) {
+        // every value of the lane is verified (a right guess is kept)
 #pragma unroll
-    for (int n = 0; n < N; ++n) {
-        a[n] = edges[k[n] - 1];
-        b[n] = edges[k[n]];
-    }
-#pragma unroll
-    for (int n = 0; n < N; ++n) {
-        const int h = n % 3;
-        if (s[n] >= 1 && s[n] <= F.nb[h] && (x[n] < a[n] || x[n] >= b[n]))
-            s[n] = bin_search(edges + F.eb[h], F.nb[h], x[n]);
+        for (int n = 0; n < N; ++n) {
+            const int h = n % 3;
+            const float *E = edges + F.eb[h];
+            if (s[n] >= 1 && s[n] <= F.nb[h] && (x[n] < E[s[n] - 1] || x[n] >= E[s[n]]))
+                s[n] = bin_search(E, F.nb[h], x[n]);
+        }
     }
 }
 
@@ -388,11 +422,11 @@ struct WaveLds {
 
 // Adds weight w to the histograms of scales v0 + n / 3 (observable n % 3)
 // of the lanes whose pass[n / 3] is set; NaN values are not filled.
-template <int N, bool LDSH, bool W2>
+template <int N, bool CERT, bool LDSH, bool W2>
 __device__ __forceinline__ void fill_bins(const HistSink<LDSH, W2> &sink, const FillC &F, const float *edges,
                                           const float (&xs)[N], const bool (&pass)[N / 3], int v0, double w) {
     int sl[N];
-    find_bins<N>(F, edges, xs, sl);
+    find_bins<N, CERT>(F, edges, xs, sl);
 #pragma unroll
     for (int n = 0; n < N; ++n)
         if (pass[n / 3] && xs[n] == xs[n]) sink.add(F.base + (v0 + n / 3) * F.per + F.off[n % 3] + sl[n], w);
@@ -988,15 +1022,15 @@ pipeline_kernel(PipeArgs P) {
                 }
                 wave_sync();
                 // ---- 5. per-event reductions, event cut, fills
-                const FillC F = fill_consts<LDSH>(Q);
+                const FillC F = fill_consts<LDSH, MS>(Q);
                 // separate calls for the two places the edges live, so each
                 // knows its address space (no flat loads)
                 auto fill = [&](const auto &xs, const auto &pass, int v0, double w) {
                     constexpr int N = std::extent<std::remove_reference_t<decltype(xs)>>::value;
                     if (P.edges_in_lds)
-                        fill_bins<N>(sink, F, e_s, xs, pass, v0, w);
+                        fill_bins<N, MS>(sink, F, e_s, xs, pass, v0, w);
                     else
-                        fill_bins<N>(sink, F, P.edges, xs, pass, v0, w);
+                        fill_bins<N, MS>(sink, F, P.edges, xs, pass, v0, w);
                 };
                 if (!MS) {
                     const float sc[1] = {pin<float>(as_const(P.scales)[Q.scale0])};
