@@ -63,7 +63,8 @@ def log(*a):
 def kernel_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("paper_1906_06242_amd/csrc/common.hpp", "paper_1906_06242_amd/csrc/pipeline_kernel.hpp",
+    for f in ("paper_1906_06242_amd/csrc/common.hpp", "paper_1906_06242_amd/csrc/lookup.hpp",
+              "paper_1906_06242_amd/csrc/pipeline_kernel.hpp", "paper_1906_06242_amd/csrc/plan.hpp",
               "paper_1906_06242_amd/csrc/pipeline.hip", "paper_1906_06242_amd/csrc/pipeline_ms.hip"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
