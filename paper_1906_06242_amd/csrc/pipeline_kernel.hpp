@@ -394,7 +394,12 @@ struct Caps {
 // the high 16 bits, first | count << 8 each) until the cone test reads it;
 // the same word then holds the jet's pt (or NaN) for the per-event walk
 // (with one scale and jet_pt >= 0: pt * s of a selected jet, else +0).
-template <int EVPL, bool EXT, bool LK>
+// With several scales (MS) the cone test instead compacts the jets that can
+// be selected at some scale (the candidates) into jr, bt and jd in tile
+// order, and cpre[j] holds the number of candidates (low 16 bits) and of
+// b-tagged candidates (high 16 bits) before tile jet j; cpre shares space
+// with the compacted leptons, which are dead by then.
+template <int EVPL, bool EXT, bool LK, bool MS>
 struct WaveLds {
     using C = Caps<EVPL, EXT>;
     union {
@@ -402,9 +407,14 @@ struct WaveLds {
         float pt;
     } jr[C::JC];
     uint32_t jre[(EXT && !C::PACK) ? C::JC : 1];  // electron ranges when not packed
-    float seta[C::MC + 2], sphi[C::MC + 2];        // selected muons, compacted in tile order (+2 padding)
-    float sea[EXT ? C::EC : 1], sep[EXT ? C::EC : 1];
-    float ssf[LK ? C::MC + 2 : 1];  // LK: selected muons' scale factors, compacted like seta
+    union {
+        struct {
+            float seta[C::MC + 2], sphi[C::MC + 2];  // selected muons, compacted in tile order (+2 padding)
+            float sea[EXT ? C::EC : 1], sep[EXT ? C::EC : 1];
+            float ssf[LK ? C::MC + 2 : 1];  // LK: selected muons' scale factors, compacted like seta
+        };
+        uint32_t cpre[MS ? C::JC + 1 : 1];
+    };
     float jd[LK ? C::JC : 1];       // LK: each jet's energy-scale shift (jes_mode 1)
     uint8_t bt[EXT ? C::JC : 1];
     union {
@@ -452,15 +462,18 @@ template <int G, bool EXT, bool JM, typename WL>
 __device__ __forceinline__ void walk_jets(const WL &L, int j0, int j1, const float (&sc)[G], float jet_pt,
                                           float (&ht)[G], float (&lead)[G], int (&nj)[G], int (&nb)[G]) {
     float pmax = -INFINITY;
+    // selected jets (low 16 bits) and selected b-tagged jets (high 16 bits)
+    // in one counter per scale: a range holds at most 64 * JK < 2^16 jets
+    uint32_t cnt[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         ht[g] = 0.0f;
-        nj[g] = 0;
-        nb[g] = 0;
+        cnt[g] = 0u;
         lead[g] = -INFINITY;
     }
     auto step = [&](float p, float d, int bt) {
         pmax = fmaxf(pmax, p);  // NaN (removed jet) leaves it unchanged
+        const uint32_t inc = EXT ? 1u + (static_cast<uint32_t>(bt) << 16) : 1u;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const float f = JM ? 1.0f + sc[g] * d : sc[g];
@@ -468,9 +481,8 @@ __device__ __forceinline__ void walk_jets(const WL &L, int j0, int j1, const flo
             const bool sel = x > jet_pt;
             const float hs = ht[g] + x;
             ht[g] = sel ? hs : ht[g];
-            nj[g] += sel ? 1 : 0;
+            cnt[g] += sel ? inc : 0u;
             if (JM) lead[g] = sel ? fmaxf(lead[g], x) : lead[g];
-            if (EXT) nb[g] += sel ? bt : 0;
         }
     };
     int k = j0;
@@ -482,24 +494,11 @@ __device__ __forceinline__ void walk_jets(const WL &L, int j0, int j1, const flo
         step(p1, d1, b1);
     }
     if (k < j1) step(L.jr[k].pt, JM ? L.jd[k] : 0.0f, EXT ? static_cast<int>(L.bt[k]) : 0);
-    if (!JM) {
 #pragma unroll
-        for (int g = 0; g < G; ++g) lead[g] = nj[g] > 0 ? pmax * sc[g] : -INFINITY;
-    }
-}
-
-// Upper bounds, valid at every scale in [smin, smax] of a query with shifted
-// energies, of an event's selected and b-tagged jet counts: jets whose
-// largest pt * (1 + s * d) over that range exceeds jet_pt.
-template <bool EXT, typename WL>
-__device__ __forceinline__ void walk_shift_bound(const WL &L, int j0, int j1, float smin, float smax, float jet_pt,
-                                                 int &nj, int &nb) {
-    nj = 0;
-    nb = 0;
-    for (int k = j0; k < j1; ++k) {
-        const bool sel = shifted_pt_bound(L.jr[k].pt, L.jd[k], smin, smax) > jet_pt;
-        nj += sel ? 1 : 0;
-        if (EXT) nb += sel ? static_cast<int>(L.bt[k]) : 0;
+    for (int g = 0; g < G; ++g) {
+        nj[g] = static_cast<int>(cnt[g] & 0xffffu);
+        nb[g] = EXT ? static_cast<int>(cnt[g] >> 16) : 0;
+        if (!JM) lead[g] = nj[g] > 0 ? pmax * sc[g] : -INFINITY;
     }
 }
 
@@ -601,7 +600,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(MS ?
 pipeline_kernel(PipeArgs P) {
     using C = Caps<EVPL, EXT>;
     constexpr int TW = C::TW, JK = C::JK, MK = C::MK, EK = C::EK;
-    __shared__ WaveLds<EVPL, EXT, LK> wl[WAVES];
+    __shared__ WaveLds<EVPL, EXT, LK, MS> wl[WAVES];
     // per workgroup: [sumw | sumw2 (LK) | counts (u32) | edges | scales]
     extern __shared__ double dyn[];
 
@@ -951,6 +950,12 @@ pipeline_kernel(PipeArgs P) {
                 // range's end land in the next event's muons or in the two
                 // padding entries and are unused.
                 constexpr int CB = 2;
+                // MS: per slot, whether the jet is a candidate (selected at
+                // some scale), a b-tagged candidate, and its shift (LK)
+                bool okv[MS ? JK : 1], tagv[MS ? JK : 1];
+                float dshv[(MS && LK) ? JK : 1];
+#pragma unroll
+                for (int k = 0; k < (MS ? JK : 1); ++k) okv[k] = tagv[k] = false;
 #pragma unroll
                 for (int k0 = 0; k0 < JK; k0 += CB) {
                     uint32_t pk[CB];
@@ -1007,7 +1012,11 @@ pipeline_kernel(PipeArgs P) {
                         }
                         const bool ok = need && !hit;
                         const bool tag = has_bt && jbt[EXT ? k : 0] > btag;
-                        if (zsel) {
+                        if (MS) {
+                            okv[MS ? k : 0] = ok;
+                            tagv[MS ? k : 0] = ok && tag;
+                            if (LK) dshv[(MS && LK) ? k : 0] = dsh;
+                        } else if (zsel) {
                             // one scale s (= smax): the jet's energy pt * s, or
                             // pt * (1 + s * d) when shifted
                             const float f = shift ? 1.0f + smax * dsh : smax;
@@ -1021,6 +1030,40 @@ pipeline_kernel(PipeArgs P) {
                     }
                 }
                 wave_sync();
+                if (MS) {
+                    // The candidates -- jets inside |eta|, clean, and (with
+                    // jet_pt >= 0) above jet_pt at the largest energy any
+                    // scale gives them -- compacted in tile order with their
+                    // b-tag flag (and shift).  A jet that is no candidate is
+                    // selected at no scale, so walking only the candidates
+                    // adds the same values in the same order.  cpre gives
+                    // every event its candidate range and, with jet_pt >= 0,
+                    // its candidate and b-tagged candidate counts: the jets
+                    // selected and b-tagged at the largest scale.
+                    int runc = 0, runt = 0;
+#pragma unroll
+                    for (int k = 0; k < JK; ++k) {
+                        if (64 * k >= nj) break;
+                        const int j = lane + 64 * k;
+                        const uint64_t bc = __ballot(okv[MS ? k : 0]), bg = __ballot(tagv[MS ? k : 0]);
+                        const int before = runc + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+                                                      static_cast<uint32_t>(bc >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bc), 0u)));
+                        const int tbefore = runt + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+                                                       static_cast<uint32_t>(bg >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bg), 0u)));
+                        if (j < nj) L.cpre[MS ? j : 0] = static_cast<uint32_t>(before) | (static_cast<uint32_t>(tbefore) << 16);
+                        if (okv[MS ? k : 0]) {
+                            L.jr[before].pt = jpt[k];
+                            if (EXT) L.bt[before] = tagv[MS ? k : 0] ? 1 : 0;
+                            if (LK) L.jd[LK ? before : 0] = dshv[(MS && LK) ? k : 0];
+                        }
+                        runc += __popcll(bc);
+                        runt += __popcll(bg);
+                    }
+                    if (lane == 0) L.cpre[MS ? nj : 0] = static_cast<uint32_t>(runc) | (static_cast<uint32_t>(runt) << 16);
+                    wave_sync();
+                }
                 // ---- 5. per-event reductions, event cut, fills
                 const FillC F = fill_consts<LDSH, MS>(Q);
                 // separate calls for the two places the edges live, so each
@@ -1061,31 +1104,26 @@ pipeline_kernel(PipeArgs P) {
                     // Several scales: the events that can pass at some scale are
                     // compacted, and lanes take (event, group of kG scales)
                     // pairs of them, event-major.  One walk over an event's
-                    // jets serves the kG scales of its group (kG independent
-                    // chains), and a round covers a few events, so the walks
-                    // diverge little.  An event can pass only with enough
-                    // muons and enough jets before any cut (the cuts only
-                    // remove jets); with jet_pt >= 0 also only with enough
-                    // selected jets and b-tagged jets at the largest scale: a
-                    // jet selected at s <= smax is selected at smax (rounding
-                    // pt * s is monotone in s for pt >= 0, and pt * s <= 0 <=
-                    // jet_pt otherwise), so one walk at smax bounds both counts
-                    // at every scale.
+                    // candidate jets serves the kG scales of its group (kG
+                    // independent chains), and a round covers a few events, so
+                    // the walks diverge little.  An event can pass only with
+                    // enough muons and enough jets before any cut (the cuts
+                    // only remove jets); with jet_pt >= 0 also only with
+                    // enough selected jets and b-tagged jets at the largest
+                    // scale: a jet selected at s <= smax is selected at smax
+                    // (rounding pt * s is monotone in s for pt >= 0, and
+                    // pt * s <= 0 <= jet_pt otherwise; with shifts, the
+                    // largest energy is at smin or smax), and those counts
+                    // are the event's candidates and b-tagged candidates.
                     const bool prefilter = jet_pt >= 0.0f;
-                    const float smaxa[1] = {smax};
                     int nel = 0;
 #pragma unroll
                     for (int r = 0; r < EVPL; ++r) {
+                        const uint32_t cw0 = L.cpre[MS ? jb[r] : 0], cw1 = L.cpre[MS ? je[r] : 0];
+                        const int cb = static_cast<int>(cw0 & 0xffffu), ce = static_cast<int>(cw1 & 0xffffu);
                         bool elig = lane + 64 * r < ne && nmu[r] >= min_mu && je[r] - jb[r] >= min_jet;
-                        if (prefilter && elig) {
-                            float ht1[1], lead1[1];
-                            int nj1[1], nb1[1];
-                            if (shift)
-                                walk_shift_bound<EXT>(L, jb[r], je[r], smin, smax, jet_pt, nj1[0], nb1[0]);
-                            else
-                                walk_jets<1, EXT, false>(L, jb[r], je[r], smaxa, jet_pt, ht1, lead1, nj1, nb1);
-                            elig = nj1[0] >= min_jet && nb1[0] >= min_b;
-                        }
+                        if (prefilter)
+                            elig = elig && ce - cb >= min_jet && static_cast<int>((cw1 >> 16) - (cw0 >> 16)) >= min_b;
                         if (DBG && lane + 64 * r < ne) {
                             // the muon count of every event; the rest only of
                             // events that are not walked (the walk writes the
@@ -1110,11 +1148,12 @@ pipeline_kernel(PipeArgs P) {
                                                  static_cast<uint32_t>(bal >> 32),
                                                  __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bal), 0u)));
                         if (elig) {
-                            // jet range: first in bits 0-9, end in bits 16-25
-                            // (both below 64 * JK <= 832); DBG kernels keep the
-                            // event's place in the tile in the bits between
+                            // candidate range: first in bits 0-9, end in bits
+                            // 16-25 (both at most 64 * JK <= 832); DBG kernels
+                            // keep the event's place in the tile in the bits
+                            // between
                             const uint32_t ev = static_cast<uint32_t>(lane + 64 * r);
-                            L.u.w.evjr[at] = static_cast<uint32_t>(jb[r]) | (static_cast<uint32_t>(je[r]) << 16) |
+                            L.u.w.evjr[at] = static_cast<uint32_t>(cb) | (static_cast<uint32_t>(ce) << 16) |
                                              (DBG ? (((ev & 63u) << 10) | ((ev >> 6) << 26)) : 0u);
                             L.u.w.evw[at] = wq[r];
                         }
