@@ -150,6 +150,14 @@ struct HistSink {
         else
             atomic_add_u64(&c64[slot], 1u);
     }
+    // LDS histograms: adds w (and one count) where f holds and +0 / 0 where
+    // it does not, without a branch (adding +0 changes no sum of finite
+    // weights but a -0 one, which compares equal)
+    __device__ __forceinline__ void add_if(int slot, double w, bool f) const {
+        atomic_add_f64(&sw[slot], f ? w : 0.0);
+        if (W2 && sw2) atomic_add_f64(&sw2[slot], f ? w * w : 0.0);
+        atomicAdd(&c32[slot], f ? 1u : 0u);
+    }
 };
 
 // The lookup tables of one query as axes over the edge table E.
@@ -260,13 +268,17 @@ __device__ __forceinline__ void find_bins(const FillC &F, const float *edges, co
     bool chk = false;  // some value of this lane needs the edges
 #pragma unroll
     for (int n = 0; n < N; ++n) {
+        // branch-free: the guess clamped to [0, nb - 1] before the
+        // conversion (a NaN x clamps to 0 and lands in slot 0 below), the
+        // predicates combined bitwise
         const int h = n % 3;
         const float g = (x[n] - F.lo[h]) * F.iw[h];
-        const bool in = g < static_cast<float>(F.nb[h]);
-        const int gi = g >= 0.0f ? (in ? static_cast<int>(g) + 1 : F.nb[h]) : 1;
-        s[n] = !(x[n] >= F.lo[h]) ? 0 : (x[n] >= F.hi[h] ? F.nb[h] + 1 : gi);
-        const float f = g - static_cast<float>(gi - 1);
-        chk |= s[n] >= 1 && s[n] <= F.nb[h] && (!in || !(g >= 0.0f) || fabsf(f - 0.5f) >= F.ck[h]);
+        const int gi = static_cast<int>(fminf(fmaxf(g, 0.0f), static_cast<float>(F.nb[h] - 1)));
+        const int sv = x[n] >= F.hi[h] ? F.nb[h] + 1 : gi + 1;
+        s[n] = x[n] >= F.lo[h] ? sv : 0;
+        const float f = g - static_cast<float>(gi);
+        chk |= (s[n] >= 1) & (s[n] <= F.nb[h]) &
+               (!(g < static_cast<float>(F.nb[h])) | !(g >= 0.0f) | (fabsf(f - 0.5f) >= F.ck[h]));
     }
     if (chk) {
         // every value of the lane is verified (a right guess is kept)
@@ -394,6 +406,9 @@ struct Caps {
 // the high 16 bits, first | count << 8 each) until the cone test reads it;
 // the same word then holds the jet's pt (or NaN) for the per-event walk
 // (with one scale and jet_pt >= 0: pt * s of a selected jet, else +0).
+// The selected muons and (extended schema) electrons share one pair of
+// arrays, the electrons from index EO = MC + 2 on, so one index runs over an
+// event's muons and then its electrons.
 // With several scales (MS) the cone test instead compacts the jets that can
 // be selected at some scale (the candidates) into jr, bt and jd in tile
 // order, and cpre[j] holds the number of candidates (low 16 bits) and of
@@ -409,8 +424,9 @@ struct WaveLds {
     uint32_t jre[(EXT && !C::PACK) ? C::JC : 1];  // electron ranges when not packed
     union {
         struct {
-            float seta[C::MC + 2], sphi[C::MC + 2];  // selected muons, compacted in tile order (+2 padding)
-            float sea[EXT ? C::EC : 1], sep[EXT ? C::EC : 1];
+            // selected muons, compacted in tile order (+2 padding), then
+            // (EXT) the selected electrons likewise from index EO
+            float seta[C::MC + 2 + (EXT ? C::EC + 2 : 0)], sphi[C::MC + 2 + (EXT ? C::EC + 2 : 0)];
             float ssf[LK ? C::MC + 2 : 1];  // LK: selected muons' scale factors, compacted like seta
         };
         uint32_t cpre[MS ? C::JC + 1 : 1];
@@ -431,12 +447,23 @@ struct WaveLds {
 };
 
 // Adds weight w to the histograms of scales v0 + n / 3 (observable n % 3)
-// of the lanes whose pass[n / 3] is set; NaN values are not filled.
+// of the lanes whose pass[n / 3] is set; NaN values are not filled.  With
+// several scales and LDS histograms every lane adds, zero where it does not
+// fill, at a slot of a scale no later than vlast (the query's last), so no
+// value needs its own branch.
 template <int N, bool CERT, bool LDSH, bool W2>
 __device__ __forceinline__ void fill_bins(const HistSink<LDSH, W2> &sink, const FillC &F, const float *edges,
-                                          const float (&xs)[N], const bool (&pass)[N / 3], int v0, double w) {
+                                          const float (&xs)[N], const bool (&pass)[N / 3], int v0, double w,
+                                          int vlast) {
     int sl[N];
     find_bins<N, CERT>(F, edges, xs, sl);
+    if (CERT && LDSH) {
+#pragma unroll
+        for (int n = 0; n < N; ++n)
+            sink.add_if(F.base + min(v0 + n / 3, vlast) * F.per + F.off[n % 3] + sl[n], w,
+                        pass[n / 3] & (xs[n] == xs[n]));
+        return;
+    }
 #pragma unroll
     for (int n = 0; n < N; ++n)
         if (pass[n / 3] && xs[n] == xs[n]) sink.add(F.base + (v0 + n / 3) * F.per + F.off[n % 3] + sl[n], w);
@@ -879,7 +906,7 @@ pipeline_kernel(PipeArgs P) {
 #pragma unroll
                     for (int k = 0; k < EK; ++k)
                         sel[k] = (lane + 64 * k < nl) & (lpt[k] > el_pt) & (fabsf(leta[k]) < el_abseta);
-                    compact<EK>(sel, leta, lphi, nl, lane, L.sea, L.sep, L.u.p.epre);
+                    compact<EK>(sel, leta, lphi, nl, lane, L.seta + (C::MC + 2), L.sphi + (C::MC + 2), L.u.p.epre);
                 }
                 wave_sync();
                 // ---- 3. each event lane writes its selected-lepton range over
@@ -942,14 +969,17 @@ pipeline_kernel(PipeArgs P) {
                 // any other as +0, for walk_selected.
                 const bool zsel = !MS && jet_pt >= 0.0f;
                 // Slots in pairs (CB; three at a time spills registers): the
-                // pair's packed ranges, then the first two selected muons of
+                // pair's packed ranges, then the first two selected leptons of
                 // each slot's event, each set of reads in flight together (two
-                // LDS round trips per pair); only events with more muons loop
-                // over the rest.  A slot past the tile's jets reads a stale
-                // word: its first and count are forced to 0.  Reads past a
-                // range's end land in the next event's muons or in the two
-                // padding entries and are unused.
+                // LDS round trips per pair); only events with more leptons loop
+                // over the rest.  An event's leptons are its selected muons,
+                // then (EXT) its selected electrons: lepton i is seta[s0 + i]
+                // for i < nmu, else seta[EO + u0 + i - nmu].  A slot past the
+                // tile's jets reads a stale word: its firsts and counts are
+                // forced to 0.  Reads past a range's end land on other
+                // events' leptons or on the padding entries and are unused.
                 constexpr int CB = 2;
+                constexpr int EO = C::MC + 2;
                 // MS: per slot, whether the jet is a candidate (selected at
                 // some scale), a b-tagged candidate, and its shift (LK)
                 bool okv[MS ? JK : 1], tagv[MS ? JK : 1];
@@ -958,21 +988,35 @@ pipeline_kernel(PipeArgs P) {
                 for (int k = 0; k < (MS ? JK : 1); ++k) okv[k] = tagv[k] = false;
 #pragma unroll
                 for (int k0 = 0; k0 < JK; k0 += CB) {
-                    uint32_t pk[CB];
+                    uint32_t pk[CB], pe[CB];
 #pragma unroll
-                    for (int b = 0; b < CB; ++b)
-                        if (k0 + b < JK) pk[b] = L.jr[lane + 64 * (k0 + b)].rng;
+                    for (int b = 0; b < CB; ++b) {
+                        if (k0 + b >= JK) continue;
+                        pk[b] = L.jr[lane + 64 * (k0 + b)].rng;
+                        pe[b] = (EXT && !C::PACK) ? L.jre[(EXT && !C::PACK) ? lane + 64 * (k0 + b) : 0] : 0u;
+                    }
+                    // per slot: first muon, muon count, offset of the electrons
+                    // in the lepton index, lepton count
+                    int s0[CB], nmu_[CB], ofe[CB], nlep[CB];
                     float e0[CB], p0[CB], e1[CB], p1[CB];
 #pragma unroll
                     for (int b = 0; b < CB; ++b) {
                         if (k0 + b >= JK) continue;
-                        const int c0 = lane + 64 * (k0 + b) < nj
-                                           ? static_cast<int>(C::PACK ? (pk[b] & 0xffu) : (pk[b] & 0xffffu))
-                                           : 0;
-                        e0[b] = L.seta[c0];
-                        p0[b] = L.sphi[c0];
-                        e1[b] = L.seta[c0 + 1];
-                        p1[b] = L.sphi[c0 + 1];
+                        const bool live = lane + 64 * (k0 + b) < nj;
+                        const uint32_t wm = live ? pk[b] : 0u;
+                        const uint32_t we = live ? (C::PACK ? (pk[b] >> 16) : pe[b]) : 0u;
+                        s0[b] = static_cast<int>(C::PACK ? (wm & 0xffu) : (wm & 0xffffu));
+                        nmu_[b] = static_cast<int>(C::PACK ? ((wm >> 8) & 0xffu) : (wm >> 16));
+                        const int u0 = EXT ? static_cast<int>(C::PACK ? (we & 0xffu) : (we & 0xffffu)) : 0;
+                        const int nel = EXT ? static_cast<int>(C::PACK ? ((we >> 8) & 0xffu) : (we >> 16)) : 0;
+                        ofe[b] = EXT ? EO + u0 - nmu_[b] : s0[b];
+                        nlep[b] = nmu_[b] + nel;
+                        const int i0 = nmu_[b] >= 1 ? s0[b] : ofe[b];
+                        const int i1 = nmu_[b] >= 2 ? s0[b] + 1 : ofe[b] + 1;
+                        e0[b] = L.seta[i0];
+                        p0[b] = L.sphi[i0];
+                        e1[b] = L.seta[i1];
+                        p1[b] = L.sphi[i1];
                     }
 #pragma unroll
                     for (int b = 0; b < CB; ++b) {
@@ -984,31 +1028,22 @@ pipeline_kernel(PipeArgs P) {
                         const float dsh = shift ? jes_shift(ax, edges, Q.jd, jpt[k], jeta[k]) : 0.0f;
                         const float ub = shift ? shifted_pt_bound(jpt[k], dsh, smin, smax) : jpt[k] * smax;
                         const bool need = fabsf(jeta[k]) < jet_abseta && (jet_pt < 0.0f || ub > jet_pt);
-                        const int c0 = static_cast<int>(C::PACK ? (pk[b] & 0xffu) : (pk[b] & 0xffffu));
-                        const int cn = need ? static_cast<int>(C::PACK ? ((pk[b] >> 8) & 0xffu) : (pk[b] >> 16)) : 0;
+                        const int cn = need ? nlep[b] : 0;
                         bool hit = (cn >= 1 & delta_r2(jeta[k], jphi[k], e0[b], p0[b]) <= thr2) |
                                    (cn >= 2 & delta_r2(jeta[k], jphi[k], e1[b], p1[b]) <= thr2);
-                        const int c1 = c0 + cn;
-                        int i = c0 + 2;
+                        const int sm = s0[b], nm_ = nmu_[b], oe = ofe[b];
+                        auto lidx = [&](int i) { return i < nm_ ? sm + i : oe + i; };
+                        int i = 2;
                         // two leptons per step: both LDS reads in flight before the math
-                        for (; i + 2 <= c1; i += 2) {
-                            const float e0 = L.seta[i], p0 = L.sphi[i], e1 = L.seta[i + 1], p1 = L.sphi[i + 1];
-                            hit |= delta_r2(jeta[k], jphi[k], e0, p0) <= thr2;
-                            hit |= delta_r2(jeta[k], jphi[k], e1, p1) <= thr2;
+                        for (; i + 2 <= cn; i += 2) {
+                            const int ia = lidx(i), ib = lidx(i + 1);
+                            const float ea = L.seta[ia], pa = L.sphi[ia], eb = L.seta[ib], pb = L.sphi[ib];
+                            hit |= delta_r2(jeta[k], jphi[k], ea, pa) <= thr2;
+                            hit |= delta_r2(jeta[k], jphi[k], eb, pb) <= thr2;
                         }
-                        if (i < c1) hit |= delta_r2(jeta[k], jphi[k], L.seta[i], L.sphi[i]) <= thr2;
-                        if (EXT) {
-                            const uint32_t pe = C::PACK ? (pk[b] >> 16) : L.jre[C::PACK ? 0 : j];
-                            const int u0 = static_cast<int>(C::PACK ? (pe & 0xffu) : (pe & 0xffffu));
-                            const int u1 =
-                                u0 + (need ? static_cast<int>(C::PACK ? ((pe >> 8) & 0xffu) : (pe >> 16)) : 0);
-                            int i = u0;
-                            for (; i + 2 <= u1; i += 2) {
-                                const float e0 = L.sea[i], p0 = L.sep[i], e1 = L.sea[i + 1], p1 = L.sep[i + 1];
-                                hit |= delta_r2(jeta[k], jphi[k], e0, p0) <= thr2;
-                                hit |= delta_r2(jeta[k], jphi[k], e1, p1) <= thr2;
-                            }
-                            if (i < u1) hit |= delta_r2(jeta[k], jphi[k], L.sea[i], L.sep[i]) <= thr2;
+                        if (i < cn) {
+                            const int ia = lidx(i);
+                            hit |= delta_r2(jeta[k], jphi[k], L.seta[ia], L.sphi[ia]) <= thr2;
                         }
                         const bool ok = need && !hit;
                         const bool tag = has_bt && jbt[EXT ? k : 0] > btag;
@@ -1068,12 +1103,13 @@ pipeline_kernel(PipeArgs P) {
                 const FillC F = fill_consts<LDSH, MS>(Q);
                 // separate calls for the two places the edges live, so each
                 // knows its address space (no flat loads)
+                const int vlast = Q.n_scale - 1;
                 auto fill = [&](const auto &xs, const auto &pass, int v0, double w) {
                     constexpr int N = std::extent<std::remove_reference_t<decltype(xs)>>::value;
                     if (P.edges_in_lds)
-                        fill_bins<N, MS>(sink, F, e_s, xs, pass, v0, w);
+                        fill_bins<N, MS>(sink, F, e_s, xs, pass, v0, w, vlast);
                     else
-                        fill_bins<N, MS>(sink, F, P.edges, xs, pass, v0, w);
+                        fill_bins<N, MS>(sink, F, P.edges, xs, pass, v0, w, vlast);
                 };
                 if (!MS) {
                     const float sc[1] = {pin<float>(as_const(P.scales)[Q.scale0])};
