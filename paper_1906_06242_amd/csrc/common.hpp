@@ -80,6 +80,25 @@ __device__ __forceinline__ float buf_ldf(buf_t r, int i) {
 }
 
 // The 32-bit word at byte offset `byte` of a buffer (0 beyond the range).
+// Element i of a float32 or float16 buffer as its raw bits (0 beyond the
+// range), converted by raw_f only where the value is used: a load whose
+// conversion sits right behind it would be waited for there.
+template <typename T>
+__device__ __forceinline__ uint32_t buf_raw(buf_t r, int i) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, 0);
+    else
+        return __builtin_amdgcn_raw_buffer_load_b16(r, i * 2, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ float raw_f(uint32_t b) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(float, b);
+    else
+        return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(b)));
+}
+
 __device__ __forceinline__ uint32_t buf_u32(buf_t r, int byte) {
     return __builtin_amdgcn_raw_buffer_load_b32(r, byte, 0, 0);
 }
@@ -120,12 +139,16 @@ __device__ __forceinline__ bool cmp_i(int32_t v, int32_t op, int32_t t) {
 // whenever |dphi| > pi: for dphi > pi that is dphi - 2*pi itself, for
 // dphi < -pi it is -(dphi + 2*pi), and negation is exact (round-to-nearest
 // is symmetric in sign).  So the square equals that of the two-sided wrap
-// bit for bit, in three instructions (sub with |.| modifier, cmp, cndmask).
+// bit for bit.  It is taken as min(x, 2*pi - x), x = |dphi| (two
+// instructions, both with the |.| modifier): 2*pi - x = -(x - 2*pi) exactly,
+// and with 2*pi = 2 * pi exact and rounding monotone, x <= pi gives
+// 2*pi - x >= pi >= x while x > pi gives 2*pi - x <= pi < x, so the minimum
+// is the wrapped magnitude exactly when |dphi| > pi (x = inf gives -inf,
+// whose square is inf as before; a NaN x stays NaN).
 __device__ __forceinline__ float delta_r2(float eta_a, float phi_a, float eta_b, float phi_b) {
     const float deta = eta_a - eta_b;
     const float adphi = fabsf(phi_a - phi_b);
-    const float wrapped = adphi - kTwoPi;
-    const float dphi = (adphi > kPi) ? wrapped : adphi;
+    const float dphi = fminf(adphi, kTwoPi - adphi);
     const float a = deta * deta;
     const float b = dphi * dphi;
     return a + b;

@@ -665,6 +665,9 @@ pipeline_kernel(PipeArgs P) {
     const int64_t nT = chs[P.chunk_end - 1].pre + (chs[P.chunk_end - 1].t1 - chs[P.chunk_end - 1].t0) - T0;
     const int64_t my0 = T0 + nT * blockIdx.x / gridDim.x;
     const int64_t my1 = T0 + nT * (blockIdx.x + 1) / gridDim.x;
+    int qlast = -1;  // the last active query (its cone test ends a tile's use of the columns)
+    for (int q = 0; q < P.n_q; ++q)
+        if (as_const(P.qs)[q].active) qlast = q;
     int cfirst = P.chunk_begin;
     for (int hi = P.chunk_end - 1; cfirst < hi;) {  // last chunk with pre <= my0
         const int mid = (cfirst + hi + 1) >> 1;
@@ -695,15 +698,21 @@ pipeline_kernel(PipeArgs P) {
         const bool has_el = EXT && D.eoff != nullptr;
         const bool has_bt = EXT && D.jbt != nullptr;
 
+        // several scales: the next (sub-)tile's loads fly during the walks and
+        // fills (see the tile loop below) -- where the registers allow it
+        // (LDS histograms, workgroups of at most 512 threads, one event per
+        // lane: up to 256 VGPRs; the other shapes would spill)
+        constexpr bool PIPE = MS && LDSH && WAVES <= 8 && EVPL == 1;
         // The raw loads of one tile (the offsets as their low 32-bit words:
         // tile-relative differences are exact modulo 2^32).
+        // (content as raw bits: float32, or float16 in the low half)
         struct Raw {
             uint32_t j0[EVPL], j1[EVPL], m0[EVPL], m1[EVPL], l0[EVPL], l1[EVPL];
             float w[EVPL];
             float npu[LK ? EVPL : 1];
-            float jpt[JK], jeta[JK], jphi[JK], jbt[EXT ? JK : 1];
-            float mpt[MK], meta[MK], mphi[MK], miso[MK];
-            float lpt[EK], leta[EK], lphi[EK];
+            uint32_t jpt[JK], jeta[JK], jphi[JK], jbt[EXT ? JK : 1];
+            uint32_t mpt[MK], meta[MK], mphi[MK], miso[MK];
+            uint32_t lpt[EK], leta[EK], lphi[EK];
         };
         // The chunk's tiles are counted from c_t0 in 32 bits (a workgroup's
         // share of one dataset has far fewer than 2^31 tiles); only the last
@@ -759,15 +768,15 @@ pipeline_kernel(PipeArgs P) {
 #pragma unroll
             for (int k = 0; k < JK; ++k) {
                 const int j = lane + 64 * k;
-                R.jpt[k] = buf_ldf<T>(bjpt, j);
-                R.jeta[k] = buf_ldf<T>(bjeta, j);
-                R.jphi[k] = buf_ldf<T>(bjphi, j);
-                if (EXT) R.jbt[EXT ? k : 0] = 0.0f;
+                R.jpt[k] = buf_raw<T>(bjpt, j);
+                R.jeta[k] = buf_raw<T>(bjeta, j);
+                R.jphi[k] = buf_raw<T>(bjphi, j);
+                if (EXT) R.jbt[EXT ? k : 0] = 0u;
             }
             if (EXT && has_bt) {
                 const buf_t bjbt = buf_span(static_cast<const T *>(D.jbt) + b.J0, nj * es);
 #pragma unroll
-                for (int k = 0; k < JK; ++k) R.jbt[EXT ? k : 0] = buf_ldf<T>(bjbt, lane + 64 * k);
+                for (int k = 0; k < JK; ++k) R.jbt[EXT ? k : 0] = buf_raw<T>(bjbt, lane + 64 * k);
             }
             const buf_t bmpt = buf_span(static_cast<const T *>(D.mpt) + b.M0, nm * es);
             const buf_t bmeta = buf_span(static_cast<const T *>(D.meta) + b.M0, nm * es);
@@ -775,18 +784,18 @@ pipeline_kernel(PipeArgs P) {
 #pragma unroll
             for (int k = 0; k < MK; ++k) {
                 const int m = lane + 64 * k;
-                R.mpt[k] = buf_ldf<T>(bmpt, m);
-                R.meta[k] = buf_ldf<T>(bmeta, m);
-                R.mphi[k] = buf_ldf<T>(bmphi, m);
-                R.miso[k] = 0.0f;
+                R.mpt[k] = buf_raw<T>(bmpt, m);
+                R.meta[k] = buf_raw<T>(bmeta, m);
+                R.mphi[k] = buf_raw<T>(bmphi, m);
+                R.miso[k] = 0u;
             }
             if (has_iso) {
                 const buf_t bmiso = buf_span(static_cast<const T *>(D.miso) + b.M0, nm * es);
 #pragma unroll
-                for (int k = 0; k < MK; ++k) R.miso[k] = buf_ldf<T>(bmiso, lane + 64 * k);
+                for (int k = 0; k < MK; ++k) R.miso[k] = buf_raw<T>(bmiso, lane + 64 * k);
             }
 #pragma unroll
-            for (int k = 0; k < EK; ++k) R.lpt[k] = R.leta[k] = R.lphi[k] = 0.0f;
+            for (int k = 0; k < EK; ++k) R.lpt[k] = R.leta[k] = R.lphi[k] = 0u;
             if (EXT && has_el) {
                 const buf_t bept = buf_span(static_cast<const T *>(D.ept) + b.L0, nl * es);
                 const buf_t beeta = buf_span(static_cast<const T *>(D.eeta) + b.L0, nl * es);
@@ -794,9 +803,9 @@ pipeline_kernel(PipeArgs P) {
 #pragma unroll
                 for (int k = 0; k < EK; ++k) {
                     const int m = lane + 64 * k;
-                    R.lpt[k] = buf_ldf<T>(bept, m);
-                    R.leta[k] = buf_ldf<T>(beeta, m);
-                    R.lphi[k] = buf_ldf<T>(bephi, m);
+                    R.lpt[k] = buf_raw<T>(bept, m);
+                    R.leta[k] = buf_raw<T>(beeta, m);
+                    R.lphi[k] = buf_raw<T>(bephi, m);
                 }
             }
         };
@@ -825,7 +834,7 @@ pipeline_kernel(PipeArgs P) {
             }
         };
         // Steps 2-5 for every query on a settled tile.
-        auto work = [&](int64_t e0, int ne, const TileBounds &B, Raw &R) {
+        auto work = [&](int64_t e0, int ne, const TileBounds &B, Raw &R, auto &&after_cone) {
             const int nj = B.nj, nm = B.nm, nl = B.nl;
             int32_t jb[EVPL], je[EVPL], mb[EVPL], me[EVPL], lb[EVPL], le[EVPL];
             float wv[EVPL];
@@ -840,17 +849,29 @@ pipeline_kernel(PipeArgs P) {
                 le[r] = (in && EXT && has_el) ? static_cast<int32_t>(R.l1[r] - static_cast<uint32_t>(B.L0)) : 0;
                 wv[r] = R.w[r];
             }
-            float(&jpt)[JK] = R.jpt;
-            float(&jeta)[JK] = R.jeta;
-            float(&jphi)[JK] = R.jphi;
-            float(&jbt)[EXT ? JK : 1] = R.jbt;
-            float(&mpt)[MK] = R.mpt;
-            float(&meta)[MK] = R.meta;
-            float(&mphi)[MK] = R.mphi;
-            float(&miso)[MK] = R.miso;
-            float(&lpt)[EK] = R.lpt;
-            float(&leta)[EK] = R.leta;
-            float(&lphi)[EK] = R.lphi;
+            float jpt[JK], jeta[JK], jphi[JK], jbt[EXT ? JK : 1];
+            float mpt[MK], meta[MK], mphi[MK], miso[MK];
+            float lpt[EK], leta[EK], lphi[EK];
+#pragma unroll
+            for (int k = 0; k < JK; ++k) {
+                jpt[k] = raw_f<T>(R.jpt[k]);
+                jeta[k] = raw_f<T>(R.jeta[k]);
+                jphi[k] = raw_f<T>(R.jphi[k]);
+                if (EXT) jbt[EXT ? k : 0] = raw_f<T>(R.jbt[EXT ? k : 0]);
+            }
+#pragma unroll
+            for (int k = 0; k < MK; ++k) {
+                mpt[k] = raw_f<T>(R.mpt[k]);
+                meta[k] = raw_f<T>(R.meta[k]);
+                mphi[k] = raw_f<T>(R.mphi[k]);
+                miso[k] = raw_f<T>(R.miso[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < EK; ++k) {
+                lpt[k] = raw_f<T>(R.lpt[k]);
+                leta[k] = raw_f<T>(R.leta[k]);
+                lphi[k] = raw_f<T>(R.lphi[k]);
+            }
             (void)jbt;
             (void)lpt;
             for (int q = 0; q < P.n_q; ++q) {
@@ -988,21 +1009,28 @@ pipeline_kernel(PipeArgs P) {
                 for (int k = 0; k < (MS ? JK : 1); ++k) okv[k] = tagv[k] = false;
 #pragma unroll
                 for (int k0 = 0; k0 < JK; k0 += CB) {
+                    if (64 * k0 >= nj) break;  // no jet in this pair or later (uniform)
+                    // both slots' range words, then both slots' first two
+                    // leptons, each set read together and waited for once (the
+                    // pins keep the compiler from moving a read into the
+                    // per-slot code)
                     uint32_t pk[CB], pe[CB];
 #pragma unroll
                     for (int b = 0; b < CB; ++b) {
+                        pk[b] = pe[b] = 0u;
                         if (k0 + b >= JK) continue;
                         pk[b] = L.jr[lane + 64 * (k0 + b)].rng;
-                        pe[b] = (EXT && !C::PACK) ? L.jre[(EXT && !C::PACK) ? lane + 64 * (k0 + b) : 0] : 0u;
+                        if (EXT && !C::PACK) pe[b] = L.jre[(EXT && !C::PACK) ? lane + 64 * (k0 + b) : 0];
                     }
+                    asm volatile("" : "+v"(pk[0]), "+v"(pk[1]));
+                    if (EXT && !C::PACK) asm volatile("" : "+v"(pe[0]), "+v"(pe[1]));
                     // per slot: first muon, muon count, offset of the electrons
                     // in the lepton index, lepton count
                     int s0[CB], nmu_[CB], ofe[CB], nlep[CB];
                     float e0[CB], p0[CB], e1[CB], p1[CB];
 #pragma unroll
                     for (int b = 0; b < CB; ++b) {
-                        if (k0 + b >= JK) continue;
-                        const bool live = lane + 64 * (k0 + b) < nj;
+                        const bool live = k0 + b < JK && lane + 64 * (k0 + b) < nj;
                         const uint32_t wm = live ? pk[b] : 0u;
                         const uint32_t we = live ? (C::PACK ? (pk[b] >> 16) : pe[b]) : 0u;
                         s0[b] = static_cast<int>(C::PACK ? (wm & 0xffu) : (wm & 0xffffu));
@@ -1018,16 +1046,19 @@ pipeline_kernel(PipeArgs P) {
                         e1[b] = L.seta[i1];
                         p1[b] = L.sphi[i1];
                     }
+                    asm volatile("" : "+v"(e0[0]), "+v"(p0[0]), "+v"(e1[0]), "+v"(p1[0]), "+v"(e0[1]), "+v"(p0[1]),
+                                 "+v"(e1[1]), "+v"(p1[1]));
 #pragma unroll
                     for (int b = 0; b < CB; ++b) {
                         const int k = k0 + b;
                         const int j = lane + 64 * k;
-                        if (k >= JK || j >= nj) continue;
+                        if (k >= JK) continue;
+                        const bool live = j < nj;
                         // with shifted energies, the jet's shift and the largest
                         // energy it takes over the query's scales
                         const float dsh = shift ? jes_shift(ax, edges, Q.jd, jpt[k], jeta[k]) : 0.0f;
                         const float ub = shift ? shifted_pt_bound(jpt[k], dsh, smin, smax) : jpt[k] * smax;
-                        const bool need = fabsf(jeta[k]) < jet_abseta && (jet_pt < 0.0f || ub > jet_pt);
+                        const bool need = live & (fabsf(jeta[k]) < jet_abseta) & ((jet_pt < 0.0f) | (ub > jet_pt));
                         const int cn = need ? nlep[b] : 0;
                         bool hit = (cn >= 1 & delta_r2(jeta[k], jphi[k], e0[b], p0[b]) <= thr2) |
                                    (cn >= 2 & delta_r2(jeta[k], jphi[k], e1[b], p1[b]) <= thr2);
@@ -1051,6 +1082,7 @@ pipeline_kernel(PipeArgs P) {
                             okv[MS ? k : 0] = ok;
                             tagv[MS ? k : 0] = ok && tag;
                             if (LK) dshv[(MS && LK) ? k : 0] = dsh;
+                        } else if (!live) {
                         } else if (zsel) {
                             // one scale s (= smax): the jet's energy pt * s, or
                             // pt * (1 + s * d) when shifted
@@ -1098,6 +1130,9 @@ pipeline_kernel(PipeArgs P) {
                     }
                     if (lane == 0) L.cpre[MS ? nj : 0] = static_cast<uint32_t>(runc) | (static_cast<uint32_t>(runt) << 16);
                     wave_sync();
+                    // the tile's columns are dead from here on: the next
+                    // tile's loads can fly during this query's walk and fills
+                    if (q == qlast) after_cone();
                 }
                 // ---- 5. per-event reductions, event cut, fills
                 const FillC F = fill_consts<LDSH, MS>(Q);
@@ -1235,15 +1270,24 @@ pipeline_kernel(PipeArgs P) {
                             }
                         }
                         if (any) {
-                            // two scales' bins per search: the batch that fits the
+                            // FS scales' bins per search: the batch that fits the
                             // registers of 1024-thread workgroups without spilling
+                            // (one while the next tile's loads are in flight)
+                            constexpr int FS = PIPE ? 1 : 2;
                             const double w = static_cast<double>(L.u.w.evw[e]);
 #pragma unroll
-                            for (int u = 0; u < kG; u += 2) {
-                                const float xs[6] = {ht[u], lead[u], static_cast<float>(njs[u]),
-                                                     ht[u + 1], lead[u + 1], static_cast<float>(njs[u + 1])};
-                                const bool pu[2] = {pass[u], pass[u + 1]};
-                                if (pu[0] || pu[1]) fill(xs, pu, g * kG + u, w);
+                            for (int u = 0; u < kG; u += FS) {
+                                float xs[3 * FS];
+                                bool pu[FS], anyu = false;
+#pragma unroll
+                                for (int t = 0; t < FS; ++t) {
+                                    xs[3 * t] = ht[u + t];
+                                    xs[3 * t + 1] = lead[u + t];
+                                    xs[3 * t + 2] = static_cast<float>(njs[u + t]);
+                                    pu[t] = pass[u + t];
+                                    anyu |= pu[t];
+                                }
+                                if (anyu) fill(xs, pu, g * kG + u, w);
                             }
                         }
                         e += de;
@@ -1263,11 +1307,15 @@ pipeline_kernel(PipeArgs P) {
         // event not yet run, the event count is halved until the objects fit
         // (a few scalar loads), that sub-tile runs like a tile, and the rest
         // of the tile follows.  Only a single event beyond the capacity goes
-        // one lane, straight from HBM.
+        // one lane, straight from HBM.  With several scales (PIPE) the next
+        // (sub-)tile's loads are issued into R as soon as the last query's
+        // cone test is done, so they are in flight during the walks and fills.
         int r = wave;  // this wavefront's tile (relative to c_t0)
         int eo = 0;    // events of tile r already run
         TileBounds nb{};
         if (r < nt) nb = bounds_of(r);
+        Raw R;
+        bool have = false;  // R already holds the loads of the current (sub-)tile
         while (r < nt) {
             // the lane index is re-read here so that values derived from it
             // are recomputed per tile instead of held (and spilled) across it
@@ -1286,20 +1334,39 @@ pipeline_kernel(PipeArgs P) {
                 n = (n + 1) >> 1;
                 B = tile_bounds<EXT>(D, has_el, e, n);
             }
+            // the position after this (sub-)tile; nb holds the bounds of
+            // tile r + WAVES whenever it starts a tile
+            int r2 = r, eo2 = eo + n;
+            if (eo2 >= tn) {
+                r2 = r + WAVES;
+                eo2 = 0;
+            }
             if (oversize(B)) {
                 const DsDev Dc = D;
                 if (lane == 0) event_direct<T, EXT, LDSH, DBG, LK>(P, Dc, e, edges, sink);
+                have = false;
             } else {
-                Raw R;
-                issue(e, n, B, R);
+                if (!have) issue(e, n, B, R);
                 settle(R);
-                work(e, n, B, R);
+                bool issued = false;
+                auto next_loads = [&]() {
+                    if (!PIPE || r2 >= nt) return;
+                    const int64_t e2 = ebase + static_cast<int64_t>(r2) * TW + eo2;
+                    int n2 = tile_events(r2) - eo2;
+                    TileBounds B2 = eo2 == 0 ? nb : tile_bounds<EXT>(D, has_el, e2, n2);
+                    while (n2 > 1 && oversize(B2)) {
+                        n2 = (n2 + 1) >> 1;
+                        B2 = tile_bounds<EXT>(D, has_el, e2, n2);
+                    }
+                    if (oversize(B2)) return;
+                    issue(e2, n2, B2, R);
+                    issued = true;
+                };
+                work(e, n, B, R, next_loads);
+                have = issued;
             }
-            eo += n;
-            if (eo >= tn) {
-                r += WAVES;
-                eo = 0;
-            }
+            r = r2;
+            eo = eo2;
         }
         // merge the LDS histograms into the dataset's block in HBM (the next
         // chunk, if any, is another dataset)
