@@ -181,6 +181,106 @@ __device__ __forceinline__ float jes_shift(const LkAxes &a, const float *E, int 
     return lookup_interp(a.jc, E + jd + (row - 1) * a.jc.nb, pt);
 }
 
+// lookup_bin of N values at once (the values with use[n] unset give 1): a
+// branch-free binary search taking the same fixed steps for every value, so
+// the reads of a step go out together; it counts the edges at or below x
+// (the slot hist_slot_lohi finds), and a NaN x gives the quiet NaN.
+template <int N>
+__device__ __forceinline__ void lookup_bin_n(const Axis &a, const float *C, const float (&x)[N],
+                                             const bool (&use)[N], float (&out)[N]) {
+    const int nb = a.nb;
+    int pos[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) pos[n] = 0;
+    int top = 1;
+    while (top * 2 <= nb + 1) top *= 2;
+    for (int step = top; step > 0; step >>= 1) {
+        float e[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) e[n] = a.E[min(pos[n] + step, nb + 1) - 1];
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const int t = pos[n] + step;
+            pos[n] = (t <= nb + 1 && e[n] <= x[n]) ? t : pos[n];
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const float c = C[pos[n]];
+        out[n] = use[n] ? ((x[n] != x[n]) ? __builtin_nanf("") : c) : 1.0f;
+    }
+}
+
+// jes_shift of N jets at once: branch-free binary searches over the |eta|
+// row edges and the pt edges that take the same fixed steps for every jet
+// (so the N jets' LDS reads of a step go out together, one round trip per
+// step, the two searches interleaved), then every value the interpolation
+// may need read in one round; the arithmetic is lookup_interp's.  A search
+// counts the edges at or below its value (0 for NaN), which is the slot
+// hist_slot_lohi finds; the row is that count clamped to the rows, as in
+// lookup_row.
+template <int N>
+__device__ __forceinline__ void jes_shift_n(const LkAxes &a, const float *E, int jd, const float (&pt)[N],
+                                            const float (&eta)[N], float (&out)[N]) {
+    const Axis &c = a.jc, &rw = a.jr;
+    const int nb = c.nb, nr = rw.nb;
+    int rpos[N], pos[N];
+    float ae[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        ae[n] = fabsf(eta[n]);
+        rpos[n] = 0;
+        pos[n] = 0;
+    }
+    int top = 1, rtop = 1;
+    while (top * 2 <= nb + 1) top *= 2;
+    while (rtop * 2 <= nr + 1) rtop *= 2;
+    for (int step = top, rstep = rtop; step > 0 || rstep > 0; step >>= 1, rstep >>= 1) {
+        float e[N], re[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            if (step > 0) e[n] = c.E[min(pos[n] + step, nb + 1) - 1];
+            if (rstep > 0) re[n] = rw.E[min(rpos[n] + rstep, nr + 1) - 1];
+        }
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            if (step > 0) {
+                const int t = pos[n] + step;
+                pos[n] = (t <= nb + 1 && e[n] <= pt[n]) ? t : pos[n];
+            }
+            if (rstep > 0) {
+                const int t = rpos[n] + rstep;
+                rpos[n] = (t <= nr + 1 && re[n] <= ae[n]) ? t : rpos[n];
+            }
+        }
+    }
+    int row[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) row[n] = min(max(rpos[n], 1), nr);
+    const float mfirst = bin_centre(c.E[0], c.E[1]), mlast = bin_centre(c.E[nb - 1], c.E[nb]);
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const float *V = E + jd + (row[n] - 1) * nb;
+        const float x = pt[n];
+        // the interval is s - 1 or s (s clamped so every read stays inside
+        // the table; outside m_1 < x < m_nb the result is replaced below)
+        const int s = min(max(pos[n], 1), nb);
+        const float ea = c.E[max(s - 2, 0)], eb = c.E[s - 1], ec = c.E[s], ed = c.E[min(s + 1, nb)];
+        const float va = V[max(s - 2, 0)], vb = V[s - 1], vc = V[min(s, nb - 1)];
+        const float v_first = V[0], v_last = V[nb - 1];
+        const float ms = bin_centre(eb, ec);
+        const bool at_s = ms <= x;
+        const float m0 = at_s ? ms : bin_centre(ea, eb);
+        const float m1 = at_s ? bin_centre(ec, ed) : ms;
+        const float v0 = at_s ? vb : va, v1 = at_s ? vc : vb;
+        const float slope = (v1 - v0) / (m1 - m0);
+        const float d = x - m0;
+        const float p = d * slope;
+        const float r = v0 + p;
+        out[n] = (x != x) ? __builtin_nanf("") : (x <= mfirst ? v_first : (x >= mlast ? v_last : r));
+    }
+}
+
 // Largest pt * (1 + s * d) over the scales in [smin, smax]: the factor is
 // monotone in s (its rounding is monotone) and the product monotone in the
 // factor, so the extremes are at smin or smax.  NaN when pt or d is NaN.
@@ -656,6 +756,15 @@ pipeline_kernel(PipeArgs P) {
     if (P.scales_in_lds)
         for (int i = tid; i < P.n_scales; i += 64 * WAVES) s_s[i] = as_const(P.scales)[i];
     __syncthreads();
+    // Runs f on the table (edges and lookup tables) where it lives, with a
+    // pointer whose address space the compiler can see (LDS reads rather
+    // than flat ones).
+    auto on_tables = [&](auto &&f) {
+        if (P.edges_in_lds)
+            f(static_cast<const float *>(e_s));
+        else
+            f(static_cast<const float *>(P.edges));
+    };
 
     // This workgroup's work: an equal slice [my0, my1) of the concatenated
     // tiles of chunks [chunk_begin, chunk_end); its first chunk is found by a
@@ -901,8 +1010,6 @@ pipeline_kernel(PipeArgs P) {
                 const bool use_sf = LK && Q.sf_nb > 0;
                 const bool shift = LK && Q.jes_mode == 1;
                 const float smin = LK ? Q.smin : 0.0f;
-                LkAxes ax{};
-                if (LK) ax = lk_axes(Q, edges);
                 // ---- 2. lepton selection; selected leptons compacted into LDS
                 // (all compares evaluated: no branches per slot)
                 {
@@ -914,9 +1021,7 @@ pipeline_kernel(PipeArgs P) {
                     if (use_sf) {
                         // each selected muon's scale factor, compacted beside it
                         float sfv[MK];
-#pragma unroll
-                        for (int k = 0; k < MK; ++k)
-                            sfv[k] = sel[k] ? lookup_bin(ax.sf, edges + Q.sf_c, mpt[k]) : 1.0f;
+                        on_tables([&](const float *E) { lookup_bin_n<MK>(lk_axes(Q, E).sf, E + Q.sf_c, mpt, sel, sfv); });
                         compact<MK, true>(sel, meta, mphi, nm, lane, L.seta, L.sphi, L.u.p.mpre, sfv, L.ssf);
                     } else {
                         compact<MK>(sel, meta, mphi, nm, lane, L.seta, L.sphi, L.u.p.mpre);
@@ -944,7 +1049,10 @@ pipeline_kernel(PipeArgs P) {
                     if (ev < ne) {
                         const int s0 = L.u.p.mpre[mb[r]];
                         nmu[r] = L.u.p.mpre[me[r]] - s0;
-                        if (use_pu) wq[r] = wq[r] * lookup_bin(ax.pu, edges + Q.pu_c, R.npu[LK ? r : 0]);
+                        if (use_pu)
+                            on_tables([&](const float *E) {
+                                wq[r] = wq[r] * lookup_bin(lk_axes(Q, E).pu, E + Q.pu_c, R.npu[LK ? r : 0]);
+                            });
                         if (use_sf) {
                             // product of the selected muons' scale factors, in order from 1
                             float prod = 1.0f;
@@ -1001,6 +1109,16 @@ pipeline_kernel(PipeArgs P) {
                 // events' leptons or on the padding entries and are unused.
                 constexpr int CB = 2;
                 constexpr int EO = C::MC + 2;
+                // with shifted energies, every slot's shift, the searches of
+                // all slots in lockstep (their LDS reads in flight together)
+                float dsh_all[LK ? JK : 1];
+                if constexpr (LK) {
+                    if (shift)
+                        on_tables([&](const float *E) { jes_shift_n<JK>(lk_axes(Q, E), E, Q.jd, jpt, jeta, dsh_all); });
+                    else
+#pragma unroll
+                        for (int k = 0; k < JK; ++k) dsh_all[LK ? k : 0] = 0.0f;
+                }
                 // MS: per slot, whether the jet is a candidate (selected at
                 // some scale), a b-tagged candidate, and its shift (LK)
                 bool okv[MS ? JK : 1], tagv[MS ? JK : 1];
@@ -1022,7 +1140,10 @@ pipeline_kernel(PipeArgs P) {
                         pk[b] = L.jr[lane + 64 * (k0 + b)].rng;
                         if (EXT && !C::PACK) pe[b] = L.jre[(EXT && !C::PACK) ? lane + 64 * (k0 + b) : 0];
                     }
-                    asm volatile("" : "+v"(pk[0]), "+v"(pk[1]));
+                    // (pinned in the extended schema only: the base kernel hides
+                    // the latency with more wavefronts and measured faster
+                    // with the compiler's own placement)
+                    if (EXT) asm volatile("" : "+v"(pk[0]), "+v"(pk[1]));
                     if (EXT && !C::PACK) asm volatile("" : "+v"(pe[0]), "+v"(pe[1]));
                     // per slot: first muon, muon count, offset of the electrons
                     // in the lepton index, lepton count
@@ -1046,8 +1167,9 @@ pipeline_kernel(PipeArgs P) {
                         e1[b] = L.seta[i1];
                         p1[b] = L.sphi[i1];
                     }
-                    asm volatile("" : "+v"(e0[0]), "+v"(p0[0]), "+v"(e1[0]), "+v"(p1[0]), "+v"(e0[1]), "+v"(p0[1]),
-                                 "+v"(e1[1]), "+v"(p1[1]));
+                    if (EXT)
+                        asm volatile("" : "+v"(e0[0]), "+v"(p0[0]), "+v"(e1[0]), "+v"(p1[0]), "+v"(e0[1]),
+                                     "+v"(p0[1]), "+v"(e1[1]), "+v"(p1[1]));
 #pragma unroll
                     for (int b = 0; b < CB; ++b) {
                         const int k = k0 + b;
@@ -1056,7 +1178,7 @@ pipeline_kernel(PipeArgs P) {
                         const bool live = j < nj;
                         // with shifted energies, the jet's shift and the largest
                         // energy it takes over the query's scales
-                        const float dsh = shift ? jes_shift(ax, edges, Q.jd, jpt[k], jeta[k]) : 0.0f;
+                        const float dsh = shift ? dsh_all[LK ? k : 0] : 0.0f;
                         const float ub = shift ? shifted_pt_bound(jpt[k], dsh, smin, smax) : jpt[k] * smax;
                         const bool need = live & (fabsf(jeta[k]) < jet_abseta) & ((jet_pt < 0.0f) | (ub > jet_pt));
                         const int cn = need ? nlep[b] : 0;
