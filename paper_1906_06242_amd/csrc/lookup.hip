@@ -9,6 +9,8 @@
 // the arrays are aligned to that, and written with one 16-byte store.  Each
 // workgroup first copies the tables into LDS when they fit (the bin search
 // reads a few edges per element), else reads them from HBM through the cache.
+// A thread's four lookups search in lockstep (the *_n forms in lookup.hpp):
+// their reads of each search step go out together.
 #include "lookup.hpp"
 
 namespace hepk {
@@ -78,13 +80,20 @@ __global__ __launch_bounds__(LB) void lookup1_kernel(const X *__restrict__ x, in
         c = lk_lds + nb + 1;
     }
     const Axis a{e, nb, lo, hi, bin_inv_width(lo, hi, nb)};
+    // guess first for near-uniform edges (tested once per workgroup on the
+    // LDS copy; tables left in HBM always guess first)
+    const bool guess = LDS ? near_uniform(e, nb) : true;
     const int64_t ng = (n + 3) >> 2;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * LB;
     for (int64_t g = static_cast<int64_t>(blockIdx.x) * LB + threadIdx.x; g < ng; g += stride) {
         float v[4], r[4];
         load_quad<X, VEC>(x, g, n, v);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) r[j] = MODE == 0 ? lookup_bin(a, c, v[j]) : lookup_interp(a, c + 1, v[j]);
+        if (MODE == 0) {
+            const bool use[4] = {true, true, true, true};
+            lookup_bin_n<4>(a, c, v, use, r, guess);
+        } else {
+            lookup_interp_n<4>(a, c + 1, v, r, guess);
+        }
         store_quad<VEC>(out, g, n, r);
     }
 }
@@ -117,11 +126,7 @@ __global__ __launch_bounds__(LB) void jes_delta_kernel(const X *__restrict__ pt,
         float p[4], h[4], r[4];
         load_quad<X, VEC>(pt, g, n, p);
         load_quad<X, VEC>(eta, g, n, h);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int row = lookup_row(rows, fabsf(h[j]));
-            r[j] = lookup_interp(cols, d + static_cast<int64_t>(row - 1) * np, p[j]);
-        }
+        lookup2_n<4>(rows, cols, d, p, h, r);
         store_quad<VEC>(out, g, n, r);
     }
 }

@@ -181,104 +181,11 @@ __device__ __forceinline__ float jes_shift(const LkAxes &a, const float *E, int 
     return lookup_interp(a.jc, E + jd + (row - 1) * a.jc.nb, pt);
 }
 
-// lookup_bin of N values at once (the values with use[n] unset give 1): a
-// branch-free binary search taking the same fixed steps for every value, so
-// the reads of a step go out together; it counts the edges at or below x
-// (the slot hist_slot_lohi finds), and a NaN x gives the quiet NaN.
-template <int N>
-__device__ __forceinline__ void lookup_bin_n(const Axis &a, const float *C, const float (&x)[N],
-                                             const bool (&use)[N], float (&out)[N]) {
-    const int nb = a.nb;
-    int pos[N];
-#pragma unroll
-    for (int n = 0; n < N; ++n) pos[n] = 0;
-    int top = 1;
-    while (top * 2 <= nb + 1) top *= 2;
-    for (int step = top; step > 0; step >>= 1) {
-        float e[N];
-#pragma unroll
-        for (int n = 0; n < N; ++n) e[n] = a.E[min(pos[n] + step, nb + 1) - 1];
-#pragma unroll
-        for (int n = 0; n < N; ++n) {
-            const int t = pos[n] + step;
-            pos[n] = (t <= nb + 1 && e[n] <= x[n]) ? t : pos[n];
-        }
-    }
-#pragma unroll
-    for (int n = 0; n < N; ++n) {
-        const float c = C[pos[n]];
-        out[n] = use[n] ? ((x[n] != x[n]) ? __builtin_nanf("") : c) : 1.0f;
-    }
-}
-
-// jes_shift of N jets at once: branch-free binary searches over the |eta|
-// row edges and the pt edges that take the same fixed steps for every jet
-// (so the N jets' LDS reads of a step go out together, one round trip per
-// step, the two searches interleaved), then every value the interpolation
-// may need read in one round; the arithmetic is lookup_interp's.  A search
-// counts the edges at or below its value (0 for NaN), which is the slot
-// hist_slot_lohi finds; the row is that count clamped to the rows, as in
-// lookup_row.
+// jes_shift of N jets at once (lookup2_n over the query's table).
 template <int N>
 __device__ __forceinline__ void jes_shift_n(const LkAxes &a, const float *E, int jd, const float (&pt)[N],
                                             const float (&eta)[N], float (&out)[N]) {
-    const Axis &c = a.jc, &rw = a.jr;
-    const int nb = c.nb, nr = rw.nb;
-    int rpos[N], pos[N];
-    float ae[N];
-#pragma unroll
-    for (int n = 0; n < N; ++n) {
-        ae[n] = fabsf(eta[n]);
-        rpos[n] = 0;
-        pos[n] = 0;
-    }
-    int top = 1, rtop = 1;
-    while (top * 2 <= nb + 1) top *= 2;
-    while (rtop * 2 <= nr + 1) rtop *= 2;
-    for (int step = top, rstep = rtop; step > 0 || rstep > 0; step >>= 1, rstep >>= 1) {
-        float e[N], re[N];
-#pragma unroll
-        for (int n = 0; n < N; ++n) {
-            if (step > 0) e[n] = c.E[min(pos[n] + step, nb + 1) - 1];
-            if (rstep > 0) re[n] = rw.E[min(rpos[n] + rstep, nr + 1) - 1];
-        }
-#pragma unroll
-        for (int n = 0; n < N; ++n) {
-            if (step > 0) {
-                const int t = pos[n] + step;
-                pos[n] = (t <= nb + 1 && e[n] <= pt[n]) ? t : pos[n];
-            }
-            if (rstep > 0) {
-                const int t = rpos[n] + rstep;
-                rpos[n] = (t <= nr + 1 && re[n] <= ae[n]) ? t : rpos[n];
-            }
-        }
-    }
-    int row[N];
-#pragma unroll
-    for (int n = 0; n < N; ++n) row[n] = min(max(rpos[n], 1), nr);
-    const float mfirst = bin_centre(c.E[0], c.E[1]), mlast = bin_centre(c.E[nb - 1], c.E[nb]);
-#pragma unroll
-    for (int n = 0; n < N; ++n) {
-        const float *V = E + jd + (row[n] - 1) * nb;
-        const float x = pt[n];
-        // the interval is s - 1 or s (s clamped so every read stays inside
-        // the table; outside m_1 < x < m_nb the result is replaced below)
-        const int s = min(max(pos[n], 1), nb);
-        const float ea = c.E[max(s - 2, 0)], eb = c.E[s - 1], ec = c.E[s], ed = c.E[min(s + 1, nb)];
-        const float va = V[max(s - 2, 0)], vb = V[s - 1], vc = V[min(s, nb - 1)];
-        const float v_first = V[0], v_last = V[nb - 1];
-        const float ms = bin_centre(eb, ec);
-        const bool at_s = ms <= x;
-        const float m0 = at_s ? ms : bin_centre(ea, eb);
-        const float m1 = at_s ? bin_centre(ec, ed) : ms;
-        const float v0 = at_s ? vb : va, v1 = at_s ? vc : vb;
-        const float slope = (v1 - v0) / (m1 - m0);
-        const float d = x - m0;
-        const float p = d * slope;
-        const float r = v0 + p;
-        out[n] = (x != x) ? __builtin_nanf("") : (x <= mfirst ? v_first : (x >= mlast ? v_last : r));
-    }
+    lookup2_n<N>(a.jr, a.jc, E + jd, pt, eta, out);
 }
 
 // Largest pt * (1 + s * d) over the scales in [smin, smax]: the factor is
@@ -1021,7 +928,7 @@ pipeline_kernel(PipeArgs P) {
                     if (use_sf) {
                         // each selected muon's scale factor, compacted beside it
                         float sfv[MK];
-                        on_tables([&](const float *E) { lookup_bin_n<MK>(lk_axes(Q, E).sf, E + Q.sf_c, mpt, sel, sfv); });
+                        on_tables([&](const float *E) { lookup_bin_n<MK>(lk_axes(Q, E).sf, E + Q.sf_c, mpt, sel, sfv, false); });
                         compact<MK, true>(sel, meta, mphi, nm, lane, L.seta, L.sphi, L.u.p.mpre, sfv, L.ssf);
                     } else {
                         compact<MK>(sel, meta, mphi, nm, lane, L.seta, L.sphi, L.u.p.mpre);
