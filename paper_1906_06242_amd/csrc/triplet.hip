@@ -10,14 +10,15 @@
 // tile's triplets evenly over its 64 lanes:
 //   1. the tile's objects are loaded with all loads in flight, and the
 //      selected ones compacted by wavefront ballot into LDS (four-momenta and
-//      local index), so each event's selected objects are contiguous;
+//      index in the tile), so each event's selected objects are contiguous;
 //   2. the events' triplet counts C(n_e, 3) are prefix-summed across the
 //      wavefront;
 //   3. lane l takes the l-th 1/64 of the tile's triplets in lexicographic
 //      order (i < j < k within an event, events in order), finds its first
 //      triplet by a search over the prefix sums and the combinatorial number
 //      system, and walks on from there;
-//   4. per triplet: three float32 sums per component, the mass square
+//   4. per triplet: three float32 sums per component (the pair sum of i and
+//      j kept while only k moves), the mass square
 //      E^2 - px^2 - py^2 - pz^2 (each product and difference rounded on its
 //      own), a correctly rounded square root and the distance d to the
 //      target; a lane keeps the smallest (d, rank in the event) and merges it
@@ -34,7 +35,10 @@ namespace hepk {
 
 constexpr int TB = 256;
 constexpr int TWV = TB / 64;
-constexpr int TK = 8;  // objects per lane staged for a tile (512 per tile)
+// objects per lane staged for a tile (384 per tile: 3.6 standard deviations
+// above the 320 jets of 64 events of the analysis workloads; 9.1 KB of LDS
+// per wavefront, so four wavefronts per SIMD instead of three with 512)
+constexpr int TK = 6;
 
 __global__ __launch_bounds__(256) void p4_kernel(const float *__restrict__ pt, const float *__restrict__ eta,
                                                  const float *__restrict__ phi, const float *__restrict__ mass,
@@ -138,7 +142,7 @@ __device__ __forceinline__ void unrank(int64_t r, int n, int &i, int &j, int &k)
 
 struct TripletLds {
     float x[64 * TK], y[64 * TK], z[64 * TK], e[64 * TK];  // selected objects, compacted
-    uint16_t li[64 * TK];                                  // their local index in the event
+    uint16_t li[64 * TK];                                  // their index in the tile
     uint16_t pre[64 * TK + 1];                             // selected objects before each object
     int64_t tp[65];                                        // triplets of the events before each
     uint64_t key[64];                                      // per event: min (d bits << 32 | rank)
@@ -181,23 +185,31 @@ __global__ __launch_bounds__(TB) void best_triplet_kernel(const int64_t *__restr
             }
             continue;
         }
-        // 1. loads, then the selected objects compacted in tile order
+        // 1. loads (buffer loads over exactly the tile's objects: 0 past the
+        // end, no per-slot branch, all in flight and waited for once), then
+        // the selected objects compacted in tile order
         const int nobj = static_cast<int>(tot);
+        const uint32_t nb4 = static_cast<uint32_t>(nobj) * 4u;
+        const buf_t bx = buf_span(px + A, nb4), by = buf_span(py + A, nb4);
+        const buf_t bz = buf_span(pz + A, nb4), be = buf_span(en + A, nb4);
+        const buf_t bm = buf_span(om ? static_cast<const void *>(om + A) : static_cast<const void *>(px),
+                                  om ? static_cast<uint32_t>(nobj) : 0u);
         float vx[TK], vy[TK], vz[TK], ve[TK];
+        uint32_t mk[TK];
         bool sel[TK];
 #pragma unroll
         for (int k = 0; k < TK; ++k) {
             const int i = lane + 64 * k;
-            vx[k] = vy[k] = vz[k] = ve[k] = 0.0f;
-            sel[k] = false;
-            if (i < nobj) {
-                vx[k] = px[A + i];
-                vy[k] = py[A + i];
-                vz[k] = pz[A + i];
-                ve[k] = en[A + i];
-                sel[k] = !om || om[A + i] != 0;
-            }
+            vx[k] = __builtin_bit_cast(float, buf_u32(bx, i * 4));
+            vy[k] = __builtin_bit_cast(float, buf_u32(by, i * 4));
+            vz[k] = __builtin_bit_cast(float, buf_u32(bz, i * 4));
+            ve[k] = __builtin_bit_cast(float, buf_u32(be, i * 4));
+            mk[k] = om ? __builtin_amdgcn_raw_buffer_load_b8(bm, i, 0, 0) : 1u;
         }
+#pragma unroll
+        for (int k = 0; k < TK; ++k) asm volatile("" ::"v"(vx[k]), "v"(vy[k]), "v"(vz[k]), "v"(ve[k]), "v"(mk[k]));
+#pragma unroll
+        for (int k = 0; k < TK; ++k) sel[k] = (lane + 64 * k < nobj) & (mk[k] != 0u);
         int run = 0;
 #pragma unroll
         for (int k = 0; k < TK; ++k) {
@@ -212,19 +224,18 @@ __global__ __launch_bounds__(TB) void best_triplet_kernel(const int64_t *__restr
                 L.y[before] = vy[k];
                 L.z[before] = vz[k];
                 L.e[before] = ve[k];
+                L.li[before] = static_cast<uint16_t>(i);
             }
             run += __popcll(bal);
         }
         if (lane == 0) L.pre[nobj] = static_cast<uint16_t>(run);
         wave_fence_t();
-        // 2. per event: first selected object, count, triplets; the local
-        // index of each selected object; prefix sums over the tile
+        // 2. per event: first selected object, count, triplets; prefix sums
+        // over the tile
         int s0 = 0, nn = 0;
         if (act) {
             s0 = L.pre[a0];
             nn = L.pre[a1] - s0;
-            for (int64_t i = a0; i < a1; ++i)
-                if (L.pre[i + 1] != L.pre[i]) L.li[L.pre[i]] = static_cast<uint16_t>(i - a0);
         }
         const int64_t tcount = act ? c3(nn) : 0;
         int64_t incl = tcount;
@@ -259,9 +270,19 @@ __global__ __launch_bounds__(TB) void best_triplet_kernel(const int64_t *__restr
             int i, j, k;
             unrank(rank, n, i, j, k);
             uint64_t best = ~0ull;
+            // the pair sums (X[i] + X[j]) of the current (i, j), reread only
+            // when i or j moves: the same value the mass adds X[k] to
+            float pxij = L.x[base + i] + L.x[base + j], pyij = L.y[base + i] + L.y[base + j];
+            float pzij = L.z[base + i] + L.z[base + j], peij = L.e[base + i] + L.e[base + j];
             for (int64_t tt = t0; tt < t1; ++tt) {
-                float mm, d;
-                triplet_mass(L.x + base, L.y + base, L.z + base, L.e + base, i, j, k, target, mm, d);
+                const float sx = pxij + L.x[base + k], sy = pyij + L.y[base + k];
+                const float sz = pzij + L.z[base + k], se = peij + L.e[base + k];
+                float m2 = se * se;
+                m2 = m2 - sx * sx;
+                m2 = m2 - sy * sy;
+                m2 = m2 - sz * sz;
+                const float mm = (m2 < 0.0f) ? 0.0f : sqrtf(m2);
+                const float d = fabsf(mm - target);
                 if (d < INFINITY) {  // NaN and infinite distances are never taken
                     const uint64_t key = (static_cast<uint64_t>(__float_as_uint(d)) << 32) | static_cast<uint64_t>(rank);
                     best = key < best ? key : best;
@@ -287,6 +308,10 @@ __global__ __launch_bounds__(TB) void best_triplet_kernel(const int64_t *__restr
                         j = i + 1;
                     }
                     k = j + 1;
+                    pxij = L.x[base + i] + L.x[base + j];
+                    pyij = L.y[base + i] + L.y[base + j];
+                    pzij = L.z[base + i] + L.z[base + j];
+                    peij = L.e[base + i] + L.e[base + j];
                 }
             }
             if (best != ~0ull) atomicMin(reinterpret_cast<unsigned long long *>(&L.key[ev]), best);
@@ -302,9 +327,10 @@ __global__ __launch_bounds__(TB) void best_triplet_kernel(const int64_t *__restr
                 unrank(static_cast<int64_t>(key & 0xffffffffu), nn, i, j, k);
                 float d;
                 triplet_mass(L.x + s0, L.y + s0, L.z + s0, L.e + s0, i, j, k, target, mm, d);
-                bi = L.li[s0 + i];
-                bj = L.li[s0 + j];
-                bk = L.li[s0 + k];
+                // local index = tile index of the compacted object - the event's first
+                bi = static_cast<int32_t>(L.li[s0 + i]) - static_cast<int32_t>(a0);
+                bj = static_cast<int32_t>(L.li[s0 + j]) - static_cast<int32_t>(a0);
+                bk = static_cast<int32_t>(L.li[s0 + k]) - static_cast<int32_t>(a0);
             }
             out_mass[e] = mm;
             out_idx[3 * e] = bi;
