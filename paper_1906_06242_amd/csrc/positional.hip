@@ -72,13 +72,18 @@ __device__ __forceinline__ bool pt_before(float pi, int64_t i, float pj, int64_t
 
 __device__ __forceinline__ bool opposite_sign(int32_t a, int32_t b) { return (a > 0 && b < 0) || (a < 0 && b > 0); }
 
-// Per event: rank every selected object in pT order (the number of selected
-// objects before it), then take the pair of selected objects with opposite
-// charges whose (rank, rank) is smallest in lexicographic order -- the first
-// object in pT order that has an opposite-charge partner after it, and its
-// first such partner.  Both get mask 1, every other object of the event 0.
-// Events of up to kOsRegs objects are held in registers (one read of each
-// column per object); larger ones are ranked straight from memory.
+// Per event, the first pair (p, r), p before r in pT order, of selected
+// objects with charges of opposite sign -- which is always the highest-pT
+// object of positive charge and the highest-pT object of negative charge:
+// with both present, say the positive one P first, every selected object
+// before P has charge 0 (P is the first positive and the first negative
+// comes after it), so P is the first object with a partner after it and
+// its first partner is the first negative; with either absent there is no
+// pair.  So one pass keeps the best (in pT order) positive and negative
+// object.  Both get mask 1, every other object of the event 0.  Events of
+// up to kOsRegs objects are read into registers in one batch (indices
+// clamped into the event, so no load waits on another); larger ones are
+// scanned straight from memory.
 constexpr int kOsRegs = 8;
 
 template <typename T>
@@ -90,75 +95,53 @@ __global__ __launch_bounds__(PB) void opposite_sign_kernel(const int64_t *__rest
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * PB + threadIdx.x; e < n_events; e += stride) {
         const int64_t i0 = off[e], i1 = off[e + 1];
         const int64_t n = i1 - i0;
+        // best positive and negative object so far (local index, its pt)
+        int64_t bp = -1, bn = -1;
+        float pp = 0.0f, pn = 0.0f;
+        auto take = [&](bool sel, int32_t c, float pa, int64_t a) {
+            if (sel && c > 0 && (bp < 0 || pt_before(pa, a, pp, bp))) {
+                bp = a;
+                pp = pa;
+            }
+            if (sel && c < 0 && (bn < 0 || pt_before(pa, a, pn, bn))) {
+                bn = a;
+                pn = pa;
+            }
+        };
         if (n <= kOsRegs) {
             float p[kOsRegs];
             int32_t c[kOsRegs];
-            bool s[kOsRegs];
+            uint32_t m[kOsRegs];
 #pragma unroll
             for (int k = 0; k < kOsRegs; ++k) {
                 p[k] = 0.0f;
                 c[k] = 0;
-                s[k] = false;
-                if (k < n) {
-                    p[k] = ldf(pt, i0 + k);
-                    c[k] = q[i0 + k];
-                    s[k] = !om || om[i0 + k] != 0;
+                m[k] = 0u;
+            }
+            if (n > 0) {
+#pragma unroll
+                for (int k = 0; k < kOsRegs; ++k) {
+                    const int64_t ix = i0 + min<int64_t>(k, n - 1);
+                    p[k] = ldf(pt, ix);
+                    c[k] = q[ix];
+                    m[k] = om ? static_cast<uint32_t>(om[ix]) : 1u;
                 }
             }
-            int rank[kOsRegs];
 #pragma unroll
-            for (int a = 0; a < kOsRegs; ++a) {
-                rank[a] = 0;
-#pragma unroll
-                for (int b = 0; b < kOsRegs; ++b)
-                    rank[a] += (b != a && s[b] && pt_before(p[b], b, p[a], a)) ? 1 : 0;
-            }
-            int ba = -1, bb = -1, ra = kOsRegs, rb = kOsRegs;
-#pragma unroll
-            for (int a = 0; a < kOsRegs; ++a)
-#pragma unroll
-                for (int b = 0; b < kOsRegs; ++b) {
-                    const bool ok = s[a] && s[b] && rank[a] < rank[b] && opposite_sign(c[a], c[b]);
-                    if (ok && (rank[a] < ra || (rank[a] == ra && rank[b] < rb))) {
-                        ra = rank[a];
-                        rb = rank[b];
-                        ba = a;
-                        bb = b;
-                    }
-                }
+            for (int k = 0; k < kOsRegs; ++k) take((k < n) & (m[k] != 0u), c[k], p[k], k);
+            const bool pair = bp >= 0 && bn >= 0;
 #pragma unroll
             for (int k = 0; k < kOsRegs; ++k)
-                if (k < n) out[i0 + k] = (k == ba || k == bb) ? 1 : 0;
+                if (k < n) out[i0 + k] = (pair && (k == bp || k == bn)) ? 1 : 0;
             continue;
         }
-        int64_t ba = -1, bb = -1, ra = INT64_MAX, rb = INT64_MAX;
-        for (int64_t a = i0; a < i1; ++a) {
-            out[a] = 0;
-            if (om && !om[a]) continue;
-            const float pa = ldf(pt, a);
-            const int32_t qa = q[a];
-            int64_t rank_a = 0;
-            for (int64_t c = i0; c < i1; ++c)
-                if ((!om || om[c]) && c != a && pt_before(ldf(pt, c), c, pa, a)) ++rank_a;
-            if (rank_a > ra) continue;  // cannot improve the pair
-            for (int64_t b = i0; b < i1; ++b) {
-                if (b == a || (om && !om[b]) || !opposite_sign(qa, q[b])) continue;
-                const float pb = ldf(pt, b);
-                if (!pt_before(pa, a, pb, b)) continue;  // b must come after a
-                int64_t rank_b = 0;
-                for (int64_t c = i0; c < i1; ++c)
-                    if ((!om || om[c]) && c != b && pt_before(ldf(pt, c), c, pb, b)) ++rank_b;
-                if (rank_a < ra || (rank_a == ra && rank_b < rb)) {
-                    ra = rank_a;
-                    rb = rank_b;
-                    ba = a;
-                    bb = b;
-                }
-            }
+        for (int64_t a = 0; a < n; ++a) {
+            out[i0 + a] = 0;
+            take(!om || om[i0 + a] != 0, q[i0 + a], ldf(pt, i0 + a), a);
         }
-        if (ba >= 0) {
-            out[ba] = 1;
-            out[bb] = 1;
+        if (bp >= 0 && bn >= 0) {
+            out[i0 + bp] = 1;
+            out[i0 + bn] = 1;
         }
     }
 }
