@@ -19,11 +19,28 @@ constexpr int PB = 256;
 
 // Content index of the n-th (from 0) object of [i0, i1) with m set (every
 // object when m is NULL); -1 when there are fewer.
+// The first kNthBatch mask bytes are read in one batch (indices clamped
+// into the range, so no read waits on another); only a range whose n-th
+// selected object lies beyond them goes on byte by byte.
+constexpr int kNthBatch = 8;
 __device__ __forceinline__ int64_t nth_selected(int64_t i0, int64_t i1, const uint8_t *m, int32_t n) {
     if (n < 0) return -1;
     if (!m) return (n < i1 - i0) ? i0 + n : -1;
+    const int64_t len = i1 - i0;
+    if (len <= 0) return -1;
+    uint32_t b[kNthBatch];
+#pragma unroll
+    for (int k = 0; k < kNthBatch; ++k) b[k] = m[i0 + min<int64_t>(k, len - 1)];
     int32_t seen = 0;
-    for (int64_t i = i0; i < i1; ++i) {
+    int64_t found = -1;
+#pragma unroll
+    for (int k = 0; k < kNthBatch; ++k) {
+        const bool hit = k < len && b[k] != 0u;
+        found = (hit && seen == n && found < 0) ? i0 + k : found;
+        seen += hit ? 1 : 0;
+    }
+    if (found >= 0 || len <= kNthBatch) return found;
+    for (int64_t i = i0 + kNthBatch; i < i1; ++i) {
         if (!m[i]) continue;
         if (seen == n) return i;
         ++seen;
