@@ -181,6 +181,8 @@ struct Elem<4> {
     using T = uint32_t;
 };
 
+constexpr int kCompactChunks = 8;  // chunks of 64 objects a tile reads in one batch
+
 template <int ES>
 __global__ __launch_bounds__(PB) void compact_kernel(const int64_t *__restrict__ off, int64_t n_events,
                                                      const typename Elem<ES>::T *__restrict__ content,
@@ -196,6 +198,41 @@ __global__ __launch_bounds__(PB) void compact_kernel(const int64_t *__restrict__
         const int64_t e1 = min<int64_t>(e0 + 64, n_events);
         const int64_t A = as_const(off)[e0], B = as_const(off)[e1];
         int64_t base = as_const(offsets_out)[e0];
+        if (B - A <= 64 * kCompactChunks) {
+            // the whole tile: every chunk's mask bytes and elements as
+            // buffer loads over exactly [A, B) (0 past the end), all in
+            // flight and waited for once
+            const int nobj = static_cast<int>(B - A);
+            const buf_t bc = buf_span(content + A, static_cast<uint32_t>(nobj) * ES);
+            const buf_t bm = buf_span(om ? static_cast<const void *>(om + A) : static_cast<const void *>(content),
+                                      om ? static_cast<uint32_t>(nobj) : 0u);
+            uint32_t mk[kCompactChunks], v[kCompactChunks];
+#pragma unroll
+            for (int c = 0; c < kCompactChunks; ++c) {
+                const int i = lane + 64 * c;
+                mk[c] = om ? __builtin_amdgcn_raw_buffer_load_b8(bm, i, 0, 0) : 1u;
+                if constexpr (ES == 4)
+                    v[c] = __builtin_amdgcn_raw_buffer_load_b32(bc, i * 4, 0, 0);
+                else if constexpr (ES == 2)
+                    v[c] = __builtin_amdgcn_raw_buffer_load_b16(bc, i * 2, 0, 0);
+                else
+                    v[c] = __builtin_amdgcn_raw_buffer_load_b8(bc, i, 0, 0);
+            }
+#pragma unroll
+            for (int c = 0; c < kCompactChunks; ++c) asm volatile("" ::"v"(mk[c]), "v"(v[c]));
+#pragma unroll
+            for (int c = 0; c < kCompactChunks; ++c) {
+                if (64 * c >= nobj) break;
+                const bool keep = (lane + 64 * c < nobj) & (mk[c] != 0u);
+                const uint64_t bal = __ballot(keep);
+                const int before = static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+                    static_cast<uint32_t>(bal >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bal), 0u)));
+                const int64_t dst = base + before;
+                if (keep && dst < n_out) out[dst] = static_cast<typename Elem<ES>::T>(v[c]);
+                base += __popcll(bal);
+            }
+            continue;
+        }
         for (int64_t k0 = A; k0 < B; k0 += 64) {
             const int64_t i = k0 + lane;
             const bool in = i < B;

@@ -164,6 +164,29 @@ def test_compact(n, dtype):
             assert np.array_equal(got[:10], ref.compact(off, c, mask)[:10]) and np.all(got[10:] == 0x5A)
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float16, np.uint8])
+def test_compact_dense_tiles(dtype):
+    """Tiles of more objects than the kernel reads in one batch (events of
+    12 to 20 objects), and tiles on either side of that bound."""
+    say(f"compact dense {np.dtype(dtype).name}")
+    off, cols = dense_jets(77)
+    counts = np.diff(off)
+    # events of 8 objects: 512 per tile, exactly the batch; then 9: 576
+    counts = np.concatenate([counts, np.full(64, 8), np.full(64, 9), counts[:50]])
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    m = int(off[-1])
+    rng = np.random.default_rng(77)
+    c = rng.normal(0, 1000, m).astype(dtype)
+    mask = (rng.uniform(size=m) < 0.7).astype(np.uint8)
+    for om in (None, mask):
+        want = ref.compact(off, c, om)
+        cnt, offo = H.reduce(H.COUNT, dev(off), obj_mask=None if om is None else dev(om), want_offsets=True)
+        n_out = int(offo[-1].item())
+        assert n_out == len(want)
+        got = H.compact(dev(off), dev(c), offo, n_out, obj_mask=None if om is None else dev(om))
+        assert np.array_equal(got.cpu().numpy().view(np.uint8), want.view(np.uint8))
+
+
 def test_p4_within_float32_ulps():
     say("p4")
     ds, j = jets_of(100003, 74)
