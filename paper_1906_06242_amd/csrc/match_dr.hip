@@ -45,12 +45,10 @@ __device__ __forceinline__ MaskWords<W> mask_words(const uint8_t *p, int n, int 
     MaskWords<W> m;
     m.s = static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3u);
     m.nw = n > 0 ? (n + m.s + 3) >> 2 : 0;
-    const uint32_t *pw = reinterpret_cast<const uint32_t *>(p - m.s);
+    // buffer loads over exactly the nw words (0 past them): no branch per word
+    const buf_t bw = buf_span(p - m.s, static_cast<uint32_t>(m.nw) * 4u);
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-        const int w = lane + 64 * k;
-        m.v[k] = w < m.nw ? pw[w] : 0u;
-    }
+    for (int k = 0; k < W; ++k) m.v[k] = buf_u32(bw, (lane + 64 * k) * 4);
     return m;
 }
 template <int W>
@@ -120,40 +118,58 @@ __global__ __launch_bounds__(64 * MW) void match_dr_kernel(
             continue;
         }
         const int na = static_cast<int>(A1 - A0), nb = static_cast<int>(B1 - B0);
-        // ---- every load of the tile in flight at once
-        int32_t ab = 0, ae = 0, bb = 0, bn = 0;
-        if (lane < ne) {
-            ab = static_cast<int32_t>(off_a[e] - A0);
-            ae = static_cast<int32_t>(off_a[e + 1] - A0);
-            bb = static_cast<int32_t>(off_b[e] - B0);
-            bn = static_cast<int32_t>(off_b[e + 1] - B0) - bb;
-        }
-        float veb[MKB], vpb[MKB];
+        // ---- every load of the tile in flight at once: buffer loads over
+        // exactly the tile's ranges (0 past their ends, so no slot needs a
+        // bounds test or a branch), raw bits converted after one wait
+        const uint32_t ob = static_cast<uint32_t>(ne + 1) * 8u;
+        const buf_t boa = buf_span(off_a + e0, ob), bob = buf_span(off_b + e0, ob);
+        const uint32_t oa0 = buf_u32(boa, lane * 8), oa1 = buf_u32(boa, lane * 8 + 8);
+        const uint32_t ob0 = buf_u32(bob, lane * 8), ob1 = buf_u32(bob, lane * 8 + 8);
+        const uint32_t es = sizeof(T);
+        const buf_t bea = buf_span(eta_a + A0, na * es), bpa = buf_span(phi_a + A0, na * es);
+        const buf_t beb = buf_span(eta_b + B0, nb * es), bpb = buf_span(phi_b + B0, nb * es);
+        uint32_t reb[MKB], rpb[MKB], rea[MKA], rpa[MKA];
 #pragma unroll
         for (int k = 0; k < MKB; ++k) {
-            const int i = lane + 64 * k;
-            veb[k] = vpb[k] = 0.0f;
-            if (i < nb) {
-                veb[k] = ldf(eta_b, B0 + i);
-                vpb[k] = ldf(phi_b, B0 + i);
-            }
+            reb[k] = buf_raw<T>(beb, lane + 64 * k);
+            rpb[k] = buf_raw<T>(bpb, lane + 64 * k);
         }
-        float vea[MKA], vpa[MKA];
-        bool oka[MKA];
 #pragma unroll
         for (int k = 0; k < MKA; ++k) {
-            const int i = lane + 64 * k;
-            vea[k] = vpa[k] = 0.0f;
-            oka[k] = true;
-            if (i < na) {
-                vea[k] = ldf(eta_a, A0 + i);
-                vpa[k] = ldf(phi_a, A0 + i);
-            }
+            rea[k] = buf_raw<T>(bea, lane + 64 * k);
+            rpa[k] = buf_raw<T>(bpa, lane + 64 * k);
         }
         MaskWords<MBW> mwb{};
         MaskWords<MAW> mwa{};
         if (mask_b) mwb = mask_words<MBW>(mask_b + B0, nb, lane);
         if (mask_a) mwa = mask_words<MAW>(mask_a + A0, na, lane);
+        asm volatile("" ::"v"(oa0), "v"(oa1), "v"(ob0), "v"(ob1));
+#pragma unroll
+        for (int k = 0; k < MKB; ++k) asm volatile("" ::"v"(reb[k]), "v"(rpb[k]));
+#pragma unroll
+        for (int k = 0; k < MKA; ++k) asm volatile("" ::"v"(rea[k]), "v"(rpa[k]));
+#pragma unroll
+        for (int k = 0; k < MBW; ++k) asm volatile("" ::"v"(mwb.v[k]));
+#pragma unroll
+        for (int k = 0; k < MAW; ++k) asm volatile("" ::"v"(mwa.v[k]));
+        const bool in = lane < ne;
+        const int32_t ab = in ? static_cast<int32_t>(oa0 - static_cast<uint32_t>(A0)) : 0;
+        const int32_t ae = in ? static_cast<int32_t>(oa1 - static_cast<uint32_t>(A0)) : 0;
+        const int32_t bb = in ? static_cast<int32_t>(ob0 - static_cast<uint32_t>(B0)) : 0;
+        const int32_t bn = in ? static_cast<int32_t>(ob1 - static_cast<uint32_t>(B0)) - bb : 0;
+        float veb[MKB], vpb[MKB], vea[MKA], vpa[MKA];
+        bool oka[MKA];
+#pragma unroll
+        for (int k = 0; k < MKB; ++k) {
+            veb[k] = raw_f<T>(reb[k]);
+            vpb[k] = raw_f<T>(rpb[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < MKA; ++k) {
+            vea[k] = raw_f<T>(rea[k]);
+            vpa[k] = raw_f<T>(rpa[k]);
+            oka[k] = true;
+        }
         if (mask_b || mask_a) {
             const uint8_t *mbs = mask_b ? mask_stage<MBW>(mwb, mskb_s[wave], lane) : nullptr;
             const uint8_t *mas = mask_a ? mask_stage<MAW>(mwa, mska_s[wave], lane) : nullptr;
