@@ -67,6 +67,7 @@ __global__ __launch_bounds__(64 * MW) void match_dr_kernel(
     const uint8_t *__restrict__ mask_a, const int64_t *__restrict__ off_b, const T *__restrict__ eta_b,
     const T *__restrict__ phi_b, const uint8_t *__restrict__ mask_b, int64_t n_events, float thr2,
     float *__restrict__ min_dr2, int32_t *__restrict__ idx_b, uint8_t *__restrict__ clean) {
+    static_assert(__is_same(T, float) || __is_same(T, _Float16), "content is float32 or float16 (raw_f)");
     __shared__ float beta_s[MW][64 * MKB + 2], bphi_s[MW][64 * MKB + 2];  // +2: reads past a range's end
     __shared__ uint32_t arng_s[MW][64 * MKA];  // per a object: its event's b range (first | count << 16)
     __shared__ uint32_t mskb_s[MW][64 * MBW], mska_s[MW][64 * MAW];

@@ -77,6 +77,7 @@ __global__ __launch_bounds__(RB) void reduce_kernel(const int64_t *__restrict__ 
                                                     const uint8_t *__restrict__ obj_mask,
                                                     const uint8_t *__restrict__ evt_mask, void *out,
                                                     int32_t *out_arg, int index_only) {
+    static_assert(__is_same(T, float) || __is_same(T, _Float16), "content is float32 or float16 (raw_f)");
     __shared__ float val_s[RW][(OP == R_COUNT) ? 1 : 64 * RK];
     // the tile's mask bytes as the 4-byte words that hold them (the first
     // byte of the range at byte s of the first word)
@@ -107,41 +108,56 @@ __global__ __launch_bounds__(RB) void reduce_kernel(const int64_t *__restrict__ 
         if (t + step < n_tiles) bounds(t + step, nA, nB);
         const int64_t e = e0 + lane;
         const bool act = lane < ne;
+        // the tile's loads are buffer loads over exactly its ranges (0 past
+        // their ends: no per-lane or per-slot branch), waited for together:
+        // both offsets of each event lane's event (their low 32-bit words:
+        // tile-relative differences are exact modulo 2^32), its event mask
+        // byte, and below the objects and their mask words
+        const buf_t bo = buf_span(off + e0, static_cast<uint32_t>(ne + 1) * 8u);
+        const uint32_t o0 = buf_u32(bo, lane * 8), o1 = buf_u32(bo, lane * 8 + 8);
+        const buf_t bev = buf_span(evt_mask ? static_cast<const void *>(evt_mask + e0) : static_cast<const void *>(off),
+                                   evt_mask ? static_cast<uint32_t>(ne) : 0u);
+        const uint32_t evb = evt_mask ? __builtin_amdgcn_raw_buffer_load_b8(bev, lane, 0, 0) : 1u;
         int64_t a0 = 0, a1 = 0;  // the event's objects, relative to the tile's first
         bool take = false;
-        if (act) {
-            a0 = off[e] - A;
-            a1 = off[e + 1] - A;
-            take = !evt_mask || evt_mask[e] != 0;
-        }
+        auto event_range = [&]() {
+            a0 = act ? static_cast<int32_t>(o0 - static_cast<uint32_t>(A)) : 0;
+            a1 = act ? static_cast<int32_t>(o1 - static_cast<uint32_t>(A)) : 0;
+            take = act && evb != 0u;
+        };
         Acc<OP> r;
         if (!walk_objects) {
+            event_range();
             r.cnt = take ? static_cast<int32_t>(a1 - a0) : 0;
         } else if (tot <= 64 * RK) {
             const int n = static_cast<int>(tot);
-            float v[RK];
+            const buf_t bc = buf_span(content + A, static_cast<uint32_t>(n) * sizeof(T));
+            uint32_t rv[RK];
 #pragma unroll
-            for (int k = 0; k < RK; ++k) {
-                const int i = lane + 64 * k;
-                v[k] = 0.0f;
-                if (OP != R_COUNT && i < n) v[k] = ldf(content, A + i);
-            }
+            for (int k = 0; k < RK; ++k) rv[k] = OP != R_COUNT ? buf_raw<T>(bc, lane + 64 * k) : 0u;
             // mask bytes in 4-byte loads: the aligned words that hold bytes
-            // [A, A + n) (each holds one of them, so it lies in the buffer's
-            // pages)
+            // [A, A + n)
             int s = 0, nw = 0;
             uint32_t mw[RMW];
+#pragma unroll
+            for (int k = 0; k < RMW; ++k) mw[k] = 0u;
             if (obj_mask) {
                 const uint8_t *p = obj_mask + A;
                 s = static_cast<int>(reinterpret_cast<uintptr_t>(p) & 3u);
-                const uint32_t *pw = reinterpret_cast<const uint32_t *>(p - s);
-                nw = n > 0 ? (n + s + 3) >> 2 : 0;  // every word holds a byte of the range
+                nw = n > 0 ? (n + s + 3) >> 2 : 0;
+                const buf_t bw = buf_span(p - s, static_cast<uint32_t>(nw) * 4u);
 #pragma unroll
-                for (int k = 0; k < RMW; ++k) {
-                    const int w = lane + 64 * k;
-                    mw[k] = w < nw ? pw[w] : 0u;
-                }
+                for (int k = 0; k < RMW; ++k) mw[k] = buf_u32(bw, (lane + 64 * k) * 4);
             }
+            asm volatile("" ::"v"(o0), "v"(o1), "v"(evb));
+#pragma unroll
+            for (int k = 0; k < RK; ++k) asm volatile("" ::"v"(rv[k]));
+#pragma unroll
+            for (int k = 0; k < RMW; ++k) asm volatile("" ::"v"(mw[k]));
+            event_range();
+            float v[RK];
+#pragma unroll
+            for (int k = 0; k < RK; ++k) v[k] = raw_f<T>(rv[k]);
 #pragma unroll
             for (int k = 0; k < RK; ++k) {
                 const int i = lane + 64 * k;
@@ -170,7 +186,7 @@ __global__ __launch_bounds__(RB) void reduce_kernel(const int64_t *__restrict__ 
                 if (k < b1) r.add(OP != R_COUNT ? vs[k] : 0.0f, all || ms[k] != 0, k - b0);
             }
             wave_fence();  // the next tile overwrites the staging
-        } else if (take) {
+        } else if (event_range(), take) {
             for (int64_t k = a0; k < a1; ++k)
                 r.add(OP != R_COUNT ? ldf(content, A + k) : 0.0f, !obj_mask || obj_mask[A + k] != 0,
                       static_cast<int32_t>(k - a0));
