@@ -83,12 +83,16 @@ __device__ __forceinline__ float buf_ldf(buf_t r, int i) {
 // Element i of a float32 or float16 buffer as its raw bits (0 beyond the
 // range), converted by raw_f only where the value is used: a load whose
 // conversion sits right behind it would be waited for there.
-template <typename T>
+// AUX is the load's cache policy: 0, or kBufNt for the nontemporal hint
+// (data read once; it measured faster in some kernels and slower in others).
+constexpr int kBufNt = 2;
+
+template <typename T, int AUX = 0>
 __device__ __forceinline__ uint32_t buf_raw(buf_t r, int i) {
     if constexpr (sizeof(T) == 4)
-        return __builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, 0);
+        return __builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, AUX);
     else
-        return __builtin_amdgcn_raw_buffer_load_b16(r, i * 2, 0, 0);
+        return __builtin_amdgcn_raw_buffer_load_b16(r, i * 2, 0, AUX);
 }
 
 template <typename T>
@@ -99,8 +103,9 @@ __device__ __forceinline__ float raw_f(uint32_t b) {
         return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(b)));
 }
 
+template <int AUX = 0>
 __device__ __forceinline__ uint32_t buf_u32(buf_t r, int byte) {
-    return __builtin_amdgcn_raw_buffer_load_b32(r, byte, 0, 0);
+    return __builtin_amdgcn_raw_buffer_load_b32(r, byte, 0, AUX);
 }
 
 __device__ __forceinline__ float ld_any(const void *p, int32_t dtype, int64_t i) {

@@ -210,13 +210,13 @@ __global__ __launch_bounds__(PB) void compact_kernel(const int64_t *__restrict__
 #pragma unroll
             for (int c = 0; c < kCompactChunks; ++c) {
                 const int i = lane + 64 * c;
-                mk[c] = om ? __builtin_amdgcn_raw_buffer_load_b8(bm, i, 0, 0) : 1u;
+                mk[c] = om ? __builtin_amdgcn_raw_buffer_load_b8(bm, i, 0, kBufNt) : 1u;
                 if constexpr (ES == 4)
-                    v[c] = __builtin_amdgcn_raw_buffer_load_b32(bc, i * 4, 0, 0);
+                    v[c] = __builtin_amdgcn_raw_buffer_load_b32(bc, i * 4, 0, kBufNt);
                 else if constexpr (ES == 2)
-                    v[c] = __builtin_amdgcn_raw_buffer_load_b16(bc, i * 2, 0, 0);
+                    v[c] = __builtin_amdgcn_raw_buffer_load_b16(bc, i * 2, 0, kBufNt);
                 else
-                    v[c] = __builtin_amdgcn_raw_buffer_load_b8(bc, i, 0, 0);
+                    v[c] = __builtin_amdgcn_raw_buffer_load_b8(bc, i, 0, kBufNt);
             }
 #pragma unroll
             for (int c = 0; c < kCompactChunks; ++c) asm volatile("" ::"v"(mk[c]), "v"(v[c]));

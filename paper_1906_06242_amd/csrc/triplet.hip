@@ -200,11 +200,11 @@ __global__ __launch_bounds__(TB) void best_triplet_kernel(const int64_t *__restr
 #pragma unroll
         for (int k = 0; k < TK; ++k) {
             const int i = lane + 64 * k;
-            vx[k] = __builtin_bit_cast(float, buf_u32(bx, i * 4));
-            vy[k] = __builtin_bit_cast(float, buf_u32(by, i * 4));
-            vz[k] = __builtin_bit_cast(float, buf_u32(bz, i * 4));
-            ve[k] = __builtin_bit_cast(float, buf_u32(be, i * 4));
-            mk[k] = om ? __builtin_amdgcn_raw_buffer_load_b8(bm, i, 0, 0) : 1u;
+            vx[k] = __builtin_bit_cast(float, buf_u32<kBufNt>(bx, i * 4));
+            vy[k] = __builtin_bit_cast(float, buf_u32<kBufNt>(by, i * 4));
+            vz[k] = __builtin_bit_cast(float, buf_u32<kBufNt>(bz, i * 4));
+            ve[k] = __builtin_bit_cast(float, buf_u32<kBufNt>(be, i * 4));
+            mk[k] = om ? __builtin_amdgcn_raw_buffer_load_b8(bm, i, 0, kBufNt) : 1u;
         }
 #pragma unroll
         for (int k = 0; k < TK; ++k) asm volatile("" ::"v"(vx[k]), "v"(vy[k]), "v"(vz[k]), "v"(ve[k]), "v"(mk[k]));

@@ -82,6 +82,29 @@ def test_select_matches_oracle(n):
             assert np.array_equal(host(got), want)
 
 
+def test_select_every_cut_count():
+    """Every cut count 0..8 (one kernel each), rows not a multiple of four,
+    and 4e7 rows: more than one grid-stride step, the last one partial (its
+    lanes past the end load the last group again and store nothing)."""
+    say("select every cut count, 4e7 rows")
+    rng = np.random.default_rng(77)
+    N = 40_000_003
+    a = rng.normal(30, 10, N).astype(np.float32)
+    b = rng.normal(0, 2, N).astype(np.float16)
+    c = rng.integers(-5, 6, N).astype(np.int32)
+    m = (rng.uniform(size=N) < 0.9).astype(np.uint8)
+    da, db, dc, dm = dev(a), dev(b), dev(c), dev(m)
+    pool = [(a, da, H.GT, 15.0), (b, db, H.ABS_LT, 3.0), (c, dc, H.GE, -4), (a, da, H.LT, 50.0),
+            (b, db, H.GE, -3.5), (c, dc, H.ABS_LE, 4), (a, da, H.ABS_LE, 48.0), (b, db, H.LE, 3.7)]
+    for k in range(len(pool) + 1):
+        for n in (4003, N):
+            for masked in (False, True):
+                cuts = pool[:k]
+                want = ref.select([(x[:n], op, t) for x, _, op, t in cuts], n, mask_in=m[:n] if masked else None)
+                got = H.select([(d[:n], op, t) for _, d, op, t in cuts], n, mask_in=dm[:n] if masked else None)
+                assert np.array_equal(host(got), want), (k, n, masked)
+
+
 def test_select_unaligned_masks():
     import torch
     say("select unaligned")
