@@ -1,7 +1,7 @@
 // hepk_hist_fill: weighted 1-D histogram fill (Sec. III fill-histogram
 // kernel), accumulating into the caller's histogram.
 //
-// Each workgroup (1024 threads, two per CU) keeps a private copy of the
+// Each workgroup (1024 threads, one per CU) keeps a private copy of the
 // histogram in LDS (float64 sums via ds_add_f64, uint32 counts via
 // ds_add_u32) together with the bin edges, walks a grid-stride range of rows
 // eight at a time per thread (loads of the eight rows in flight together,
@@ -19,6 +19,9 @@ namespace hepk {
 
 constexpr int HB = 1024;
 constexpr int HR = 8;  // rows per thread in flight
+// One workgroup per CU: a sweep of 1-4 per CU and 4-16 rows per thread in
+// flight put the best at one and 8 (two workgroups: 5% slower).
+constexpr int kHistWgPerCu = 1;
 constexpr int kMaxLdsSlots = 3000;    // 36 KiB of histogram + 12 KiB of edges
 constexpr int kMaxLdsSlotsW2 = 2400;  // with the squared weights: 48 KiB + 9.6 KiB
 
@@ -124,17 +127,25 @@ __global__ __launch_bounds__(HB) void hist_kernel(const X *__restrict__ x, const
 }
 
 // Four consecutive values of x as float (one 16- or 8-byte load).
+typedef float hf32x4 __attribute__((ext_vector_type(4)));
+typedef int hi32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int hu32x2 __attribute__((ext_vector_type(2)));
+// Nontemporal loads: every row is read once (3-5% faster than plain loads).
+template <typename V>
+__device__ __forceinline__ V ldv(const V *p) {
+    return __builtin_nontemporal_load(p);
+}
 __device__ __forceinline__ void load4(const float *p, float (&o)[4]) {
-    const float4 v = *reinterpret_cast<const float4 *>(p);
+    const hf32x4 v = ldv(reinterpret_cast<const hf32x4 *>(p));
     o[0] = v.x, o[1] = v.y, o[2] = v.z, o[3] = v.w;
 }
 __device__ __forceinline__ void load4(const int32_t *p, float (&o)[4]) {
-    const int4 v = *reinterpret_cast<const int4 *>(p);
+    const hi32x4 v = ldv(reinterpret_cast<const hi32x4 *>(p));
     o[0] = static_cast<float>(v.x), o[1] = static_cast<float>(v.y);
     o[2] = static_cast<float>(v.z), o[3] = static_cast<float>(v.w);
 }
 __device__ __forceinline__ void load4(const _Float16 *p, float (&o)[4]) {
-    const uint2 v = *reinterpret_cast<const uint2 *>(p);
+    const hu32x2 v = ldv(reinterpret_cast<const hu32x2 *>(p));
     const uint32_t u[2] = {v.x, v.y};
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -195,11 +206,12 @@ __global__ __launch_bounds__(HB) void hist_vec_kernel(const X *__restrict__ x, c
             float xv[4] = {0.0f, 0.0f, 0.0f, 0.0f}, wv[4] = {1.0f, 1.0f, 1.0f, 1.0f};
             uint32_t mv = 0xffffffffu;
             const bool in = qq < nq;
-            if (in) {
-                load4(x + 4 * qq, xv);
-                if (w) load4(w + 4 * qq, wv);
-                if (m) mv = *reinterpret_cast<const uint32_t *>(m + 4 * qq);
-            }
+            // quads past the end load the last quad again (kept out by
+            // `in`), so no load sits under a per-lane branch
+            const int64_t qc = in ? qq : nq - 1;
+            load4(x + 4 * qc, xv);
+            if (w) load4(w + 4 * qc, wv);
+            if (m) mv = ldv(reinterpret_cast<const uint32_t *>(m + 4 * qc));
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 v[4 * h + j] = xv[j];
@@ -231,7 +243,7 @@ static int launch_hist(const void *x, const float *w, const uint8_t *m, int64_t 
                        double *sumw2, hipStream_t stream) {
     const int nslots = h->nbins + 2;
     const bool lds = nslots <= (W2 ? kMaxLdsSlotsW2 : kMaxLdsSlots);
-    const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n, HB * HR), 2 * device_cus()));
+    const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n, HB * HR), kHistWgPerCu * device_cus()));
     const size_t lds_bytes = static_cast<size_t>(nslots) * ((W2 ? 2 : 1) * sizeof(double) + sizeof(uint32_t)) +
                              static_cast<size_t>(h->nbins + 1) * sizeof(float);
     auto aligned = [](const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; };

@@ -40,21 +40,59 @@ constexpr int TWV = TB / 64;
 // per wavefront, so four wavefronts per SIMD instead of three with 512)
 constexpr int TK = 6;
 
+__device__ __forceinline__ void p4_one(float p, float h, float f, float m, float &x, float &y, float &z, float &e) {
+    float s, c;
+    sincosf(f, &s, &c);
+    x = p * c, y = p * s, z = p * sinhf(h);
+    const float xx = x * x, yy = y * y, zz = z * z, mm = m * m;
+    e = sqrtf(((xx + yy) + zz) + mm);
+}
+
 __global__ __launch_bounds__(256) void p4_kernel(const float *__restrict__ pt, const float *__restrict__ eta,
                                                  const float *__restrict__ phi, const float *__restrict__ mass,
                                                  int64_t n, float *__restrict__ px, float *__restrict__ py,
                                                  float *__restrict__ pz, float *__restrict__ en) {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) {
-        const float p = pt[i], h = eta[i], f = phi[i], m = mass[i];
-        float s, c;
-        sincosf(f, &s, &c);
-        const float x = p * c, y = p * s, z = p * sinhf(h);
-        const float xx = x * x, yy = y * y, zz = z * z, mm = m * m;
-        px[i] = x;
-        py[i] = y;
-        pz[i] = z;
-        en[i] = sqrtf(((xx + yy) + zz) + mm);
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride)
+        p4_one(pt[i], eta[i], phi[i], mass[i], px[i], py[i], pz[i], en[i]);
+}
+
+// Up to 64 workgroups per CU (a sweep of 8-64: 64 best; with nontemporal
+// loads and stores, every byte touched once: 312 -> 284 us on 5e7 jets).
+constexpr int kP4WgPerCu = 64;
+typedef float p4f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ p4f32x4 p4ld(const float *p, int64_t q) {
+    return __builtin_nontemporal_load(reinterpret_cast<const p4f32x4 *>(p) + q);
+}
+__device__ __forceinline__ void p4st(p4f32x4 v, float *p, int64_t q) {
+    __builtin_nontemporal_store(v, reinterpret_cast<p4f32x4 *>(p) + q);
+}
+
+// Four consecutive objects per thread and step (all eight columns 16-byte
+// aligned): one 16-byte load per input column and one 16-byte store per
+// output column; the n % 4 last objects one per thread.
+__global__ __launch_bounds__(256) void p4_vec4_kernel(const float *__restrict__ pt, const float *__restrict__ eta,
+                                                      const float *__restrict__ phi, const float *__restrict__ mass,
+                                                      int64_t n, float *__restrict__ px, float *__restrict__ py,
+                                                      float *__restrict__ pz, float *__restrict__ en) {
+    const int64_t n4 = n / 4;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (gid < n - 4 * n4) {
+        const int64_t i = 4 * n4 + gid;
+        p4_one(pt[i], eta[i], phi[i], mass[i], px[i], py[i], pz[i], en[i]);
+    }
+    for (int64_t q = gid; q < n4; q += stride) {
+        const p4f32x4 p = p4ld(pt, q), h = p4ld(eta, q), f = p4ld(phi, q), m = p4ld(mass, q);
+        float xs[4], ys[4], zs[4], es[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) p4_one(p[j], h[j], f[j], m[j], xs[j], ys[j], zs[j], es[j]);
+        const p4f32x4 x = {xs[0], xs[1], xs[2], xs[3]}, y = {ys[0], ys[1], ys[2], ys[3]};
+        const p4f32x4 z = {zs[0], zs[1], zs[2], zs[3]}, e = {es[0], es[1], es[2], es[3]};
+        p4st(x, px, q);
+        p4st(y, py, q);
+        p4st(z, pz, q);
+        p4st(e, en, q);
     }
 }
 
@@ -350,6 +388,17 @@ extern "C" int hepk_p4(const float *pt, const float *eta, const float *phi, cons
     HEPK_REQUIRE(n >= 0, "hepk_p4: n < 0");
     HEPK_REQUIRE(n == 0 || (pt && eta && phi && mass && px && py && pz && en), "hepk_p4: NULL column");
     if (n == 0) return HEPK_OK;
+    bool al = true;
+    for (const void *p : {static_cast<const void *>(pt), static_cast<const void *>(eta), static_cast<const void *>(phi),
+                          static_cast<const void *>(mass), static_cast<const void *>(px), static_cast<const void *>(py),
+                          static_cast<const void *>(pz), static_cast<const void *>(en)})
+        al = al && reinterpret_cast<uintptr_t>(p) % 16 == 0;
+    if (al) {
+        const int g = static_cast<int>(
+            std::max<int64_t>(1, std::min<int64_t>(ceil_div(n / 4, 256), kP4WgPerCu * device_cus())));
+        p4_vec4_kernel<<<g, 256, 0, stream>>>(pt, eta, phi, mass, n, px, py, pz, en);
+        return check_launch("hepk_p4");
+    }
     const int g = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 16 * device_cus())));
     p4_kernel<<<g, 256, 0, stream>>>(pt, eta, phi, mass, n, px, py, pz, en);
     return check_launch("hepk_p4");

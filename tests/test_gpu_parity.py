@@ -359,6 +359,29 @@ def test_hist_fill_matches_oracle(edges_kind):
         assert_hist((host(s), host(c)), (ws, wc), f"{edges_kind} views at {k}")
 
 
+def test_hist_fill_several_grid_steps():
+    """5e6 + 3 rows: more rows than one grid step covers (one 1024-thread
+    workgroup per CU, eight rows per thread), so both kernels walk several
+    steps, the last one partial; aligned inputs (four rows at a time) and
+    inputs offset by one row (row at a time)."""
+    import torch
+    say("hist several grid steps")
+    rng = np.random.default_rng(8)
+    n = 5_000_003
+    edges = datagen.uniform_edges(100, 0.0, 2000.0)
+    x = rng.uniform(-100, 2100, n + 1).astype(np.float32)
+    w = rng.normal(1, 0.1, n + 1).astype(np.float32)
+    m = (rng.uniform(size=n + 1) < 0.75).astype(np.uint8)
+    de, dx, dw, dm = dev(edges), dev(x), dev(w), dev(m)
+    for off in (0, 1):
+        for masked in (False, True):
+            ws, wc = ref.hist_fill(x[off:off + n], edges, w[off:off + n], m[off:off + n] if masked else None)
+            s = torch.zeros(len(edges) + 1, dtype=torch.float64, device="cuda")
+            c = torch.zeros(len(edges) + 1, dtype=torch.int64, device="cuda")
+            H.hist_fill(dx[off:off + n], de, s, c, w=dw[off:off + n], evt_mask=dm[off:off + n] if masked else None)
+            assert_hist((host(s), host(c)), (ws, wc), f"offset {off} masked {masked}")
+
+
 def test_hist_fill_int_and_half_inputs():
     import torch
     say("hist int32/f16")

@@ -202,6 +202,23 @@ def test_p4_within_float32_ulps():
         assert np.all(err <= 16 * ulp * s), f"{name}: max err / scale {np.max(err / s) / ulp:.1f} ulp"
 
 
+def test_p4_vector_and_row_kernels_agree():
+    """Columns offset by one object (not 16-byte aligned: one object per
+    thread) and the same values in fresh allocations (four objects per thread,
+    the n % 4 last ones one per thread) give the same bits."""
+    import torch
+    say("p4 vector and row kernels")
+    ds, j = jets_of(50001, 75)
+    c = j.cols
+    n = c["pt"].size - (1 if c["pt"].size % 4 == 0 else 0)
+    cols = [dev(np.concatenate([[0.0], c[k][:n]]).astype(np.float32)) for k in ("pt", "eta", "phi", "mass")]
+    rows = H.p4(*[x[1:] for x in cols])
+    vec = H.p4(*[x[1:].clone() for x in cols])
+    assert n % 4 != 0
+    for u, v, name in zip(rows, vec, ("px", "py", "pz", "E")):
+        assert torch.equal(u.view(torch.int32), v.view(torch.int32)), name
+
+
 @pytest.mark.parametrize("source", ["analysis", "dense"])
 def test_best_triplet_bit_exact(source):
     say(f"best triplet {source}")
