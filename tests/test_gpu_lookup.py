@@ -124,6 +124,26 @@ def test_lookup_tables_of_the_analysis():
     assert_same_f32(H.interp(dev(mpt), dev(se), dev(sc)).cpu().numpy(), ref.interp(mpt, se, sc), "muon sf interp")
 
 
+def test_lookups_several_grid_steps():
+    """2e7 + 3 rows: more rows than one grid step covers (16 workgroups per
+    CU for the one-dimensional lookups, 64 for the shift), so every kernel
+    walks several steps, the last one partial; bits equal to the oracle's."""
+    say("lookups several grid steps")
+    rng = np.random.default_rng(91)
+    n = 20_000_003
+    pe, pc = datagen.pileup_table()
+    se, sc = datagen.muon_sf_table()
+    ee, pte, d = datagen.jes_table()
+    x = rng.uniform(0.0, 200.0, n).astype(np.float32)
+    h = rng.uniform(-5.0, 5.0, n).astype(np.float32)
+    dx = dev(x)
+    assert_same_f32(H.get_bin_contents(dx, dev(pe), dev(pc)).cpu().numpy(), ref.get_bin_contents(x, pe, pc),
+                    "contents")
+    assert_same_f32(H.interp(dx, dev(se), dev(sc)).cpu().numpy(), ref.interp(x, se, sc), "interp")
+    assert_same_f32(H.jes_delta(dx, dev(h), dev(ee), dev(pte), dev(d)).cpu().numpy(),
+                    ref.jes_delta(x, h, ee, pte, d), "jes shift")
+
+
 @pytest.mark.parametrize("n", [0, 3, 4099, 200001])
 @pytest.mark.parametrize("content", ["f32", "f16"])
 def test_jes_delta(n, content):
