@@ -19,6 +19,9 @@
 
 namespace hepk {
 
+// Workgroups per CU, at most: a sweep of 8-64 put the best at 64 (16: 5% slower).
+constexpr int kTileWgPerCu = 64;
+
 constexpr int MW = 4;    // wavefronts per workgroup
 constexpr int MKA = 8;   // a objects per lane: 512 per tile
 constexpr int MKB = 4;   // b objects per lane: 256 per tile
@@ -281,7 +284,7 @@ extern "C" int hepk_match_dr(const int64_t *off_a, const void *eta_a, const void
     if (n_events == 0 || (!min_dr2 && !idx_b && !clean_out)) return HEPK_OK;
     const float thr2 = dr * dr;  // rounded once to float32
     const int64_t n_tiles = ceil_div(n_events, 64);
-    const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n_tiles, MW), 16 * device_cus()));
+    const int grid = static_cast<int>(std::min<int64_t>(ceil_div(n_tiles, MW), kTileWgPerCu * device_cus()));
     if (dtype == HEPK_F16)
         match_dr_kernel<_Float16><<<grid, 64 * MW, 0, stream>>>(
             off_a, static_cast<const _Float16 *>(eta_a), static_cast<const _Float16 *>(phi_a), mask_a, off_b,
